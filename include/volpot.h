@@ -1,0 +1,149 @@
+/* volpot.h -- C ABI of the MI355X machine code for the 2D Laplace volume potential.
+ *
+ * What is computed (Sec. 4.2, eq. (vbulk) of Fortunato, Stein & Barnett, "A fully adaptive,
+ * high-order, fast Poisson solver for complex two-dimensional geometries"): the volume
+ * potential of leaf data on an adaptive, 2:1-balanced quadtree,
+ *
+ *     u(x) = int_{Omega_B} G(x - y) f_h(y) dy,      G(r) = -(1/2 pi) log |r|,
+ *
+ * evaluated at every leaf node. Omega_B is the union of the leaves; on each leaf f_h is the
+ * order-p tensor Chebyshev interpolant of the nodal values the caller supplies (Sec. 4.2.1,
+ * "Constructing a quadtree approximation to f"). The sign is chosen so that -Lap u = f; the
+ * paper's v_bulk equals -u.
+ *
+ * Conventions
+ *   root box      [-1,1]^2 at level 0; a level-l box has half-width s_l = 2^-l; levels 0..29.
+ *   leaf nodes    p = 16 first-kind Chebyshev points per dimension,
+ *                 t_i = -cos((2i-1) pi / (2p)), i = 1..p (ascending); see volpot_nodes.
+ *   leaf data     FP64, contiguous [n_leaves][p][p]: leaf in the caller's order, then the y
+ *                 index j, then the x index i (x fastest). Same layout for f, u, their
+ *                 cotangents, and for every tree of a forest (trees concatenated).
+ *   balance       neighbouring leaves (sharing an edge or a corner) differ by at most one level
+ *                 (the 2:1 balance the paper applies after building the tree, Sec. 4.2.1).
+ *
+ * Ownership and streams
+ *   A plan owns every device table, list and workspace it needs; they are allocated by
+ *   volpot_plan / volpot_plan_forest, so volpot_apply and volpot_apply_adjoint allocate
+ *   nothing. The caller owns f, u and the stream. Both apply calls are asynchronous on the
+ *   given hipStream_t (NULL = the default stream) and do not synchronise the host. One plan
+ *   serves one stream at a time (its workspace is shared); destroy a plan only after work
+ *   queued on it has completed. Input and output arrays must not alias.
+ *
+ * Errors
+ *   Every call returns a status code (VOLPOT_OK = 0, negative on error) and never throws.
+ *   Invalid trees are rejected at plan time; volpot_validate_tree reports the first offending
+ *   leaf. NaN/Inf in the data are not checked and propagate.
+ */
+#ifndef VOLPOT_H
+#define VOLPOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct volpot_plan_s* volpot_plan_t;
+
+enum {
+  VOLPOT_OK = 0,
+  VOLPOT_ERR_ARG = -1,         /* null pointer, bad size or option */
+  VOLPOT_ERR_TREE = -2,        /* leaves do not tile the root, overlap, or are off the level grid */
+  VOLPOT_ERR_UNBALANCED = -3,  /* two adjacent leaves differ by more than one level */
+  VOLPOT_ERR_UNSUPPORTED = -4, /* p other than 16, level above 29 */
+  VOLPOT_ERR_HIP = -5,         /* a HIP runtime call failed */
+  VOLPOT_ERR_OOM = -6,         /* device or host allocation failed */
+  VOLPOT_ERR_STATE = -7        /* plan built host-only, or destroyed */
+};
+
+typedef struct {
+  int32_t host_only;       /* 1: build lists and tables on the host only (no device memory;
+                              apply calls return VOLPOT_ERR_STATE). Default 0. */
+  int32_t use_graph;       /* 1: capture each apply once per (input, output) pointer pair into
+                              a hipGraph and replay it. Default 0. */
+  int32_t tile_leaf;       /* slots per tile of the leaf-output stages: 32 or 64; 0 = default */
+  int32_t tile_box;        /* slots per tile of the expansion stages: 16, 32 or 64; 0 = default */
+  const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
+} volpot_options;
+
+/* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
+ * non-zeros of every applied real matrix (zero padding of MFMA tiles not counted). */
+typedef struct {
+  int64_t n_leaves, n_boxes, n_trees;
+  int32_t max_level, order, n_reals, n_stages;
+  int64_t pairs_near, pairs_v, pairs_w, pairs_x, n_m2m, n_l2l, n_s2m, n_l2t;
+  double flops_total;       /* forward apply; the adjoint does the same work */
+  double flops_leaf_stage;  /* near field + M2T + L2T (the leaf-output stage) */
+  double flops_up, flops_down;
+  double bytes_min;         /* mandatory HBM traffic: 16 B per unknown (f in, u out) */
+  int64_t device_bytes;     /* device memory the plan holds (tables shared per device) */
+} volpot_info;
+
+/* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
+ *   centres  host, n_leaves x 2 (x, y) leaf centres; must sit on their level's grid
+ *   levels   host, n_leaves leaf levels (0..29)
+ *   opt      nullable; defaults as documented in volpot_options
+ *   out      receives the plan; untouched on error
+ * Returns VOLPOT_ERR_TREE / _UNBALANCED for invalid trees, _UNSUPPORTED for p != 16. */
+int volpot_plan(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p,
+                const volpot_options* opt, volpot_plan_t* out);
+
+/* Plan for n_trees independent trees applied together (one launch per stage for all trees).
+ *   tree_offsets  host, n_trees + 1 ascending offsets into centres/levels (first 0)
+ * Each tree has its own root [-1,1]^2; data of tree t occupy leaves
+ * [tree_offsets[t], tree_offsets[t+1]) of f and u. */
+int volpot_plan_forest(int32_t n_trees, const int64_t* tree_offsets, const double* centres,
+                       const int32_t* levels, int32_t p, const volpot_options* opt,
+                       volpot_plan_t* out);
+
+/* u = A f: the volume potential of the leaf data at all leaf nodes (eq. (vbulk) with the
+ * sign -Lap u = f). f_dev, u_dev: device FP64 arrays [n_leaves][16][16]. */
+int volpot_apply(volpot_plan_t plan, const double* f_dev, double* u_dev, void* hip_stream);
+
+/* fbar = A^T ubar: the exact transpose of the discrete operator applied by volpot_apply
+ * (the gradient of <ubar, A f> with respect to f). Same layout and stream rules. */
+int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fbar_dev,
+                         void* hip_stream);
+
+/* Sizes and algorithmic flop/byte counts of the plan. */
+int volpot_plan_info(volpot_plan_t plan, volpot_info* out);
+
+/* Host-only check of a tree (tiling of the root, level grid, 2:1 balance over edges and
+ * corners). On error *bad_index (nullable) receives the first offending leaf. */
+int volpot_validate_tree(const double* centres, const int32_t* levels, int64_t n_leaves,
+                         int32_t p, int64_t* bad_index);
+
+/* The node convention: t[i] (p ascending first-kind Chebyshev points) and w[i], the weights
+ * of the interpolatory rule on them (w_i = integral over [-1,1] of the i-th Lagrange basis). */
+int volpot_nodes(int32_t p, double* t, double* w);
+
+/* Release a plan (NULL is ignored). Work queued on it must have completed. */
+void volpot_plan_destroy(volpot_plan_t plan);
+
+/* Static text for a status code. */
+const char* volpot_status_string(int status);
+
+/* Timing hooks for measurement. When enabled, apply calls record a HIP event pair around
+ * every stage launch on the apply stream; volpot_stage_times synchronises those events and
+ * returns, per stage kind k (0 upward, 1 downward, 2 leaf, 3 adjoint-upward,
+ * 4 adjoint-downward, 5 adjoint-leaf, 6 adjoint-sum), the summed milliseconds ms[k] and
+ * launch counts n[k] since the last reset, then resets. Disabled by default; not available
+ * with use_graph. */
+int volpot_set_timing(volpot_plan_t plan, int32_t enable);
+int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_t n_kinds);
+
+/* Inspection: copy a host-side table of the plan (row-major) into out (n doubles).
+ *   kind 0: near table of relation index (0..32, see volpot_near_relation), 256 x 256
+ *   kind 1: S2M (80 x 256);   kind 2: L2T (256 x 80)
+ * Returns VOLPOT_ERR_ARG for an unknown kind/index or n too small. */
+int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
+
+/* Geometry of near relation r (0..32): offset (dx, dy) of the source leaf centre from the
+ * target leaf centre in target half-widths, and rho = source / target half-width. */
+int volpot_near_relation(int32_t r, double* dx, double* dy, double* rho);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOLPOT_H */

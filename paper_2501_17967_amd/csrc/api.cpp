@@ -1,0 +1,514 @@
+// C ABI of the box code (declared in include/volpot.h): plan lifecycle, device upload of the
+// shared tables and per-plan schedules, and the stage launch sequence of apply / adjoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "../../include/volpot.h"
+#include "device.hpp"
+#include "plan.hpp"
+
+using namespace vp;
+
+namespace {
+
+// ---------------------------------------------------------------- shared device tables
+struct DeviceTables {
+  int device = -1;
+  double* buf = nullptr;
+  RelDesc* d_rels = nullptr;
+  size_t bytes = 0;
+  int refs = 0;
+};
+std::mutex g_mu;
+std::map<int, DeviceTables*> g_tables;
+
+int acquire_tables(int device, DeviceTables** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tables.find(device);
+  if (it != g_tables.end()) {
+    it->second->refs++;
+    *out = it->second;
+    return VOLPOT_OK;
+  }
+  const Matrices& M = matrices();
+  std::vector<size_t> off(kNumRel);
+  size_t total = 0;
+  for (int r = 0; r < kNumRel; ++r) {
+    off[r] = total;
+    total += size_t(M.M[r]) * M.K[r];
+  }
+  std::vector<double> host(total);
+  for (int r = 0; r < kNumRel; ++r) {
+    const int rows = M.M[r], cols = M.K[r], nt = rows / 16;
+    const double* a = M.a[r].data();
+    double* f = host.data() + off[r];
+    for (int kk = 0; kk < cols / 4; ++kk)
+      for (int i = 0; i < nt; ++i)
+        for (int l = 0; l < 64; ++l) f[(size_t(kk) * nt + i) * 64 + l] = a[size_t(16 * i + (l & 15)) * cols + 4 * kk + (l >> 4)];
+  }
+  auto* T = new (std::nothrow) DeviceTables();
+  if (!T) return VOLPOT_ERR_OOM;
+  T->device = device;
+  T->bytes = total * sizeof(double) + kNumRel * sizeof(RelDesc);
+  if (hipMalloc(&T->buf, total * sizeof(double)) != hipSuccess) { delete T; return VOLPOT_ERR_OOM; }
+  if (hipMalloc(&T->d_rels, kNumRel * sizeof(RelDesc)) != hipSuccess) { (void)hipFree(T->buf); delete T; return VOLPOT_ERR_OOM; }
+  std::vector<RelDesc> rd(kNumRel);
+  for (int r = 0; r < kNumRel; ++r) rd[r] = {T->buf + off[r], M.M[r], M.K[r]};
+  if (hipMemcpy(T->buf, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(T->d_rels, rd.data(), kNumRel * sizeof(RelDesc), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(T->buf); (void)hipFree(T->d_rels); delete T;
+    return VOLPOT_ERR_HIP;
+  }
+  T->refs = 1;
+  g_tables[device] = T;
+  *out = T;
+  return VOLPOT_OK;
+}
+
+void release_tables(DeviceTables* T) {
+  if (!T) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (--T->refs == 0) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(T->device);
+    (void)hipFree(T->buf);
+    (void)hipFree(T->d_rels);
+    (void)hipSetDevice(prev);
+    g_tables.erase(T->device);
+    delete T;
+  }
+}
+
+struct DevStage {
+  const Stage* st = nullptr;
+  int32_t *tile_tgt = nullptr, *tile_seg_ptr = nullptr, *seg_rel = nullptr, *seg_src = nullptr;
+  int8_t* seg_fam = nullptr;
+  int32_t *r1_ptr = nullptr, *r1_idx = nullptr;
+  int8_t* r1_fam = nullptr;
+  double* r1_coef = nullptr;
+};
+
+struct GraphEntry {
+  const void* in;
+  void* out;
+  bool adjoint;
+  hipGraphExec_t exec;
+};
+
+struct Pending { int kind; hipEvent_t a, b; };
+
+}  // namespace
+
+struct volpot_plan_s {
+  Plan host;
+  bool host_only = false;
+  bool use_graph = false;
+  int device = -1;
+  DeviceTables* tables = nullptr;
+  char* d_block = nullptr;
+  double *d_mp = nullptr, *d_loc = nullptr, *d_lb = nullptr, *d_ab = nullptr, *d_usum = nullptr, *d_leaf_s2 = nullptr;
+  std::vector<DevStage> dfwd, dadj;
+  int64_t device_bytes = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<Pending> pending;
+  double ms[K_NUM] = {0};
+  int64_t cnt[K_NUM] = {0};
+  hipStream_t cap_stream = nullptr;
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (dev >= 0 && dev != prev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+size_t add_bytes(size_t& total, const std::vector<T>& v) {
+  size_t o = (total + 255) & ~size_t(255);
+  total = o + std::max<size_t>(v.size(), 1) * sizeof(T);
+  return o;
+}
+
+int upload(volpot_plan_s* p) {
+  Plan& P = p->host;
+  size_t total = 0;
+  const size_t nb = size_t(P.n_boxes) * kNE * sizeof(double);
+  struct Off { size_t tt, tsp, sr, sf, ss, rp, ri, rf, rc; };
+  auto plan_stage = [&](const Stage& s) {
+    Off o;
+    o.tt = add_bytes(total, s.tile_tgt); o.tsp = add_bytes(total, s.tile_seg_ptr); o.sr = add_bytes(total, s.seg_rel);
+    o.sf = add_bytes(total, s.seg_fam); o.ss = add_bytes(total, s.seg_src); o.rp = add_bytes(total, s.r1_ptr);
+    o.ri = add_bytes(total, s.r1_idx); o.rf = add_bytes(total, s.r1_fam); o.rc = add_bytes(total, s.r1_coef);
+    return o;
+  };
+  std::vector<Off> ofw, oad;
+  for (auto& s : P.fwd) ofw.push_back(plan_stage(s));
+  for (auto& s : P.adj) oad.push_back(plan_stage(s));
+  size_t o_mp = (total + 255) & ~size_t(255); total = o_mp + nb;
+  size_t o_loc = (total + 255) & ~size_t(255); total = o_loc + nb;
+  size_t o_lb = (total + 255) & ~size_t(255); total = o_lb + nb;
+  size_t o_ab = (total + 255) & ~size_t(255); total = o_ab + nb;
+  size_t o_us = (total + 255) & ~size_t(255); total = o_us + size_t(P.n_leaves) * sizeof(double);
+  std::vector<double> s2(P.leaf_s2);
+  size_t o_s2 = add_bytes(total, s2);
+  std::vector<char> host(total, 0);
+  auto put = [&](size_t o, const auto& v) {
+    if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
+  };
+  for (size_t i = 0; i < P.fwd.size(); ++i) {
+    const Stage& s = P.fwd[i]; const Off& o = ofw[i];
+    put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sr, s.seg_rel); put(o.sf, s.seg_fam); put(o.ss, s.seg_src);
+    put(o.rp, s.r1_ptr); put(o.ri, s.r1_idx); put(o.rf, s.r1_fam); put(o.rc, s.r1_coef);
+  }
+  for (size_t i = 0; i < P.adj.size(); ++i) {
+    const Stage& s = P.adj[i]; const Off& o = oad[i];
+    put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sr, s.seg_rel); put(o.sf, s.seg_fam); put(o.ss, s.seg_src);
+    put(o.rp, s.r1_ptr); put(o.ri, s.r1_idx); put(o.rf, s.r1_fam); put(o.rc, s.r1_coef);
+  }
+  put(o_s2, s2);
+  if (hipMalloc(&p->d_block, total) != hipSuccess) return VOLPOT_ERR_OOM;
+  p->device_bytes = int64_t(total);
+  if (hipMemcpy(p->d_block, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return VOLPOT_ERR_HIP;
+  char* b = p->d_block;
+  auto mk = [&](const Stage& s, const Off& o) {
+    DevStage d;
+    d.st = &s;
+    d.tile_tgt = reinterpret_cast<int32_t*>(b + o.tt); d.tile_seg_ptr = reinterpret_cast<int32_t*>(b + o.tsp);
+    d.seg_rel = reinterpret_cast<int32_t*>(b + o.sr); d.seg_fam = reinterpret_cast<int8_t*>(b + o.sf);
+    d.seg_src = reinterpret_cast<int32_t*>(b + o.ss); d.r1_ptr = reinterpret_cast<int32_t*>(b + o.rp);
+    d.r1_idx = reinterpret_cast<int32_t*>(b + o.ri); d.r1_fam = reinterpret_cast<int8_t*>(b + o.rf);
+    d.r1_coef = reinterpret_cast<double*>(b + o.rc);
+    return d;
+  };
+  for (size_t i = 0; i < P.fwd.size(); ++i) p->dfwd.push_back(mk(P.fwd[i], ofw[i]));
+  for (size_t i = 0; i < P.adj.size(); ++i) p->dadj.push_back(mk(P.adj[i], oad[i]));
+  p->d_mp = reinterpret_cast<double*>(b + o_mp);
+  p->d_loc = reinterpret_cast<double*>(b + o_loc);
+  p->d_lb = reinterpret_cast<double*>(b + o_lb);
+  p->d_ab = reinterpret_cast<double*>(b + o_ab);
+  p->d_usum = reinterpret_cast<double*>(b + o_us);
+  p->d_leaf_s2 = reinterpret_cast<double*>(b + o_s2);
+  return VOLPOT_OK;
+}
+
+const double* arr_ptr(volpot_plan_s* p, int8_t a, const double* in, double* out) {
+  switch (a) {
+    case A_IN: return in;
+    case A_OUT: return out;
+    case A_MP: return p->d_mp;
+    case A_LOC: return p->d_loc;
+    case A_LB: return p->d_lb;
+    case A_AB: return p->d_ab;
+    case A_USUM: return p->d_usum;
+    default: return nullptr;
+  }
+}
+
+hipEvent_t take_event(volpot_plan_s* p) {
+  if (!p->ev_free.empty()) {
+    hipEvent_t e = p->ev_free.back();
+    p->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int run_stages(volpot_plan_s* p, std::vector<DevStage>& stages, const double* in, double* out, hipStream_t stream,
+               bool timing) {
+  for (DevStage& d : stages) {
+    const Stage& s = *d.st;
+    if (s.n_tiles == 0) continue;
+    GrgParams g;
+    std::memset(&g, 0, sizeof(g));
+    g.tile_tgt = d.tile_tgt; g.tile_seg_ptr = d.tile_seg_ptr; g.seg_rel = d.seg_rel; g.seg_fam = d.seg_fam;
+    g.seg_src = d.seg_src; g.rels = p->tables->d_rels;
+    for (int f = 0; f < 4; ++f) {
+      g.fam_base[f] = arr_ptr(p, s.fam[f].arr, in, out);
+      g.fam_stride[f] = s.fam[f].stride;
+      g.fam_scaled[f] = s.fam[f].scaled;
+    }
+    g.leaf_s2 = p->d_leaf_s2;
+    g.r1_ptr = d.r1_ptr; g.r1_idx = d.r1_idx; g.r1_fam = d.r1_fam; g.r1_coef = d.r1_coef;
+    for (int f = 0; f < 3; ++f) {
+      g.r1_base[f] = arr_ptr(p, s.r1fam[f].arr, in, out);
+      g.r1_stride[f] = s.r1fam[f].stride;
+    }
+    g.out = const_cast<double*>(arr_ptr(p, s.out_arr, in, out));
+    g.out_stride = s.out_stride;
+    g.out_scaled = s.out_scaled;
+    g.r1_all_rows = s.r1_all_rows;
+    g.n_tiles = s.n_tiles;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (timing) {
+      ea = take_event(p);
+      eb = take_event(p);
+      if (ea) (void)hipEventRecord(ea, stream);
+    }
+    hipError_t e = launch_grg(s.M, s.NT, g, stream);
+    if (timing && ea && eb) {
+      (void)hipEventRecord(eb, stream);
+      p->pending.push_back({s.kind, ea, eb});
+    }
+    if (e != hipSuccess) return VOLPOT_ERR_HIP;
+  }
+  return VOLPOT_OK;
+}
+
+int run_adjoint(volpot_plan_s* p, const double* in, double* out, hipStream_t stream, bool timing) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (timing) {
+    ea = take_event(p);
+    eb = take_event(p);
+    if (ea) (void)hipEventRecord(ea, stream);
+  }
+  if (launch_rowsum(in, p->d_usum, p->host.n_leaves, stream) != hipSuccess) return VOLPOT_ERR_HIP;
+  if (timing && ea && eb) {
+    (void)hipEventRecord(eb, stream);
+    p->pending.push_back({K_ASUM, ea, eb});
+  }
+  return run_stages(p, p->dadj, in, out, stream, timing);
+}
+
+int run_graph(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t stream) {
+  for (auto& g : p->graphs)
+    if (g.in == in && g.out == out && g.adjoint == adjoint)
+      return hipGraphLaunch(g.exec, stream) == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
+  if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return VOLPOT_ERR_HIP;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return VOLPOT_ERR_HIP;
+  int rc = adjoint ? run_adjoint(p, in, out, p->cap_stream, false) : run_stages(p, p->dfwd, in, out, p->cap_stream, false);
+  hipError_t ec = hipStreamEndCapture(p->cap_stream, &graph);
+  if (rc != VOLPOT_OK || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return VOLPOT_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ec != hipSuccess) return VOLPOT_ERR_HIP;
+  p->graphs.push_back({in, out, adjoint, exec});
+  return hipGraphLaunch(exec, stream) == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
+}
+
+void free_plan(volpot_plan_s* p) {
+  if (!p) return;
+  if (p->device >= 0) {
+    DeviceGuard dg(p->device);
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (auto& e : p->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (auto e : p->ev_free) (void)hipEventDestroy(e);
+    if (p->d_block) (void)hipFree(p->d_block);
+    release_tables(p->tables);
+  }
+  delete p;
+}
+
+int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels, int32_t p,
+              const volpot_options* opt, volpot_plan_t* out) {
+  if (!out || !offsets || !centres || !levels || n_trees <= 0) return VOLPOT_ERR_ARG;
+  if (p != kP) return VOLPOT_ERR_UNSUPPORTED;
+  if (offsets[0] != 0) return VOLPOT_ERR_ARG;
+  for (int t = 0; t < n_trees; ++t)
+    if (offsets[t + 1] <= offsets[t]) return VOLPOT_ERR_ARG;
+  if (offsets[n_trees] > (int64_t(1) << 31) - 1) return VOLPOT_ERR_UNSUPPORTED;
+  volpot_options o;
+  std::memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  if (o.table_cache) set_table_cache_dir(o.table_cache);
+  auto* plan = new (std::nothrow) volpot_plan_s();
+  if (!plan) return VOLPOT_ERR_OOM;
+  int rc;
+  try {
+    rc = build_plan(n_trees, offsets, centres, levels, o.tile_leaf, o.tile_box, plan->host, nullptr);
+  } catch (const std::bad_alloc&) {
+    rc = VOLPOT_ERR_OOM;
+  } catch (...) {
+    rc = VOLPOT_ERR_TREE;
+  }
+  if (rc != VOLPOT_OK) { delete plan; return rc; }
+  plan->host_only = o.host_only != 0;
+  plan->use_graph = o.use_graph != 0;
+  if (!plan->host_only) {
+    if (hipGetDevice(&plan->device) != hipSuccess) { delete plan; return VOLPOT_ERR_HIP; }
+    rc = acquire_tables(plan->device, &plan->tables);
+    if (rc == VOLPOT_OK) rc = upload(plan);
+    if (rc != VOLPOT_OK) { free_plan(plan); return rc; }
+  }
+  *out = plan;
+  return VOLPOT_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int volpot_plan(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p, const volpot_options* opt,
+                volpot_plan_t* out) {
+  if (n_leaves <= 0) return VOLPOT_ERR_ARG;
+  int64_t off[2] = {0, n_leaves};
+  return make_plan(1, off, centres, levels, p, opt, out);
+}
+
+int volpot_plan_forest(int32_t n_trees, const int64_t* tree_offsets, const double* centres, const int32_t* levels,
+                       int32_t p, const volpot_options* opt, volpot_plan_t* out) {
+  return make_plan(n_trees, tree_offsets, centres, levels, p, opt, out);
+}
+
+int volpot_apply(volpot_plan_t plan, const double* f_dev, double* u_dev, void* hip_stream) {
+  if (!plan || !f_dev || !u_dev || !aligned16(f_dev) || !aligned16(u_dev) || f_dev == u_dev) return VOLPOT_ERR_ARG;
+  if (plan->host_only) return VOLPOT_ERR_STATE;
+  DeviceGuard dg(plan->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (plan->use_graph) return run_graph(plan, false, f_dev, u_dev, s);
+  return run_stages(plan, plan->dfwd, f_dev, u_dev, s, plan->timing);
+}
+
+int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fbar_dev, void* hip_stream) {
+  if (!plan || !ubar_dev || !fbar_dev || !aligned16(ubar_dev) || !aligned16(fbar_dev) || ubar_dev == fbar_dev)
+    return VOLPOT_ERR_ARG;
+  if (plan->host_only) return VOLPOT_ERR_STATE;
+  DeviceGuard dg(plan->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (plan->use_graph) return run_graph(plan, true, ubar_dev, fbar_dev, s);
+  return run_adjoint(plan, ubar_dev, fbar_dev, s, plan->timing);
+}
+
+int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
+  if (!plan || !out) return VOLPOT_ERR_ARG;
+  const Plan& P = plan->host;
+  std::memset(out, 0, sizeof(*out));
+  out->n_leaves = P.n_leaves;
+  out->n_boxes = P.n_boxes;
+  out->n_trees = P.n_trees;
+  out->max_level = P.max_level;
+  out->order = kTerms - 1;
+  out->n_reals = kNE;
+  out->n_stages = int32_t(P.fwd.size() + P.adj.size());
+  out->pairs_near = P.pairs_near; out->pairs_v = P.pairs_v; out->pairs_w = P.pairs_w; out->pairs_x = P.pairs_x;
+  out->n_m2m = P.n_m2m; out->n_l2l = P.n_l2l; out->n_s2m = P.n_s2m; out->n_l2t = P.n_l2t;
+  for (const Stage& s : P.fwd) {
+    out->flops_total += s.flops;
+    if (s.kind == K_LEAF) out->flops_leaf_stage += s.flops;
+    if (s.kind == K_UP) out->flops_up += s.flops;
+    if (s.kind == K_DOWN) out->flops_down += s.flops;
+  }
+  out->bytes_min = 16.0 * double(P.n_leaves) * kNP;
+  out->device_bytes = plan->device_bytes + (plan->tables ? int64_t(plan->tables->bytes) : 0);
+  return VOLPOT_OK;
+}
+
+int volpot_validate_tree(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p, int64_t* bad_index) {
+  if (!centres || !levels || n_leaves <= 0) return VOLPOT_ERR_ARG;
+  if (p != kP) return VOLPOT_ERR_UNSUPPORTED;
+  int64_t off[2] = {0, n_leaves};
+  try {
+    return validate_forest(1, off, centres, levels, bad_index);
+  } catch (const std::bad_alloc&) {
+    return VOLPOT_ERR_OOM;
+  } catch (...) {
+    return VOLPOT_ERR_TREE;
+  }
+}
+
+int volpot_nodes(int32_t p, double* t, double* w) {
+  if (p < 1 || p > 64 || !t || !w) return VOLPOT_ERR_ARG;
+  for (int i = 0; i < p; ++i) {
+    double th = (2.0 * i + 1.0) * M_PI / (2.0 * p);
+    t[i] = -std::cos(th);
+    double s = 0.0;
+    for (int j = 1; j <= p / 2; ++j) s += std::cos(2.0 * j * th) / (4.0 * j * j - 1.0);
+    w[i] = (2.0 / p) * (1.0 - 2.0 * s);
+  }
+  return VOLPOT_OK;
+}
+
+void volpot_plan_destroy(volpot_plan_t plan) { free_plan(plan); }
+
+const char* volpot_status_string(int status) {
+  switch (status) {
+    case VOLPOT_OK: return "ok";
+    case VOLPOT_ERR_ARG: return "invalid argument";
+    case VOLPOT_ERR_TREE: return "leaves do not form a tiling of the root on the level grid";
+    case VOLPOT_ERR_UNBALANCED: return "tree is not 2:1 balanced over edges and corners";
+    case VOLPOT_ERR_UNSUPPORTED: return "unsupported order or level";
+    case VOLPOT_ERR_HIP: return "HIP runtime error";
+    case VOLPOT_ERR_OOM: return "out of memory";
+    case VOLPOT_ERR_STATE: return "plan has no device state (host-only or destroyed)";
+    default: return "unknown status";
+  }
+}
+
+int volpot_set_timing(volpot_plan_t plan, int32_t enable) {
+  if (!plan) return VOLPOT_ERR_ARG;
+  if (plan->use_graph && enable) return VOLPOT_ERR_STATE;
+  plan->timing = enable != 0;
+  return VOLPOT_OK;
+}
+
+int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_t n_kinds) {
+  if (!plan || !ms || !launches || n_kinds < 1) return VOLPOT_ERR_ARG;
+  if (plan->device >= 0) {
+    DeviceGuard dg(plan->device);
+    for (auto& e : plan->pending) {
+      float t = 0.0f;
+      if (hipEventSynchronize(e.b) != hipSuccess || hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) return VOLPOT_ERR_HIP;
+      plan->ms[e.kind] += t;
+      plan->cnt[e.kind] += 1;
+      plan->ev_free.push_back(e.a);
+      plan->ev_free.push_back(e.b);
+    }
+    plan->pending.clear();
+  }
+  for (int k = 0; k < n_kinds; ++k) {
+    ms[k] = k < K_NUM ? plan->ms[k] : 0.0;
+    launches[k] = k < K_NUM ? plan->cnt[k] : 0;
+  }
+  for (int k = 0; k < K_NUM; ++k) { plan->ms[k] = 0.0; plan->cnt[k] = 0; }
+  return VOLPOT_OK;
+}
+
+int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n) {
+  if (!plan || !out) return VOLPOT_ERR_ARG;
+  const Matrices& M = matrices();
+  int id;
+  if (kind == 0 && index >= 0 && index < 33) id = kRelNear + index;
+  else if (kind == 1 && index == 0) id = kRelS2M;
+  else if (kind == 2 && index == 0) id = kRelL2T;
+  else return VOLPOT_ERR_ARG;
+  if (n < int64_t(M.a[id].size())) return VOLPOT_ERR_ARG;
+  std::memcpy(out, M.a[id].data(), M.a[id].size() * sizeof(double));
+  return VOLPOT_OK;
+}
+
+int volpot_near_relation(int32_t r, double* dx, double* dy, double* rho) {
+  if (r < 0 || r >= 33 || !dx || !dy || !rho) return VOLPOT_ERR_ARG;
+  const Offset& o = near_offsets()[r];
+  *dx = o.dx; *dy = o.dy; *rho = o.rho;
+  return VOLPOT_OK;
+}
+
+}  // extern "C"

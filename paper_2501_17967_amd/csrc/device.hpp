@@ -1,0 +1,45 @@
+// Device-side interface between the C ABI (api.cpp) and the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vp {
+
+struct RelDesc {
+  const double* A;  // fragment-major: frag[(kk * (M/16) + row_tile) * 64 + lane] = A[16 row_tile + lane%16][4 kk + lane/16]
+  int32_t M, K;
+};
+
+// Arguments of one stage launch (grouped-relation GEMM). Passed by value.
+struct GrgParams {
+  const int32_t* tile_tgt;      // n_tiles * NT, -1 = empty slot
+  const int32_t* tile_seg_ptr;  // n_tiles + 1
+  const int32_t* seg_rel;       // relation id per segment
+  const int8_t* seg_fam;        // source family per segment
+  const int32_t* seg_src;       // n_seg * NT source index, -1 = none
+  const RelDesc* rels;          // device table of relations
+  const double* fam_base[4];
+  int32_t fam_stride[4];
+  int32_t fam_scaled[4];        // 1: scale source by leaf_s2[source]
+  const double* leaf_s2;
+  const int32_t* r1_ptr;        // n_tiles * NT + 1
+  const int32_t* r1_idx;
+  const int8_t* r1_fam;
+  const double* r1_coef;
+  const double* r1_base[3];
+  int32_t r1_stride[3];
+  double* out;
+  int32_t out_stride;
+  int32_t out_scaled;           // 1: multiply the output of target t by leaf_s2[t]
+  int32_t r1_all_rows;          // 1: rank-one term on every row, else on row 0 only
+  int32_t n_tiles;
+};
+
+// Launch one stage; M in {80, 256}, NT in {16, 32, 64} (M = 256 needs NT in {32, 64}).
+hipError_t launch_grg(int M, int NT, const GrgParams& p, hipStream_t stream);
+// usum[a] = sum of the 256 values of leaf a
+hipError_t launch_rowsum(const double* x, double* usum, int64_t n_leaves, hipStream_t stream);
+
+}  // namespace vp

@@ -1,0 +1,531 @@
+// Host plan: tree validation, integer box keys, adaptive-FMM interaction lists, and the
+// stage/tile schedules consumed by the grouped-relation kernels (plan.hpp).
+//
+// Lists (geometric definitions of the adaptive FMM; the box code of Sec. 4.2 is one):
+//   U(a)  leaves adjacent to leaf a, a included   -> near tables (33 relations)
+//   V(b)  same-level children of the colleagues of b's parent, not adjacent to b -> M2L
+//   W(a)  children of leaf a's colleagues, not adjacent to a                    -> M2T
+//   X(b)  leaves c with b in W(c)                                               -> S2L
+// 2:1 balance over edges and corners (Sec. 4.2.1) bounds adjacent levels to l-1..l+1, which
+// is what makes the 33 near relations and the 20 W / X offsets exhaustive.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+
+#include "../../include/volpot.h"
+#include "plan.hpp"
+
+namespace vp {
+
+// ---------------------------------------------------------------- offsets
+static std::vector<Offset> make_near() {
+  std::vector<Offset> v;
+  v.push_back({0, 0, 1});
+  for (int dy = -2; dy <= 2; dy += 2)
+    for (int dx = -2; dx <= 2; dx += 2)
+      if (dx || dy) v.push_back({double(dx), double(dy), 1.0});
+  for (double a : {-1.5, -0.5, 0.5, 1.5})
+    for (double b : {-1.5, -0.5, 0.5, 1.5})
+      if (std::fabs(a) == 1.5 || std::fabs(b) == 1.5) v.push_back({a, b, 0.5});
+  for (double a : {-3.0, -1.0, 1.0, 3.0})
+    for (double b : {-3.0, -1.0, 1.0, 3.0})
+      if (std::fabs(a) == 3.0 || std::fabs(b) == 3.0) v.push_back({a, b, 2.0});
+  return v;
+}
+static std::vector<Offset> make_v() {
+  std::vector<Offset> v;
+  for (int j = -3; j <= 3; ++j)
+    for (int i = -3; i <= 3; ++i)
+      if (std::max(std::abs(i), std::abs(j)) >= 2) v.push_back({2.0 * i, 2.0 * j, 1.0});
+  return v;
+}
+static std::vector<Offset> make_w() {
+  std::vector<Offset> v;
+  for (double a : {-2.5, -1.5, -0.5, 0.5, 1.5, 2.5})
+    for (double b : {-2.5, -1.5, -0.5, 0.5, 1.5, 2.5})
+      if (std::fabs(a) == 2.5 || std::fabs(b) == 2.5) v.push_back({a, b, 0.5});
+  return v;
+}
+static std::vector<Offset> make_x() {
+  std::vector<Offset> v;
+  for (double a : {-5.0, -3.0, -1.0, 1.0, 3.0, 5.0})
+    for (double b : {-5.0, -3.0, -1.0, 1.0, 3.0, 5.0})
+      if (std::fabs(a) == 5.0 || std::fabs(b) == 5.0) v.push_back({a, b, 2.0});
+  return v;
+}
+const std::vector<Offset>& near_offsets() { static const auto v = make_near(); return v; }
+const std::vector<Offset>& v_offsets() { static const auto v = make_v(); return v; }
+const std::vector<Offset>& w_offsets() { static const auto v = make_w(); return v; }
+const std::vector<Offset>& x_offsets() { static const auto v = make_x(); return v; }
+
+int find_offset(const std::vector<Offset>& v, double dx, double dy, double rho) {
+  for (size_t i = 0; i < v.size(); ++i)
+    if (std::fabs(v[i].dx - dx) < 1e-9 && std::fabs(v[i].dy - dy) < 1e-9 && std::fabs(v[i].rho - rho) < 1e-12)
+      return int(i);
+  return -1;
+}
+
+// ---------------------------------------------------------------- keys
+static inline uint64_t pack(int l, int64_t x, int64_t y) {
+  return (uint64_t(l) << 58) | (uint64_t(x) << 29) | uint64_t(y);
+}
+static inline int key_l(uint64_t k) { return int(k >> 58); }
+static inline int64_t key_x(uint64_t k) { return int64_t((k >> 29) & ((1ull << 29) - 1)); }
+static inline int64_t key_y(uint64_t k) { return int64_t(k & ((1ull << 29) - 1)); }
+static inline uint64_t parent_key(uint64_t k) {
+  return pack(key_l(k) - 1, key_x(k) >> 1, key_y(k) >> 1);
+}
+static inline uint64_t child_key(uint64_t k, int q) {
+  return pack(key_l(k) + 1, 2 * key_x(k) + (q & 1), 2 * key_y(k) + (q >> 1));
+}
+static inline bool touch(uint64_t a, uint64_t b) {
+  int la = key_l(a), lb = key_l(b), L = std::max(la, lb);
+  int64_t ax0 = key_x(a) << (L - la), ax1 = (key_x(a) + 1) << (L - la);
+  int64_t bx0 = key_x(b) << (L - lb), bx1 = (key_x(b) + 1) << (L - lb);
+  int64_t ay0 = key_y(a) << (L - la), ay1 = (key_y(a) + 1) << (L - la);
+  int64_t by0 = key_y(b) << (L - lb), by1 = (key_y(b) + 1) << (L - lb);
+  return std::max(ax0, bx0) <= std::min(ax1, bx1) && std::max(ay0, by0) <= std::min(ay1, by1);
+}
+static inline uint64_t morton(int64_t x, int64_t y) {
+  uint64_t m = 0;
+  for (int b = 0; b < 29; ++b) m |= ((uint64_t(x) >> b) & 1) << (2 * b) | ((uint64_t(y) >> b) & 1) << (2 * b + 1);
+  return m;
+}
+static inline double centre_of(int64_t i, int l) { return -1.0 + (2.0 * double(i) + 1.0) * std::ldexp(1.0, -l); }
+
+struct TreeBoxes {
+  std::unordered_map<uint64_t, int64_t> leaf;  // key -> caller leaf index
+  std::unordered_map<uint64_t, int32_t> box;   // key -> global box id (filled later)
+};
+
+// Validate one tree; fill the leaf map and the set of boxes (ids assigned later).
+static int validate_tree(int64_t off, int64_t n, const double* centres, const int32_t* levels,
+                         TreeBoxes& tb, std::vector<uint64_t>& keys, int64_t* bad) {
+  keys.resize(n);
+  int L = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int l = levels[off + i];
+    if (l < 0 || l > kMaxLevel) { if (bad) *bad = off + i; return l < 0 ? VOLPOT_ERR_TREE : VOLPOT_ERR_UNSUPPORTED; }
+    double s = std::ldexp(1.0, -l);
+    double fx = (centres[2 * (off + i)] + 1.0) / (2.0 * s) - 0.5;
+    double fy = (centres[2 * (off + i) + 1] + 1.0) / (2.0 * s) - 0.5;
+    double rx = std::nearbyint(fx), ry = std::nearbyint(fy);
+    double lim = std::ldexp(1.0, l);
+    if (!(std::fabs(fx - rx) < 1e-6) || !(std::fabs(fy - ry) < 1e-6) || !(rx >= 0 && rx < lim) || !(ry >= 0 && ry < lim)) {
+      if (bad) *bad = off + i;
+      return VOLPOT_ERR_TREE;
+    }
+    keys[i] = pack(l, int64_t(rx), int64_t(ry));
+    if (!tb.leaf.emplace(keys[i], off + i).second) { if (bad) *bad = off + i; return VOLPOT_ERR_TREE; }
+    L = std::max(L, l);
+  }
+  unsigned __int128 area = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t k = keys[i];
+    area += (unsigned __int128)1 << (2 * (L - key_l(k)));
+    while (key_l(k) > 0) {
+      k = parent_key(k);
+      if (tb.leaf.count(k)) { if (bad) *bad = off + i; return VOLPOT_ERR_TREE; }
+      if (!tb.box.emplace(k, -1).second) break;  // ancestors above are present already
+    }
+  }
+  if (area != ((unsigned __int128)1 << (2 * L))) { if (bad) *bad = off; return VOLPOT_ERR_TREE; }
+  for (int64_t i = 0; i < n; ++i) tb.box.emplace(keys[i], -1);
+  // 2:1 balance over edges and corners
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t k = keys[i];
+    int l = key_l(k);
+    int64_t nmax = int64_t(1) << l;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (!dx && !dy) continue;
+        int64_t qx = key_x(k) + dx, qy = key_y(k) + dy;
+        if (qx < 0 || qy < 0 || qx >= nmax || qy >= nmax) continue;
+        uint64_t q = pack(l, qx, qy);
+        if (tb.box.count(q)) {
+          if (tb.leaf.count(q)) continue;
+          for (int c = 0; c < 4; ++c) {
+            uint64_t ch = child_key(q, c);
+            if (touch(ch, k) && !tb.leaf.count(ch)) { if (bad) *bad = off + i; return VOLPOT_ERR_UNBALANCED; }
+          }
+        } else {
+          uint64_t c = q;
+          while (!tb.leaf.count(c)) c = parent_key(c);
+          if (key_l(c) < l - 1) { if (bad) *bad = off + i; return VOLPOT_ERR_UNBALANCED; }
+        }
+      }
+  }
+  return VOLPOT_OK;
+}
+
+int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
+                    int64_t* bad) {
+  for (int t = 0; t < n_trees; ++t) {
+    int64_t n = offsets[t + 1] - offsets[t];
+    if (n <= 0) { if (bad) *bad = offsets[t]; return VOLPOT_ERR_TREE; }
+    TreeBoxes tb;
+    std::vector<uint64_t> keys;
+    int rc = validate_tree(offsets[t], n, centres, levels, tb, keys, bad);
+    if (rc != VOLPOT_OK) return rc;
+  }
+  return VOLPOT_OK;
+}
+
+struct Entry { int32_t rel; int8_t fam; int32_t src; };
+struct R1 { int8_t fam; int32_t idx; double coef; };
+
+static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
+                       const std::vector<std::vector<Entry>>& entries,
+                       const std::vector<std::vector<R1>>& r1, const Matrices& mats) {
+  const int NT = st.NT;
+  st.n_tiles = int((targets.size() + NT - 1) / NT);
+  st.tile_tgt.assign(size_t(st.n_tiles) * NT, -1);
+  st.tile_seg_ptr.assign(st.n_tiles + 1, 0);
+  st.r1_ptr.assign(size_t(st.n_tiles) * NT + 1, 0);
+  st.seg_rel.clear(); st.seg_fam.clear(); st.seg_src.clear();
+  st.r1_idx.clear(); st.r1_fam.clear(); st.r1_coef.clear();
+  st.flops = 0; st.n_pairs = 0;
+  for (int t = 0; t < st.n_tiles; ++t) {
+    std::map<int32_t, size_t> segs;  // rel -> segment index (ordered by rel id)
+    std::map<int32_t, int8_t> segfam;
+    for (int s = 0; s < NT; ++s) {
+      size_t ti = size_t(t) * NT + s;
+      if (ti >= targets.size()) break;
+      st.tile_tgt[ti] = targets[ti];
+      for (const Entry& e : entries[ti]) {
+        // the kernel reads M x K of the relation's table and K values of each source
+        if (mats.M[e.rel] != st.M) throw std::runtime_error("relation rows differ from stage rows");
+        if (st.fam[e.fam].stride < mats.K[e.rel]) throw std::runtime_error("source shorter than relation");
+        segs.emplace(e.rel, 0);
+        segfam[e.rel] = e.fam;
+      }
+    }
+    size_t base = st.seg_rel.size();
+    size_t n = 0;
+    for (auto& kv : segs) {
+      kv.second = base + n++;
+      st.seg_rel.push_back(kv.first);
+      st.seg_fam.push_back(segfam[kv.first]);
+    }
+    st.seg_src.resize(st.seg_rel.size() * NT, -1);
+    for (int s = 0; s < NT; ++s) {
+      size_t ti = size_t(t) * NT + s;
+      if (ti >= targets.size()) break;
+      for (const Entry& e : entries[ti]) {
+        int32_t& slot = st.seg_src[segs[e.rel] * NT + s];
+        if (slot != -1) throw std::runtime_error("duplicate relation for one target");
+        slot = e.src;
+        st.flops += 2.0 * mats.nnz[e.rel];
+        st.n_pairs += 1;
+      }
+    }
+    st.tile_seg_ptr[t + 1] = int32_t(st.seg_rel.size());
+  }
+  for (size_t ti = 0; ti < st.tile_tgt.size(); ++ti) {
+    if (ti < targets.size())
+      for (const R1& e : r1[ti]) {
+        st.r1_idx.push_back(e.idx);
+        st.r1_fam.push_back(e.fam);
+        st.r1_coef.push_back(e.coef);
+        st.flops += st.r1_all_rows ? 2.0 * st.M : 2.0;
+      }
+    st.r1_ptr[ti + 1] = int32_t(st.r1_idx.size());
+  }
+}
+
+int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
+               int tile_leaf, int tile_box, Plan& P, int64_t* bad) {
+  const double kLn2 = std::log(2.0);
+  const double kInv2Pi = 1.0 / (2.0 * M_PI);
+  P = Plan();
+  P.n_trees = n_trees;
+  P.n_leaves = offsets[n_trees];
+  std::vector<TreeBoxes> trees(n_trees);
+  std::vector<std::vector<uint64_t>> tkeys(n_trees);
+  for (int t = 0; t < n_trees; ++t) {
+    int64_t n = offsets[t + 1] - offsets[t];
+    if (n <= 0) { if (bad) *bad = offsets[t]; return VOLPOT_ERR_TREE; }
+    int rc = validate_tree(offsets[t], n, centres, levels, trees[t], tkeys[t], bad);
+    if (rc != VOLPOT_OK) return rc;
+  }
+  // global box numbering: by (level, tree, morton)
+  struct BK { int l; int32_t tree; uint64_t m; uint64_t key; };
+  std::vector<BK> all;
+  for (int t = 0; t < n_trees; ++t)
+    for (auto& kv : trees[t].box) all.push_back({key_l(kv.first), t, morton(key_x(kv.first), key_y(kv.first)), kv.first});
+  std::sort(all.begin(), all.end(), [](const BK& a, const BK& b) {
+    if (a.l != b.l) return a.l < b.l;
+    if (a.tree != b.tree) return a.tree < b.tree;
+    return a.m < b.m;
+  });
+  P.n_boxes = int64_t(all.size());
+  P.box_level.resize(all.size()); P.box_tree.resize(all.size()); P.box_parent.assign(all.size(), -1);
+  P.box_leaf.assign(all.size(), -1); P.box_x.resize(all.size()); P.box_y.resize(all.size());
+  P.box_child.assign(all.size(), {-1, -1, -1, -1});
+  P.leaf_box.assign(P.n_leaves, -1);
+  for (size_t i = 0; i < all.size(); ++i) {
+    trees[all[i].tree].box[all[i].key] = int32_t(i);
+    P.box_level[i] = all[i].l; P.box_tree[i] = all[i].tree;
+    P.box_x[i] = key_x(all[i].key); P.box_y[i] = key_y(all[i].key);
+    P.max_level = std::max(P.max_level, all[i].l);
+  }
+  for (size_t i = 0; i < all.size(); ++i) {
+    TreeBoxes& tb = trees[all[i].tree];
+    uint64_t k = all[i].key;
+    auto lf = tb.leaf.find(k);
+    if (lf != tb.leaf.end()) { P.box_leaf[i] = int32_t(lf->second); P.leaf_box[lf->second] = int32_t(i); }
+    if (key_l(k) > 0) {
+      int32_t p = tb.box.at(parent_key(k));
+      P.box_parent[i] = p;
+      int q = int(key_x(k) & 1) + 2 * int(key_y(k) & 1);
+      P.box_child[p][q] = int32_t(i);
+    }
+  }
+  P.leaf_s2.resize(P.n_leaves); P.leaf_kappa.resize(P.n_leaves);
+  for (int64_t a = 0; a < P.n_leaves; ++a) {
+    int l = levels[a];
+    P.leaf_s2[a] = std::ldexp(1.0, -2 * l);
+    P.leaf_kappa[a] = l * kLn2 * kInv2Pi;  // -(1/2pi) ln s
+  }
+  auto key_of = [&](int32_t b) { return pack(P.box_level[b], P.box_x[b], P.box_y[b]); };
+  auto find_box = [&](int32_t tree, uint64_t k) -> int32_t {
+    auto it = trees[tree].box.find(k);
+    return it == trees[tree].box.end() ? -1 : it->second;
+  };
+  auto cx = [&](int32_t b) { return centre_of(P.box_x[b], P.box_level[b]); };
+  auto cy = [&](int32_t b) { return centre_of(P.box_y[b], P.box_level[b]); };
+  auto hw = [&](int32_t b) { return std::ldexp(1.0, -P.box_level[b]); };
+
+  // ---------------------------------------------------------------- lists
+  const int64_t NB = P.n_boxes;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> Ulist(P.n_leaves);  // (near rel, src leaf)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> Wlist(P.n_leaves);  // (w rel, src box)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> Vlist(NB);          // (v rel, src box)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> Xlist(NB);          // (x rel, src leaf)
+  const auto& NO = near_offsets();
+  const auto& VO = v_offsets();
+  const auto& WO = w_offsets();
+  const auto& XO = x_offsets();
+  for (int64_t a = 0; a < P.n_leaves; ++a) {
+    int32_t ba = P.leaf_box[a];
+    int32_t tr = P.box_tree[ba];
+    uint64_t k = key_of(ba);
+    int l = key_l(k);
+    int64_t nmax = int64_t(1) << l;
+    double sa = hw(ba);
+    std::vector<int32_t> adj{ba};
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (!dx && !dy) continue;
+        int64_t qx = key_x(k) + dx, qy = key_y(k) + dy;
+        if (qx < 0 || qy < 0 || qx >= nmax || qy >= nmax) continue;
+        uint64_t q = pack(l, qx, qy);
+        int32_t bq = find_box(tr, q);
+        if (bq >= 0) {
+          if (P.box_leaf[bq] >= 0) { adj.push_back(bq); continue; }
+          for (int c = 0; c < 4; ++c) {
+            int32_t ch = P.box_child[bq][c];
+            if (touch(key_of(ch), k)) adj.push_back(ch);  // leaves by 2:1 balance
+            else Wlist[a].push_back({find_offset(WO, (cx(ch) - cx(ba)) / sa, (cy(ch) - cy(ba)) / sa, 0.5), ch});
+          }
+        } else {
+          uint64_t c = q;
+          while (find_box(tr, c) < 0 || P.box_leaf[find_box(tr, c)] < 0) c = parent_key(c);
+          adj.push_back(find_box(tr, c));
+        }
+      }
+    std::sort(adj.begin(), adj.end());
+    adj.erase(std::unique(adj.begin(), adj.end()), adj.end());
+    for (int32_t bb : adj) {
+      int r = find_offset(NO, (cx(bb) - cx(ba)) / sa, (cy(bb) - cy(ba)) / sa, hw(bb) / sa);
+      if (r < 0) throw std::runtime_error("near relation not found");
+      Ulist[a].push_back({r, P.box_leaf[bb]});
+    }
+    for (auto& w : Wlist[a])
+      if (w.first < 0) throw std::runtime_error("W relation not found");
+  }
+  for (int32_t b = 0; b < NB; ++b) {
+    int l = P.box_level[b];
+    if (l < 2) continue;
+    int32_t tr = P.box_tree[b];
+    uint64_t k = key_of(b);
+    int32_t par = P.box_parent[b];
+    uint64_t pk = key_of(par);
+    int64_t nmax = int64_t(1) << (l - 1);
+    double s = hw(b);
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (!dx && !dy) continue;
+        int64_t qx = key_x(pk) + dx, qy = key_y(pk) + dy;
+        if (qx < 0 || qy < 0 || qx >= nmax || qy >= nmax) continue;
+        int32_t pc = find_box(tr, pack(l - 1, qx, qy));
+        if (pc < 0 || P.box_leaf[pc] >= 0) continue;
+        for (int c = 0; c < 4; ++c) {
+          int32_t ch = P.box_child[pc][c];
+          if (touch(key_of(ch), k)) continue;
+          int r = find_offset(VO, (cx(ch) - cx(b)) / s, (cy(ch) - cy(b)) / s, 1.0);
+          if (r < 0) throw std::runtime_error("V relation not found");
+          Vlist[b].push_back({r, ch});
+        }
+      }
+  }
+  for (int64_t a = 0; a < P.n_leaves; ++a)
+    for (auto& w : Wlist[a]) {
+      int32_t c = w.second, ba = P.leaf_box[a];
+      double s = hw(c);
+      int r = find_offset(XO, (cx(ba) - cx(c)) / s, (cy(ba) - cy(c)) / s, 2.0);
+      if (r < 0) throw std::runtime_error("X relation not found");
+      Xlist[c].push_back({r, int32_t(a)});
+    }
+
+  // ---------------------------------------------------------------- stages
+  const Matrices& mats = matrices();
+  const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 64;
+  const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 64;
+  auto quadrant = [&](int32_t b) { return int(P.box_x[b] & 1) + 2 * int(P.box_y[b] & 1); };
+  std::vector<std::vector<int32_t>> boxes_at(P.max_level + 1);
+  for (int32_t b = 0; b < NB; ++b) boxes_at[P.box_level[b]].push_back(b);
+  auto lnS = [&](int l) { return -double(l) * kLn2; };
+  std::vector<int32_t> leaf_order(P.n_leaves);
+  for (int64_t a = 0; a < P.n_leaves; ++a) leaf_order[a] = int32_t(a);
+  std::sort(leaf_order.begin(), leaf_order.end(), [&](int32_t x, int32_t y) { return P.leaf_box[x] < P.leaf_box[y]; });
+
+  // inverse lists for the adjoint
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> Uinv(P.n_leaves), Winv(NB), Vinv(NB), Xinv(P.n_leaves);
+  for (int64_t a = 0; a < P.n_leaves; ++a) {
+    for (auto& e : Ulist[a]) Uinv[e.second].push_back({e.first, int32_t(a)});
+    for (auto& e : Wlist[a]) Winv[e.second].push_back({e.first, int32_t(a)});
+  }
+  for (int32_t b = 0; b < NB; ++b) {
+    for (auto& e : Vlist[b]) Vinv[e.second].push_back({e.first, b});
+    for (auto& e : Xlist[b]) Xinv[e.second].push_back({e.first, b});
+  }
+  for (int64_t a = 0; a < P.n_leaves; ++a) {
+    P.pairs_near += int64_t(Ulist[a].size());
+    P.pairs_w += int64_t(Wlist[a].size());
+  }
+  for (int32_t b = 0; b < NB; ++b) { P.pairs_v += int64_t(Vlist[b].size()); P.pairs_x += int64_t(Xlist[b].size()); }
+
+  auto init_stage = [](Stage& st, int kind, int level, int M, int NT, int8_t out, int32_t ostride) {
+    st.kind = kind; st.level = level; st.M = M; st.NT = NT; st.out_arr = out; st.out_stride = ostride;
+    for (auto& f : st.fam) f = {A_NONE, 0, 0};
+    for (auto& f : st.r1fam) f = {A_NONE, 0, 0};
+  };
+  // ---- forward UP
+  for (int l = P.max_level; l >= 0; --l) {
+    std::vector<int32_t> tg;
+    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0) tg.push_back(b);
+    if (l >= 2) for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
+    if (tg.empty()) continue;
+    Stage st; init_stage(st, K_UP, l, kNE, NTB, A_MP, kNE);
+    st.fam[0] = {A_IN, kNP, 1}; st.fam[1] = {A_MP, kNE, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) {
+      int32_t b = tg[i];
+      if (P.box_leaf[b] >= 0) { E[i].push_back({kRelS2M, 0, P.box_leaf[b]}); P.n_s2m++; }
+      else for (int q = 0; q < 4; ++q) { E[i].push_back({kRelM2M + q, 1, P.box_child[b][q]}); P.n_m2m++; }
+    }
+    make_tiles(st, tg, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  // ---- forward DOWN
+  for (int l = 2; l <= P.max_level; ++l) {
+    std::vector<int32_t> tg = boxes_at[l];
+    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
+    Stage st; init_stage(st, K_DOWN, l, kNE, NTB, A_LOC, kNE);
+    st.fam[0] = {A_LOC, kNE, 0}; st.fam[1] = {A_MP, kNE, 0}; st.fam[2] = {A_IN, kNP, 1};
+    st.r1fam[0] = {A_MP, kNE, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) {
+      int32_t b = tg[i];
+      if (l >= 3) { E[i].push_back({kRelL2L + quadrant(b), 0, P.box_parent[b]}); P.n_l2l++; }
+      for (auto& e : Vlist[b]) { E[i].push_back({kRelM2L + e.first, 1, e.second}); R[i].push_back({0, e.second, lnS(l)}); }
+      for (auto& e : Xlist[b]) { E[i].push_back({kRelS2L + e.first, 2, e.second}); R[i].push_back({0, P.leaf_box[e.second], lnS(l)}); }
+    }
+    make_tiles(st, tg, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  // ---- forward LEAF
+  {
+    Stage st; init_stage(st, K_LEAF, -1, kNP, NTL, A_OUT, kNP);
+    st.r1_all_rows = 1;
+    st.fam[0] = {A_IN, kNP, 1}; st.fam[1] = {A_MP, kNE, 0}; st.fam[2] = {A_LOC, kNE, 0};
+    st.r1fam[0] = {A_MP, kNE, 0};
+    std::vector<std::vector<Entry>> E(P.n_leaves);
+    std::vector<std::vector<R1>> R(P.n_leaves);
+    for (size_t i = 0; i < leaf_order.size(); ++i) {
+      int32_t a = leaf_order[i];
+      double kap = P.leaf_kappa[a];
+      for (auto& e : Ulist[a]) { E[i].push_back({kRelNear + e.first, 0, e.second}); R[i].push_back({0, P.leaf_box[e.second], kap}); }
+      for (auto& e : Wlist[a]) { E[i].push_back({kRelM2T + e.first, 1, e.second}); R[i].push_back({0, e.second, kap}); }
+      if (levels[a] >= 2) { E[i].push_back({kRelL2T, 2, P.leaf_box[a]}); P.n_l2t++; }
+    }
+    make_tiles(st, leaf_order, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  // ---- adjoint AUP
+  for (int l = P.max_level; l >= 2; --l) {
+    std::vector<int32_t> tg;
+    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0) tg.push_back(b);
+    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
+    Stage st; init_stage(st, K_AUP, l, kNE, NTB, A_LB, kNE);
+    st.fam[0] = {A_IN, kNP, 0}; st.fam[1] = {A_LB, kNE, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) {
+      int32_t b = tg[i];
+      if (P.box_leaf[b] >= 0) E[i].push_back({kRelL2T + kNumFwd, 0, P.box_leaf[b]});
+      else for (int q = 0; q < 4; ++q) E[i].push_back({kRelL2L + q + kNumFwd, 1, P.box_child[b][q]});
+    }
+    make_tiles(st, tg, E, R, mats);
+    P.adj.push_back(std::move(st));
+  }
+  // ---- adjoint ADOWN
+  for (int l = 0; l <= P.max_level; ++l) {
+    std::vector<int32_t> tg;
+    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0 || l >= 2) tg.push_back(b);
+    if (tg.empty()) continue;
+    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
+    Stage st; init_stage(st, K_ADOWN, l, kNE, NTB, A_AB, kNE);
+    st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_LB, kNE, 0}; st.fam[2] = {A_IN, kNP, 0};
+    st.r1fam[0] = {A_LB, kNE, 0}; st.r1fam[1] = {A_USUM, 1, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) {
+      int32_t b = tg[i];
+      if (l >= 3) E[i].push_back({kRelM2M + quadrant(b) + kNumFwd, 0, P.box_parent[b]});
+      for (auto& e : Vinv[b]) { E[i].push_back({kRelM2L + e.first + kNumFwd, 1, e.second}); R[i].push_back({0, e.second, lnS(l)}); }
+      for (auto& e : Winv[b]) { E[i].push_back({kRelM2T + e.first + kNumFwd, 2, e.second}); R[i].push_back({1, e.second, P.leaf_kappa[e.second]}); }
+      int32_t leaf = P.box_leaf[b];
+      if (leaf >= 0) {
+        for (auto& e : Uinv[leaf]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
+        for (auto& e : Xinv[leaf]) R[i].push_back({0, e.second, lnS(P.box_level[e.second])});
+      }
+    }
+    make_tiles(st, tg, E, R, mats);
+    P.adj.push_back(std::move(st));
+  }
+  // ---- adjoint ALEAF
+  {
+    Stage st; init_stage(st, K_ALEAF, -1, kNP, NTL, A_OUT, kNP);
+    st.out_scaled = 1;
+    st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_IN, kNP, 0}; st.fam[2] = {A_LB, kNE, 0};
+    std::vector<std::vector<Entry>> E(P.n_leaves);
+    std::vector<std::vector<R1>> R(P.n_leaves);
+    for (size_t i = 0; i < leaf_order.size(); ++i) {
+      int32_t b = leaf_order[i];
+      E[i].push_back({kRelS2M + kNumFwd, 0, P.leaf_box[b]});
+      for (auto& e : Uinv[b]) E[i].push_back({kRelNear + e.first + kNumFwd, 1, e.second});
+      for (auto& e : Xinv[b]) E[i].push_back({kRelS2L + e.first + kNumFwd, 2, e.second});
+    }
+    make_tiles(st, leaf_order, E, R, mats);
+    P.adj.push_back(std::move(st));
+  }
+  return VOLPOT_OK;
+}
+
+}  // namespace vp

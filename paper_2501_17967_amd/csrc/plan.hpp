@@ -1,0 +1,119 @@
+// Host-side plan of the box code: tree, interaction lists, stage schedules, tables.
+//
+// The box code (Sec. 4.2 evaluates eq. (vbulk) with one) is organised here as a short
+// sequence of "stages". Each stage writes one output array, one launch per tree level.
+// Within a stage every output vector (a "target") is owned by exactly one slot of one tile
+// and receives a sum of small dense products A_r * source, grouped by relation r:
+//
+//   forward   UP[l]    multipoles   mp  = S2M (leaves) or sum_q M2M_q mp[child q]
+//             DOWN[l]  locals       loc = L2L_q loc[parent] + sum_V M2L_r mp + sum_X S2L_r f
+//             LEAF     potential    u   = sum_U T_r f + sum_W M2T_r mp + L2T loc
+//   adjoint   ASUM     usum = row sums of ubar
+//             AUP[l]   lbar = L2T^T ubar (leaves) or sum_q L2L_q^T lbar[child q]
+//             ADOWN[l] abar = M2M_q^T abar[parent] + sum_V M2L_r^T lbar + sum_W M2T_r^T ubar
+//             ALEAF    fbar = s^2 [S2M^T abar + sum_U T_r^T ubar + sum_X S2L_r^T lbar]
+//
+// plus rank-one log-scale terms (ln s_l * mass) folded into each stage's epilogue. Owner-
+// computes with a fixed relation order gives bitwise-deterministic results without atomics.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace vp {
+
+constexpr int kP = 16;         // nodes per dimension
+constexpr int kNP = 256;       // nodes per leaf
+constexpr int kTerms = 40;     // complex expansion terms (order 39)
+constexpr int kNE = 80;        // reals per expansion (Re, Im interleaved)
+constexpr int kMaxLevel = 29;
+
+// ---------------------------------------------------------------- relations (matrix ids)
+// Forward families occupy ids [0, kNumFwd); the adjoint uses id + kNumFwd for the transpose.
+constexpr int kRelS2M = 0;
+constexpr int kRelM2M = 1;    // +q, q = quadrant 0..3 (child dx, dy = -/+ 1/2: q = (dy>0)*2 + (dx>0))
+constexpr int kRelL2L = 5;    // +q
+constexpr int kRelM2L = 9;    // +40 offsets
+constexpr int kRelS2L = 49;   // +20 offsets
+constexpr int kRelNear = 69;  // +33 relations
+constexpr int kRelM2T = 102;  // +20 offsets
+constexpr int kRelL2T = 122;
+constexpr int kNumFwd = 123;
+constexpr int kNumRel = 2 * kNumFwd;
+
+struct Offset { double dx, dy, rho; };
+const std::vector<Offset>& near_offsets();  // 33, in target half-widths
+const std::vector<Offset>& v_offsets();     // 40, in half-widths (rho 1)
+const std::vector<Offset>& w_offsets();     // 20 (rho 1/2)
+const std::vector<Offset>& x_offsets();     // 20 (rho 2)
+int find_offset(const std::vector<Offset>& v, double dx, double dy, double rho);
+
+// ---------------------------------------------------------------- matrices
+struct Matrices {
+  // row-major real matrices, indexed by relation id (forward and transposed)
+  std::vector<int> M, K;
+  std::vector<std::vector<double>> a;
+  std::vector<double> nnz;  // non-zero count of each
+};
+const Matrices& matrices();  // built once per process (near tables by polar quadrature)
+void set_table_cache_dir(const char* dir);
+
+// ---------------------------------------------------------------- plan
+enum Arr : int8_t { A_IN = 0, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_NONE };
+enum StageKind : int { K_UP = 0, K_DOWN, K_LEAF, K_AUP, K_ADOWN, K_ALEAF, K_ASUM, K_NUM };
+
+struct FamDesc { int8_t arr; int32_t stride; int8_t scaled; };  // scaled: times s_b^2 of leaf
+
+struct Stage {
+  int kind = 0, level = 0;
+  int M = 0;       // output rows (80 or 256)
+  int NT = 0;      // slots per tile
+  int n_tiles = 0;
+  int8_t out_arr = A_NONE;
+  int32_t out_stride = 0;
+  int8_t out_scaled = 0;   // multiply output by s^2 of the target leaf
+  int8_t r1_all_rows = 0;  // rank-one term added to all rows (else row 0 only)
+  FamDesc fam[4];
+  FamDesc r1fam[3];
+  std::vector<int32_t> tile_tgt;      // n_tiles * NT, -1 = empty slot
+  std::vector<int32_t> tile_seg_ptr;  // n_tiles + 1
+  std::vector<int32_t> seg_rel;       // relation id
+  std::vector<int8_t> seg_fam;        // index into fam[]
+  std::vector<int32_t> seg_src;       // n_seg * NT source index, -1 = none
+  std::vector<int32_t> r1_ptr;        // n_tiles * NT + 1
+  std::vector<int32_t> r1_idx;
+  std::vector<int8_t> r1_fam;
+  std::vector<double> r1_coef;
+  double flops = 0.0;
+  int64_t n_pairs = 0;
+};
+
+struct Plan {
+  int64_t n_leaves = 0, n_boxes = 0;
+  int32_t n_trees = 0, max_level = 0;
+  // boxes sorted by (level, tree, morton)
+  std::vector<int32_t> box_level, box_tree, box_parent, box_leaf;  // box_leaf: caller leaf or -1
+  std::vector<int64_t> box_x, box_y;
+  std::vector<std::array<int32_t, 4>> box_child;
+  std::vector<int32_t> leaf_box;     // caller leaf -> box
+  std::vector<double> leaf_s2;       // s^2 per caller leaf
+  std::vector<double> leaf_kappa;    // -(1/2pi) ln s per caller leaf
+  std::vector<Stage> fwd, adj;
+  // pair counts
+  int64_t pairs_near = 0, pairs_v = 0, pairs_w = 0, pairs_x = 0, n_m2m = 0, n_l2l = 0, n_s2m = 0,
+          n_l2t = 0;
+};
+
+// Validates trees only (tiling, level grid, 2:1 balance); no tables are built.
+int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
+                    int64_t* bad_leaf);
+
+// Validates and builds the host plan. Returns a VOLPOT_* status; bad_leaf gets the first
+// offending caller leaf index on tree errors.
+int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
+               const int32_t* levels, int tile_leaf, int tile_box, Plan& plan, int64_t* bad_leaf);
+
+}  // namespace vp

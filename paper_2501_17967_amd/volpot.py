@@ -1,0 +1,257 @@
+"""Python binding of the C-ABI box code (libvolpot.so): argument marshalling only.
+
+Every step of the volume potential runs in the HIP library; PyTorch supplies device memory
+(``data_ptr()``) and the stream. There is no fallback: if the library is missing the import of
+``lib()`` raises.
+
+    plan = Plan(centres, levels)            # host arrays; validates the tree, uploads tables
+    u = plan.apply(f)                       # f: cuda float64 (n_leaves, 16, 16) or (n, 256)
+    fbar = plan.apply_adjoint(ubar)         # exact transpose
+    u = volume_potential(f, plan)           # autograd: backward runs apply_adjoint
+
+Sign convention: u = int G f with G = -(1/2pi) log|x - y| (so -Lap u = f); the paper's v_bulk
+(Sec. 4.2, eq. (vbulk)) is -u.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvolpot.so")
+
+OK = 0
+ERR_ARG, ERR_TREE, ERR_UNBALANCED, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
+
+EXPORTED = [
+    "volpot_plan", "volpot_plan_forest", "volpot_apply", "volpot_apply_adjoint", "volpot_plan_info",
+    "volpot_validate_tree", "volpot_nodes", "volpot_plan_destroy", "volpot_status_string",
+    "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
+]
+
+STAGE_KINDS = ["up", "down", "leaf", "adj_up", "adj_down", "adj_leaf", "adj_sum"]
+
+
+class VolpotError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().volpot_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__("%s: %s (status %d)" % (what, msg, code))
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
+                ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int64), ("n_boxes", ctypes.c_int64), ("n_trees", ctypes.c_int64),
+                ("max_level", ctypes.c_int32), ("order", ctypes.c_int32), ("n_reals", ctypes.c_int32),
+                ("n_stages", ctypes.c_int32), ("pairs_near", ctypes.c_int64), ("pairs_v", ctypes.c_int64),
+                ("pairs_w", ctypes.c_int64), ("pairs_x", ctypes.c_int64), ("n_m2m", ctypes.c_int64),
+                ("n_l2l", ctypes.c_int64), ("n_s2m", ctypes.c_int64), ("n_l2t", ctypes.c_int64),
+                ("flops_total", ctypes.c_double), ("flops_leaf_stage", ctypes.c_double),
+                ("flops_up", ctypes.c_double), ("flops_down", ctypes.c_double), ("bytes_min", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libvolpot.so (raises if it has not been built).
+
+    PyTorch is imported first: it ships its own libamdhip64 / libhsa-runtime64, and the library
+    must bind to that same HIP runtime (same soname) so that torch's streams and device pointers
+    are valid in our launches. Loading the library first would pull in a second runtime.
+    """
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (binds the process to torch's HIP runtime, see above)
+
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libvolpot.so is not built; run `python -m paper_2501_17967_amd.build` "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.volpot_plan.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(_vp)]
+        L.volpot_plan_forest.argtypes = [ctypes.c_int32, _lp, _dp, _ip, ctypes.c_int32, ctypes.POINTER(Options),
+                                         ctypes.POINTER(_vp)]
+        L.volpot_apply.argtypes = [_vp, _vp, _vp, _vp]
+        L.volpot_apply_adjoint.argtypes = [_vp, _vp, _vp, _vp]
+        L.volpot_plan_info.argtypes = [_vp, ctypes.POINTER(Info)]
+        L.volpot_validate_tree.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_int32, _lp]
+        L.volpot_nodes.argtypes = [ctypes.c_int32, _dp, _dp]
+        L.volpot_plan_destroy.argtypes = [_vp]
+        L.volpot_plan_destroy.restype = None
+        L.volpot_status_string.argtypes = [ctypes.c_int]
+        L.volpot_status_string.restype = ctypes.c_char_p
+        L.volpot_set_timing.argtypes = [_vp, ctypes.c_int32]
+        L.volpot_stage_times.argtypes = [_vp, _dp, _lp, ctypes.c_int32]
+        L.volpot_plan_table.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int64]
+        L.volpot_near_relation.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != OK:
+        raise VolpotError(code, what)
+
+
+def _host_tree(centres, levels):
+    c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 2))
+    l = np.ascontiguousarray(np.asarray(levels, dtype=np.int32).reshape(-1))
+    if c.shape[0] != l.shape[0]:
+        raise ValueError("centres and levels differ in length")
+    return c, l
+
+
+def validate_tree(centres, levels, p=16):
+    """(status, first bad leaf or -1) from the library's host-side tree check."""
+    c, l = _host_tree(centres, levels)
+    bad = ctypes.c_int64(-1)
+    rc = lib().volpot_validate_tree(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), c.shape[0], p, ctypes.byref(bad))
+    return rc, int(bad.value)
+
+
+def nodes(p=16):
+    t = np.zeros(p)
+    w = np.zeros(p)
+    _check(lib().volpot_nodes(p, t.ctypes.data_as(_dp), w.ctypes.data_as(_dp)), "volpot_nodes")
+    return t, w
+
+
+def near_relation(r):
+    dx, dy, rho = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().volpot_near_relation(r, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(rho)), "volpot_near_relation")
+    return dx.value, dy.value, rho.value
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A plan for one tree or, with ``tree_offsets``, a forest of independent trees."""
+
+    def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
+                 tile_leaf=0, tile_box=0, table_cache=None):
+        c, l = _host_tree(centres, levels)
+        self.n_leaves = c.shape[0]
+        opt = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
+                      table_cache.encode() if table_cache else None)
+        h = _vp()
+        L = lib()
+        if tree_offsets is None:
+            rc = L.volpot_plan(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), self.n_leaves, p, ctypes.byref(opt), ctypes.byref(h))
+            self.n_trees = 1
+        else:
+            off = np.ascontiguousarray(np.asarray(tree_offsets, dtype=np.int64))
+            rc = L.volpot_plan_forest(off.size - 1, off.ctypes.data_as(_lp), c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), p,
+                                      ctypes.byref(opt), ctypes.byref(h))
+            self.n_trees = off.size - 1
+        _check(rc, "volpot_plan")
+        self._h = h
+        self.host_only = host_only
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().volpot_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = Info()
+        _check(lib().volpot_plan_info(self._h, ctypes.byref(inf)), "volpot_plan_info")
+        return {name: getattr(inf, name) for name, _ in Info._fields_}
+
+    def table(self, kind, index=0):
+        shape = {0: (256, 256), 1: (80, 256), 2: (256, 80)}[kind]
+        out = np.zeros(shape)
+        _check(lib().volpot_plan_table(self._h, kind, index, out.ctypes.data_as(_dp), out.size), "volpot_plan_table")
+        return out
+
+    def set_timing(self, enable):
+        _check(lib().volpot_set_timing(self._h, int(enable)), "volpot_set_timing")
+
+    def stage_times(self):
+        """{kind: (ms summed, launches)} since the last call (synchronises the timing events)."""
+        ms = np.zeros(len(STAGE_KINDS))
+        n = np.zeros(len(STAGE_KINDS), dtype=np.int64)
+        _check(lib().volpot_stage_times(self._h, ms.ctypes.data_as(_dp), n.ctypes.data_as(_lp), len(STAGE_KINDS)),
+               "volpot_stage_times")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGE_KINDS)}
+
+    # ------------------------------------------------------------------
+    def _prep(self, x, out):
+        import torch
+
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
+            raise TypeError("expected a CUDA float64 tensor")
+        if x.numel() != self.n_leaves * 256:
+            raise ValueError("expected %d leaves x 256 values" % self.n_leaves)
+        x = x.contiguous()
+        if x.data_ptr() % 16:
+            x = x.clone()
+        if out is None:
+            out = torch.empty_like(x)
+        elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == x.numel()):
+            raise ValueError("bad output tensor")
+        return x, out
+
+    def apply(self, f, out=None, stream=None):
+        """u = A f (asynchronous on ``stream``, default the current stream)."""
+        f, out = self._prep(f, out)
+        _check(lib().volpot_apply(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _stream_handle(stream)), "volpot_apply")
+        return out
+
+    def apply_adjoint(self, ubar, out=None, stream=None):
+        """fbar = A^T ubar."""
+        ubar, out = self._prep(ubar, out)
+        _check(lib().volpot_apply_adjoint(self._h, ctypes.c_void_p(ubar.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          _stream_handle(stream)), "volpot_apply_adjoint")
+        return out
+
+
+def _autograd_cls():
+    import torch
+
+    class VolPot(torch.autograd.Function):
+        """u = A f with dJ/df = A^T dJ/du from the hand-written adjoint kernels."""
+
+        @staticmethod
+        def forward(ctx, f, plan):
+            ctx.plan = plan
+            return plan.apply(f).view_as(f)
+
+        @staticmethod
+        def backward(ctx, grad):
+            return ctx.plan.apply_adjoint(grad.contiguous()).view_as(grad), None
+
+    return VolPot
+
+
+_VolPot = None
+
+
+def volume_potential(f, plan):
+    """Differentiable u = A f (torch.autograd.Function backed by volpot_apply / _adjoint)."""
+    global _VolPot
+    if _VolPot is None:
+        _VolPot = _autograd_cls()
+    return _VolPot.apply(f, plan)

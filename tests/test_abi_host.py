@@ -1,0 +1,146 @@
+"""CPU-side checks of the C-ABI library: every declared symbol is exported, host validation
+and error codes, and the host plan (lists, tables) against the oracle. No GPU calls."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import nodes as onodes
+from oracle import quad, tree
+from workloads import gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def vp():
+    from paper_2501_17967_amd import volpot
+
+    if not os.path.exists(volpot.LIB_PATH):
+        from paper_2501_17967_amd import build
+
+        build.build()
+    volpot.lib()
+    return volpot
+
+
+def test_header_symbols_are_exported(vp):
+    hdr = open(os.path.join(ROOT, "include", "volpot.h")).read()
+    names = sorted(set(re.findall(r"\b(volpot_[a-z_]+)\s*\(", hdr)))
+    assert len(names) >= 13
+    L = vp.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(vp.EXPORTED) == names
+
+
+def test_nodes_match_oracle_convention(vp):
+    t, w = vp.nodes(16)
+    assert np.max(np.abs(t - onodes.cheb1_points(16))) < 1e-15
+    assert np.max(np.abs(w - onodes.fejer1_weights(16))) < 1e-15
+
+
+def _tree_arrays(keys):
+    keys = sorted(keys)
+    cen = [(-1 + (2 * x + 1) * 2.0 ** -l, -1 + (2 * y + 1) * 2.0 ** -l) for l, x, y in keys]
+    return np.array(cen), np.array([k[0] for k in keys], dtype=np.int32)
+
+
+def test_validate_tree_status_codes(vp):
+    c, l = _tree_arrays(gen.uniform_tree(2))
+    assert vp.validate_tree(c, l) == (vp.OK, -1)
+    rc, bad = vp.validate_tree(c[1:], l[1:])  # gap
+    assert rc == vp.ERR_TREE
+    c2 = c.copy()
+    c2[3, 0] += 0.01  # off grid
+    rc, bad = vp.validate_tree(c2, l)
+    assert rc == vp.ERR_TREE and bad == 3
+    c3 = np.vstack([c, [[-0.875, -0.875]]])  # overlap with a level-3 leaf
+    l3 = np.concatenate([l, [3]])
+    assert vp.validate_tree(c3, l3)[0] == vp.ERR_TREE
+    # unbalanced: level 3 next to level 1
+    leaves = {(1, 1, 0), (1, 0, 1), (1, 1, 1), (2, 0, 0), (2, 1, 0), (2, 0, 1)} | {(3, x, y) for x in (2, 3) for y in (2, 3)}
+    c4, l4 = _tree_arrays(leaves)
+    assert vp.validate_tree(c4, l4)[0] == vp.ERR_UNBALANCED
+    l5 = l.copy()
+    l5[0] = 31
+    assert vp.validate_tree(c, l5)[0] in (vp.ERR_TREE, vp.ERR_UNSUPPORTED)
+    c6 = c.copy()
+    c6[0, 0] = np.nan
+    assert vp.validate_tree(c6, l)[0] == vp.ERR_TREE
+    assert vp.validate_tree(c, l, p=8)[0] == vp.ERR_UNSUPPORTED
+
+
+def test_plan_errors(vp):
+    c, l = _tree_arrays(gen.uniform_tree(1))
+    with pytest.raises(vp.VolpotError) as e:
+        vp.Plan(c, l, p=12, host_only=True)
+    assert e.value.code == vp.ERR_UNSUPPORTED
+    with pytest.raises(vp.VolpotError) as e:
+        vp.Plan(c[:3], l[:3], host_only=True)
+    assert e.value.code == vp.ERR_TREE
+
+
+@pytest.fixture(scope="module")
+def host_plan(vp):
+    w = gen.config1(0)
+    return vp.Plan(w.centres, w.levels, host_only=True)
+
+
+def test_host_only_plan_refuses_apply(vp, host_plan):
+    L = vp.lib()
+    import ctypes
+
+    rc = L.volpot_apply(host_plan._h, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
+    assert rc == vp.ERR_STATE
+
+
+def test_near_tables_agree_with_oracle(vp, host_plan):
+    # two independent quadratures (polar/graded in the library, subdivision in the oracle)
+    OT = quad.near_tables()
+    worst = 0.0
+    for r in range(33):
+        ro = quad.relation_index(*vp.near_relation(r))
+        assert ro >= 0
+        worst = max(worst, np.max(np.abs(host_plan.table(0, r) - OT[ro])))
+    assert worst < 1e-14
+
+
+def test_s2m_and_l2t_reproduce_definitions(vp, host_plan):
+    # S2M row 0 is the leaf mass weights W; rows 2, 3 (n = 1) are -int l_k eta_x, -int l_k eta_y
+    W = onodes.tensor_weights()
+    S = host_plan.table(1)
+    assert np.max(np.abs(S[0] - W)) < 1e-15 and np.max(np.abs(S[1])) == 0.0
+    gx, gw = np.polynomial.legendre.leggauss(32)
+    L = onodes.lagrange_matrix(gx)
+    m0, m1 = L @ gw, L @ (gw * gx)  # exact 1D moments of each L_i
+    assert np.max(np.abs(S[2] + np.outer(m0, m1).reshape(-1))) < 1e-15  # index [j, i]
+    assert np.max(np.abs(S[3] + np.outer(m1, m0).reshape(-1))) < 1e-15
+    t = onodes.cheb1_points()
+    X, Y = np.meshgrid(t, t, indexing="xy")
+    Lt = host_plan.table(2)
+    assert np.allclose(Lt[:, 0], -1 / (2 * np.pi)) and np.allclose(Lt[:, 2], -X.reshape(-1) / (2 * np.pi))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pair_counts_match_oracle_lists(vp, seed):
+    w = gen.random_small_tree(seed, max_level=5, n_splits=9)
+    T = tree.Tree(w.centres, w.levels)
+    U, V, W, X = T.lists()
+    inf = vp.Plan(w.centres, w.levels, host_only=True).info()
+    assert inf["pairs_near"] == sum(len(v) for v in U.values())
+    assert inf["pairs_v"] == sum(len(v) for v in V.values())
+    assert inf["pairs_w"] == sum(len(v) for v in W.values())
+    assert inf["pairs_x"] == sum(len(v) for v in X.values())
+
+
+def test_forest_pair_counts_add_up(vp):
+    ws = [gen.random_small_tree(s, max_level=4, n_splits=5) for s in range(3)]
+    infs = [vp.Plan(w.centres, w.levels, host_only=True).info() for w in ws]
+    off = np.cumsum([0] + [w.n_leaves for w in ws])
+    f = vp.Plan(np.vstack([w.centres for w in ws]), np.concatenate([w.levels for w in ws]), tree_offsets=off,
+                host_only=True).info()
+    for k in ("pairs_near", "pairs_v", "pairs_w", "pairs_x", "n_boxes", "n_leaves"):
+        assert f[k] == sum(i[k] for i in infs), k
+    assert abs(f["flops_total"] - sum(i["flops_total"] for i in infs)) < 1e-6 * f["flops_total"]

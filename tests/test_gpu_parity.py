@@ -1,0 +1,266 @@
+"""GPU parity: the HIP box code (through the C ABI) against the CPU oracle.
+
+Tolerance: relative max-norm error <= 1e-11 (rel err = max|u_gpu - u_ref| / max|u_ref|), the
+bar for the FP64 path. Both sides truncate expansions (GPU order 39, oracle order 50) far below
+it; near tables come from two independent quadratures that agree to ~1e-16.
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from oracle import fmm, nodes, quad, tree
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def vp():
+    from paper_2501_17967_amd import volpot
+
+    volpot.lib()
+    return volpot
+
+
+def _gpu(torch_mod, a):
+    return torch_mod.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _run(vp, torch_mod, w, adjoint_input=None, **kw):
+    plan = vp.Plan(w.centres, w.levels, **kw)
+    u = plan.apply(_gpu(torch_mod, w.f)).cpu().numpy()
+    fb = None
+    if adjoint_input is not None:
+        fb = plan.apply_adjoint(_gpu(torch_mod, adjoint_input)).cpu().numpy()
+    plan.close()
+    return u, fb
+
+
+# ------------------------------------------------------------------------ forward
+def test_config1_forward_vs_direct_sum(vp, torch_mod):
+    w = gen.config1(0)
+    _say("case config1 seed 0 (64 leaves)")
+    u, _ = _run(vp, torch_mod, w)
+    ud = quad.direct_potential(tree.Tree(w.centres, w.levels), w.f)
+    assert rel(u, ud) <= TOL
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_config1_seeds_vs_box_code_oracle(vp, torch_mod, seed):
+    w = gen.config1(seed)
+    _say("case config1 seed %d" % seed)
+    r = np.random.default_rng(seed).standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_random_adaptive_trees_forward_and_adjoint(vp, torch_mod, seed):
+    # small random balanced trees in shuffled caller order: every list type, ragged tiles
+    w = gen.random_small_tree(seed, max_level=6, n_splits=12)
+    _say("case random tree seed %d (%d leaves)" % (seed, w.n_leaves))
+    r = np.random.default_rng(10 + seed).standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
+def test_config2_forward_and_adjoint_vs_box_code_oracle(vp, torch_mod):
+    w = gen.config2(0)
+    _say("case config2 seed 0 (%d leaves)" % w.n_leaves)
+    r = np.random.default_rng(7).standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
+def test_config2_forward_sampled_vs_direct_sum(vp, torch_mod):
+    w = gen.config2(1)
+    _say("case config2 seed 1 sampled direct (%d leaves)" % w.n_leaves)
+    u, _ = _run(vp, torch_mod, w)
+    rng = np.random.default_rng(3)
+    samples = [(int(a), int(m)) for a, m in zip(rng.integers(0, w.n_leaves, 48), rng.integers(0, 256, 48))]
+    ud = quad.direct_potential(tree.Tree(w.centres, w.levels), w.f, samples)
+    ug = np.array([u[a, m] for a, m in samples])
+    assert np.max(np.abs(ug - ud)) / np.max(np.abs(u)) <= TOL
+
+
+def test_size_matched_config2_sampled_vs_direct_sum(vp, torch_mod):
+    # the benchmark workload (about 20k leaves), in the launch configuration bench.py times
+    w = gen.config2(0, size_matched=True)
+    _say("case config2-sm seed 0 sampled direct (%d leaves)" % w.n_leaves)
+    u, _ = _run(vp, torch_mod, w)
+    rng = np.random.default_rng(5)
+    samples = [(int(a), int(m)) for a, m in zip(rng.integers(0, w.n_leaves, 32), rng.integers(0, 256, 32))]
+    ud = quad.direct_potential(tree.Tree(w.centres, w.levels), w.f, samples)
+    ug = np.array([u[a, m] for a, m in samples])
+    assert np.max(np.abs(ug - ud)) / np.max(np.abs(u)) <= TOL
+
+
+def test_config1_against_gaussian_closed_form(vp, torch_mod):
+    # analysis check: the closed-form whole-plane potential minus the part of each Gaussian
+    # outside the root; differs only by the leaf interpolation error of f (level 3).
+    w = gen.config1(0)
+    _say("case config1 closed form")
+    u, _ = _run(vp, torch_mod, w)
+    rng = np.random.default_rng(2)
+    g = w.src
+    errs = []
+    for a, m in zip(rng.integers(0, w.n_leaves, 6), rng.integers(0, 256, 6)):
+        x, y = nodes.leaf_nodes(w.centres[a], 2.0 ** -w.levels[a])[m]
+        ref = 0.0
+        for (cx, cy), s, A in zip(g.centres, g.sigmas, g.amps):
+            ref += cf.gaussian_potential(x, y, cx, cy, s, A) - cf.gaussian_exterior_tail(x, y, cx, cy, s, A)
+        errs.append(abs(u[a, m] - ref))
+    assert max(errs) / np.max(np.abs(u)) < 1e-8
+
+
+# ------------------------------------------------------------------------ invariants
+def test_dot_product_transpose(vp, torch_mod):
+    w = gen.config2(2)
+    _say("case dot product config2 seed 2")
+    plan = vp.Plan(w.centres, w.levels)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal(w.f.shape)
+    r = rng.standard_normal(w.f.shape)
+    Af = plan.apply(_gpu(torch_mod, f)).cpu().numpy()
+    Atr = plan.apply_adjoint(_gpu(torch_mod, r)).cpu().numpy()
+    plan.close()
+    lhs, rhs = np.sum(Af * r), np.sum(f * Atr)
+    assert abs(lhs - rhs) / (np.linalg.norm(Af) * np.linalg.norm(r)) < 1e-13
+
+
+def test_bitwise_determinism(vp, torch_mod):
+    w = gen.config2(0)
+    _say("case determinism")
+    plan = vp.Plan(w.centres, w.levels)
+    f = _gpu(torch_mod, w.f)
+    a = plan.apply(f).cpu().numpy()
+    b = plan.apply(f).cpu().numpy()
+    c = plan.apply_adjoint(f).cpu().numpy()
+    d = plan.apply_adjoint(f).cpu().numpy()
+    plan.close()
+    assert np.array_equal(a, b) and np.array_equal(c, d)
+
+
+def test_forest_equals_single_tree_applies(vp, torch_mod):
+    ws = [gen.random_small_tree(s, max_level=5, n_splits=8) for s in range(4)] + [gen.config1(0)]
+    _say("case forest of %d trees" % len(ws))
+    off = np.cumsum([0] + [w.n_leaves for w in ws])
+    F = np.vstack([w.f for w in ws])
+    forest = vp.Plan(np.vstack([w.centres for w in ws]), np.concatenate([w.levels for w in ws]), tree_offsets=off)
+    u = forest.apply(_gpu(torch_mod, F)).cpu().numpy()
+    fb = forest.apply_adjoint(_gpu(torch_mod, F)).cpu().numpy()
+    forest.close()
+    for t, w in enumerate(ws):
+        us, fs = _run(vp, torch_mod, w, adjoint_input=w.f)
+        assert np.array_equal(u[off[t]:off[t + 1]], us)
+        assert np.array_equal(fb[off[t]:off[t + 1]], fs)
+
+
+def test_graph_replays_match_eager(vp, torch_mod):
+    w = gen.config2(0)
+    _say("case graph replay")
+    eager = vp.Plan(w.centres, w.levels)
+    graph = vp.Plan(w.centres, w.levels, use_graph=True)
+    f = _gpu(torch_mod, w.f)
+    ref = eager.apply(f).cpu().numpy()
+    refa = eager.apply_adjoint(f).cpu().numpy()
+    out = torch_mod.empty_like(f)
+    outa = torch_mod.empty_like(f)
+    for rep in range(3):
+        graph.apply(f, out=out)
+        graph.apply_adjoint(f, out=outa)
+        torch_mod.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref)
+        assert np.array_equal(outa.cpu().numpy(), refa)
+        eager.apply(f)  # eager work between replays
+        torch_mod.cuda.synchronize()
+    eager.close()
+    graph.close()
+
+
+def _deep_tree(depth, point=(0.0013, -0.0021)):
+    leaves = {(1, x, y) for x in (0, 1) for y in (0, 1)}
+    for lev in range(1, depth):
+        k = (lev, int((point[0] + 1) / 2 * (1 << lev)), int((point[1] + 1) / 2 * (1 << lev)))
+        leaves.remove(k)
+        leaves |= {(lev + 1, 2 * k[1] + a, 2 * k[2] + b) for a in (0, 1) for b in (0, 1)}
+        leaves = gen.balance(leaves)
+    return leaves
+
+
+@pytest.mark.parametrize("case", ["root", "level1", "deep12", "deep20"])
+def test_edge_trees(vp, torch_mod, case):
+    # root-only leaf (no far field), the four level-1 leaves, deep thin refinements
+    leaves = {"root": {(0, 0, 0)}, "level1": gen.uniform_tree(1), "deep12": _deep_tree(12),
+              "deep20": _deep_tree(20)}[case]
+    g = gen.Gaussians(np.array([[0.01, -0.02], [0.0011, -0.002]]), np.array([0.3, 2e-4]), np.array([1.0, -0.5]))
+    w = gen.make_workload("edge-" + case, g, leaves, shuffle_seed=3)
+    _say("case edge tree %s: %d leaves, max level %d" % (case, w.n_leaves, w.levels.max()))
+    r = np.random.default_rng(1).standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
+def test_zero_input_gives_zero(vp, torch_mod):
+    w = gen.config1(0)
+    plan = vp.Plan(w.centres, w.levels)
+    z = torch_mod.zeros((w.n_leaves, 256), dtype=torch_mod.float64, device="cuda:0")
+    assert float(plan.apply(z).abs().max()) == 0.0
+    assert float(plan.apply_adjoint(z).abs().max()) == 0.0
+    plan.close()
+
+
+# ------------------------------------------------------------------------ autograd
+def test_autograd_gradient_matches_finite_differences(vp, torch_mod):
+    # J(f) = 1/2 sum W s^2 (A f - u_t)^2 on the config-2 tree; dJ/df through the adjoint kernels
+    from paper_2501_17967_amd import volume_potential
+
+    w, f2, dirs = gen.config5(n_dirs=4)
+    _say("case autograd FD (%d leaves)" % w.n_leaves)
+    plan = vp.Plan(w.centres, w.levels)
+    Wq = _gpu(torch_mod, nodes.tensor_weights()[None, :] * (2.0 ** (-2 * w.levels.astype(float)))[:, None])
+    ut = plan.apply(_gpu(torch_mod, f2))
+
+    def J(fv):
+        return 0.5 * torch_mod.sum(Wq * (volume_potential(fv, plan) - ut) ** 2)
+
+    f = _gpu(torch_mod, w.f).requires_grad_(True)
+    j = J(f)
+    (g,) = torch_mod.autograd.grad(j, f)
+    h = 1e-6
+    for d in dirs:
+        dt = _gpu(torch_mod, d)
+        with torch_mod.no_grad():
+            fd = (J(f + h * dt) - J(f - h * dt)) / (2 * h)
+        an = torch_mod.sum(g * dt)
+        assert abs(float(fd - an)) <= 1e-6 * abs(float(an)) + 1e-9 * abs(float(j))
+    # against the oracle's transpose: grad = A^T (W s^2 (A f - u_t))
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    resid = Wq.cpu().numpy() * (bc.apply(w.f) - ut.cpu().numpy())
+    assert rel(g.cpu().numpy(), bc.apply_adjoint(resid)) <= 1e-10
+    plan.close()
