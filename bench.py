@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X machine code: volume-potential unknowns/s, FP64, forward + adjoint.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline] [--no-batched]
+
+Workload (one "step" = one forward apply and one adjoint apply, every stage of the box code):
+the adaptive 20-Gaussian source on the size-matched quadtree (background level 7, Chebyshev-
+tail rule eps = 1e-11, 2:1 balanced; 16,837 leaves = 4.31M unknowns for seed 0), p = 16. Inputs
+are resident in HBM before the timed region; plan and table construction are outside it.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel (the leaf-output
+stage: near field + M2T + L2T, and its transpose in the adjoint), the CPU oracle timed on this
+host, and the batched-forest (256 uneven trees, hipGraph replay) versus 256 sequential applies.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "volume-potential unknowns/s FP64 (rel err ≤1e-11), fwd+adjoint, batched vs serial"
+PEAK_FP64_MFMA = 78.6e12  # MI355X dense FP64 matrix peak, FLOP/s
+PEAK_HBM = 8.0e12  # bytes/s
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2501_17967_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n_launch_flops):
+    """HBM bytes per launch of the leaf-stage kernel from the committed counter summary, or
+    None when the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "leaf_stage_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-trees", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the box code has no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2501_17967_amd import Plan
+    from workloads import gen
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = gen.config2(args.seed, size_matched=True)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = Plan(w.centres, w.levels)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info()
+    N = w.unknowns
+    print("bench: %s, %d leaves, %d unknowns, max level %d; gen %.1fs plan %.2fs"
+          % (w.name, w.n_leaves, N, info["max_level"], t_gen, t_plan), file=sys.stderr, flush=True)
+
+    f = torch.from_numpy(w.f).to(dev)
+    rng = np.random.default_rng(args.seed + 1)
+    ubar = torch.from_numpy(rng.standard_normal(w.f.shape)).to(dev)
+    u = torch.empty_like(f)
+    fbar = torch.empty_like(f)
+    for _ in range(args.warmup):
+        plan.apply(f, out=u)
+        plan.apply_adjoint(ubar, out=fbar)
+    torch.cuda.synchronize()
+
+    # timed region: K steps of forward + adjoint, HIP events around every stage launch
+    plan.set_timing(True)
+    plan.stage_times()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(f, out=u)
+        plan.apply_adjoint(ubar, out=fbar)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    st = plan.stage_times()
+    plan.set_timing(False)
+    ms_step = 1e3 * t_total / args.steps
+    value = N * args.steps / t_total
+
+    # forward-only and adjoint-only throughput (no timing events)
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps
+
+    t_fwd = timed(lambda: plan.apply(f, out=u), args.steps)
+    t_adj = timed(lambda: plan.apply_adjoint(ubar, out=fbar), args.steps)
+
+    # roofline of the dominant kernel: the leaf-output stage (forward) and its transpose
+    # (adjoint) -- the same kernel instantiation, one launch each per step
+    leaf_ms = st["leaf"][0] + st["adj_leaf"][0]
+    leaf_n = st["leaf"][1] + st["adj_leaf"][1]
+    flops_per_launch = (info["flops_kind"]["leaf"] + info["flops_kind"]["adj_leaf"]) / 2.0
+    avg_ms = leaf_ms / max(leaf_n, 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3)
+    traffic = traffic_from_profile(flops_per_launch)
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
+                "kernel": "grg_kernel<4,4,4,1> (leaf stage: near field + M2T + L2T; adjoint leaf stage)",
+                "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms, "launches": leaf_n}
+    stage_ms = {k: v[0] / args.steps for k, v in st.items()}
+    whole = (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + " (adaptive 20-Gaussian source, size-matched quadtree, seed %d)" % args.seed,
+                   "n_leaves": int(w.n_leaves), "unknowns": int(N), "max_level": int(info["max_level"]), "p": 16,
+                   "expansion_order": int(info["order"]), "step": "forward + adjoint"},
+        "roofline": roofline,
+        "fwd_unknowns_per_s": N / t_fwd,
+        "adj_unknowns_per_s": N / t_adj,
+        "whole_path_tflops": whole / 1e12,
+        "stage_ms_per_step": stage_ms,
+        "plan_s": t_plan,
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import fmm, tree
+
+        print("bench: cpu baseline (oracle box code on the same workload)", file=sys.stderr, flush=True)
+        try:
+            from threadpoolctl import threadpool_info
+
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            cores = len(os.sched_getaffinity(0))
+        bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+        ub = ubar.cpu().numpy()
+        a = time.perf_counter()
+        u_o = bc.apply(w.f)
+        fb_o = bc.apply_adjoint(ub)
+        t_cpu = time.perf_counter() - a
+        u_g = u.cpu().numpy()
+        fb_g = fbar.cpu().numpy()
+        out["cpu_baseline"] = {"value": N / t_cpu, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
+                               "sample": "the full workload, one forward + one adjoint apply of the oracle box "
+                                         "(NumPy, order 50); %.1f s" % t_cpu}
+        out["rel_err_vs_oracle"] = {
+            "forward": float(np.max(np.abs(u_g - u_o)) / np.max(np.abs(u_o))),
+            "adjoint": float(np.max(np.abs(fb_g - fb_o)) / np.max(np.abs(fb_o)))}
+
+    if not args.no_batched:
+        print("bench: batched forest of %d trees" % args.batched_trees, file=sys.stderr, flush=True)
+        trees = gen.config4(0, n_trees=args.batched_trees)
+        off = np.cumsum([0] + [t.n_leaves for t in trees])
+        Nb = int(off[-1]) * 256
+        forest = Plan(np.vstack([t.centres for t in trees]), np.concatenate([t.levels for t in trees]),
+                      tree_offsets=off, use_graph=True)
+        F = torch.from_numpy(np.vstack([t.f for t in trees])).to(dev)
+        Ub = torch.empty_like(F)
+        Fb = torch.empty_like(F)
+        for _ in range(2):
+            forest.apply(F, out=Ub)
+            forest.apply_adjoint(F, out=Fb)
+        reps = max(3, args.steps // 2)
+        tb_f = timed(lambda: forest.apply(F, out=Ub), reps)
+        tb_a = timed(lambda: forest.apply_adjoint(F, out=Fb), reps)
+        singles = [Plan(t.centres, t.levels) for t in trees]
+        views = [F[off[i]:off[i + 1]] for i in range(len(trees))]
+        outs = [Ub[off[i]:off[i + 1]].clone() for i in range(len(trees))]
+        outa = [o.clone() for o in outs]
+
+        def seq_fwd():
+            for p_, x, o in zip(singles, views, outs):
+                p_.apply(x, out=o)
+
+        def seq_adj():
+            for p_, x, o in zip(singles, views, outa):
+                p_.apply_adjoint(x, out=o)
+
+        seq_fwd(); seq_adj()
+        ts_f = timed(seq_fwd, 2)
+        ts_a = timed(seq_adj, 2)
+        same = all(torch.equal(outs[i], Ub[off[i]:off[i + 1]]) for i in range(len(trees)))
+        out["batched"] = {"workload": "forest of %d adaptive trees, 1-40 Gaussians each, min level 3" % len(trees),
+                          "n_leaves": int(off[-1]), "unknowns": Nb,
+                          "leaves_min": int(min(t.n_leaves for t in trees)),
+                          "leaves_max": int(max(t.n_leaves for t in trees)),
+                          "batched_fwd_unknowns_per_s": Nb / tb_f, "batched_adj_unknowns_per_s": Nb / tb_a,
+                          "batched_fwd_adj_unknowns_per_s": Nb / (tb_f + tb_a),
+                          "sequential_fwd_adj_unknowns_per_s": Nb / (ts_f + ts_a),
+                          "speedup_fwd_adj": (ts_f + ts_a) / (tb_f + tb_a),
+                          "batched_equals_sequential_bitwise": bool(same)}
+        for p_ in singles:
+            p_.close()
+        forest.close()
+
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,9 +72,12 @@ typedef struct {
   int64_t n_leaves, n_boxes, n_trees;
   int32_t max_level, order, n_reals, n_stages;
   int64_t pairs_near, pairs_v, pairs_w, pairs_x, n_m2m, n_l2l, n_s2m, n_l2t;
-  double flops_total;       /* forward apply; the adjoint does the same work */
-  double flops_leaf_stage;  /* near field + M2T + L2T (the leaf-output stage) */
-  double flops_up, flops_down;
+  double flops_total;       /* forward apply */
+  double flops_adjoint;     /* adjoint apply (the same pairs, transposed) */
+  double flops_kind[7];     /* per stage kind: 0 upward (S2M, M2M), 1 downward (M2L, S2L, L2L),
+                               2 leaf (near, M2T, L2T), 3 adjoint-upward, 4 adjoint-downward,
+                               5 adjoint-leaf, 6 adjoint row sums */
+  int64_t launches_kind[7]; /* kernel launches per apply of each stage kind */
   double bytes_min;         /* mandatory HBM traffic: 16 B per unknown (f in, u out) */
   int64_t device_bytes;     /* device memory the plan holds (tables shared per device) */
 } volpot_info;

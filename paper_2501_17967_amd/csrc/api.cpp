@@ -412,10 +412,17 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   out->n_m2m = P.n_m2m; out->n_l2l = P.n_l2l; out->n_s2m = P.n_s2m; out->n_l2t = P.n_l2t;
   for (const Stage& s : P.fwd) {
     out->flops_total += s.flops;
-    if (s.kind == K_LEAF) out->flops_leaf_stage += s.flops;
-    if (s.kind == K_UP) out->flops_up += s.flops;
-    if (s.kind == K_DOWN) out->flops_down += s.flops;
+    out->flops_kind[s.kind] += s.flops;
+    out->launches_kind[s.kind] += s.n_tiles > 0;
   }
+  for (const Stage& s : P.adj) {
+    out->flops_adjoint += s.flops;
+    out->flops_kind[s.kind] += s.flops;
+    out->launches_kind[s.kind] += s.n_tiles > 0;
+  }
+  out->flops_kind[K_ASUM] = double(P.n_leaves) * kNP;
+  out->flops_adjoint += out->flops_kind[K_ASUM];
+  out->launches_kind[K_ASUM] = 1;
   out->bytes_min = 16.0 * double(P.n_leaves) * kNP;
   out->device_bytes = plan->device_bytes + (plan->tables ? int64_t(plan->tables->bytes) : 0);
   return VOLPOT_OK;

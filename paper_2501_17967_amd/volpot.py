@@ -50,9 +50,9 @@ class Info(ctypes.Structure):
                 ("n_stages", ctypes.c_int32), ("pairs_near", ctypes.c_int64), ("pairs_v", ctypes.c_int64),
                 ("pairs_w", ctypes.c_int64), ("pairs_x", ctypes.c_int64), ("n_m2m", ctypes.c_int64),
                 ("n_l2l", ctypes.c_int64), ("n_s2m", ctypes.c_int64), ("n_l2t", ctypes.c_int64),
-                ("flops_total", ctypes.c_double), ("flops_leaf_stage", ctypes.c_double),
-                ("flops_up", ctypes.c_double), ("flops_down", ctypes.c_double), ("bytes_min", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("flops_total", ctypes.c_double), ("flops_adjoint", ctypes.c_double),
+                ("flops_kind", ctypes.c_double * 7), ("launches_kind", ctypes.c_int64 * 7),
+                ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -177,7 +177,11 @@ class Plan:
     def info(self):
         inf = Info()
         _check(lib().volpot_plan_info(self._h, ctypes.byref(inf)), "volpot_plan_info")
-        return {name: getattr(inf, name) for name, _ in Info._fields_}
+        out = {}
+        for name, _ in Info._fields_:
+            v = getattr(inf, name)
+            out[name] = {k: v[i] for i, k in enumerate(STAGE_KINDS)} if name in ("flops_kind", "launches_kind") else v
+        return out
 
     def table(self, kind, index=0):
         shape = {0: (256, 256), 1: (80, 256), 2: (256, 80)}[kind]
