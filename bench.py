@@ -8,9 +8,9 @@ the adaptive 20-Gaussian source on the size-matched quadtree (background level 7
 tail rule eps = 1e-11, 2:1 balanced; 16,837 leaves = 4.31M unknowns for seed 0), p = 16. Inputs
 are resident in HBM before the timed region; plan and table construction are outside it.
 
-Printed: one JSON line with the metric, the roofline of the dominant kernel (the leaf-output
-stage: near field + M2T + L2T, and its transpose in the adjoint), the CPU oracle timed on this
-host, and the batched-forest (256 uneven trees, hipGraph replay) versus 256 sequential applies.
+Printed: one JSON line with the metric, the roofline of the dominant kernel (the near-field
+stage and its transpose in the adjoint), the CPU oracle timed on this host, and the batched
+forest (256 uneven trees, hipGraph replay) versus 256 sequential applies.
 """
 import argparse
 import hashlib
@@ -58,6 +58,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-trees", type=int, default=256)
+    ap.add_argument("--tile-leaf", type=int, default=32)
+    ap.add_argument("--tile-box", type=int, default=64)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the box code has no multi-GPU path); "
@@ -67,6 +71,16 @@ def main():
     import numpy as np
     import torch
 
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.calibrate_copy_mib, "copies": 5}))
+        return
+
     from paper_2501_17967_amd import Plan
     from workloads import gen
 
@@ -75,7 +89,7 @@ def main():
     w = gen.config2(args.seed, size_matched=True)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = Plan(w.centres, w.levels)
+    plan = Plan(w.centres, w.levels, tile_leaf=args.tile_leaf, tile_box=args.tile_box)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
@@ -120,17 +134,17 @@ def main():
     t_fwd = timed(lambda: plan.apply(f, out=u), args.steps)
     t_adj = timed(lambda: plan.apply_adjoint(ubar, out=fbar), args.steps)
 
-    # roofline of the dominant kernel: the leaf-output stage (forward) and its transpose
+    # roofline of the dominant kernel: the near-field stage (forward) and its transpose
     # (adjoint) -- the same kernel instantiation, one launch each per step
-    leaf_ms = st["leaf"][0] + st["adj_leaf"][0]
-    leaf_n = st["leaf"][1] + st["adj_leaf"][1]
-    flops_per_launch = (info["flops_kind"]["leaf"] + info["flops_kind"]["adj_leaf"]) / 2.0
+    leaf_ms = st["near"][0] + st["adj_near"][0]
+    leaf_n = st["near"][1] + st["adj_near"][1]
+    flops_per_launch = (info["flops_kind"]["near"] + info["flops_kind"]["adj_near"]) / 2.0
     avg_ms = leaf_ms / max(leaf_n, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3)
     traffic = traffic_from_profile(flops_per_launch)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
-                "kernel": "grg_kernel<4,4,4,1> (leaf stage: near field + M2T + L2T; adjoint leaf stage)",
+                "kernel": "grg_kernel, 256-row tiles: near-field stage (forward) and its transpose (adjoint)",
                 "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms, "launches": leaf_n}
     stage_ms = {k: v[0] / args.steps for k, v in st.items()}
     whole = (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps)
@@ -150,7 +164,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name + " (adaptive 20-Gaussian source, size-matched quadtree, seed %d)" % args.seed,
                    "n_leaves": int(w.n_leaves), "unknowns": int(N), "max_level": int(info["max_level"]), "p": 16,
-                   "expansion_order": int(info["order"]), "step": "forward + adjoint"},
+                   "expansion_order": int(info["order"]), "step": "forward + adjoint",
+                   "tile_leaf": args.tile_leaf, "tile_box": args.tile_box},
         "roofline": roofline,
         "fwd_unknowns_per_s": N / t_fwd,
         "adj_unknowns_per_s": N / t_adj,

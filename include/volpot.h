@@ -61,8 +61,10 @@ typedef struct {
                               apply calls return VOLPOT_ERR_STATE). Default 0. */
   int32_t use_graph;       /* 1: capture each apply once per (input, output) pointer pair into
                               a hipGraph and replay it. Default 0. */
-  int32_t tile_leaf;       /* slots per tile of the leaf-output stages: 32 or 64; 0 = default */
-  int32_t tile_box;        /* slots per tile of the expansion stages: 16, 32 or 64; 0 = default */
+  int32_t tile_leaf;       /* slots per tile of the 256-row (leaf-output) stages: 32 or 64;
+                              0 = default (32) */
+  int32_t tile_box;        /* slots per tile of the 80-row (expansion) stages: 16, 32 or 64;
+                              0 = default (64) */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
 } volpot_options;
 
@@ -74,12 +76,17 @@ typedef struct {
   int64_t pairs_near, pairs_v, pairs_w, pairs_x, n_m2m, n_l2l, n_s2m, n_l2t;
   double flops_total;       /* forward apply */
   double flops_adjoint;     /* adjoint apply (the same pairs, transposed) */
-  double flops_kind[7];     /* per stage kind: 0 upward (S2M, M2M), 1 downward (M2L, S2L, L2L),
-                               2 leaf (near, M2T, L2T), 3 adjoint-upward, 4 adjoint-downward,
-                               5 adjoint-leaf, 6 adjoint row sums */
-  int64_t launches_kind[7]; /* kernel launches per apply of each stage kind */
+  double flops_kind[9];     /* per stage kind: 0 upward (S2M, M2M chain), 1 downward (M2L + S2L
+                               for all levels, L2L chain), 2 near field, 3 L2T + M2T + log terms,
+                               4 adjoint upward (L2T^T, L2L^T chain), 5 adjoint downward (M2L^T,
+                               M2T^T, M2M^T chain), 6 adjoint near field, 7 S2M^T + S2L^T,
+                               8 adjoint row sums */
+  int64_t launches_kind[9]; /* kernel launches per apply of each stage kind */
   double bytes_min;         /* mandatory HBM traffic: 16 B per unknown (f in, u out) */
   int64_t device_bytes;     /* device memory the plan holds (tables shared per device) */
+  double flops_issued_kind[9]; /* matrix-core work the kernels issue per stage kind: every tile
+                                  multiplies each of its relation tables by all of its slots,
+                                  occupied or not (>= flops_kind) */
 } volpot_info;
 
 /* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
@@ -127,11 +134,11 @@ void volpot_plan_destroy(volpot_plan_t plan);
 const char* volpot_status_string(int status);
 
 /* Timing hooks for measurement. When enabled, apply calls record a HIP event pair around
- * every stage launch on the apply stream; volpot_stage_times synchronises those events and
- * returns, per stage kind k (0 upward, 1 downward, 2 leaf, 3 adjoint-upward,
- * 4 adjoint-downward, 5 adjoint-leaf, 6 adjoint-sum), the summed milliseconds ms[k] and
- * launch counts n[k] since the last reset, then resets. Disabled by default; not available
- * with use_graph. */
+ * every stage launch on the stream that launch uses (the near field runs on the caller's
+ * stream, the far-field chain on a plan-owned helper stream forked from and joined back into
+ * it); volpot_stage_times synchronises those events and returns, per stage kind k (numbered
+ * as in volpot_info.flops_kind), the summed milliseconds ms[k] and launch counts n[k] since
+ * the last reset, then resets. Disabled by default; not available with use_graph. */
 int volpot_set_timing(volpot_plan_t plan, int32_t enable);
 int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_t n_kinds);
 

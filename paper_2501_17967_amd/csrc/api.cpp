@@ -116,6 +116,7 @@ struct volpot_plan_s {
   DeviceTables* tables = nullptr;
   char* d_block = nullptr;
   double *d_mp = nullptr, *d_loc = nullptr, *d_lb = nullptr, *d_ab = nullptr, *d_usum = nullptr, *d_leaf_s2 = nullptr;
+  double* d_fs = nullptr;  // prescaled input s^2 f
   std::vector<DevStage> dfwd, dadj;
   int64_t device_bytes = 0;
   bool timing = false;
@@ -125,6 +126,8 @@ struct volpot_plan_s {
   int64_t cnt[K_NUM] = {0};
   hipStream_t cap_stream = nullptr;
   std::vector<GraphEntry> graphs;
+  hipStream_t helper = nullptr;  // far-field chain runs here, forked from the caller's stream
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_end = nullptr;
 };
 
 namespace {
@@ -168,6 +171,7 @@ int upload(volpot_plan_s* p) {
   size_t o_lb = (total + 255) & ~size_t(255); total = o_lb + nb;
   size_t o_ab = (total + 255) & ~size_t(255); total = o_ab + nb;
   size_t o_us = (total + 255) & ~size_t(255); total = o_us + size_t(P.n_leaves) * sizeof(double);
+  size_t o_fs = (total + 255) & ~size_t(255); total = o_fs + size_t(P.n_leaves) * kNP * sizeof(double);
   std::vector<double> s2(P.leaf_s2);
   size_t o_s2 = add_bytes(total, s2);
   std::vector<char> host(total, 0);
@@ -206,13 +210,20 @@ int upload(volpot_plan_s* p) {
   p->d_lb = reinterpret_cast<double*>(b + o_lb);
   p->d_ab = reinterpret_cast<double*>(b + o_ab);
   p->d_usum = reinterpret_cast<double*>(b + o_us);
+  p->d_fs = reinterpret_cast<double*>(b + o_fs);
   p->d_leaf_s2 = reinterpret_cast<double*>(b + o_s2);
+  if (hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_end, hipEventDisableTiming) != hipSuccess)
+    return VOLPOT_ERR_HIP;
   return VOLPOT_OK;
 }
 
 const double* arr_ptr(volpot_plan_s* p, int8_t a, const double* in, double* out) {
   switch (a) {
     case A_IN: return in;
+    case A_INS: return p->d_fs;
     case A_OUT: return out;
     case A_MP: return p->d_mp;
     case A_LOC: return p->d_loc;
@@ -234,11 +245,49 @@ hipEvent_t take_event(volpot_plan_s* p) {
   return e;
 }
 
-int run_stages(volpot_plan_s* p, std::vector<DevStage>& stages, const double* in, double* out, hipStream_t stream,
-               bool timing) {
+void timed_begin(volpot_plan_s* p, bool timing, hipStream_t st, hipEvent_t* ea, hipEvent_t* eb) {
+  *ea = *eb = nullptr;
+  if (!timing) return;
+  *ea = take_event(p);
+  *eb = take_event(p);
+  if (*ea) (void)hipEventRecord(*ea, st);
+}
+void timed_end(volpot_plan_s* p, int kind, hipStream_t st, hipEvent_t ea, hipEvent_t eb) {
+  if (ea && eb) {
+    (void)hipEventRecord(eb, st);
+    p->pending.push_back({kind, ea, eb});
+  }
+}
+
+// The whole apply: fork the helper stream from the caller's stream, issue every stage on its
+// stream in plan order (far-field chain on the helper, near field on the caller's stream),
+// join before the stages that combine both, and join again at the end so that the caller's
+// stream orders everything.
+int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t main, bool timing) {
+  std::vector<DevStage>& stages = adjoint ? p->dadj : p->dfwd;
+  hipStream_t helper = p->helper;
+  if (!adjoint) {  // every forward source read uses s^2 f: scale once, before the fork
+    hipEvent_t ea, eb;
+    timed_begin(p, timing, main, &ea, &eb);
+    if (launch_prescale(in, p->d_leaf_s2, p->d_fs, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
+    timed_end(p, K_UP, main, ea, eb);
+  }
+  if (hipEventRecord(p->ev_fork, main) != hipSuccess || hipStreamWaitEvent(helper, p->ev_fork, 0) != hipSuccess)
+    return VOLPOT_ERR_HIP;
+  if (adjoint) {
+    hipEvent_t ea, eb;
+    timed_begin(p, timing, helper, &ea, &eb);
+    if (launch_rowsum(in, p->d_usum, p->host.n_leaves, helper) != hipSuccess) return VOLPOT_ERR_HIP;
+    timed_end(p, K_ASUM, helper, ea, eb);
+  }
   for (DevStage& d : stages) {
     const Stage& s = *d.st;
+    if (s.join_before) {
+      if (hipEventRecord(p->ev_join, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_join, 0) != hipSuccess)
+        return VOLPOT_ERR_HIP;
+    }
     if (s.n_tiles == 0) continue;
+    hipStream_t st = s.helper ? helper : main;
     GrgParams g;
     std::memset(&g, 0, sizeof(g));
     g.tile_tgt = d.tile_tgt; g.tile_seg_ptr = d.tile_seg_ptr; g.seg_rel = d.seg_rel; g.seg_fam = d.seg_fam;
@@ -246,7 +295,6 @@ int run_stages(volpot_plan_s* p, std::vector<DevStage>& stages, const double* in
     for (int f = 0; f < 4; ++f) {
       g.fam_base[f] = arr_ptr(p, s.fam[f].arr, in, out);
       g.fam_stride[f] = s.fam[f].stride;
-      g.fam_scaled[f] = s.fam[f].scaled;
     }
     g.leaf_s2 = p->d_leaf_s2;
     g.r1_ptr = d.r1_ptr; g.r1_idx = d.r1_idx; g.r1_fam = d.r1_fam; g.r1_coef = d.r1_coef;
@@ -258,36 +306,17 @@ int run_stages(volpot_plan_s* p, std::vector<DevStage>& stages, const double* in
     g.out_stride = s.out_stride;
     g.out_scaled = s.out_scaled;
     g.r1_all_rows = s.r1_all_rows;
+    g.accumulate = s.accumulate;
     g.n_tiles = s.n_tiles;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    if (timing) {
-      ea = take_event(p);
-      eb = take_event(p);
-      if (ea) (void)hipEventRecord(ea, stream);
-    }
-    hipError_t e = launch_grg(s.M, s.NT, g, stream);
-    if (timing && ea && eb) {
-      (void)hipEventRecord(eb, stream);
-      p->pending.push_back({s.kind, ea, eb});
-    }
+    hipEvent_t ea, eb;
+    timed_begin(p, timing, st, &ea, &eb);
+    hipError_t e = launch_grg(s.M, s.NT, s.KC, g, st);
+    timed_end(p, s.kind, st, ea, eb);
     if (e != hipSuccess) return VOLPOT_ERR_HIP;
   }
+  if (hipEventRecord(p->ev_end, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_end, 0) != hipSuccess)
+    return VOLPOT_ERR_HIP;
   return VOLPOT_OK;
-}
-
-int run_adjoint(volpot_plan_s* p, const double* in, double* out, hipStream_t stream, bool timing) {
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (timing) {
-    ea = take_event(p);
-    eb = take_event(p);
-    if (ea) (void)hipEventRecord(ea, stream);
-  }
-  if (launch_rowsum(in, p->d_usum, p->host.n_leaves, stream) != hipSuccess) return VOLPOT_ERR_HIP;
-  if (timing && ea && eb) {
-    (void)hipEventRecord(eb, stream);
-    p->pending.push_back({K_ASUM, ea, eb});
-  }
-  return run_stages(p, p->dadj, in, out, stream, timing);
 }
 
 int run_graph(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t stream) {
@@ -297,7 +326,7 @@ int run_graph(volpot_plan_s* p, bool adjoint, const double* in, double* out, hip
   if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return VOLPOT_ERR_HIP;
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return VOLPOT_ERR_HIP;
-  int rc = adjoint ? run_adjoint(p, in, out, p->cap_stream, false) : run_stages(p, p->dfwd, in, out, p->cap_stream, false);
+  int rc = run(p, adjoint, in, out, p->cap_stream, false);
   hipError_t ec = hipStreamEndCapture(p->cap_stream, &graph);
   if (rc != VOLPOT_OK || ec != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -317,6 +346,10 @@ void free_plan(volpot_plan_s* p) {
     DeviceGuard dg(p->device);
     for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->helper) (void)hipStreamDestroy(p->helper);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->ev_end) (void)hipEventDestroy(p->ev_end);
     for (auto& e : p->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     if (p->d_block) (void)hipFree(p->d_block);
@@ -384,7 +417,7 @@ int volpot_apply(volpot_plan_t plan, const double* f_dev, double* u_dev, void* h
   DeviceGuard dg(plan->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   if (plan->use_graph) return run_graph(plan, false, f_dev, u_dev, s);
-  return run_stages(plan, plan->dfwd, f_dev, u_dev, s, plan->timing);
+  return run(plan, false, f_dev, u_dev, s, plan->timing);
 }
 
 int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fbar_dev, void* hip_stream) {
@@ -394,7 +427,7 @@ int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fba
   DeviceGuard dg(plan->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   if (plan->use_graph) return run_graph(plan, true, ubar_dev, fbar_dev, s);
-  return run_adjoint(plan, ubar_dev, fbar_dev, s, plan->timing);
+  return run(plan, true, ubar_dev, fbar_dev, s, plan->timing);
 }
 
 int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
@@ -413,14 +446,16 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   for (const Stage& s : P.fwd) {
     out->flops_total += s.flops;
     out->flops_kind[s.kind] += s.flops;
+    out->flops_issued_kind[s.kind] += s.flops_issued;
     out->launches_kind[s.kind] += s.n_tiles > 0;
   }
   for (const Stage& s : P.adj) {
     out->flops_adjoint += s.flops;
     out->flops_kind[s.kind] += s.flops;
+    out->flops_issued_kind[s.kind] += s.flops_issued;
     out->launches_kind[s.kind] += s.n_tiles > 0;
   }
-  out->flops_kind[K_ASUM] = double(P.n_leaves) * kNP;
+  out->flops_kind[K_ASUM] = double(P.n_leaves) * kNP;  // one add per value
   out->flops_adjoint += out->flops_kind[K_ASUM];
   out->launches_kind[K_ASUM] = 1;
   out->bytes_min = 16.0 * double(P.n_leaves) * kNP;

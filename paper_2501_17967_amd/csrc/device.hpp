@@ -22,8 +22,7 @@ struct GrgParams {
   const RelDesc* rels;          // device table of relations
   const double* fam_base[4];
   int32_t fam_stride[4];
-  int32_t fam_scaled[4];        // 1: scale source by leaf_s2[source]
-  const double* leaf_s2;
+  const double* leaf_s2;        // s^2 per leaf (output scaling of the adjoint leaf stages)
   const int32_t* r1_ptr;        // n_tiles * NT + 1
   const int32_t* r1_idx;
   const int8_t* r1_fam;
@@ -34,11 +33,14 @@ struct GrgParams {
   int32_t out_stride;
   int32_t out_scaled;           // 1: multiply the output of target t by leaf_s2[t]
   int32_t r1_all_rows;          // 1: rank-one term on every row, else on row 0 only
+  int32_t accumulate;           // 1: add to the existing output, else overwrite
   int32_t n_tiles;
 };
 
-// Launch one stage; M in {80, 256}, NT in {16, 32, 64} (M = 256 needs NT in {32, 64}).
-hipError_t launch_grg(int M, int NT, const GrgParams& p, hipStream_t stream);
+// Launch one stage: (M, NT, KC) in {(256, 32|64, 16|32), (80, 16|32|64, 40)}.
+hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream);
+// out = s2[leaf] * x  (n_leaves x 256)
+hipError_t launch_prescale(const double* x, const double* s2, double* out, int64_t n_leaves, hipStream_t stream);
 // usum[a] = sum of the 256 values of leaf a
 hipError_t launch_rowsum(const double* x, double* usum, int64_t n_leaves, hipStream_t stream);
 

@@ -1,12 +1,16 @@
 // HIP kernels of the box code for gfx950 (CDNA4), FP64 throughout.
 //
 // One kernel template serves every stage: a grouped-relation GEMM. A workgroup owns a tile of
-// NT output vectors ("slots") of M rows each and loops over the relations present in the tile
-// (sorted by relation id). For relation r it stages the NT source vectors (gathered by index,
-// optionally scaled by s^2 of the source leaf) in LDS in k-chunks of 64 and accumulates
+// NT output vectors ("slots") of M rows each and walks the relation segments present in the
+// tile (sorted by relation id). For relation r it accumulates
 //     C[:, slot] += A_r[:, k-chunk] * B[k-chunk, slot]
-// with v_mfma_f64_16x16x4f64. A_r is streamed from global memory (L2-resident tables) in a
-// fragment-major layout so every fragment load is one contiguous 512-byte wave access.
+// with v_mfma_f64_16x16x4f64, where B gathers the NT source vectors by index. Both operands are
+// staged through LDS in k-chunks of KC; the global loads of chunk c+1 are issued into registers
+// before chunk c is multiplied, so memory latency overlaps the MFMA work. A_r is stored
+// fragment-major, which makes every chunk of A one contiguous block (a straight coalesced
+// copy) and every LDS fragment read a contiguous 512-byte wave access. A segment's metadata
+// (table pointer, source family, this thread's source indices) is fetched once per segment.
+//
 // Each output vector has exactly one owner and a fixed relation order: no atomics, bitwise
 // deterministic, identical whether a tree is applied alone or inside a forest.
 //
@@ -19,6 +23,7 @@
 namespace vp {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));  // native vector: keeps staging arrays in registers
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
 // tiles so neighbouring tiles (which share source leaves) share an L2.
@@ -27,13 +32,125 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return x * q + min(x, r) + (b >> 3);
 }
 
-template <int MT, int NTT, int WM, int WN>
+// Kernel-argument arrays indexed with a runtime value would be copied to scratch; pick with
+// constant indices instead.
+template <typename T>
+__device__ __forceinline__ T pick4(const T (&a)[4], int i) {
+  return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : a[3]));
+}
+template <typename T>
+__device__ __forceinline__ T pick3(const T (&a)[3], int i) {
+  return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+
+// Global-memory pointers: loads through them compile to global_load (vmcnt only), not flat
+// loads, which would also count against the LDS wait counter and serialise the pipeline.
+#define GLOBAL __attribute__((address_space(1)))
+typedef const GLOBAL double* gdp;
+typedef const GLOBAL d2* gd2p;
+typedef const GLOBAL int32_t* gip;
+
+// The loading side of a tile's walk over (segment, k-chunk) steps. Every relation of a stage has
+// the same K, a multiple of KC, so every chunk is full. Thread tid owns the A pairs
+// tid + q NTHR of each chunk and the B pairs idx = tid + q NTHR, i.e. slot t = idx / (KC/2) and
+// k pair kp = idx % (KC/2); the source indices of a segment are fetched once per segment.
+template <int M, int NT, int NTHR, int KC>
+struct Loader {
+  static constexpr int A_V2 = M * KC / 2;
+  static constexpr int A_PER = (A_V2 + NTHR - 1) / NTHR;
+  static constexpr int B_V2 = NT * KC / 2;
+  static constexpr int B_PER = (B_V2 + NTHR - 1) / NTHR;
+  static constexpr int HALF = KC / 2;
+  int s, k0;              // step being loaded
+  gdp A;                  // table of segment s
+  int K;
+  gdp base;               // source family of segment s
+  int stride;
+  int si[B_PER];          // this thread's source index per B pair (-1: none)
+  d2 ra[A_PER], rb[B_PER];
+
+  __device__ __forceinline__ void segment(const GrgParams& p, int tid) {
+    const RelDesc rd = p.rels[p.seg_rel[s]];
+    A = (gdp)rd.A;
+    K = rd.K;
+    const int fam = p.seg_fam[s];
+    base = (gdp)pick4(p.fam_base, fam);
+    stride = pick4(p.fam_stride, fam);
+    gip src = (gip)(p.seg_src + (size_t)s * NT);
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const int t = (tid + q * NTHR) / HALF;
+      si[q] = t < NT ? src[t] : -1;
+    }
+  }
+  __device__ __forceinline__ void load(int tid) {
+    gd2p A2 = (gd2p)(A + (size_t)k0 * M);
+#pragma unroll
+    for (int q = 0; q < A_PER; ++q) {
+      const int idx = tid + q * NTHR;
+      ra[q] = A2[(A_V2 % NTHR == 0 || idx < A_V2) ? idx : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const int kp = (tid + q * NTHR) % HALF;
+      const bool ok = si[q] >= 0;
+      const d2 v = *(gd2p)(base + (size_t)(ok ? si[q] : 0) * stride + k0 + 2 * kp);
+      rb[q] = ok ? v : d2{0.0, 0.0};
+    }
+  }
+  template <int LDB>
+  __device__ __forceinline__ void store(int tid, double* As, double* Bs) const {
+    d2* As2 = reinterpret_cast<d2*>(As);
+#pragma unroll
+    for (int q = 0; q < A_PER; ++q) {
+      const int idx = tid + q * NTHR;
+      if (A_V2 % NTHR == 0 || idx < A_V2) As2[idx] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const int idx = tid + q * NTHR;
+      const int t = idx / HALF, kp = idx % HALF;
+      if (B_V2 % NTHR == 0 || t < NT) {
+        Bs[t * LDB + 2 * kp] = rb[q].x;
+        Bs[t * LDB + 2 * kp + 1] = rb[q].y;
+      }
+    }
+  }
+  // advance to the next step; returns false past the last segment
+  __device__ __forceinline__ bool next(const GrgParams& p, int tid, int s1) {
+    k0 += KC;
+    if (k0 >= K) {
+      ++s;
+      k0 = 0;
+      if (s >= s1) return false;
+      segment(p, tid);
+    }
+    return true;
+  }
+};
+
+// One k-step (4 values of k) of the tile product for one wave: MT x NTT MFMA fragments.
+template <int MT, int NTT, int M, int LDB>
+__device__ __forceinline__ void mfma_step(const double* __restrict__ Aw, const double* __restrict__ Bw, int kk,
+                                          d4 (&acc)[MT][NTT]) {
+  double a[MT], b[NTT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) a[i] = Aw[(kk * (M / 16) + i) * 64];
+#pragma unroll
+  for (int j = 0; j < NTT; ++j) b[j] = Bw[j * 16 * LDB + kk * 4];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NTT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+}
+
+template <int MT, int NTT, int WM, int WN, int KC>
 __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
   constexpr int M = 16 * MT * WM;
   constexpr int NT = 16 * NTT * WN;
   constexpr int NTHR = 64 * WM * WN;
-  constexpr int KC = 64;
-  constexpr int LDB = KC + 2;
+  constexpr int LDB = KC + 1;  // odd row stride: conflict-free B fragment reads
+  __shared__ double As[M * KC];
   __shared__ double Bs[NT * LDB];
   __shared__ double r1s[NT];
 
@@ -48,58 +165,35 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
     for (int j = 0; j < NTT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int s0 = p.tile_seg_ptr[tile], s1 = p.tile_seg_ptr[tile + 1];
-  for (int s = s0; s < s1; ++s) {
-    const RelDesc rd = p.rels[p.seg_rel[s]];
-    const int fam = p.seg_fam[s];
-    const double* __restrict__ base = p.fam_base[fam];
-    const int stride = p.fam_stride[fam];
-    const bool scaled = p.fam_scaled[fam] != 0;
-    const int32_t* __restrict__ src = p.seg_src + (size_t)s * NT;
-    for (int k0 = 0; k0 < rd.K; k0 += KC) {
-      const int kc = min(KC, rd.K - k0);
-      const int half = kc >> 1;
-      __syncthreads();
-      for (int idx = tid; idx < NT * half; idx += NTHR) {
-        const int t = idx / half, kp = idx - t * half;
-        const int si = src[t];
-        double2 v = make_double2(0.0, 0.0);
-        if (si >= 0) {
-          v = *reinterpret_cast<const double2*>(base + (size_t)si * stride + k0 + 2 * kp);
-          if (scaled) {
-            const double sc = p.leaf_s2[si];
-            v.x *= sc;
-            v.y *= sc;
-          }
-        }
-        Bs[t * LDB + 2 * kp] = v.x;
-        Bs[t * LDB + 2 * kp + 1] = v.y;
-      }
-      __syncthreads();
-      const int nk = kc >> 2;
-      const double* __restrict__ Ab = rd.A + (size_t)(k0 >> 2) * (M / 16) * 64 + (size_t)(wm * MT) * 64 + lane;
-      const double* __restrict__ Bw = Bs + ((wn * NTT) * 16 + (lane & 15)) * LDB + (lane >> 4);
-      for (int kk = 0; kk < nk; ++kk) {
-        double a[MT], b[NTT];
+  if (s0 < s1) {
+    Loader<M, NT, NTHR, KC> L;
+    L.s = s0;
+    L.k0 = 0;
+    L.segment(p, tid);
+    L.load(tid);
+    L.template store<LDB>(tid, As, Bs);
+    __syncthreads();
+    const double* __restrict__ Aw = As + (wm * MT) * 64 + lane;
+    const double* __restrict__ Bw = Bs + ((wn * NTT) * 16 + (lane & 15)) * LDB + (lane >> 4);
+    for (;;) {
+      const bool more = L.next(p, tid, s1);
+      if (more) L.load(tid);  // next chunk in flight while this one is multiplied
 #pragma unroll
-        for (int i = 0; i < MT; ++i) a[i] = Ab[((size_t)kk * (M / 16) + i) * 64];
-#pragma unroll
-        for (int j = 0; j < NTT; ++j) b[j] = Bw[j * 16 * LDB + kk * 4];
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-#pragma unroll
-          for (int j = 0; j < NTT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
+      for (int kk = 0; kk < KC / 4; ++kk) mfma_step<MT, NTT, M, LDB>(Aw, Bw, kk, acc);
+      if (!more) break;
+      __syncthreads();  // every wave is done reading the chunk
+      L.template store<LDB>(tid, As, Bs);
+      __syncthreads();  // the next chunk is visible
     }
   }
 
   // rank-one log-scale terms, one scalar per slot
-  __syncthreads();
   for (int t = tid; t < NT; t += NTHR) {
     const int ti = tile * NT + t;
     double c = 0.0;
     for (int e = p.r1_ptr[ti]; e < p.r1_ptr[ti + 1]; ++e) {
       const int f = p.r1_fam[e];
-      c += p.r1_coef[e] * p.r1_base[f][(size_t)p.r1_idx[e] * p.r1_stride[f]];
+      c += p.r1_coef[e] * ((gdp)pick3(p.r1_base, f))[(size_t)p.r1_idx[e] * pick3(p.r1_stride, f)];
     }
     r1s[t] = c;
   }
@@ -113,6 +207,11 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
     const double sc = p.out_scaled ? p.leaf_s2[tgt] : 1.0;
     const double r1 = r1s[slot];
     double* __restrict__ o = p.out + (size_t)tgt * p.out_stride;
+    double prev[MT][4];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) prev[i][r] = p.accumulate ? o[(wm * MT + i) * 16 + 4 * r + (lane >> 4)] : 0.0;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -120,9 +219,19 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
         const int row = (wm * MT + i) * 16 + 4 * r + (lane >> 4);
         double v = acc[i][j][r];
         if (p.r1_all_rows || row == 0) v += r1;
-        o[row] = v * sc;
+        o[row] = v * sc + prev[i][r];
       }
   }
+}
+
+// out[leaf][k] = s2[leaf] * x[leaf][k]  (the s^2 Jacobian of each source leaf, applied once)
+__global__ void prescale_kernel(const double* __restrict__ x, const double* __restrict__ s2, double* __restrict__ out,
+                                int64_t n_leaves) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one double pair per thread
+  if (i >= n_leaves * 128) return;
+  const d2 v = reinterpret_cast<const d2*>(x)[i];
+  const double s = s2[i >> 7];
+  reinterpret_cast<d2*>(out)[i] = v * s;
 }
 
 __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__ out, int64_t n) {
@@ -135,22 +244,31 @@ __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__
   if (lane == 0) out[leaf] = s;
 }
 
-hipError_t launch_grg(int M, int NT, const GrgParams& p, hipStream_t stream) {
+hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream) {
   if (p.n_tiles <= 0) return hipSuccess;
   dim3 grid(p.n_tiles);
-  if (M == 256 && NT == 64) {
-    hipLaunchKernelGGL((grg_kernel<4, 4, 4, 1>), grid, dim3(256), 0, stream, p);
-  } else if (M == 256 && NT == 32) {
-    hipLaunchKernelGGL((grg_kernel<4, 2, 4, 1>), grid, dim3(256), 0, stream, p);
-  } else if (M == 80 && NT == 64) {
-    hipLaunchKernelGGL((grg_kernel<5, 1, 1, 4>), grid, dim3(256), 0, stream, p);
-  } else if (M == 80 && NT == 32) {
-    hipLaunchKernelGGL((grg_kernel<5, 1, 1, 2>), grid, dim3(128), 0, stream, p);
-  } else if (M == 80 && NT == 16) {
-    hipLaunchKernelGGL((grg_kernel<5, 1, 1, 1>), grid, dim3(64), 0, stream, p);
-  } else {
-    return hipErrorInvalidValue;
-  }
+#define VP_LAUNCH(MT, NTT, WM, WN, KCV, THR) \
+  hipLaunchKernelGGL((grg_kernel<MT, NTT, WM, WN, KCV>), grid, dim3(THR), 0, stream, p)
+  if (M == 256 && NT == 32 && KC == 32) VP_LAUNCH(4, 2, 4, 1, 32, 256);
+  else if (M == 256 && NT == 64 && KC == 32) VP_LAUNCH(4, 4, 4, 1, 32, 256);
+  else if (M == 256 && NT == 32 && KC == 16) VP_LAUNCH(4, 2, 4, 1, 16, 256);
+  else if (M == 256 && NT == 64 && KC == 16) VP_LAUNCH(4, 4, 4, 1, 16, 256);
+  else if (M == 80 && NT == 64 && KC == 40) VP_LAUNCH(5, 1, 1, 4, 40, 256);
+  else if (M == 80 && NT == 32 && KC == 40) VP_LAUNCH(5, 1, 1, 2, 40, 128);
+  else if (M == 80 && NT == 16 && KC == 40) VP_LAUNCH(5, 1, 1, 1, 40, 64);
+  else if (M == 80 && NT == 64 && KC == 32) VP_LAUNCH(5, 1, 1, 4, 32, 256);
+  else if (M == 80 && NT == 32 && KC == 32) VP_LAUNCH(5, 1, 1, 2, 32, 128);
+  else if (M == 80 && NT == 16 && KC == 32) VP_LAUNCH(5, 1, 1, 1, 32, 64);
+  else return hipErrorInvalidValue;
+#undef VP_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_prescale(const double* x, const double* s2, double* out, int64_t n_leaves, hipStream_t stream) {
+  if (n_leaves <= 0) return hipSuccess;
+  const int64_t n = n_leaves * 128;
+  dim3 grid((unsigned)((n + 255) / 256));
+  hipLaunchKernelGGL(prescale_kernel, grid, dim3(256), 0, stream, x, s2, out, n_leaves);
   return hipGetLastError();
 }
 

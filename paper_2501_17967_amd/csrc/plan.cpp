@@ -186,7 +186,7 @@ static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
   st.r1_ptr.assign(size_t(st.n_tiles) * NT + 1, 0);
   st.seg_rel.clear(); st.seg_fam.clear(); st.seg_src.clear();
   st.r1_idx.clear(); st.r1_fam.clear(); st.r1_coef.clear();
-  st.flops = 0; st.n_pairs = 0;
+  st.flops = 0; st.n_pairs = 0; st.flops_issued = 0;
   for (int t = 0; t < st.n_tiles; ++t) {
     std::map<int32_t, size_t> segs;  // rel -> segment index (ordered by rel id)
     std::map<int32_t, int8_t> segfam;
@@ -198,6 +198,8 @@ static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
         // the kernel reads M x K of the relation's table and K values of each source
         if (mats.M[e.rel] != st.M) throw std::runtime_error("relation rows differ from stage rows");
         if (st.fam[e.fam].stride < mats.K[e.rel]) throw std::runtime_error("source shorter than relation");
+        // the kernel walks K in full chunks of KC
+        if (mats.K[e.rel] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
         segs.emplace(e.rel, 0);
         segfam[e.rel] = e.fam;
       }
@@ -208,6 +210,7 @@ static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
       kv.second = base + n++;
       st.seg_rel.push_back(kv.first);
       st.seg_fam.push_back(segfam[kv.first]);
+      st.flops_issued += 2.0 * st.M * mats.K[kv.first] * NT;
     }
     st.seg_src.resize(st.seg_rel.size() * NT, -1);
     for (int s = 0; s < NT; ++s) {
@@ -382,7 +385,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
 
   // ---------------------------------------------------------------- stages
   const Matrices& mats = matrices();
-  const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 64;
+  const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
   const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 64;
   auto quadrant = [&](int32_t b) { return int(P.box_x[b] & 1) + 2 * int(P.box_y[b] & 1); };
   std::vector<std::vector<int32_t>> boxes_at(P.max_level + 1);
@@ -408,98 +411,174 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   }
   for (int32_t b = 0; b < NB; ++b) { P.pairs_v += int64_t(Vlist[b].size()); P.pairs_x += int64_t(Xlist[b].size()); }
 
-  auto init_stage = [](Stage& st, int kind, int level, int M, int NT, int8_t out, int32_t ostride) {
-    st.kind = kind; st.level = level; st.M = M; st.NT = NT; st.out_arr = out; st.out_stride = ostride;
+  // K: the inner dimension shared by every relation of the stage; it fixes the k-chunk
+  auto init_stage = [](Stage& st, int kind, const std::string& name, int level, int M, int K, int NT, int8_t out,
+                       int32_t ostride) {
+    st.kind = kind; st.name = name; st.level = level; st.M = M; st.NT = NT; st.out_arr = out; st.out_stride = ostride;
+    st.KC = (K == kNP) ? 32 : (M == kNP ? 16 : 40);
     for (auto& f : st.fam) f = {A_NONE, 0, 0};
     for (auto& f : st.r1fam) f = {A_NONE, 0, 0};
   };
-  // ---- forward UP
-  for (int l = P.max_level; l >= 0; --l) {
-    std::vector<int32_t> tg;
-    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0) tg.push_back(b);
-    if (l >= 2) for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
-    if (tg.empty()) continue;
-    Stage st; init_stage(st, K_UP, l, kNE, NTB, A_MP, kNE);
-    st.fam[0] = {A_IN, kNP, 1}; st.fam[1] = {A_MP, kNE, 0};
-    std::vector<std::vector<Entry>> E(tg.size());
-    std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i) {
-      int32_t b = tg[i];
-      if (P.box_leaf[b] >= 0) { E[i].push_back({kRelS2M, 0, P.box_leaf[b]}); P.n_s2m++; }
-      else for (int q = 0; q < 4; ++q) { E[i].push_back({kRelM2M + q, 1, P.box_child[b][q]}); P.n_m2m++; }
-    }
-    make_tiles(st, tg, E, R, mats);
-    P.fwd.push_back(std::move(st));
-  }
-  // ---- forward DOWN
+  auto lvl = [](const char* n, int l) { return std::string(n) + "[" + std::to_string(l) + "]"; };
+  // boxes at levels >= 2 ordered by (level, quadrant, tree, morton): targets of one tile then
+  // share their V-list offset pattern
+  std::vector<int32_t> deep_by_quadrant;
   for (int l = 2; l <= P.max_level; ++l) {
     std::vector<int32_t> tg = boxes_at[l];
     std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
-    Stage st; init_stage(st, K_DOWN, l, kNE, NTB, A_LOC, kNE);
-    st.fam[0] = {A_LOC, kNE, 0}; st.fam[1] = {A_MP, kNE, 0}; st.fam[2] = {A_IN, kNP, 1};
+    deep_by_quadrant.insert(deep_by_quadrant.end(), tg.begin(), tg.end());
+  }
+
+  // ================================================================ forward
+  {  // S2M: every leaf's multipole
+    std::vector<int32_t> tg;
+    for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0) tg.push_back(b);
+    Stage st; init_stage(st, K_UP, "S2M", -1, kNE, kNP, NTB, A_MP, kNE);
+    st.helper = 1;
+    st.fam[0] = {A_INS, kNP, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) { E[i].push_back({kRelS2M, 0, P.box_leaf[tg[i]]}); P.n_s2m++; }
+    make_tiles(st, tg, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  for (int l = P.max_level - 1; l >= 2; --l) {  // M2M chain, upward
+    std::vector<int32_t> tg;
+    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
+    if (tg.empty()) continue;
+    Stage st; init_stage(st, K_UP, lvl("M2M", l), l, kNE, kNE, NTB, A_MP, kNE);
+    st.helper = 1;
+    st.fam[0] = {A_MP, kNE, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i)
+      for (int q = 0; q < 4; ++q) { E[i].push_back({kRelM2M + q, 0, P.box_child[tg[i]][q]}); P.n_m2m++; }
+    make_tiles(st, tg, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  if (!deep_by_quadrant.empty()) {  // FARV: M2L for every box of every level >= 2, plus all log terms
+    const auto& tg = deep_by_quadrant;
+    Stage st; init_stage(st, K_DOWN, "FARV", -1, kNE, kNE, NTB, A_LOC, kNE);
+    st.helper = 1;
+    st.fam[0] = {A_MP, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
     for (size_t i = 0; i < tg.size(); ++i) {
       int32_t b = tg[i];
-      if (l >= 3) { E[i].push_back({kRelL2L + quadrant(b), 0, P.box_parent[b]}); P.n_l2l++; }
-      for (auto& e : Vlist[b]) { E[i].push_back({kRelM2L + e.first, 1, e.second}); R[i].push_back({0, e.second, lnS(l)}); }
-      for (auto& e : Xlist[b]) { E[i].push_back({kRelS2L + e.first, 2, e.second}); R[i].push_back({0, P.leaf_box[e.second], lnS(l)}); }
+      double ls = lnS(P.box_level[b]);
+      for (auto& e : Vlist[b]) { E[i].push_back({kRelM2L + e.first, 0, e.second}); R[i].push_back({0, e.second, ls}); }
+      for (auto& e : Xlist[b]) R[i].push_back({0, P.leaf_box[e.second], ls});
     }
     make_tiles(st, tg, E, R, mats);
     P.fwd.push_back(std::move(st));
   }
-  // ---- forward LEAF
-  {
-    Stage st; init_stage(st, K_LEAF, -1, kNP, NTL, A_OUT, kNP);
+  {  // FARX: S2L, added onto FARV for the boxes that have an X list
+    std::vector<int32_t> tg;
+    for (int32_t b : deep_by_quadrant) if (!Xlist[b].empty()) tg.push_back(b);
+    if (!tg.empty()) {
+      Stage st; init_stage(st, K_DOWN, "FARX", -1, kNE, kNP, NTB, A_LOC, kNE);
+      st.helper = 1;
+      st.accumulate = 1;
+      st.fam[0] = {A_INS, kNP, 0};
+      std::vector<std::vector<Entry>> E(tg.size());
+      std::vector<std::vector<R1>> R(tg.size());
+      for (size_t i = 0; i < tg.size(); ++i)
+        for (auto& e : Xlist[tg[i]]) E[i].push_back({kRelS2L + e.first, 0, e.second});
+      make_tiles(st, tg, E, R, mats);
+      P.fwd.push_back(std::move(st));
+    }
+  }
+  for (int l = 3; l <= P.max_level; ++l) {  // L2L chain, downward, added onto FAR's locals
+    std::vector<int32_t> tg = boxes_at[l];
+    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
+    Stage st; init_stage(st, K_DOWN, lvl("L2L", l), l, kNE, kNE, NTB, A_LOC, kNE);
+    st.helper = 1;
+    st.accumulate = 1;
+    st.fam[0] = {A_LOC, kNE, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) { E[i].push_back({kRelL2L + quadrant(tg[i]), 0, P.box_parent[tg[i]]}); P.n_l2l++; }
+    make_tiles(st, tg, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  {  // NEAR: the adjacent-leaf tables, on the caller's stream
+    Stage st; init_stage(st, K_NEAR, "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+    st.fam[0] = {A_INS, kNP, 0};
+    std::vector<std::vector<Entry>> E(P.n_leaves);
+    std::vector<std::vector<R1>> R(P.n_leaves);
+    for (size_t i = 0; i < leaf_order.size(); ++i)
+      for (auto& e : Ulist[leaf_order[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
+    make_tiles(st, leaf_order, E, R, mats);
+    P.fwd.push_back(std::move(st));
+  }
+  {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
+    Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
+    st.join_before = 1;
+    st.accumulate = 1;
     st.r1_all_rows = 1;
-    st.fam[0] = {A_IN, kNP, 1}; st.fam[1] = {A_MP, kNE, 0}; st.fam[2] = {A_LOC, kNE, 0};
+    st.fam[0] = {A_MP, kNE, 0}; st.fam[1] = {A_LOC, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
     for (size_t i = 0; i < leaf_order.size(); ++i) {
       int32_t a = leaf_order[i];
       double kap = P.leaf_kappa[a];
-      for (auto& e : Ulist[a]) { E[i].push_back({kRelNear + e.first, 0, e.second}); R[i].push_back({0, P.leaf_box[e.second], kap}); }
-      for (auto& e : Wlist[a]) { E[i].push_back({kRelM2T + e.first, 1, e.second}); R[i].push_back({0, e.second, kap}); }
-      if (levels[a] >= 2) { E[i].push_back({kRelL2T, 2, P.leaf_box[a]}); P.n_l2t++; }
+      for (auto& e : Ulist[a]) R[i].push_back({0, P.leaf_box[e.second], kap});
+      for (auto& e : Wlist[a]) { E[i].push_back({kRelM2T + e.first, 0, e.second}); R[i].push_back({0, e.second, kap}); }
+      if (levels[a] >= 2) { E[i].push_back({kRelL2T, 1, P.leaf_box[a]}); P.n_l2t++; }
     }
     make_tiles(st, leaf_order, E, R, mats);
     P.fwd.push_back(std::move(st));
   }
-  // ---- adjoint AUP
-  for (int l = P.max_level; l >= 2; --l) {
+
+  // ================================================================ adjoint
+  {  // AL2T: lbar of leaves at level >= 2
     std::vector<int32_t> tg;
-    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0) tg.push_back(b);
+    for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0 && P.box_level[b] >= 2) tg.push_back(b);
+    if (!tg.empty()) {
+      Stage st; init_stage(st, K_AUP, "AL2T", -1, kNE, kNP, NTB, A_LB, kNE);
+      st.helper = 1;
+      st.fam[0] = {A_IN, kNP, 0};
+      std::vector<std::vector<Entry>> E(tg.size());
+      std::vector<std::vector<R1>> R(tg.size());
+      for (size_t i = 0; i < tg.size(); ++i) E[i].push_back({kRelL2T + kNumFwd, 0, P.box_leaf[tg[i]]});
+      make_tiles(st, tg, E, R, mats);
+      P.adj.push_back(std::move(st));
+    }
+  }
+  for (int l = P.max_level - 1; l >= 2; --l) {  // AL2L chain, upward (transpose of L2L)
+    std::vector<int32_t> tg;
     for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
-    Stage st; init_stage(st, K_AUP, l, kNE, NTB, A_LB, kNE);
-    st.fam[0] = {A_IN, kNP, 0}; st.fam[1] = {A_LB, kNE, 0};
+    if (tg.empty()) continue;
+    Stage st; init_stage(st, K_AUP, lvl("AL2L", l), l, kNE, kNE, NTB, A_LB, kNE);
+    st.helper = 1;
+    st.fam[0] = {A_LB, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i) {
-      int32_t b = tg[i];
-      if (P.box_leaf[b] >= 0) E[i].push_back({kRelL2T + kNumFwd, 0, P.box_leaf[b]});
-      else for (int q = 0; q < 4; ++q) E[i].push_back({kRelL2L + q + kNumFwd, 1, P.box_child[b][q]});
-    }
+    for (size_t i = 0; i < tg.size(); ++i)
+      for (int q = 0; q < 4; ++q) E[i].push_back({kRelL2L + q + kNumFwd, 0, P.box_child[tg[i]][q]});
     make_tiles(st, tg, E, R, mats);
     P.adj.push_back(std::move(st));
   }
-  // ---- adjoint ADOWN
-  for (int l = 0; l <= P.max_level; ++l) {
-    std::vector<int32_t> tg;
-    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0 || l >= 2) tg.push_back(b);
-    if (tg.empty()) continue;
-    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
-    Stage st; init_stage(st, K_ADOWN, l, kNE, NTB, A_AB, kNE);
-    st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_LB, kNE, 0}; st.fam[2] = {A_IN, kNP, 0};
+  // abar is needed for every box whose multipole is used: all leaves and boxes of level >= 2
+  std::vector<int32_t> afar_tg;
+  for (int l = 0; l < 2 && l <= P.max_level; ++l)
+    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0) afar_tg.push_back(b);
+  afar_tg.insert(afar_tg.end(), deep_by_quadrant.begin(), deep_by_quadrant.end());
+  {  // AFARV: M2L^T plus every log term
+    const auto& tg = afar_tg;
+    Stage st; init_stage(st, K_ADOWN, "AFARV", -1, kNE, kNE, NTB, A_AB, kNE);
+    st.helper = 1;
+    st.fam[0] = {A_LB, kNE, 0};
     st.r1fam[0] = {A_LB, kNE, 0}; st.r1fam[1] = {A_USUM, 1, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
     for (size_t i = 0; i < tg.size(); ++i) {
       int32_t b = tg[i];
-      if (l >= 3) E[i].push_back({kRelM2M + quadrant(b) + kNumFwd, 0, P.box_parent[b]});
-      for (auto& e : Vinv[b]) { E[i].push_back({kRelM2L + e.first + kNumFwd, 1, e.second}); R[i].push_back({0, e.second, lnS(l)}); }
-      for (auto& e : Winv[b]) { E[i].push_back({kRelM2T + e.first + kNumFwd, 2, e.second}); R[i].push_back({1, e.second, P.leaf_kappa[e.second]}); }
+      double ls = lnS(P.box_level[b]);
+      for (auto& e : Vinv[b]) { E[i].push_back({kRelM2L + e.first + kNumFwd, 0, e.second}); R[i].push_back({0, e.second, ls}); }
+      for (auto& e : Winv[b]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
       int32_t leaf = P.box_leaf[b];
       if (leaf >= 0) {
         for (auto& e : Uinv[leaf]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
@@ -509,18 +588,58 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     make_tiles(st, tg, E, R, mats);
     P.adj.push_back(std::move(st));
   }
-  // ---- adjoint ALEAF
-  {
-    Stage st; init_stage(st, K_ALEAF, -1, kNP, NTL, A_OUT, kNP);
+  {  // AFARW: M2T^T, added onto AFARV for the boxes that have a W^-1 list
+    std::vector<int32_t> tg;
+    for (int32_t b : afar_tg) if (!Winv[b].empty()) tg.push_back(b);
+    if (!tg.empty()) {
+      Stage st; init_stage(st, K_ADOWN, "AFARW", -1, kNE, kNP, NTB, A_AB, kNE);
+      st.helper = 1;
+      st.accumulate = 1;
+      st.fam[0] = {A_IN, kNP, 0};
+      std::vector<std::vector<Entry>> E(tg.size());
+      std::vector<std::vector<R1>> R(tg.size());
+      for (size_t i = 0; i < tg.size(); ++i)
+        for (auto& e : Winv[tg[i]]) E[i].push_back({kRelM2T + e.first + kNumFwd, 0, e.second});
+      make_tiles(st, tg, E, R, mats);
+      P.adj.push_back(std::move(st));
+    }
+  }
+  for (int l = 3; l <= P.max_level; ++l) {  // AM2M chain, downward (transpose of M2M)
+    std::vector<int32_t> tg = boxes_at[l];
+    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
+    Stage st; init_stage(st, K_ADOWN, lvl("AM2M", l), l, kNE, kNE, NTB, A_AB, kNE);
+    st.helper = 1;
+    st.accumulate = 1;
+    st.fam[0] = {A_AB, kNE, 0};
+    std::vector<std::vector<Entry>> E(tg.size());
+    std::vector<std::vector<R1>> R(tg.size());
+    for (size_t i = 0; i < tg.size(); ++i) E[i].push_back({kRelM2M + quadrant(tg[i]) + kNumFwd, 0, P.box_parent[tg[i]]});
+    make_tiles(st, tg, E, R, mats);
+    P.adj.push_back(std::move(st));
+  }
+  {  // ANEAR: transposed near tables, on the caller's stream
+    Stage st; init_stage(st, K_ANEAR, "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
     st.out_scaled = 1;
-    st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_IN, kNP, 0}; st.fam[2] = {A_LB, kNE, 0};
+    st.fam[0] = {A_IN, kNP, 0};
+    std::vector<std::vector<Entry>> E(P.n_leaves);
+    std::vector<std::vector<R1>> R(P.n_leaves);
+    for (size_t i = 0; i < leaf_order.size(); ++i)
+      for (auto& e : Uinv[leaf_order[i]]) E[i].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
+    make_tiles(st, leaf_order, E, R, mats);
+    P.adj.push_back(std::move(st));
+  }
+  {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
+    Stage st; init_stage(st, K_ALOCT, "ALOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
+    st.join_before = 1;
+    st.accumulate = 1;
+    st.out_scaled = 1;
+    st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_LB, kNE, 0};
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
     for (size_t i = 0; i < leaf_order.size(); ++i) {
       int32_t b = leaf_order[i];
       E[i].push_back({kRelS2M + kNumFwd, 0, P.leaf_box[b]});
-      for (auto& e : Uinv[b]) E[i].push_back({kRelNear + e.first + kNumFwd, 1, e.second});
-      for (auto& e : Xinv[b]) E[i].push_back({kRelS2L + e.first + kNumFwd, 2, e.second});
+      for (auto& e : Xinv[b]) E[i].push_back({kRelS2L + e.first + kNumFwd, 1, e.second});
     }
     make_tiles(st, leaf_order, E, R, mats);
     P.adj.push_back(std::move(st));

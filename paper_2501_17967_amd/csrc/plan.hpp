@@ -1,20 +1,32 @@
 // Host-side plan of the box code: tree, interaction lists, stage schedules, tables.
 //
 // The box code (Sec. 4.2 evaluates eq. (vbulk) with one) is organised here as a short
-// sequence of "stages". Each stage writes one output array, one launch per tree level.
+// sequence of "stages". Each stage writes (or adds to) one output array in a single launch.
 // Within a stage every output vector (a "target") is owned by exactly one slot of one tile
 // and receives a sum of small dense products A_r * source, grouped by relation r:
 //
-//   forward   UP[l]    multipoles   mp  = S2M (leaves) or sum_q M2M_q mp[child q]
-//             DOWN[l]  locals       loc = L2L_q loc[parent] + sum_V M2L_r mp + sum_X S2L_r f
-//             LEAF     potential    u   = sum_U T_r f + sum_W M2T_r mp + L2T loc
-//   adjoint   ASUM     usum = row sums of ubar
-//             AUP[l]   lbar = L2T^T ubar (leaves) or sum_q L2L_q^T lbar[child q]
-//             ADOWN[l] abar = M2M_q^T abar[parent] + sum_V M2L_r^T lbar + sum_W M2T_r^T ubar
-//             ALEAF    fbar = s^2 [S2M^T abar + sum_U T_r^T ubar + sum_X S2L_r^T lbar]
+//   forward   S2M      mp  = S2M f                       all leaves        (helper stream)
+//             M2M[l]   mp  = sum_q M2M_q mp[child q]     per level, up     (helper)
+//             FARV     loc = sum_V M2L_r mp              levels >= 2       (helper)
+//             FARX     loc += sum_X S2L_r f              boxes with X list (helper)
+//             L2L[l]   loc += L2L_q loc[parent]          per level, down   (helper)
+//             NEAR     u   = sum_U T_r f                 all leaves        (main, concurrent)
+//             LOCT     u  += L2T loc + sum_W M2T_r mp    all leaves        (main, after join)
+//   adjoint   ASUM     usum = row sums of ubar                             (helper)
+//             AL2T     lbar = L2T^T ubar                 leaves            (helper)
+//             AL2L[l]  lbar = sum_q L2L_q^T lbar[child q]   per level, up  (helper)
+//             AFARV    abar = sum_V M2L_r^T lbar                           (helper)
+//             AFARW    abar += sum_W M2T_r^T ubar       boxes with W list  (helper)
+//             AM2M[l]  abar += M2M_q^T abar[parent]      per level, down   (helper)
+//             ANEAR    fbar = s^2 sum_U T_r^T ubar                         (main, concurrent)
+//             ALOCT    fbar += s^2 [S2M^T abar + sum_X S2L_r^T lbar]       (main, after join)
 //
-// plus rank-one log-scale terms (ln s_l * mass) folded into each stage's epilogue. Owner-
-// computes with a fixed relation order gives bitwise-deterministic results without atomics.
+// All relations of one stage share the inner dimension K (80 for expansions, 256 for leaf
+// values), which the k-chunk KC of the stage's kernel divides, so the kernel's chunks are
+// always full. Rank-one log-scale terms (ln s_l times a box mass) are folded into the
+// epilogues of FARV, LOCT and AFARV. The near field depends on nothing but f, so it runs on the caller's stream
+// while the far-field chain runs on a helper stream; LOCT waits for both. Owner-computes with
+// a fixed relation order gives bitwise-deterministic results without atomics.
 #pragma once
 
 #include <array>
@@ -62,20 +74,30 @@ const Matrices& matrices();  // built once per process (near tables by polar qua
 void set_table_cache_dir(const char* dir);
 
 // ---------------------------------------------------------------- plan
-enum Arr : int8_t { A_IN = 0, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_NONE };
-enum StageKind : int { K_UP = 0, K_DOWN, K_LEAF, K_AUP, K_ADOWN, K_ALEAF, K_ASUM, K_NUM };
+// A_INS: the input with each leaf scaled by its s^2 (forward only; written by a prescale pass)
+enum Arr : int8_t { A_IN = 0, A_INS, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_NONE };
+// timing / accounting kinds: 0 upward (S2M, M2M), 1 downward (FARV/X, L2L), 2 NEAR, 3 LOCT,
+// 4 adjoint upward (AL2T, AL2L), 5 adjoint downward (AFARV/W, AM2M), 6 ANEAR, 7 ALOCT,
+// 8 adjoint row sums
+enum StageKind : int { K_UP = 0, K_DOWN, K_NEAR, K_LOCT, K_AUP, K_ADOWN, K_ANEAR, K_ALOCT, K_ASUM, K_NUM };
 
-struct FamDesc { int8_t arr; int32_t stride; int8_t scaled; };  // scaled: times s_b^2 of leaf
+struct FamDesc { int8_t arr; int32_t stride; int8_t unused; };
 
 struct Stage {
   int kind = 0, level = 0;
   int M = 0;       // output rows (80 or 256)
   int NT = 0;      // slots per tile
+  int KC = 0;      // k-chunk of the kernel instantiation
+  double flops_issued = 0;  // MFMA work of the tiles, empty slots included
   int n_tiles = 0;
   int8_t out_arr = A_NONE;
   int32_t out_stride = 0;
   int8_t out_scaled = 0;   // multiply output by s^2 of the target leaf
   int8_t r1_all_rows = 0;  // rank-one term added to all rows (else row 0 only)
+  int8_t accumulate = 0;   // add to the output (else overwrite)
+  int8_t helper = 0;       // runs on the helper stream (far-field chain)
+  int8_t join_before = 0;  // waits for the helper stream's work before launching
+  std::string name;        // stage name for reports, e.g. NEAR or M2M[5]
   FamDesc fam[4];
   FamDesc r1fam[3];
   std::vector<int32_t> tile_tgt;      // n_tiles * NT, -1 = empty slot

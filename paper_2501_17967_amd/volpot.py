@@ -29,7 +29,7 @@ EXPORTED = [
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
 ]
 
-STAGE_KINDS = ["up", "down", "leaf", "adj_up", "adj_down", "adj_leaf", "adj_sum"]
+STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
 
 
 class VolpotError(RuntimeError):
@@ -51,8 +51,9 @@ class Info(ctypes.Structure):
                 ("pairs_w", ctypes.c_int64), ("pairs_x", ctypes.c_int64), ("n_m2m", ctypes.c_int64),
                 ("n_l2l", ctypes.c_int64), ("n_s2m", ctypes.c_int64), ("n_l2t", ctypes.c_int64),
                 ("flops_total", ctypes.c_double), ("flops_adjoint", ctypes.c_double),
-                ("flops_kind", ctypes.c_double * 7), ("launches_kind", ctypes.c_int64 * 7),
-                ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("flops_kind", ctypes.c_double * 9), ("launches_kind", ctypes.c_int64 * 9),
+                ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("flops_issued_kind", ctypes.c_double * 9)]
 
 
 _lib = None
@@ -180,7 +181,7 @@ class Plan:
         out = {}
         for name, _ in Info._fields_:
             v = getattr(inf, name)
-            out[name] = {k: v[i] for i, k in enumerate(STAGE_KINDS)} if name in ("flops_kind", "launches_kind") else v
+            out[name] = {k: v[i] for i, k in enumerate(STAGE_KINDS)} if name in ("flops_kind", "launches_kind", "flops_issued_kind") else v
         return out
 
     def table(self, kind, index=0):
