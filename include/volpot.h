@@ -66,6 +66,9 @@ typedef struct {
   int32_t tile_box;        /* slots per tile of the 80-row (expansion) stages: 16, 32 or 64;
                               0 = default (64) */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
+  int32_t split_min;       /* each stage is cut into as many equal shares of its k-chunks as the
+                              device runs blocks at once; a share has at least this many chunks
+                              (0 = default: one relation's worth, K / chunk) */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -147,6 +150,21 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
  *   kind 1: S2M (80 x 256);   kind 2: L2T (256 x 80)
  * Returns VOLPOT_ERR_ARG for an unknown kind/index or n too small. */
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
+
+/* One stage (one kernel launch) of an apply, for inspection and tuning. */
+typedef struct {
+  char name[24];           /* e.g. "NEAR", "M2M[5]", "AFARV" */
+  int32_t kind;            /* stage kind, numbered as in volpot_info.flops_kind */
+  int32_t rows, tile, kchunk; /* output rows per slot (80 or 256), slots per tile, k-chunk */
+  int32_t helper;          /* 1: runs on the plan's helper stream */
+  int64_t n_tiles, n_segments, n_blocks, n_split_tiles;
+  double flops, flops_issued;
+} volpot_stage_info;
+
+/* Number of stages of the forward (adjoint = 0) or adjoint (1) apply, in launch order. */
+int volpot_plan_n_stages(volpot_plan_t plan, int32_t adjoint, int32_t* n);
+/* Stage index (0 .. n-1) of the forward or adjoint apply. */
+int volpot_plan_stage(volpot_plan_t plan, int32_t adjoint, int32_t index, volpot_stage_info* out);
 
 /* Geometry of near relation r (0..32): offset (dx, dy) of the source leaf centre from the
  * target leaf centre in target half-widths, and rho = source / target half-width. */

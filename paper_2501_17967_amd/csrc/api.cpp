@@ -95,6 +95,8 @@ struct DevStage {
   int32_t *r1_ptr = nullptr, *r1_idx = nullptr;
   int8_t* r1_fam = nullptr;
   double* r1_coef = nullptr;
+  PieceDesc* pieces = nullptr;
+  int32_t *blk_ptr = nullptr, *tile_count = nullptr;
 };
 
 struct GraphEntry {
@@ -117,6 +119,8 @@ struct volpot_plan_s {
   char* d_block = nullptr;
   double *d_mp = nullptr, *d_loc = nullptr, *d_lb = nullptr, *d_ab = nullptr, *d_usum = nullptr, *d_leaf_s2 = nullptr;
   double* d_fs = nullptr;  // prescaled input s^2 f
+  double* d_part[2] = {nullptr, nullptr};  // partial sums of split tiles: helper-stream, caller-stream stages
+  int split_min = 0;
   std::vector<DevStage> dfwd, dadj;
   int64_t device_bytes = 0;
   bool timing = false;
@@ -151,16 +155,46 @@ size_t add_bytes(size_t& total, const std::vector<T>& v) {
   return o;
 }
 
+// Balanced schedules for every stage of the plan on the current device: each launch has as
+// many blocks as fit on the device at once (fewer for small stages), each given an equal
+// share of the stage's k-chunks. nominal > 0 replaces the device query (host-only plans).
+int schedule_all(volpot_plan_s* p, int nominal) {
+  std::map<std::array<int, 3>, int> resident;
+  try {
+    for (auto* v : {&p->host.fwd, &p->host.adj})
+      for (Stage& s : *v) {
+        auto key = std::array<int, 3>{s.M, s.NT, s.KC};
+        auto it = resident.find(key);
+        if (it == resident.end())
+          it = resident.emplace(key, nominal > 0 ? nominal : grg_resident_blocks(s.M, s.NT, s.KC)).first;
+        if (it->second <= 0) return VOLPOT_ERR_HIP;
+        // default: a block gets at least one whole segment (K / KC chunks)
+        build_schedule(s, it->second, p->split_min > 0 ? p->split_min : s.K / s.KC);
+      }
+  } catch (const std::bad_alloc&) {
+    return VOLPOT_ERR_OOM;
+  } catch (...) {
+    return VOLPOT_ERR_ARG;
+  }
+  return VOLPOT_OK;
+}
+
 int upload(volpot_plan_s* p) {
   Plan& P = p->host;
+  int rc = schedule_all(p, 0);
+  if (rc != VOLPOT_OK) return rc;
   size_t total = 0;
   const size_t nb = size_t(P.n_boxes) * kNE * sizeof(double);
-  struct Off { size_t tt, tsp, sr, sf, ss, rp, ri, rf, rc; };
+  struct Off { size_t tt, tsp, sr, sf, ss, rp, ri, rf, rc, pc, bp, tc; };
+  std::vector<std::vector<int32_t>> zeros;  // arrival counters start at zero
   auto plan_stage = [&](const Stage& s) {
     Off o;
     o.tt = add_bytes(total, s.tile_tgt); o.tsp = add_bytes(total, s.tile_seg_ptr); o.sr = add_bytes(total, s.seg_rel);
     o.sf = add_bytes(total, s.seg_fam); o.ss = add_bytes(total, s.seg_src); o.rp = add_bytes(total, s.r1_ptr);
     o.ri = add_bytes(total, s.r1_idx); o.rf = add_bytes(total, s.r1_fam); o.rc = add_bytes(total, s.r1_coef);
+    o.pc = add_bytes(total, s.pieces); o.bp = add_bytes(total, s.blk_ptr);
+    zeros.emplace_back(size_t(std::max(s.n_tiles, 1)), 0);
+    o.tc = add_bytes(total, zeros.back());
     return o;
   };
   std::vector<Off> ofw, oad;
@@ -178,16 +212,14 @@ int upload(volpot_plan_s* p) {
   auto put = [&](size_t o, const auto& v) {
     if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
   };
-  for (size_t i = 0; i < P.fwd.size(); ++i) {
-    const Stage& s = P.fwd[i]; const Off& o = ofw[i];
+  auto put_stage = [&](const Stage& s, const Off& o) {
     put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sr, s.seg_rel); put(o.sf, s.seg_fam); put(o.ss, s.seg_src);
     put(o.rp, s.r1_ptr); put(o.ri, s.r1_idx); put(o.rf, s.r1_fam); put(o.rc, s.r1_coef);
-  }
-  for (size_t i = 0; i < P.adj.size(); ++i) {
-    const Stage& s = P.adj[i]; const Off& o = oad[i];
-    put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sr, s.seg_rel); put(o.sf, s.seg_fam); put(o.ss, s.seg_src);
-    put(o.rp, s.r1_ptr); put(o.ri, s.r1_idx); put(o.rf, s.r1_fam); put(o.rc, s.r1_coef);
-  }
+    put(o.pc, s.pieces); put(o.bp, s.blk_ptr);
+  };
+  for (size_t i = 0; i < P.fwd.size(); ++i) put_stage(P.fwd[i], ofw[i]);
+  for (size_t i = 0; i < P.adj.size(); ++i) put_stage(P.adj[i], oad[i]);
+  static_assert(sizeof(Piece) == sizeof(PieceDesc), "piece layouts differ");
   put(o_s2, s2);
   if (hipMalloc(&p->d_block, total) != hipSuccess) return VOLPOT_ERR_OOM;
   p->device_bytes = int64_t(total);
@@ -201,6 +233,8 @@ int upload(volpot_plan_s* p) {
     d.seg_src = reinterpret_cast<int32_t*>(b + o.ss); d.r1_ptr = reinterpret_cast<int32_t*>(b + o.rp);
     d.r1_idx = reinterpret_cast<int32_t*>(b + o.ri); d.r1_fam = reinterpret_cast<int8_t*>(b + o.rf);
     d.r1_coef = reinterpret_cast<double*>(b + o.rc);
+    d.pieces = reinterpret_cast<PieceDesc*>(b + o.pc); d.blk_ptr = reinterpret_cast<int32_t*>(b + o.bp);
+    d.tile_count = reinterpret_cast<int32_t*>(b + o.tc);
     return d;
   };
   for (size_t i = 0; i < P.fwd.size(); ++i) p->dfwd.push_back(mk(P.fwd[i], ofw[i]));
@@ -212,6 +246,18 @@ int upload(volpot_plan_s* p) {
   p->d_usum = reinterpret_cast<double*>(b + o_us);
   p->d_fs = reinterpret_cast<double*>(b + o_fs);
   p->d_leaf_s2 = reinterpret_cast<double*>(b + o_s2);
+  // partial-sum buffers, one per stream (stages on one stream run one after another)
+  size_t part[2] = {0, 0};
+  for (auto* v : {&P.fwd, &P.adj})
+    for (const Stage& s : *v) {
+      size_t need = size_t(s.n_slots) * s.M * s.NT * sizeof(double);
+      part[s.helper ? 0 : 1] = std::max(part[s.helper ? 0 : 1], need);
+    }
+  for (int i = 0; i < 2; ++i)
+    if (part[i]) {
+      if (hipMalloc(&p->d_part[i], part[i]) != hipSuccess) return VOLPOT_ERR_OOM;
+      p->device_bytes += int64_t(part[i]);
+    }
   if (hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess ||
@@ -307,7 +353,9 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     g.out_scaled = s.out_scaled;
     g.r1_all_rows = s.r1_all_rows;
     g.accumulate = s.accumulate;
-    g.n_tiles = s.n_tiles;
+    g.pieces = d.pieces; g.blk_ptr = d.blk_ptr; g.tile_count = d.tile_count;
+    g.partial = p->d_part[s.helper ? 0 : 1];
+    g.n_blocks = s.n_blocks;
     hipEvent_t ea, eb;
     timed_begin(p, timing, st, &ea, &eb);
     hipError_t e = launch_grg(s.M, s.NT, s.KC, g, st);
@@ -353,6 +401,8 @@ void free_plan(volpot_plan_s* p) {
     for (auto& e : p->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     if (p->d_block) (void)hipFree(p->d_block);
+    for (double* d : p->d_part)
+      if (d) (void)hipFree(d);
     release_tables(p->tables);
   }
   delete p;
@@ -383,7 +433,11 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   if (rc != VOLPOT_OK) { delete plan; return rc; }
   plan->host_only = o.host_only != 0;
   plan->use_graph = o.use_graph != 0;
-  if (!plan->host_only) {
+  plan->split_min = o.split_min;
+  if (plan->host_only) {  // schedules for a nominal device, so that they can be inspected
+    rc = schedule_all(plan, 1024);
+    if (rc != VOLPOT_OK) { delete plan; return rc; }
+  } else {
     if (hipGetDevice(&plan->device) != hipSuccess) { delete plan; return VOLPOT_ERR_HIP; }
     rc = acquire_tables(plan->device, &plan->tables);
     if (rc == VOLPOT_OK) rc = upload(plan);
@@ -460,6 +514,35 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   out->launches_kind[K_ASUM] = 1;
   out->bytes_min = 16.0 * double(P.n_leaves) * kNP;
   out->device_bytes = plan->device_bytes + (plan->tables ? int64_t(plan->tables->bytes) : 0);
+  return VOLPOT_OK;
+}
+
+int volpot_plan_n_stages(volpot_plan_t plan, int32_t adjoint, int32_t* n) {
+  if (!plan || !n) return VOLPOT_ERR_ARG;
+  *n = int32_t((adjoint ? plan->host.adj : plan->host.fwd).size());
+  return VOLPOT_OK;
+}
+
+int volpot_plan_stage(volpot_plan_t plan, int32_t adjoint, int32_t index, volpot_stage_info* out) {
+  if (!plan || !out) return VOLPOT_ERR_ARG;
+  const auto& v = adjoint ? plan->host.adj : plan->host.fwd;
+  if (index < 0 || size_t(index) >= v.size()) return VOLPOT_ERR_ARG;
+  const Stage& s = v[size_t(index)];
+  std::memset(out, 0, sizeof(*out));
+  std::strncpy(out->name, s.name.c_str(), sizeof(out->name) - 1);
+  out->kind = s.kind;
+  out->rows = s.M;
+  out->tile = s.NT;
+  out->kchunk = s.KC;
+  out->helper = s.helper;
+  out->n_tiles = s.n_tiles;
+  out->n_segments = int64_t(s.seg_rel.size());
+  out->n_blocks = s.n_blocks;
+  std::vector<int32_t> pieces(size_t(std::max(s.n_tiles, 0)), 0);
+  for (const Piece& pc : s.pieces) pieces[size_t(pc.tile)]++;
+  for (int32_t c : pieces) out->n_split_tiles += c > 1;
+  out->flops = s.flops;
+  out->flops_issued = s.flops_issued;
   return VOLPOT_OK;
 }
 

@@ -7,6 +7,11 @@
 
 namespace vp {
 
+// Work of one block: n_chunks k-chunks of one tile (mirrors the host plan's Piece)
+struct PieceDesc {
+  int32_t tile, seg, k0, n_chunks, slot, slot0, n_pieces, pad;
+};
+
 struct RelDesc {
   const double* A;  // fragment-major: frag[(kk * (M/16) + row_tile) * 64 + lane] = A[16 row_tile + lane%16][4 kk + lane/16]
   int32_t M, K;
@@ -34,10 +39,17 @@ struct GrgParams {
   int32_t out_scaled;           // 1: multiply the output of target t by leaf_s2[t]
   int32_t r1_all_rows;          // 1: rank-one term on every row, else on row 0 only
   int32_t accumulate;           // 1: add to the existing output, else overwrite
-  int32_t n_tiles;
+  const PieceDesc* pieces;      // balanced schedule: block b runs pieces [blk_ptr[b], blk_ptr[b+1])
+  const int32_t* blk_ptr;       // n_blocks + 1
+  int32_t* tile_count;          // n_tiles arrival counters of split tiles, zero between launches
+  double* partial;              // partial sums of split tiles, M x NT doubles per slot
+  int32_t n_blocks;
 };
 
-// Launch one stage: (M, NT, KC) in {(256, 32|64, 16|32), (80, 16|32|64, 40)}.
+// Blocks of grg_kernel<M, NT, KC> that fit on the current device at once (0 on error).
+int grg_resident_blocks(int M, int NT, int KC);
+
+// Launch one stage: (M, NT, KC) in {(256, 32|64, 16|32), (80, 16|32|64, 32|40)}.
 hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream);
 // out = s2[leaf] * x  (n_leaves x 256)
 hipError_t launch_prescale(const double* x, const double* s2, double* out, int64_t n_leaves, hipStream_t stream);

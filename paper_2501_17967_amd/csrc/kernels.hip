@@ -116,16 +116,14 @@ struct Loader {
       }
     }
   }
-  // advance to the next step; returns false past the last segment
-  __device__ __forceinline__ bool next(const GrgParams& p, int tid, int s1) {
+  // advance to the next k-chunk (the schedule guarantees it exists)
+  __device__ __forceinline__ void advance(const GrgParams& p, int tid) {
     k0 += KC;
     if (k0 >= K) {
       ++s;
       k0 = 0;
-      if (s >= s1) return false;
       segment(p, tid);
     }
-    return true;
   }
 };
 
@@ -144,50 +142,10 @@ __device__ __forceinline__ void mfma_step(const double* __restrict__ Aw, const d
     for (int j = 0; j < NTT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
 }
 
-template <int MT, int NTT, int WM, int WN, int KC>
-__global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
-  constexpr int M = 16 * MT * WM;
-  constexpr int NT = 16 * NTT * WN;
-  constexpr int NTHR = 64 * WM * WN;
-  constexpr int LDB = KC + 1;  // odd row stride: conflict-free B fragment reads
-  __shared__ double As[M * KC];
-  __shared__ double Bs[NT * LDB];
-  __shared__ double r1s[NT];
-
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % WM, wn = wave / WM;
-
-  d4 acc[MT][NTT];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int j = 0; j < NTT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-  const int s0 = p.tile_seg_ptr[tile], s1 = p.tile_seg_ptr[tile + 1];
-  if (s0 < s1) {
-    Loader<M, NT, NTHR, KC> L;
-    L.s = s0;
-    L.k0 = 0;
-    L.segment(p, tid);
-    L.load(tid);
-    L.template store<LDB>(tid, As, Bs);
-    __syncthreads();
-    const double* __restrict__ Aw = As + (wm * MT) * 64 + lane;
-    const double* __restrict__ Bw = Bs + ((wn * NTT) * 16 + (lane & 15)) * LDB + (lane >> 4);
-    for (;;) {
-      const bool more = L.next(p, tid, s1);
-      if (more) L.load(tid);  // next chunk in flight while this one is multiplied
-#pragma unroll
-      for (int kk = 0; kk < KC / 4; ++kk) mfma_step<MT, NTT, M, LDB>(Aw, Bw, kk, acc);
-      if (!more) break;
-      __syncthreads();  // every wave is done reading the chunk
-      L.template store<LDB>(tid, As, Bs);
-      __syncthreads();  // the next chunk is visible
-    }
-  }
-
-  // rank-one log-scale terms, one scalar per slot
+// Output of one tile: rank-one terms, optional s^2 scaling, overwrite or accumulate.
+template <int MT, int NTT, int WM, int NT, int NTHR>
+__device__ __forceinline__ void tile_epilogue(const GrgParams& p, int tile, const d4 (&acc)[MT][NTT], double* r1s,
+                                              int tid, int lane, int wm, int wn) {
   for (int t = tid; t < NT; t += NTHR) {
     const int ti = tile * NT + t;
     double c = 0.0;
@@ -198,7 +156,6 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
     r1s[t] = c;
   }
   __syncthreads();
-
 #pragma unroll
   for (int j = 0; j < NTT; ++j) {
     const int slot = (wn * NTT + j) * 16 + (lane & 15);
@@ -211,7 +168,13 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) prev[i][r] = p.accumulate ? o[(wm * MT + i) * 16 + 4 * r + (lane >> 4)] : 0.0;
+      for (int r = 0; r < 4; ++r) prev[i][r] = 0.0;
+    if (p.accumulate) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) prev[i][r] = o[(wm * MT + i) * 16 + 4 * r + (lane >> 4)];
+    }
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -221,6 +184,94 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
         if (p.r1_all_rows || row == 0) v += r1;
         o[row] = v * sc + prev[i][r];
       }
+  }
+}
+
+// Persistent, balanced launch: block b runs the pieces the plan gave it. A piece that is a
+// whole tile writes the tile's output directly. A piece of a split tile stores its partial sum,
+// then counts itself in on the tile's counter; the block that arrives last adds the partials
+// in piece order (so the result does not depend on arrival order), writes the output and
+// re-arms the counter. No block ever waits for another.
+template <int MT, int NTT, int WM, int WN, int KC>
+__global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
+  constexpr int M = 16 * MT * WM;
+  constexpr int NT = 16 * NTT * WN;
+  constexpr int NTHR = 64 * WM * WN;
+  constexpr int LDB = KC + 1;  // odd row stride: conflict-free B fragment reads
+  constexpr int WPART = MT * NTT * 256;  // partial-sum doubles per wave
+  __shared__ double As[M * KC];
+  __shared__ double Bs[NT * LDB];
+  __shared__ double r1s[NT];
+  __shared__ int last_s;
+
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const double* __restrict__ Aw = As + (wm * MT) * 64 + lane;
+  const double* __restrict__ Bw = Bs + ((wn * NTT) * 16 + (lane & 15)) * LDB + (lane >> 4);
+
+  const int pc1 = p.blk_ptr[blk + 1];
+  for (int pc = p.blk_ptr[blk]; pc < pc1; ++pc) {
+    const PieceDesc P = p.pieces[pc];
+    d4 acc[MT][NTT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NTT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // the previous piece no longer reads LDS
+
+    if (P.n_chunks > 0) {
+      Loader<M, NT, NTHR, KC> L;
+      L.s = P.seg;
+      L.k0 = P.k0;
+      L.segment(p, tid);
+      L.load(tid);
+      L.template store<LDB>(tid, As, Bs);
+      __syncthreads();
+      for (int left = P.n_chunks;;) {
+        const bool more = --left > 0;
+        if (more) {  // next chunk in flight while this one is multiplied
+          L.advance(p, tid);
+          L.load(tid);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC / 4; ++kk) mfma_step<MT, NTT, M, LDB>(Aw, Bw, kk, acc);
+        if (!more) break;
+        __syncthreads();  // every wave is done reading the chunk
+        L.template store<LDB>(tid, As, Bs);
+        __syncthreads();  // the next chunk is visible
+      }
+    }
+
+    if (P.slot >= 0) {  // a piece of a split tile
+      double* __restrict__ mine = p.partial + (size_t)P.slot * (M * NT) + wave * WPART + lane;
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NTT; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine[((i * NTT + j) * 4 + r) * 64] = acc[i][j][r];
+      __threadfence();  // partial sums visible device-wide before the count
+      __syncthreads();
+      if (tid == 0) last_s = atomicAdd(p.tile_count + P.tile, 1) == P.n_pieces - 1;
+      __syncthreads();
+      if (!last_s) continue;
+      __threadfence();  // see every other piece's partial sums
+      for (int q = 0; q < P.n_pieces; ++q) {
+        const double* __restrict__ part = p.partial + (size_t)(P.slot0 + q) * (M * NT) + wave * WPART + lane;
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < NTT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const double v = part[((i * NTT + j) * 4 + r) * 64];
+              acc[i][j][r] = q == 0 ? v : acc[i][j][r] + v;
+            }
+      }
+      if (tid == 0) p.tile_count[P.tile] = 0;  // re-armed for the next launch
+    }
+    tile_epilogue<MT, NTT, WM, NT, NTHR>(p, P.tile, acc, r1s, tid, lane, wm, wn);
   }
 }
 
@@ -244,24 +295,42 @@ __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__
   if (lane == 0) out[leaf] = s;
 }
 
+// Every (M, NT, KC) instantiation: MT, NTT, WM, WN, KC, threads
+#define VP_CONFIGS(X)                                                                              \
+  X(256, 32, 32, 4, 2, 4, 1, 256) X(256, 64, 32, 4, 4, 4, 1, 256) X(256, 32, 16, 4, 2, 4, 1, 256) \
+  X(256, 64, 16, 4, 4, 4, 1, 256) X(80, 64, 40, 5, 1, 1, 4, 256) X(80, 32, 40, 5, 1, 1, 2, 128)   \
+  X(80, 16, 40, 5, 1, 1, 1, 64) X(80, 64, 32, 5, 1, 1, 4, 256) X(80, 32, 32, 5, 1, 1, 2, 128)     \
+  X(80, 16, 32, 5, 1, 1, 1, 64)
+
 hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream) {
-  if (p.n_tiles <= 0) return hipSuccess;
-  dim3 grid(p.n_tiles);
-#define VP_LAUNCH(MT, NTT, WM, WN, KCV, THR) \
-  hipLaunchKernelGGL((grg_kernel<MT, NTT, WM, WN, KCV>), grid, dim3(THR), 0, stream, p)
-  if (M == 256 && NT == 32 && KC == 32) VP_LAUNCH(4, 2, 4, 1, 32, 256);
-  else if (M == 256 && NT == 64 && KC == 32) VP_LAUNCH(4, 4, 4, 1, 32, 256);
-  else if (M == 256 && NT == 32 && KC == 16) VP_LAUNCH(4, 2, 4, 1, 16, 256);
-  else if (M == 256 && NT == 64 && KC == 16) VP_LAUNCH(4, 4, 4, 1, 16, 256);
-  else if (M == 80 && NT == 64 && KC == 40) VP_LAUNCH(5, 1, 1, 4, 40, 256);
-  else if (M == 80 && NT == 32 && KC == 40) VP_LAUNCH(5, 1, 1, 2, 40, 128);
-  else if (M == 80 && NT == 16 && KC == 40) VP_LAUNCH(5, 1, 1, 1, 40, 64);
-  else if (M == 80 && NT == 64 && KC == 32) VP_LAUNCH(5, 1, 1, 4, 32, 256);
-  else if (M == 80 && NT == 32 && KC == 32) VP_LAUNCH(5, 1, 1, 2, 32, 128);
-  else if (M == 80 && NT == 16 && KC == 32) VP_LAUNCH(5, 1, 1, 1, 32, 64);
-  else return hipErrorInvalidValue;
+  if (p.n_blocks <= 0) return hipSuccess;
+  dim3 grid(p.n_blocks);
+#define VP_LAUNCH(m, nt, kc, MT, NTT, WM, WN, THR)                                                  \
+  if (M == m && NT == nt && KC == kc) {                                                           \
+    hipLaunchKernelGGL((grg_kernel<MT, NTT, WM, WN, kc>), grid, dim3(THR), 0, stream, p);          \
+    return hipGetLastError();                                                                     \
+  }
+  VP_CONFIGS(VP_LAUNCH)
 #undef VP_LAUNCH
-  return hipGetLastError();
+  return hipErrorInvalidValue;
+}
+
+int grg_resident_blocks(int M, int NT, int KC) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+#define VP_OCC(m, nt, kc, MT, NTT, WM, WN, THR)                                                     \
+  if (M == m && NT == nt && KC == kc) {                                                           \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                             \
+            &per_cu, reinterpret_cast<const void*>(&grg_kernel<MT, NTT, WM, WN, kc>), THR, 0) !=  \
+        hipSuccess)                                                                               \
+      return 0;                                                                                   \
+    return per_cu * cus;                                                                          \
+  }
+  VP_CONFIGS(VP_OCC)
+#undef VP_OCC
+  return 0;
 }
 
 hipError_t launch_prescale(const double* x, const double* s2, double* out, int64_t n_leaves, hipStream_t stream) {

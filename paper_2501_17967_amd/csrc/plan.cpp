@@ -238,6 +238,89 @@ static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
   }
 }
 
+void build_schedule(Stage& st, int max_blocks, int min_units) {
+  const Matrices& mats = matrices();
+  const int T = st.n_tiles;
+  st.pieces.clear();
+  st.blk_ptr.assign(1, 0);
+  st.n_blocks = 0;
+  st.n_slots = 0;
+  if (T <= 0) return;
+  auto chunks = [&](int32_t seg) { return int64_t(mats.K[st.seg_rel[seg]] / st.KC); };
+  std::vector<int64_t> tu(T + 1, 0);  // first unit of each tile
+  for (int t = 0; t < T; ++t) {
+    int64_t n = 0;
+    for (int32_t g = st.tile_seg_ptr[t]; g < st.tile_seg_ptr[t + 1]; ++g) n += chunks(g);
+    tu[t + 1] = tu[t] + std::max<int64_t>(n, 1);
+  }
+  const int64_t U = tu[T];
+  const int64_t mu = std::max(1, min_units);
+  const int64_t G = std::max<int64_t>(1, std::min<int64_t>(std::max(1, max_blocks), (U + mu - 1) / mu));
+  auto first = [&](int64_t b) { return b * U / G; };  // first unit of block b
+  // pass 1: pieces per tile
+  std::vector<int32_t> npc(T, 0);
+  for (int64_t b = 0, t = 0; b < G; ++b)
+    for (int64_t u = first(b), ue = first(b + 1); u < ue;) {
+      while (tu[t + 1] <= u) ++t;
+      npc[t]++;
+      u = std::min(ue, tu[t + 1]);
+    }
+  std::vector<int32_t> slot0(T, -1), seen(T, 0);
+  for (int t = 0; t < T; ++t)
+    if (npc[t] > 1) { slot0[t] = st.n_slots; st.n_slots += npc[t]; }
+  // pass 2: the pieces, block by block
+  for (int64_t b = 0, t = 0; b < G; ++b) {
+    for (int64_t u = first(b), ue = first(b + 1); u < ue;) {
+      while (tu[t + 1] <= u) ++t;
+      const int64_t end = std::min(ue, tu[t + 1]);
+      Piece pc{};
+      pc.tile = int32_t(t);
+      pc.n_pieces = npc[t];
+      pc.slot0 = slot0[t];
+      pc.slot = npc[t] > 1 ? slot0[t] + seen[t] : -1;
+      seen[t]++;
+      const int32_t g0 = st.tile_seg_ptr[t], g1 = st.tile_seg_ptr[t + 1];
+      pc.seg = g0;
+      pc.k0 = 0;
+      pc.n_chunks = 0;
+      if (g1 > g0) {
+        int64_t o = u - tu[t];
+        int32_t g = g0;
+        while (o >= chunks(g)) { o -= chunks(g); ++g; }
+        pc.seg = g;
+        pc.k0 = int32_t(o * st.KC);
+        pc.n_chunks = int32_t(end - u);
+      }
+      st.pieces.push_back(pc);
+      u = end;
+    }
+    st.blk_ptr.push_back(int32_t(st.pieces.size()));
+  }
+  st.n_blocks = int(G);
+  // the kernel trusts these: every chunk of every tile exactly once, in order, within its tile
+  std::vector<int64_t> got(T, 0);
+  for (const Piece& pc : st.pieces) {
+    if (pc.tile < 0 || pc.tile >= T) throw std::runtime_error("schedule: bad tile");
+    if (pc.n_chunks > 0) {
+      int64_t o = 0;
+      for (int32_t g = st.tile_seg_ptr[pc.tile]; g < pc.seg; ++g) o += chunks(g);
+      if (pc.seg < st.tile_seg_ptr[pc.tile] || pc.seg >= st.tile_seg_ptr[pc.tile + 1] || pc.k0 % st.KC)
+        throw std::runtime_error("schedule: bad segment");
+      if (o + pc.k0 / st.KC != got[pc.tile]) throw std::runtime_error("schedule: chunks out of order");
+      if (tu[pc.tile] + got[pc.tile] + pc.n_chunks > tu[pc.tile + 1]) throw std::runtime_error("schedule: overrun");
+      got[pc.tile] += pc.n_chunks;
+    } else {
+      if (st.tile_seg_ptr[pc.tile + 1] != st.tile_seg_ptr[pc.tile] || pc.n_pieces != 1)
+        throw std::runtime_error("schedule: empty piece");
+    }
+    if ((pc.slot < 0) != (pc.n_pieces == 1) || (pc.slot >= 0 && (pc.slot < pc.slot0 || pc.slot >= pc.slot0 + pc.n_pieces)))
+      throw std::runtime_error("schedule: bad slot");
+  }
+  for (int t = 0; t < T; ++t)
+    if (st.tile_seg_ptr[t + 1] > st.tile_seg_ptr[t] && got[t] != tu[t + 1] - tu[t])
+      throw std::runtime_error("schedule: tile not covered");
+}
+
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
                int tile_leaf, int tile_box, Plan& P, int64_t* bad) {
   const double kLn2 = std::log(2.0);
@@ -415,6 +498,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   auto init_stage = [](Stage& st, int kind, const std::string& name, int level, int M, int K, int NT, int8_t out,
                        int32_t ostride) {
     st.kind = kind; st.name = name; st.level = level; st.M = M; st.NT = NT; st.out_arr = out; st.out_stride = ostride;
+    st.K = K;
     st.KC = (K == kNP) ? 32 : (M == kNP ? 16 : 40);
     for (auto& f : st.fam) f = {A_NONE, 0, 0};
     for (auto& f : st.r1fam) f = {A_NONE, 0, 0};

@@ -83,10 +83,25 @@ enum StageKind : int { K_UP = 0, K_DOWN, K_NEAR, K_LOCT, K_AUP, K_ADOWN, K_ANEAR
 
 struct FamDesc { int8_t arr; int32_t stride; int8_t unused; };
 
+// One piece of a stage's work as run by one block: n_chunks consecutive k-chunks of one tile,
+// starting at chunk k0 / KC of segment seg. A tile cut over several blocks ("split") has its
+// pieces' partial sums added, in piece order, by whichever of those blocks finishes last.
+struct Piece {
+  int32_t tile;
+  int32_t seg;       // first segment (index into seg_rel / seg_src)
+  int32_t k0;        // first k within that segment
+  int32_t n_chunks;  // 0 only for a tile without segments
+  int32_t slot;      // partial-sum slot of this piece; -1 when the piece is the whole tile
+  int32_t slot0;     // first slot of the tile's pieces
+  int32_t n_pieces;  // pieces of the tile
+  int32_t pad;
+};
+
 struct Stage {
   int kind = 0, level = 0;
   int M = 0;       // output rows (80 or 256)
   int NT = 0;      // slots per tile
+  int K = 0;       // inner dimension shared by every relation of the stage
   int KC = 0;      // k-chunk of the kernel instantiation
   double flops_issued = 0;  // MFMA work of the tiles, empty slots included
   int n_tiles = 0;
@@ -111,6 +126,11 @@ struct Stage {
   std::vector<double> r1_coef;
   double flops = 0.0;
   int64_t n_pairs = 0;
+  // balanced schedule (build_schedule): block b runs pieces [blk_ptr[b], blk_ptr[b+1])
+  std::vector<Piece> pieces;
+  std::vector<int32_t> blk_ptr;
+  int n_blocks = 0;
+  int n_slots = 0;  // partial-sum slots (M x NT doubles each)
 };
 
 struct Plan {
@@ -135,6 +155,10 @@ int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centr
 
 // Validates and builds the host plan. Returns a VOLPOT_* status; bad_leaf gets the first
 // offending caller leaf index on tree errors.
+// Cut a stage's work (units: one k-chunk of one segment; a tile without segments is one unit)
+// into at most max_blocks contiguous, equal ranges of at least min_units units each.
+void build_schedule(Stage& st, int max_blocks, int min_units);
+
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, Plan& plan, int64_t* bad_leaf);
 

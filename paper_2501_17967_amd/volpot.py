@@ -27,6 +27,7 @@ EXPORTED = [
     "volpot_plan", "volpot_plan_forest", "volpot_apply", "volpot_apply_adjoint", "volpot_plan_info",
     "volpot_validate_tree", "volpot_nodes", "volpot_plan_destroy", "volpot_status_string",
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
+    "volpot_plan_n_stages", "volpot_plan_stage",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -41,7 +42,7 @@ class VolpotError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
-                ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p)]
+                ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -54,6 +55,13 @@ class Info(ctypes.Structure):
                 ("flops_kind", ctypes.c_double * 9), ("launches_kind", ctypes.c_int64 * 9),
                 ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("flops_issued_kind", ctypes.c_double * 9)]
+
+
+class StageInfo(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("kind", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("kchunk", ctypes.c_int32), ("helper", ctypes.c_int32),
+                ("n_tiles", ctypes.c_int64), ("n_segments", ctypes.c_int64), ("n_blocks", ctypes.c_int64),
+                ("n_split_tiles", ctypes.c_int64), ("flops", ctypes.c_double), ("flops_issued", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +102,8 @@ def lib():
         L.volpot_stage_times.argtypes = [_vp, _dp, _lp, ctypes.c_int32]
         L.volpot_plan_table.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int64]
         L.volpot_near_relation.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
+        L.volpot_plan_n_stages.argtypes = [_vp, ctypes.c_int32, _ip]
+        L.volpot_plan_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(StageInfo)]
         _lib = L
     return _lib
 
@@ -144,11 +154,11 @@ class Plan:
     """A plan for one tree or, with ``tree_offsets``, a forest of independent trees."""
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
-                 tile_leaf=0, tile_box=0, table_cache=None):
+                 tile_leaf=0, tile_box=0, table_cache=None, split_min=0):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
-                      table_cache.encode() if table_cache else None)
+                      table_cache.encode() if table_cache else None, int(split_min))
         h = _vp()
         L = lib()
         if tree_offsets is None:
@@ -182,6 +192,21 @@ class Plan:
         for name, _ in Info._fields_:
             v = getattr(inf, name)
             out[name] = {k: v[i] for i, k in enumerate(STAGE_KINDS)} if name in ("flops_kind", "launches_kind", "flops_issued_kind") else v
+        return out
+
+    def stages(self, adjoint=False):
+        """The launches of one apply, in order: a list of dicts (name, kind, rows, tile, ...)."""
+        L = lib()
+        n = ctypes.c_int32(0)
+        _check(L.volpot_plan_n_stages(self._h, int(adjoint), ctypes.byref(n)), "volpot_plan_n_stages")
+        out = []
+        for i in range(n.value):
+            si = StageInfo()
+            _check(L.volpot_plan_stage(self._h, int(adjoint), i, ctypes.byref(si)), "volpot_plan_stage")
+            d = {k: getattr(si, k) for k, _ in StageInfo._fields_}
+            d["name"] = si.name.decode()
+            d["kind"] = STAGE_KINDS[si.kind]
+            out.append(d)
         return out
 
     def table(self, kind, index=0):
