@@ -68,7 +68,8 @@ typedef struct {
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
   int32_t split_min;       /* each stage is cut into as many equal shares of its k-chunks as the
                               device runs blocks at once; a share has at least this many chunks
-                              (0 = default: one relation's worth, K / chunk) */
+                              (0 = default: one relation's worth, K / chunk; -1 = no cut:
+                              one block per tile) */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the

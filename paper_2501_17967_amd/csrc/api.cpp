@@ -169,7 +169,7 @@ int schedule_all(volpot_plan_s* p, int nominal) {
           it = resident.emplace(key, nominal > 0 ? nominal : grg_resident_blocks(s.M, s.NT, s.KC)).first;
         if (it->second <= 0) return VOLPOT_ERR_HIP;
         // default: a block gets at least one whole segment (K / KC chunks)
-        build_schedule(s, it->second, p->split_min > 0 ? p->split_min : s.K / s.KC);
+        build_schedule(s, it->second, p->split_min != 0 ? p->split_min : s.K / s.KC);
       }
   } catch (const std::bad_alloc&) {
     return VOLPOT_ERR_OOM;

@@ -143,17 +143,40 @@ __device__ __forceinline__ void mfma_step(const double* __restrict__ Aw, const d
 }
 
 // Output of one tile: rank-one terms, optional s^2 scaling, overwrite or accumulate.
+// The rank-one sum of each slot is spread over NTHR / NT threads, each taking every
+// (NTHR / NT)-th entry four at a time (independent loads in flight), and the per-thread sums
+// are added in thread order: a fixed order, so the result is repeatable.
 template <int MT, int NTT, int WM, int NT, int NTHR>
 __device__ __forceinline__ void tile_epilogue(const GrgParams& p, int tile, const d4 (&acc)[MT][NTT], double* r1s,
-                                              int tid, int lane, int wm, int wn) {
-  for (int t = tid; t < NT; t += NTHR) {
-    const int ti = tile * NT + t;
+                                              double* r1p, int tid, int lane, int wm, int wn) {
+  constexpr int TPS = NTHR / NT;
+  static_assert(TPS >= 1 && NTHR % NT == 0, "threads per slot");
+  {
+    const int ti = tile * NT + tid / TPS;
+    const int e1 = p.r1_ptr[ti + 1];
     double c = 0.0;
-    for (int e = p.r1_ptr[ti]; e < p.r1_ptr[ti + 1]; ++e) {
-      const int f = p.r1_fam[e];
-      c += p.r1_coef[e] * ((gdp)pick3(p.r1_base, f))[(size_t)p.r1_idx[e] * pick3(p.r1_stride, f)];
+    for (int e = p.r1_ptr[ti] + tid % TPS; e < e1; e += 4 * TPS) {
+      int idx[4], fm[4];
+      double cf[4], v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int eq = e + q * TPS < e1 ? e + q * TPS : e;
+        idx[q] = p.r1_idx[eq];
+        fm[q] = p.r1_fam[eq];
+        cf[q] = e + q * TPS < e1 ? p.r1_coef[eq] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = ((gdp)pick3(p.r1_base, fm[q]))[(size_t)idx[q] * pick3(p.r1_stride, fm[q])];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c += cf[q] * v[q];
     }
-    r1s[t] = c;
+    r1p[tid] = c;
+  }
+  __syncthreads();
+  if (tid < NT) {
+    double c = r1p[tid * TPS];
+    for (int q = 1; q < TPS; ++q) c += r1p[tid * TPS + q];
+    r1s[tid] = c;
   }
   __syncthreads();
 #pragma unroll
@@ -202,6 +225,7 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
   __shared__ double As[M * KC];
   __shared__ double Bs[NT * LDB];
   __shared__ double r1s[NT];
+  __shared__ double r1p[NTHR];
   __shared__ int last_s;
 
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
@@ -244,19 +268,26 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
     }
 
     if (P.slot >= 0) {  // a piece of a split tile
+      // Partial sums go through device-coherent stores and loads (agent scope), so the hand-off
+      // needs no device-wide cache write-back or invalidate, which would also evict every other
+      // block's table lines: the stores are complete (waitcnt) before the block counts itself
+      // in, and the last block reads the partial sums only after its count has returned.
       double* __restrict__ mine = p.partial + (size_t)P.slot * (M * NT) + wave * WPART + lane;
 #pragma unroll
       for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < NTT; ++j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) mine[((i * NTT + j) * 4 + r) * 64] = acc[i][j][r];
-      __threadfence();  // partial sums visible device-wide before the count
+          for (int r = 0; r < 4; ++r)
+            __hip_atomic_store(mine + ((i * NTT + j) * 4 + r) * 64, acc[i][j][r], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (tid == 0) last_s = atomicAdd(p.tile_count + P.tile, 1) == P.n_pieces - 1;
+      if (tid == 0)
+        last_s = __hip_atomic_fetch_add(p.tile_count + P.tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 P.n_pieces - 1;
       __syncthreads();
       if (!last_s) continue;
-      __threadfence();  // see every other piece's partial sums
       for (int q = 0; q < P.n_pieces; ++q) {
         const double* __restrict__ part = p.partial + (size_t)(P.slot0 + q) * (M * NT) + wave * WPART + lane;
 #pragma unroll
@@ -265,13 +296,14 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
           for (int j = 0; j < NTT; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const double v = part[((i * NTT + j) * 4 + r) * 64];
+              const double v = __hip_atomic_load(part + ((i * NTT + j) * 4 + r) * 64, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
               acc[i][j][r] = q == 0 ? v : acc[i][j][r] + v;
             }
       }
-      if (tid == 0) p.tile_count[P.tile] = 0;  // re-armed for the next launch
+      if (tid == 0) __hip_atomic_store(p.tile_count + P.tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    tile_epilogue<MT, NTT, WM, NT, NTHR>(p, P.tile, acc, r1s, tid, lane, wm, wn);
+    tile_epilogue<MT, NTT, WM, NT, NTHR>(p, P.tile, acc, r1s, r1p, tid, lane, wm, wn);
   }
 }
 

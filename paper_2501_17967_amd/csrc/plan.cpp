@@ -254,9 +254,11 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
     tu[t + 1] = tu[t] + std::max<int64_t>(n, 1);
   }
   const int64_t U = tu[T];
+  // min_units < 0: one block per tile, no tile cut
+  const bool whole = min_units < 0;
   const int64_t mu = std::max(1, min_units);
-  const int64_t G = std::max<int64_t>(1, std::min<int64_t>(std::max(1, max_blocks), (U + mu - 1) / mu));
-  auto first = [&](int64_t b) { return b * U / G; };  // first unit of block b
+  const int64_t G = whole ? T : std::max<int64_t>(1, std::min<int64_t>(std::max(1, max_blocks), (U + mu - 1) / mu));
+  auto first = [&](int64_t b) { return whole ? tu[b] : b * U / G; };  // first unit of block b
   // pass 1: pieces per tile
   std::vector<int32_t> npc(T, 0);
   for (int64_t b = 0, t = 0; b < G; ++b)

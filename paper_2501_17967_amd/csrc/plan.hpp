@@ -157,6 +157,7 @@ int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centr
 // offending caller leaf index on tree errors.
 // Cut a stage's work (units: one k-chunk of one segment; a tile without segments is one unit)
 // into at most max_blocks contiguous, equal ranges of at least min_units units each.
+// min_units < 0 gives one block per tile instead (no tile is cut).
 void build_schedule(Stage& st, int max_blocks, int min_units);
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
