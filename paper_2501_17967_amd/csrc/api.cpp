@@ -24,6 +24,7 @@ struct DeviceTables {
   int device = -1;
   double* buf = nullptr;
   RelDesc* d_rels = nullptr;
+  std::vector<RelDesc> rels;  // host copy (device pointers)
   size_t bytes = 0;
   int refs = 0;
 };
@@ -62,6 +63,7 @@ int acquire_tables(int device, DeviceTables** out) {
   if (hipMalloc(&T->d_rels, kNumRel * sizeof(RelDesc)) != hipSuccess) { (void)hipFree(T->buf); delete T; return VOLPOT_ERR_OOM; }
   std::vector<RelDesc> rd(kNumRel);
   for (int r = 0; r < kNumRel; ++r) rd[r] = {T->buf + off[r], M.M[r], M.K[r]};
+  T->rels = rd;
   if (hipMemcpy(T->buf, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(T->d_rels, rd.data(), kNumRel * sizeof(RelDesc), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(T->buf); (void)hipFree(T->d_rels); delete T;
@@ -90,8 +92,8 @@ void release_tables(DeviceTables* T) {
 
 struct DevStage {
   const Stage* st = nullptr;
-  int32_t *tile_tgt = nullptr, *tile_seg_ptr = nullptr, *seg_rel = nullptr, *seg_src = nullptr;
-  int8_t* seg_fam = nullptr;
+  int32_t *tile_tgt = nullptr, *tile_seg_ptr = nullptr, *seg_src = nullptr;
+  SegDesc* segs = nullptr;
   int32_t *r1_ptr = nullptr, *r1_idx = nullptr;
   int8_t* r1_fam = nullptr;
   double* r1_coef = nullptr;
@@ -185,12 +187,18 @@ int upload(volpot_plan_s* p) {
   if (rc != VOLPOT_OK) return rc;
   size_t total = 0;
   const size_t nb = size_t(P.n_boxes) * kNE * sizeof(double);
-  struct Off { size_t tt, tsp, sr, sf, ss, rp, ri, rf, rc, pc, bp, tc; };
+  struct Off { size_t tt, tsp, sd, ss, rp, ri, rf, rc, pc, bp, tc; };
   std::vector<std::vector<int32_t>> zeros;  // arrival counters start at zero
+  std::vector<std::vector<SegDesc>> segd;   // segment descriptors (table pointers of this device)
   auto plan_stage = [&](const Stage& s) {
     Off o;
-    o.tt = add_bytes(total, s.tile_tgt); o.tsp = add_bytes(total, s.tile_seg_ptr); o.sr = add_bytes(total, s.seg_rel);
-    o.sf = add_bytes(total, s.seg_fam); o.ss = add_bytes(total, s.seg_src); o.rp = add_bytes(total, s.r1_ptr);
+    segd.emplace_back(s.seg_rel.size());
+    for (size_t i = 0; i < s.seg_rel.size(); ++i) {
+      const RelDesc& rd = p->tables->rels[size_t(s.seg_rel[i])];
+      segd.back()[i] = {rd.A, rd.K, int32_t(s.seg_fam[i])};
+    }
+    o.tt = add_bytes(total, s.tile_tgt); o.tsp = add_bytes(total, s.tile_seg_ptr); o.sd = add_bytes(total, segd.back());
+    o.ss = add_bytes(total, s.seg_src); o.rp = add_bytes(total, s.r1_ptr);
     o.ri = add_bytes(total, s.r1_idx); o.rf = add_bytes(total, s.r1_fam); o.rc = add_bytes(total, s.r1_coef);
     o.pc = add_bytes(total, s.pieces); o.bp = add_bytes(total, s.blk_ptr);
     zeros.emplace_back(size_t(std::max(s.n_tiles, 1)), 0);
@@ -212,8 +220,9 @@ int upload(volpot_plan_s* p) {
   auto put = [&](size_t o, const auto& v) {
     if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
   };
+  size_t si_ = 0;
   auto put_stage = [&](const Stage& s, const Off& o) {
-    put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sr, s.seg_rel); put(o.sf, s.seg_fam); put(o.ss, s.seg_src);
+    put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sd, segd[si_++]); put(o.ss, s.seg_src);
     put(o.rp, s.r1_ptr); put(o.ri, s.r1_idx); put(o.rf, s.r1_fam); put(o.rc, s.r1_coef);
     put(o.pc, s.pieces); put(o.bp, s.blk_ptr);
   };
@@ -229,7 +238,7 @@ int upload(volpot_plan_s* p) {
     DevStage d;
     d.st = &s;
     d.tile_tgt = reinterpret_cast<int32_t*>(b + o.tt); d.tile_seg_ptr = reinterpret_cast<int32_t*>(b + o.tsp);
-    d.seg_rel = reinterpret_cast<int32_t*>(b + o.sr); d.seg_fam = reinterpret_cast<int8_t*>(b + o.sf);
+    d.segs = reinterpret_cast<SegDesc*>(b + o.sd);
     d.seg_src = reinterpret_cast<int32_t*>(b + o.ss); d.r1_ptr = reinterpret_cast<int32_t*>(b + o.rp);
     d.r1_idx = reinterpret_cast<int32_t*>(b + o.ri); d.r1_fam = reinterpret_cast<int8_t*>(b + o.rf);
     d.r1_coef = reinterpret_cast<double*>(b + o.rc);
@@ -336,8 +345,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     hipStream_t st = s.helper ? helper : main;
     GrgParams g;
     std::memset(&g, 0, sizeof(g));
-    g.tile_tgt = d.tile_tgt; g.tile_seg_ptr = d.tile_seg_ptr; g.seg_rel = d.seg_rel; g.seg_fam = d.seg_fam;
-    g.seg_src = d.seg_src; g.rels = p->tables->d_rels;
+    g.tile_tgt = d.tile_tgt; g.tile_seg_ptr = d.tile_seg_ptr; g.segs = d.segs; g.seg_src = d.seg_src;
     for (int f = 0; f < 4; ++f) {
       g.fam_base[f] = arr_ptr(p, s.fam[f].arr, in, out);
       g.fam_stride[f] = s.fam[f].stride;

@@ -12,6 +12,13 @@ struct PieceDesc {
   int32_t tile, seg, k0, n_chunks, slot, slot0, n_pieces, pad;
 };
 
+// One segment of a tile: its relation table (fragment-major), inner dimension and source family
+struct SegDesc {
+  const double* A;
+  int32_t K;
+  int32_t fam;
+};
+
 struct RelDesc {
   const double* A;  // fragment-major: frag[(kk * (M/16) + row_tile) * 64 + lane] = A[16 row_tile + lane%16][4 kk + lane/16]
   int32_t M, K;
@@ -21,10 +28,8 @@ struct RelDesc {
 struct GrgParams {
   const int32_t* tile_tgt;      // n_tiles * NT, -1 = empty slot
   const int32_t* tile_seg_ptr;  // n_tiles + 1
-  const int32_t* seg_rel;       // relation id per segment
-  const int8_t* seg_fam;        // source family per segment
+  const SegDesc* segs;          // per segment
   const int32_t* seg_src;       // n_seg * NT source index, -1 = none
-  const RelDesc* rels;          // device table of relations
   const double* fam_base[4];
   int32_t fam_stride[4];
   const double* leaf_s2;        // s^2 per leaf (output scaling of the adjoint leaf stages)

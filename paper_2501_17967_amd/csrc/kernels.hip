@@ -70,18 +70,17 @@ struct Loader {
   d2 ra[A_PER], rb[B_PER];
 
   __device__ __forceinline__ void segment(const GrgParams& p, int tid) {
-    const RelDesc rd = p.rels[p.seg_rel[s]];
-    A = (gdp)rd.A;
-    K = rd.K;
-    const int fam = p.seg_fam[s];
-    base = (gdp)pick4(p.fam_base, fam);
-    stride = pick4(p.fam_stride, fam);
     gip src = (gip)(p.seg_src + (size_t)s * NT);
 #pragma unroll
     for (int q = 0; q < B_PER; ++q) {
       const int t = (tid + q * NTHR) / HALF;
       si[q] = t < NT ? src[t] : -1;
     }
+    const SegDesc sd = p.segs[s];
+    A = (gdp)sd.A;
+    K = sd.K;
+    base = (gdp)pick4(p.fam_base, sd.fam);
+    stride = pick4(p.fam_stride, sd.fam);
   }
   __device__ __forceinline__ void load(int tid) {
     gd2p A2 = (gd2p)(A + (size_t)k0 * M);
@@ -146,16 +145,34 @@ __device__ __forceinline__ void mfma_step(const double* __restrict__ Aw, const d
 // The rank-one sum of each slot is spread over NTHR / NT threads, each taking every
 // (NTHR / NT)-th entry four at a time (independent loads in flight), and the per-thread sums
 // are added in thread order: a fixed order, so the result is repeatable.
+// Indices the epilogue of a tile needs, loaded when its piece starts so that their latency
+// hides behind the piece's products.
+template <int NTT, int NT, int NTHR>
+struct EpiIdx {
+  int tgt[NTT];
+  double sc[NTT];
+  int e0, e1;
+  __device__ __forceinline__ void load(const GrgParams& p, int tile, int tid, int lane, int wn) {
+#pragma unroll
+    for (int j = 0; j < NTT; ++j) tgt[j] = p.tile_tgt[tile * NT + (wn * NTT + j) * 16 + (lane & 15)];
+    const int ti = tile * NT + tid / (NTHR / NT);
+    e0 = p.r1_ptr[ti];
+    e1 = p.r1_ptr[ti + 1];
+#pragma unroll
+    for (int j = 0; j < NTT; ++j) sc[j] = (p.out_scaled && tgt[j] >= 0) ? p.leaf_s2[tgt[j]] : 1.0;
+  }
+};
+
 template <int MT, int NTT, int WM, int NT, int NTHR>
-__device__ __forceinline__ void tile_epilogue(const GrgParams& p, int tile, const d4 (&acc)[MT][NTT], double* r1s,
-                                              double* r1p, int tid, int lane, int wm, int wn) {
+__device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<NTT, NT, NTHR>& ix,
+                                              const d4 (&acc)[MT][NTT], double* r1s, double* r1p, int tid, int lane,
+                                              int wm, int wn) {
   constexpr int TPS = NTHR / NT;
   static_assert(TPS >= 1 && NTHR % NT == 0, "threads per slot");
   {
-    const int ti = tile * NT + tid / TPS;
-    const int e1 = p.r1_ptr[ti + 1];
+    const int e1 = ix.e1;
     double c = 0.0;
-    for (int e = p.r1_ptr[ti] + tid % TPS; e < e1; e += 4 * TPS) {
+    for (int e = ix.e0 + tid % TPS; e < e1; e += 4 * TPS) {
       int idx[4], fm[4];
       double cf[4], v[4];
 #pragma unroll
@@ -182,9 +199,9 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, int tile, cons
 #pragma unroll
   for (int j = 0; j < NTT; ++j) {
     const int slot = (wn * NTT + j) * 16 + (lane & 15);
-    const int tgt = p.tile_tgt[tile * NT + slot];
+    const int tgt = ix.tgt[j];
     if (tgt < 0) continue;
-    const double sc = p.out_scaled ? p.leaf_s2[tgt] : 1.0;
+    const double sc = ix.sc[j];
     const double r1 = r1s[slot];
     double* __restrict__ o = p.out + (size_t)tgt * p.out_stride;
     double prev[MT][4];
@@ -237,6 +254,8 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
   const int pc1 = p.blk_ptr[blk + 1];
   for (int pc = p.blk_ptr[blk]; pc < pc1; ++pc) {
     const PieceDesc P = p.pieces[pc];
+    EpiIdx<NTT, NT, NTHR> ix;
+    ix.load(p, P.tile, tid, lane, wn);
     d4 acc[MT][NTT];
 #pragma unroll
     for (int i = 0; i < MT; ++i)
@@ -303,7 +322,7 @@ __global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
       }
       if (tid == 0) __hip_atomic_store(p.tile_count + P.tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    tile_epilogue<MT, NTT, WM, NT, NTHR>(p, P.tile, acc, r1s, r1p, tid, lane, wm, wn);
+    tile_epilogue<MT, NTT, WM, NT, NTHR>(p, ix, acc, r1s, r1p, tid, lane, wm, wn);
   }
 }
 
