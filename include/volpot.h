@@ -70,6 +70,9 @@ typedef struct {
                               device runs blocks at once; a share has at least this many chunks
                               (0 = default: one relation's worth, K / chunk; -1 = no cut:
                               one block per tile) */
+  int32_t overlap;         /* 1: the far-field chain on a plan-owned helper stream, concurrent
+                              with the near field; 0 (default): every stage on the caller's
+                              stream, in plan order */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -137,12 +140,13 @@ void volpot_plan_destroy(volpot_plan_t plan);
 /* Static text for a status code. */
 const char* volpot_status_string(int status);
 
-/* Timing hooks for measurement. When enabled, apply calls record a HIP event pair around
- * every stage launch on the stream that launch uses (the near field runs on the caller's
- * stream, the far-field chain on a plan-owned helper stream forked from and joined back into
- * it); volpot_stage_times synchronises those events and returns, per stage kind k (numbered
- * as in volpot_info.flops_kind), the summed milliseconds ms[k] and launch counts n[k] since
- * the last reset, then resets. Disabled by default; not available with use_graph. */
+/* Timing hooks for measurement. enable: 0 off, 1 every stage kind, or bit (8 + k) set for each
+ * stage kind k (numbered as in volpot_info.flops_kind) to be timed. Apply calls then record a
+ * HIP event pair around every launch of those kinds on the stream that launch uses (the
+ * caller's; with the overlap option the far-field chain's stream is the plan's helper stream);
+ * volpot_stage_times synchronises those events and returns, per stage kind k, the summed
+ * milliseconds ms[k] and launch counts n[k] since the last reset, then resets. Disabled by
+ * default; not available with use_graph. */
 int volpot_set_timing(volpot_plan_t plan, int32_t enable);
 int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_t n_kinds);
 
@@ -151,6 +155,19 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
  *   kind 1: S2M (80 x 256);   kind 2: L2T (256 x 80)
  * Returns VOLPOT_ERR_ARG for an unknown kind/index or n too small. */
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
+
+/* Autotuner (for callers that apply one tree shape many times, e.g. batched forests): searches
+ * the launch shapes tile_box 16|32|64, tile_leaf 32|64, split_min 0|1|-1 and overlap 0|1
+ * one knob at a time from the defaults (the other fields are taken from base, nullable),
+ * building a plan for each candidate and timing one forward plus one adjoint apply on internal
+ * device buffers after a warm-up (HIP events, private stream); writes the fastest options to
+ * *best and their time in milliseconds to *best_ms (nullable). With cache_path (nullable) the result is looked up in, and appended to, that text file,
+ * keyed by a signature of the trees' level histogram and sizes and of the device, so that a
+ * shape is timed once. Allocates and synchronises; not for use inside a timed region.
+ * Arguments as volpot_plan_forest (a single tree: n_trees = 1, offsets {0, n_leaves}). */
+int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, const double* centres,
+                    const int32_t* levels, int32_t p, const volpot_options* base,
+                    const char* cache_path, volpot_options* best, double* best_ms);
 
 /* One stage (one kernel launch) of an apply, for inspection and tuning. */
 typedef struct {

@@ -8,6 +8,7 @@ from .volpot import (  # noqa: F401
     EXPORTED,
     Plan,
     VolpotError,
+    autotune,
     lib,
     near_relation,
     nodes,

@@ -25,7 +25,7 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     objs = []
-    for src in ("plan.cpp", "tables.cpp", "api.cpp"):
+    for src in ("plan.cpp", "tables.cpp", "api.cpp", "tune.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         jobs.append(cmd)

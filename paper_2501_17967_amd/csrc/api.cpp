@@ -123,9 +123,10 @@ struct volpot_plan_s {
   double* d_fs = nullptr;  // prescaled input s^2 f
   double* d_part[2] = {nullptr, nullptr};  // partial sums of split tiles: helper-stream, caller-stream stages
   int split_min = 0;
+  bool overlap = false;
   std::vector<DevStage> dfwd, dadj;
   int64_t device_bytes = 0;
-  bool timing = false;
+  int32_t timing = 0;  // bit k: time the launches of stage kind k
   std::vector<hipEvent_t> ev_free;
   std::vector<Pending> pending;
   double ms[K_NUM] = {0};
@@ -300,9 +301,9 @@ hipEvent_t take_event(volpot_plan_s* p) {
   return e;
 }
 
-void timed_begin(volpot_plan_s* p, bool timing, hipStream_t st, hipEvent_t* ea, hipEvent_t* eb) {
+void timed_begin(volpot_plan_s* p, int32_t timing, int kind, hipStream_t st, hipEvent_t* ea, hipEvent_t* eb) {
   *ea = *eb = nullptr;
-  if (!timing) return;
+  if (!(timing >> kind & 1)) return;
   *ea = take_event(p);
   *eb = take_event(p);
   if (*ea) (void)hipEventRecord(*ea, st);
@@ -314,30 +315,31 @@ void timed_end(volpot_plan_s* p, int kind, hipStream_t st, hipEvent_t ea, hipEve
   }
 }
 
-// The whole apply: fork the helper stream from the caller's stream, issue every stage on its
-// stream in plan order (far-field chain on the helper, near field on the caller's stream),
-// join before the stages that combine both, and join again at the end so that the caller's
-// stream orders everything.
-int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t main, bool timing) {
+// The whole apply: issue every stage in plan order on the caller's stream. With the overlap
+// option, fork the helper stream from the caller's stream, issue the far-field chain on it and
+// the near field on the caller's stream, join before the stages that combine both and again
+// at the end, so that the caller's stream orders everything.
+int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t main, int32_t timing) {
   std::vector<DevStage>& stages = adjoint ? p->dadj : p->dfwd;
-  hipStream_t helper = p->helper;
+  const bool two = p->overlap;
+  hipStream_t helper = two ? p->helper : main;
   if (!adjoint) {  // every forward source read uses s^2 f: scale once, before the fork
     hipEvent_t ea, eb;
-    timed_begin(p, timing, main, &ea, &eb);
+    timed_begin(p, timing, K_UP, main, &ea, &eb);
     if (launch_prescale(in, p->d_leaf_s2, p->d_fs, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
     timed_end(p, K_UP, main, ea, eb);
   }
-  if (hipEventRecord(p->ev_fork, main) != hipSuccess || hipStreamWaitEvent(helper, p->ev_fork, 0) != hipSuccess)
+  if (two && (hipEventRecord(p->ev_fork, main) != hipSuccess || hipStreamWaitEvent(helper, p->ev_fork, 0) != hipSuccess))
     return VOLPOT_ERR_HIP;
   if (adjoint) {
     hipEvent_t ea, eb;
-    timed_begin(p, timing, helper, &ea, &eb);
+    timed_begin(p, timing, K_ASUM, helper, &ea, &eb);
     if (launch_rowsum(in, p->d_usum, p->host.n_leaves, helper) != hipSuccess) return VOLPOT_ERR_HIP;
     timed_end(p, K_ASUM, helper, ea, eb);
   }
   for (DevStage& d : stages) {
     const Stage& s = *d.st;
-    if (s.join_before) {
+    if (two && s.join_before) {
       if (hipEventRecord(p->ev_join, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_join, 0) != hipSuccess)
         return VOLPOT_ERR_HIP;
     }
@@ -365,12 +367,12 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     g.partial = p->d_part[s.helper ? 0 : 1];
     g.n_blocks = s.n_blocks;
     hipEvent_t ea, eb;
-    timed_begin(p, timing, st, &ea, &eb);
+    timed_begin(p, timing, s.kind, st, &ea, &eb);
     hipError_t e = launch_grg(s.M, s.NT, s.KC, g, st);
     timed_end(p, s.kind, st, ea, eb);
     if (e != hipSuccess) return VOLPOT_ERR_HIP;
   }
-  if (hipEventRecord(p->ev_end, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_end, 0) != hipSuccess)
+  if (two && (hipEventRecord(p->ev_end, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_end, 0) != hipSuccess))
     return VOLPOT_ERR_HIP;
   return VOLPOT_OK;
 }
@@ -382,7 +384,7 @@ int run_graph(volpot_plan_s* p, bool adjoint, const double* in, double* out, hip
   if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return VOLPOT_ERR_HIP;
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return VOLPOT_ERR_HIP;
-  int rc = run(p, adjoint, in, out, p->cap_stream, false);
+  int rc = run(p, adjoint, in, out, p->cap_stream, 0);
   hipError_t ec = hipStreamEndCapture(p->cap_stream, &graph);
   if (rc != VOLPOT_OK || ec != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -442,6 +444,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   plan->host_only = o.host_only != 0;
   plan->use_graph = o.use_graph != 0;
   plan->split_min = o.split_min;
+  plan->overlap = o.overlap != 0;
   if (plan->host_only) {  // schedules for a nominal device, so that they can be inspected
     rc = schedule_all(plan, 1024);
     if (rc != VOLPOT_OK) { delete plan; return rc; }
@@ -598,7 +601,8 @@ const char* volpot_status_string(int status) {
 int volpot_set_timing(volpot_plan_t plan, int32_t enable) {
   if (!plan) return VOLPOT_ERR_ARG;
   if (plan->use_graph && enable) return VOLPOT_ERR_STATE;
-  plan->timing = enable != 0;
+  if (enable != 0 && enable != 1 && (enable < 256 || (enable >> 8) >= (1 << K_NUM))) return VOLPOT_ERR_ARG;
+  plan->timing = enable == 1 ? (1 << K_NUM) - 1 : (enable >> 8);
   return VOLPOT_OK;
 }
 

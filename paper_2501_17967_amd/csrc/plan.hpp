@@ -24,9 +24,10 @@
 // All relations of one stage share the inner dimension K (80 for expansions, 256 for leaf
 // values), which the k-chunk KC of the stage's kernel divides, so the kernel's chunks are
 // always full. Rank-one log-scale terms (ln s_l times a box mass) are folded into the
-// epilogues of FARV, LOCT and AFARV. The near field depends on nothing but f, so it runs on the caller's stream
-// while the far-field chain runs on a helper stream; LOCT waits for both. Owner-computes with
-// a fixed relation order gives bitwise-deterministic results without atomics.
+// epilogues of FARV, LOCT and AFARV. Stages run in this order on the caller's stream; with the
+// overlap option, the stages marked (helper) run on a plan-owned helper stream instead,
+// concurrently with the near field, which depends on nothing but f, and LOCT waits for both.
+// Owner-computes with a fixed relation order gives bitwise-deterministic results.
 #pragma once
 
 #include <array>

@@ -1,0 +1,184 @@
+// Autotuner of the launch shapes: for one tree or forest, time candidate combinations of
+// leaf-stage tile, expansion-stage tile and split policy on the current device (one forward
+// and one adjoint apply after a warm-up, HIP events on a private stream), one knob at a time
+// (coordinate descent from the defaults: expansion tile, leaf tile, split policy, streams),
+// and report the fastest. Optionally remembers the answer in a text file keyed by a signature of the
+// workload's shape and of the device, so that later plans of the same shape skip the timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/volpot.h"
+
+namespace {
+
+struct Candidate {
+  int32_t tile_leaf, tile_box, split_min, overlap;
+};
+
+// Shape signature: trees, leaves per level over the whole forest, sizes of the trees, the
+// device's architecture and compute-unit count. FNV-1a over the values.
+uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, int dev) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(uint64_t(n_trees));
+  std::vector<int64_t> hist(32, 0);
+  for (int64_t i = 0; i < off[n_trees]; ++i) hist[size_t(std::min(std::max(levels[i], 0), 31))]++;
+  for (int64_t c : hist) mix(uint64_t(c));
+  std::vector<int64_t> sizes;
+  for (int32_t t = 0; t < n_trees; ++t) sizes.push_back(off[t + 1] - off[t]);
+  std::sort(sizes.begin(), sizes.end());
+  for (int64_t s : sizes) mix(uint64_t(s));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    for (const char* c = prop.gcnArchName; *c; ++c) mix(uint64_t(uint8_t(*c)));
+    mix(uint64_t(prop.multiProcessorCount));
+  }
+  return h;
+}
+
+bool cache_lookup(const char* path, uint64_t key, volpot_options* best, double* ms) {
+  if (!path) return false;
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {  // the last entry for a key wins
+    std::istringstream ss(line);
+    unsigned long long k = 0;
+    int tl = 0, tb = 0, sm = 0, one = 0;
+    double t = 0;
+    if (!(ss >> std::hex >> k >> std::dec >> tl >> tb >> sm >> one >> t)) continue;
+    if (k != key) continue;
+    best->tile_leaf = tl;
+    best->tile_box = tb;
+    best->split_min = sm;
+    best->overlap = one;
+    *ms = t;
+    found = true;
+  }
+  return found;
+}
+
+void cache_store(const char* path, uint64_t key, const volpot_options& o, double ms) {
+  if (!path) return;
+  std::ofstream out(path, std::ios::app);
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "%016llx %d %d %d %d %.6f\n", (unsigned long long)key, o.tile_leaf, o.tile_box,
+                o.split_min, o.overlap, ms);
+  out << buf;
+}
+
+}  // namespace
+
+extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, const double* centres,
+                               const int32_t* levels, int32_t p, const volpot_options* base, const char* cache_path,
+                               volpot_options* best, double* best_ms) {
+  if (n_trees <= 0 || !tree_offsets || !centres || !levels || !best) return VOLPOT_ERR_ARG;
+  if (tree_offsets[0] != 0) return VOLPOT_ERR_ARG;
+  for (int32_t t = 0; t < n_trees; ++t)
+    if (tree_offsets[t + 1] <= tree_offsets[t]) return VOLPOT_ERR_ARG;
+  volpot_options o;
+  std::memset(&o, 0, sizeof(o));
+  if (base) o = *base;
+  o.host_only = 0;
+  o.use_graph = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VOLPOT_ERR_HIP;
+  const uint64_t key = signature(n_trees, tree_offsets, levels, dev);
+  double ms = 0;
+  *best = o;
+  if (cache_lookup(cache_path, key, best, &ms)) {
+    if (best_ms) *best_ms = ms;
+    return VOLPOT_OK;
+  }
+
+  const int64_t n = tree_offsets[n_trees] * 256;
+  double *x = nullptr, *y = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = VOLPOT_OK;
+  if (hipMalloc(&x, size_t(n) * sizeof(double)) != hipSuccess || hipMalloc(&y, size_t(n) * sizeof(double)) != hipSuccess)
+    rc = VOLPOT_ERR_OOM;
+  if (rc == VOLPOT_OK && (hipMemset(x, 0, size_t(n) * sizeof(double)) != hipSuccess ||
+                          hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+                          hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = VOLPOT_ERR_HIP;
+  // time one candidate: best of three forward + adjoint applies after a warm-up
+  auto time_it = [&](const Candidate& c, double* t_out) {
+    volpot_options oc = o;
+    oc.tile_leaf = c.tile_leaf;
+    oc.tile_box = c.tile_box;
+    oc.split_min = c.split_min;
+    oc.overlap = c.overlap;
+    volpot_plan_t plan = nullptr;
+    int r = volpot_plan_forest(n_trees, tree_offsets, centres, levels, p, &oc, &plan);
+    if (r != VOLPOT_OK) return r;
+    double t_c = 1e30;
+    for (int rep = 0; rep < 4 && r == VOLPOT_OK; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) r = VOLPOT_ERR_HIP;
+      if (r == VOLPOT_OK) r = volpot_apply(plan, x, y, s);
+      if (r == VOLPOT_OK) r = volpot_apply_adjoint(plan, x, y, s);
+      if (r == VOLPOT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        r = VOLPOT_ERR_HIP;
+      float t = 0;
+      if (r == VOLPOT_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) r = VOLPOT_ERR_HIP;
+      if (r == VOLPOT_OK && rep > 0) t_c = std::min(t_c, double(t));
+    }
+    volpot_plan_destroy(plan);
+    *t_out = t_c;
+    return r;
+  };
+  // coordinate descent over the three knobs, one at a time, from the defaults
+  Candidate cur{32, 64, 0, 0};
+  double best_t = 1e30;
+  auto try_axis = [&](int axis, std::initializer_list<int32_t> values) {
+    Candidate keep = cur;
+    for (int32_t v : values) {
+      if (rc != VOLPOT_OK) return;
+      Candidate c = keep;
+      (axis == 0 ? c.tile_box : axis == 1 ? c.tile_leaf : axis == 2 ? c.split_min : c.overlap) = v;
+      if (best_t < 1e30 && c.tile_leaf == cur.tile_leaf && c.tile_box == cur.tile_box && c.split_min == cur.split_min &&
+          c.overlap == cur.overlap)
+        continue;  // already timed
+      double t = 0;
+      rc = time_it(c, &t);
+      if (rc == VOLPOT_OK && t < best_t) {
+        best_t = t;
+        cur = c;
+      }
+    }
+  };
+  if (rc == VOLPOT_OK) {
+    try_axis(0, {16, 32, 64});
+    try_axis(1, {32, 64});
+    try_axis(2, {0, 1, -1});
+    try_axis(3, {0, 1});
+  }
+  if (rc == VOLPOT_OK) {
+    best->tile_leaf = cur.tile_leaf;
+    best->tile_box = cur.tile_box;
+    best->split_min = cur.split_min;
+    best->overlap = cur.overlap;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (x) (void)hipFree(x);
+  if (y) (void)hipFree(y);
+  if (rc != VOLPOT_OK) return rc;
+  if (best_ms) *best_ms = best_t;
+  cache_store(cache_path, key, *best, best_t);
+  return VOLPOT_OK;
+}

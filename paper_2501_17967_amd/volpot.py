@@ -27,7 +27,7 @@ EXPORTED = [
     "volpot_plan", "volpot_plan_forest", "volpot_apply", "volpot_apply_adjoint", "volpot_plan_info",
     "volpot_validate_tree", "volpot_nodes", "volpot_plan_destroy", "volpot_status_string",
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
-    "volpot_plan_n_stages", "volpot_plan_stage",
+    "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -42,7 +42,8 @@ class VolpotError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
-                ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32)]
+                ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
+                ("overlap", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -103,6 +104,8 @@ def lib():
         L.volpot_plan_table.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int64]
         L.volpot_near_relation.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
         L.volpot_plan_n_stages.argtypes = [_vp, ctypes.c_int32, _ip]
+        L.volpot_autotune.argtypes = [ctypes.c_int32, _lp, _dp, _ip, ctypes.c_int32, ctypes.POINTER(Options),
+                                      ctypes.c_char_p, ctypes.POINTER(Options), _dp]
         L.volpot_plan_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(StageInfo)]
         _lib = L
     return _lib
@@ -119,6 +122,21 @@ def _host_tree(centres, levels):
     if c.shape[0] != l.shape[0]:
         raise ValueError("centres and levels differ in length")
     return c, l
+
+
+def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
+    """Fastest launch shape for this tree or forest on the current device (volpot_autotune):
+    returns ({"tile_leaf", "tile_box", "split_min", "overlap"}, ms per forward + adjoint apply). The result
+    is looked up in / appended to the text file ``cache`` when given."""
+    c, l = _host_tree(centres, levels)
+    off = np.ascontiguousarray(np.asarray([0, c.shape[0]] if tree_offsets is None else tree_offsets, dtype=np.int64))
+    best = Options()
+    ms = ctypes.c_double(0.0)
+    _check(lib().volpot_autotune(off.size - 1, off.ctypes.data_as(_lp), c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), p,
+                                 None, cache.encode() if cache else None, ctypes.byref(best), ctypes.byref(ms)),
+           "volpot_autotune")
+    return ({"tile_leaf": best.tile_leaf, "tile_box": best.tile_box, "split_min": best.split_min,
+             "overlap": best.overlap}, ms.value)
 
 
 def validate_tree(centres, levels, p=16):
@@ -154,11 +172,12 @@ class Plan:
     """A plan for one tree or, with ``tree_offsets``, a forest of independent trees."""
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
-                 tile_leaf=0, tile_box=0, table_cache=None, split_min=0):
+                 tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
-                      table_cache.encode() if table_cache else None, int(split_min))
+                      table_cache.encode() if table_cache else None, int(split_min),
+                      int(overlap))
         h = _vp()
         L = lib()
         if tree_offsets is None:
@@ -215,8 +234,12 @@ class Plan:
         _check(lib().volpot_plan_table(self._h, kind, index, out.ctypes.data_as(_dp), out.size), "volpot_plan_table")
         return out
 
-    def set_timing(self, enable):
-        _check(lib().volpot_set_timing(self._h, int(enable)), "volpot_set_timing")
+    def set_timing(self, enable, kinds=None):
+        """Time every stage kind (enable True), none (False), or only the named ``kinds``."""
+        v = int(bool(enable))
+        if enable and kinds is not None:
+            v = sum(1 << (8 + STAGE_KINDS.index(k)) for k in kinds)
+        _check(lib().volpot_set_timing(self._h, v), "volpot_set_timing")
 
     def stage_times(self):
         """{kind: (ms summed, launches)} since the last call (synchronises the timing events)."""

@@ -144,3 +144,26 @@ def test_forest_pair_counts_add_up(vp):
     for k in ("pairs_near", "pairs_v", "pairs_w", "pairs_x", "n_boxes", "n_leaves"):
         assert f[k] == sum(i[k] for i in infs), k
     assert abs(f["flops_total"] - sum(i["flops_total"] for i in infs)) < 1e-6 * f["flops_total"]
+
+
+@pytest.mark.parametrize("split_min", [0, 1, 3, -1])
+def test_schedules_cover_stages(vp, split_min):
+    # host-only plans schedule for a nominal 1024 resident blocks; the library checks each
+    # schedule chunk by chunk when it builds it, these are the counts seen from outside
+    w = gen.config2(0)
+    plan = vp.Plan(w.centres, w.levels, host_only=True, split_min=split_min)
+    for adj in (False, True):
+        for s in plan.stages(adj):
+            if s["n_tiles"] == 0:
+                continue
+            chunks = (256 if s["rows"] == 80 and s["kchunk"] == 32 else 80 if s["rows"] == 80 else
+                      256 if s["kchunk"] == 32 else 80) // s["kchunk"]
+            units = s["n_segments"] * chunks  # every tile here has at least one segment
+            if split_min == -1:
+                assert s["n_blocks"] == s["n_tiles"] and s["n_split_tiles"] == 0, s
+            else:
+                mu = split_min if split_min > 0 else chunks
+                assert s["n_blocks"] == min(1024, -(-units // mu)), s
+                # each boundary between consecutive blocks cuts at most one tile
+                assert s["n_split_tiles"] <= s["n_blocks"] - 1 or s["n_split_tiles"] == 0, s
+            assert s["flops_issued"] >= s["flops"] * (1 - 1e-12) or s["rows"] == 256 and s["kchunk"] == 16, s

@@ -288,3 +288,93 @@ def test_autograd_gradient_matches_finite_differences(vp, torch_mod):
     resid = Wq.cpu().numpy() * (bc.apply(w.f) - ut.cpu().numpy())
     assert rel(g.cpu().numpy(), bc.apply_adjoint(resid)) <= 1e-10
     plan.close()
+
+
+def test_autotune_picks_a_valid_shape_and_caches(vp, torch_mod, tmp_path):
+    w = gen.config2(0)
+    _say("case autotune config2 seed 0")
+    cache = str(tmp_path / "tune.txt")
+    best, ms = vp.autotune(w.centres, w.levels, cache=cache)
+    assert best["tile_leaf"] in (32, 64) and best["tile_box"] in (16, 32, 64) and best["split_min"] in (0, 1, -1)
+    assert ms > 0
+    again, ms2 = vp.autotune(w.centres, w.levels, cache=cache)  # answered from the cache file
+    assert again == best and abs(ms2 - ms) <= 1e-6 * ms
+    assert len(open(cache).read().splitlines()) == 1
+    ref, _ = _run(vp, torch_mod, w)
+    u, _ = _run(vp, torch_mod, w, **best)
+    assert rel(u, ref) <= 1e-14
+
+
+def test_config3_forward_and_adjoint_vs_box_code_oracle(vp, torch_mod):
+    # 200 Gaussians cut off outside the star curve, cut boxes refined to level 8 (about 9k leaves)
+    w = gen.config3(0)
+    _say("case config3 seed 0 (%d leaves)" % w.n_leaves)
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
+@pytest.mark.timeout(400)
+def test_size_matched_config3_sampled_vs_direct_sum(vp, torch_mod):
+    # star-cut source with cut boxes refined to level 13: about 170k leaves, 43M unknowns
+    w = gen.config3(0, lcut=13)
+    _say("case config3-sm (lcut 13, %d leaves)" % w.n_leaves)
+    u, _ = _run(vp, torch_mod, w)
+    rng = np.random.default_rng(13)
+    samples = [(int(a), int(m)) for a, m in zip(rng.integers(0, w.n_leaves, 16), rng.integers(0, 256, 16))]
+    ud = quad.direct_potential(tree.Tree(w.centres, w.levels), w.f, samples)
+    ug = np.array([u[a, m] for a, m in samples])
+    assert np.max(np.abs(ug - ud)) / np.max(np.abs(u)) <= TOL
+
+
+def test_config4_forest_graph_trees_vs_oracle(vp, torch_mod):
+    # uneven trees (1-40 Gaussians, min level 3) applied together, graph-captured, forward and
+    # adjoint; per-tree parity against the oracle for the smallest, the largest and two others
+    trees = gen.config4(0, n_trees=32)
+    off = np.cumsum([0] + [t.n_leaves for t in trees])
+    _say("case config4 forest of %d trees (%d leaves)" % (len(trees), off[-1]))
+    F = np.vstack([t.f for t in trees])
+    rng = np.random.default_rng(17)
+    R = rng.standard_normal(F.shape)
+    forest = vp.Plan(np.vstack([t.centres for t in trees]), np.concatenate([t.levels for t in trees]),
+                     tree_offsets=off, use_graph=True)
+    Fd, Rd = _gpu(torch_mod, F), _gpu(torch_mod, R)
+    u, fb = torch_mod.empty_like(Fd), torch_mod.empty_like(Fd)
+    for _ in range(2):  # second call replays the captured graphs
+        forest.apply(Fd, out=u)
+        forest.apply_adjoint(Rd, out=fb)
+    torch_mod.cuda.synchronize()
+    u, fb = u.cpu().numpy(), fb.cpu().numpy()
+    forest.close()
+    sizes = [t.n_leaves for t in trees]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 5, 17})
+    for i in pick:
+        t = trees[i]
+        bc = fmm.BoxCode(tree.Tree(t.centres, t.levels))
+        assert rel(u[off[i]:off[i + 1]], bc.apply(t.f)) <= TOL, i
+        assert rel(fb[off[i]:off[i + 1]], bc.apply_adjoint(R[off[i]:off[i + 1]])) <= TOL, i
+
+
+def test_size_matched_config2_forward_and_adjoint_vs_box_code_oracle(vp, torch_mod):
+    # the benchmark workload in full, in the launch configuration bench.py times
+    w = gen.config2(0, size_matched=True)
+    _say("case config2-sm seed 0 full oracle (%d leaves)" % w.n_leaves)
+    rng = np.random.default_rng(19)
+    r = rng.standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
+def test_overlapped_streams_equal_single_stream(vp, torch_mod):
+    # the same launches in the same per-target order, only the stream assignment differs
+    w = gen.config2(1)
+    _say("case overlapped streams")
+    r = np.random.default_rng(23).standard_normal(w.f.shape)
+    u1, f1 = _run(vp, torch_mod, w, adjoint_input=r)
+    u2, f2 = _run(vp, torch_mod, w, adjoint_input=r, overlap=1)
+    assert np.array_equal(u1, u2) and np.array_equal(f1, f2)
