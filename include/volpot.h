@@ -70,9 +70,11 @@ typedef struct {
                               device runs blocks at once; a share has at least this many chunks
                               (0 = default: one relation's worth, K / chunk; -1 = no cut:
                               one block per tile) */
-  int32_t overlap;         /* 1: the far-field chain on a plan-owned helper stream, concurrent
-                              with the near field; 0 (default): every stage on the caller's
-                              stream, in plan order */
+  int32_t overlap;         /* 0 (default): every stage on the caller's stream, in plan order.
+                              n > 0: the near field runs as two launches that leave n compute
+                              units' share of blocks free, each beside one latency-bound chain
+                              of the far field (upward, downward) on a plan-owned helper
+                              stream forked from and joined back into the caller's stream */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -157,7 +159,7 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
 
 /* Autotuner (for callers that apply one tree shape many times, e.g. batched forests): searches
- * the launch shapes tile_box 16|32|64, tile_leaf 32|64, split_min 0|1|-1 and overlap 0|1
+ * the launch shapes tile_box 16|32|64, tile_leaf 32|64, split_min 0|1|-1 and overlap 0|16|24|32|48
  * one knob at a time from the defaults (the other fields are taken from base, nullable),
  * building a plan for each candidate and timing one forward plus one adjoint apply on internal
  * device buffers after a warm-up (HIP events, private stream); writes the fastest options to

@@ -123,7 +123,7 @@ struct volpot_plan_s {
   double* d_fs = nullptr;  // prescaled input s^2 f
   double* d_part[2] = {nullptr, nullptr};  // partial sums of split tiles: helper-stream, caller-stream stages
   int split_min = 0;
-  bool overlap = false;
+  int overlap = 0;  // compute units left to the helper stream during the near field (0: one stream)
   std::vector<DevStage> dfwd, dadj;
   int64_t device_bytes = 0;
   int32_t timing = 0;  // bit k: time the launches of stage kind k
@@ -134,7 +134,7 @@ struct volpot_plan_s {
   hipStream_t cap_stream = nullptr;
   std::vector<GraphEntry> graphs;
   hipStream_t helper = nullptr;  // far-field chain runs here, forked from the caller's stream
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_end = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -163,6 +163,12 @@ size_t add_bytes(size_t& total, const std::vector<T>& v) {
 // share of the stage's k-chunks. nominal > 0 replaces the device query (host-only plans).
 int schedule_all(volpot_plan_s* p, int nominal) {
   std::map<std::array<int, 3>, int> resident;
+  int cus = 256;
+  if (nominal <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return VOLPOT_ERR_HIP;
+  }
   try {
     for (auto* v : {&p->host.fwd, &p->host.adj})
       for (Stage& s : *v) {
@@ -171,8 +177,11 @@ int schedule_all(volpot_plan_s* p, int nominal) {
         if (it == resident.end())
           it = resident.emplace(key, nominal > 0 ? nominal : grg_resident_blocks(s.M, s.NT, s.KC)).first;
         if (it->second <= 0) return VOLPOT_ERR_HIP;
+        // a stage that runs beside the helper stream leaves `overlap` compute units' share free
+        int blocks = it->second;
+        if (s.concurrent && p->overlap > 0) blocks = std::max(1, blocks - (blocks / std::max(cus, 1)) * p->overlap);
         // default: a block gets at least one whole segment (K / KC chunks)
-        build_schedule(s, it->second, p->split_min != 0 ? p->split_min : s.K / s.KC);
+        build_schedule(s, blocks, p->split_min != 0 ? p->split_min : s.K / s.KC);
       }
   } catch (const std::bad_alloc&) {
     return VOLPOT_ERR_OOM;
@@ -270,8 +279,7 @@ int upload(volpot_plan_s* p) {
     }
   if (hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p->ev_end, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
     return VOLPOT_ERR_HIP;
   return VOLPOT_OK;
 }
@@ -315,36 +323,46 @@ void timed_end(volpot_plan_s* p, int kind, hipStream_t st, hipEvent_t ea, hipEve
   }
 }
 
-// The whole apply: issue every stage in plan order on the caller's stream. With the overlap
-// option, fork the helper stream from the caller's stream, issue the far-field chain on it and
-// the near field on the caller's stream, join before the stages that combine both and again
-// at the end, so that the caller's stream orders everything.
+// The whole apply: every stage in plan order on the caller's stream. With the overlap option,
+// a stage marked fork_before makes the plan's helper stream wait for the caller's stream, the
+// stages marked helper then run on it (the far-field chains) while the caller's stream goes on
+// (the near field), and a stage marked join_before, and the end of the apply, make the
+// caller's stream wait for the helper's work, so that the caller's stream orders everything.
 int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t main, int32_t timing) {
   std::vector<DevStage>& stages = adjoint ? p->dadj : p->dfwd;
-  const bool two = p->overlap;
-  hipStream_t helper = two ? p->helper : main;
-  if (!adjoint) {  // every forward source read uses s^2 f: scale once, before the fork
+  const bool two = p->overlap > 0;
+  bool forked = false;  // the helper stream holds work not yet joined
+  auto fork = [&]() {
+    if (hipEventRecord(p->ev_fork, main) != hipSuccess || hipStreamWaitEvent(p->helper, p->ev_fork, 0) != hipSuccess)
+      return false;
+    forked = true;
+    return true;
+  };
+  auto join = [&]() {
+    if (!forked) return true;
+    if (hipEventRecord(p->ev_join, p->helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_join, 0) != hipSuccess)
+      return false;
+    forked = false;
+    return true;
+  };
+  {
     hipEvent_t ea, eb;
-    timed_begin(p, timing, K_UP, main, &ea, &eb);
-    if (launch_prescale(in, p->d_leaf_s2, p->d_fs, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
-    timed_end(p, K_UP, main, ea, eb);
-  }
-  if (two && (hipEventRecord(p->ev_fork, main) != hipSuccess || hipStreamWaitEvent(helper, p->ev_fork, 0) != hipSuccess))
-    return VOLPOT_ERR_HIP;
-  if (adjoint) {
-    hipEvent_t ea, eb;
-    timed_begin(p, timing, K_ASUM, helper, &ea, &eb);
-    if (launch_rowsum(in, p->d_usum, p->host.n_leaves, helper) != hipSuccess) return VOLPOT_ERR_HIP;
-    timed_end(p, K_ASUM, helper, ea, eb);
+    if (!adjoint) {  // every forward source read uses s^2 f: scale once
+      timed_begin(p, timing, K_UP, main, &ea, &eb);
+      if (launch_prescale(in, p->d_leaf_s2, p->d_fs, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
+      timed_end(p, K_UP, main, ea, eb);
+    } else {  // leaf sums of the cotangent, for the adjoint log-scale terms
+      timed_begin(p, timing, K_ASUM, main, &ea, &eb);
+      if (launch_rowsum(in, p->d_usum, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
+      timed_end(p, K_ASUM, main, ea, eb);
+    }
   }
   for (DevStage& d : stages) {
     const Stage& s = *d.st;
-    if (two && s.join_before) {
-      if (hipEventRecord(p->ev_join, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_join, 0) != hipSuccess)
-        return VOLPOT_ERR_HIP;
-    }
+    if (two && s.fork_before && !fork()) return VOLPOT_ERR_HIP;
+    if (two && s.join_before && !join()) return VOLPOT_ERR_HIP;
     if (s.n_tiles == 0) continue;
-    hipStream_t st = s.helper ? helper : main;
+    hipStream_t st = (two && s.helper && forked) ? p->helper : main;
     GrgParams g;
     std::memset(&g, 0, sizeof(g));
     g.tile_tgt = d.tile_tgt; g.tile_seg_ptr = d.tile_seg_ptr; g.segs = d.segs; g.seg_src = d.seg_src;
@@ -364,7 +382,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     g.r1_all_rows = s.r1_all_rows;
     g.accumulate = s.accumulate;
     g.pieces = d.pieces; g.blk_ptr = d.blk_ptr; g.tile_count = d.tile_count;
-    g.partial = p->d_part[s.helper ? 0 : 1];
+    g.partial = p->d_part[s.helper ? 0 : 1];  // helper-marked stages never share a buffer with the others
     g.n_blocks = s.n_blocks;
     hipEvent_t ea, eb;
     timed_begin(p, timing, s.kind, st, &ea, &eb);
@@ -372,8 +390,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     timed_end(p, s.kind, st, ea, eb);
     if (e != hipSuccess) return VOLPOT_ERR_HIP;
   }
-  if (two && (hipEventRecord(p->ev_end, helper) != hipSuccess || hipStreamWaitEvent(main, p->ev_end, 0) != hipSuccess))
-    return VOLPOT_ERR_HIP;
+  if (two && !join()) return VOLPOT_ERR_HIP;
   return VOLPOT_OK;
 }
 
@@ -407,7 +424,6 @@ void free_plan(volpot_plan_s* p) {
     if (p->helper) (void)hipStreamDestroy(p->helper);
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
-    if (p->ev_end) (void)hipEventDestroy(p->ev_end);
     for (auto& e : p->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto e : p->ev_free) (void)hipEventDestroy(e);
     if (p->d_block) (void)hipFree(p->d_block);
@@ -434,7 +450,8 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   if (!plan) return VOLPOT_ERR_OOM;
   int rc;
   try {
-    rc = build_plan(n_trees, offsets, centres, levels, o.tile_leaf, o.tile_box, plan->host, nullptr);
+    rc = build_plan(n_trees, offsets, centres, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
+                    nullptr);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {
@@ -444,7 +461,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   plan->host_only = o.host_only != 0;
   plan->use_graph = o.use_graph != 0;
   plan->split_min = o.split_min;
-  plan->overlap = o.overlap != 0;
+  plan->overlap = std::max(0, o.overlap);
   if (plan->host_only) {  // schedules for a nominal device, so that they can be inspected
     rc = schedule_all(plan, 1024);
     if (rc != VOLPOT_OK) { delete plan; return rc; }

@@ -238,6 +238,56 @@ static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
   }
 }
 
+// Launch order and stream flags. Built order: [S2M] [M2M chain] [FARV] [FARX] [L2L chain]
+// [NEAR or NEAR_A NEAR_B] [LOCT] (adjoint: [AL2T] [AL2L chain] [AFARV] [AFARW] [AM2M chain]
+// [ANEAR...] [ALOCT]). Launch order:
+//   S2M, M2M chain (helper), NEAR_A, FARV (join), FARX, L2L chain (helper), NEAR_B, LOCT (join)
+// so that, with the overlap option, each latency-bound chain runs beside half of the near
+// field, which does not depend on the far field. Without overlap everything runs in this
+// order on one stream, which is also a valid order.
+static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
+  const int k_up = adjoint ? K_AUP : K_UP, k_down = adjoint ? K_ADOWN : K_DOWN;
+  const int k_near = adjoint ? K_ANEAR : K_NEAR, k_loct = adjoint ? K_ALOCT : K_LOCT;
+  std::vector<Stage> head, up_chain, far, down_chain, near, tail;
+  for (Stage& s : v) {
+    s.helper = s.join_before = s.fork_before = s.concurrent = 0;
+    if (s.kind == k_up && s.level < 0) head.push_back(std::move(s));        // S2M / AL2T
+    else if (s.kind == k_up) up_chain.push_back(std::move(s));              // M2M[l] / AL2L[l]
+    else if (s.kind == k_down && s.level < 0) far.push_back(std::move(s));  // FARV, FARX / AFARV, AFARW
+    else if (s.kind == k_down) down_chain.push_back(std::move(s));          // L2L[l] / AM2M[l]
+    else if (s.kind == k_near) near.push_back(std::move(s));
+    else if (s.kind == k_loct) tail.push_back(std::move(s));
+    else throw std::runtime_error("unexpected stage kind");
+  }
+  v.clear();
+  auto chain = [&](std::vector<Stage>& c) {
+    for (size_t i = 0; i < c.size(); ++i) {
+      c[i].helper = 1;
+      c[i].fork_before = i == 0;
+      v.push_back(std::move(c[i]));
+    }
+  };
+  auto put_near = [&](size_t i) {
+    if (i < near.size()) {
+      near[i].concurrent = 1;
+      v.push_back(std::move(near[i]));
+    }
+  };
+  for (Stage& s : head) v.push_back(std::move(s));
+  chain(up_chain);
+  put_near(0);
+  for (size_t i = 0; i < far.size(); ++i) {
+    far[i].join_before = i == 0;
+    v.push_back(std::move(far[i]));
+  }
+  chain(down_chain);
+  put_near(1);
+  for (size_t i = 0; i < tail.size(); ++i) {
+    tail[i].join_before = i == 0;
+    v.push_back(std::move(tail[i]));
+  }
+}
+
 void build_schedule(Stage& st, int max_blocks, int min_units) {
   const Matrices& mats = matrices();
   const int T = st.n_tiles;
@@ -324,7 +374,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
 }
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
-               int tile_leaf, int tile_box, Plan& P, int64_t* bad) {
+               int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad) {
   const double kLn2 = std::log(2.0);
   const double kInv2Pi = 1.0 / (2.0 * M_PI);
   P = Plan();
@@ -520,7 +570,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg;
     for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0) tg.push_back(b);
     Stage st; init_stage(st, K_UP, "S2M", -1, kNE, kNP, NTB, A_MP, kNE);
-    st.helper = 1;
     st.fam[0] = {A_INS, kNP, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
@@ -533,7 +582,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
     if (tg.empty()) continue;
     Stage st; init_stage(st, K_UP, lvl("M2M", l), l, kNE, kNE, NTB, A_MP, kNE);
-    st.helper = 1;
     st.fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
@@ -545,7 +593,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   if (!deep_by_quadrant.empty()) {  // FARV: M2L for every box of every level >= 2, plus all log terms
     const auto& tg = deep_by_quadrant;
     Stage st; init_stage(st, K_DOWN, "FARV", -1, kNE, kNE, NTB, A_LOC, kNE);
-    st.helper = 1;
     st.fam[0] = {A_MP, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -564,8 +611,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t b : deep_by_quadrant) if (!Xlist[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
       Stage st; init_stage(st, K_DOWN, "FARX", -1, kNE, kNP, NTB, A_LOC, kNE);
-      st.helper = 1;
-      st.accumulate = 1;
+        st.accumulate = 1;
       st.fam[0] = {A_INS, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
@@ -579,7 +625,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg = boxes_at[l];
     std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
     Stage st; init_stage(st, K_DOWN, lvl("L2L", l), l, kNE, kNE, NTB, A_LOC, kNE);
-    st.helper = 1;
     st.accumulate = 1;
     st.fam[0] = {A_LOC, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -588,19 +633,28 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     make_tiles(st, tg, E, R, mats);
     P.fwd.push_back(std::move(st));
   }
-  {  // NEAR: the adjacent-leaf tables, on the caller's stream
-    Stage st; init_stage(st, K_NEAR, "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+  // with overlap the leaf stages' targets are cut in two halves (at a tile boundary): the near
+  // field then runs as two launches, each beside one far-field chain
+  std::vector<std::pair<size_t, size_t>> halves;
+  if (overlap > 0 && leaf_order.size() > size_t(NTL)) {
+    const size_t cut = (leaf_order.size() / 2 + NTL - 1) / NTL * NTL;
+    halves = {{0, cut}, {cut, leaf_order.size()}};
+  } else {
+    halves = {{0, leaf_order.size()}};
+  }
+  for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
+    const std::vector<int32_t> part(leaf_order.begin() + long(halves[h].first), leaf_order.begin() + long(halves[h].second));
+    Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
     st.fam[0] = {A_INS, kNP, 0};
-    std::vector<std::vector<Entry>> E(P.n_leaves);
-    std::vector<std::vector<R1>> R(P.n_leaves);
-    for (size_t i = 0; i < leaf_order.size(); ++i)
-      for (auto& e : Ulist[leaf_order[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
-    make_tiles(st, leaf_order, E, R, mats);
+    std::vector<std::vector<Entry>> E(part.size());
+    std::vector<std::vector<R1>> R(part.size());
+    for (size_t i = 0; i < part.size(); ++i)
+      for (auto& e : Ulist[part[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
+    make_tiles(st, part, E, R, mats);
     P.fwd.push_back(std::move(st));
   }
   {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
     Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
-    st.join_before = 1;
     st.accumulate = 1;
     st.r1_all_rows = 1;
     st.fam[0] = {A_MP, kNE, 0}; st.fam[1] = {A_LOC, kNE, 0};
@@ -624,8 +678,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0 && P.box_level[b] >= 2) tg.push_back(b);
     if (!tg.empty()) {
       Stage st; init_stage(st, K_AUP, "AL2T", -1, kNE, kNP, NTB, A_LB, kNE);
-      st.helper = 1;
-      st.fam[0] = {A_IN, kNP, 0};
+        st.fam[0] = {A_IN, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
       for (size_t i = 0; i < tg.size(); ++i) E[i].push_back({kRelL2T + kNumFwd, 0, P.box_leaf[tg[i]]});
@@ -638,7 +691,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
     if (tg.empty()) continue;
     Stage st; init_stage(st, K_AUP, lvl("AL2L", l), l, kNE, kNE, NTB, A_LB, kNE);
-    st.helper = 1;
     st.fam[0] = {A_LB, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
@@ -655,7 +707,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   {  // AFARV: M2L^T plus every log term
     const auto& tg = afar_tg;
     Stage st; init_stage(st, K_ADOWN, "AFARV", -1, kNE, kNE, NTB, A_AB, kNE);
-    st.helper = 1;
     st.fam[0] = {A_LB, kNE, 0};
     st.r1fam[0] = {A_LB, kNE, 0}; st.r1fam[1] = {A_USUM, 1, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -679,8 +730,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t b : afar_tg) if (!Winv[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
       Stage st; init_stage(st, K_ADOWN, "AFARW", -1, kNE, kNP, NTB, A_AB, kNE);
-      st.helper = 1;
-      st.accumulate = 1;
+        st.accumulate = 1;
       st.fam[0] = {A_IN, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
@@ -694,7 +744,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg = boxes_at[l];
     std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
     Stage st; init_stage(st, K_ADOWN, lvl("AM2M", l), l, kNE, kNE, NTB, A_AB, kNE);
-    st.helper = 1;
     st.accumulate = 1;
     st.fam[0] = {A_AB, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -703,20 +752,20 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     make_tiles(st, tg, E, R, mats);
     P.adj.push_back(std::move(st));
   }
-  {  // ANEAR: transposed near tables, on the caller's stream
-    Stage st; init_stage(st, K_ANEAR, "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+  for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
+    const std::vector<int32_t> part(leaf_order.begin() + long(halves[h].first), leaf_order.begin() + long(halves[h].second));
+    Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
     st.out_scaled = 1;
     st.fam[0] = {A_IN, kNP, 0};
-    std::vector<std::vector<Entry>> E(P.n_leaves);
-    std::vector<std::vector<R1>> R(P.n_leaves);
-    for (size_t i = 0; i < leaf_order.size(); ++i)
-      for (auto& e : Uinv[leaf_order[i]]) E[i].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
-    make_tiles(st, leaf_order, E, R, mats);
+    std::vector<std::vector<Entry>> E(part.size());
+    std::vector<std::vector<R1>> R(part.size());
+    for (size_t i = 0; i < part.size(); ++i)
+      for (auto& e : Uinv[part[i]]) E[i].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
+    make_tiles(st, part, E, R, mats);
     P.adj.push_back(std::move(st));
   }
   {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
     Stage st; init_stage(st, K_ALOCT, "ALOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
-    st.join_before = 1;
     st.accumulate = 1;
     st.out_scaled = 1;
     st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_LB, kNE, 0};
@@ -730,6 +779,8 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     make_tiles(st, leaf_order, E, R, mats);
     P.adj.push_back(std::move(st));
   }
+  arrange_stages(P.fwd, false);
+  arrange_stages(P.adj, true);
   return VOLPOT_OK;
 }
 

@@ -113,6 +113,8 @@ struct Stage {
   int8_t accumulate = 0;   // add to the output (else overwrite)
   int8_t helper = 0;       // runs on the helper stream (far-field chain)
   int8_t join_before = 0;  // waits for the helper stream's work before launching
+  int8_t fork_before = 0;  // the helper stream waits for the caller's stream before this stage
+  int8_t concurrent = 0;   // runs while helper-stream stages may run: leaves compute units free
   std::string name;        // stage name for reports, e.g. NEAR or M2M[5]
   FamDesc fam[4];
   FamDesc r1fam[3];
@@ -161,7 +163,9 @@ int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centr
 // min_units < 0 gives one block per tile instead (no tile is cut).
 void build_schedule(Stage& st, int max_blocks, int min_units);
 
+// overlap > 0: near field split in two launches, each concurrent with one chain of the far
+// field on the helper stream (stage order and flags below); 0: one stream, plan order.
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
-               const int32_t* levels, int tile_leaf, int tile_box, Plan& plan, int64_t* bad_leaf);
+               const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf);
 
 }  // namespace vp

@@ -164,7 +164,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     try_axis(0, {16, 32, 64});
     try_axis(1, {32, 64});
     try_axis(2, {0, 1, -1});
-    try_axis(3, {0, 1});
+    try_axis(3, {0, 16, 24, 32, 48});
   }
   if (rc == VOLPOT_OK) {
     best->tile_leaf = cur.tile_leaf;

@@ -167,3 +167,27 @@ def test_schedules_cover_stages(vp, split_min):
                 # each boundary between consecutive blocks cuts at most one tile
                 assert s["n_split_tiles"] <= s["n_blocks"] - 1 or s["n_split_tiles"] == 0, s
             assert s["flops_issued"] >= s["flops"] * (1 - 1e-12) or s["rows"] == 256 and s["kchunk"] == 16, s
+
+
+def test_overlap_launch_order(vp):
+    # with overlap the near field is cut in two launches, each placed beside one far-field
+    # chain (helper stream), and every stage still comes after the stages it reads
+    w = gen.config2(0)
+    for overlap in (0, 16):
+        plan = vp.Plan(w.centres, w.levels, host_only=True, overlap=overlap)
+        for adj, (head, up, near, far, down, tail) in (
+                (False, ("S2M", "M2M", "NEAR", ("FARV", "FARX"), "L2L", "LOCT")),
+                (True, ("AL2T", "AL2L", "ANEAR", ("AFARV", "AFARW"), "AM2M", "ALOCT"))):
+            names = [s["name"] for s in plan.stages(adj)]
+            helper = [s["name"] for s in plan.stages(adj) if s["helper"]]
+            assert names[0] == head and names[-1] == tail
+            assert helper == [n for n in names if n.startswith(up + "[") or n.startswith(down + "[")]
+            i_far = names.index(far[0])
+            assert all(names.index(n) < i_far for n in names if n.startswith(up + "["))
+            assert all(names.index(n) > names.index(far[-1]) for n in names if n.startswith(down + "["))
+            nears = [n for n in names if n.startswith(near)]
+            if overlap:
+                assert nears == [near + "_A", near + "_B"]
+                assert names.index(near + "_A") < i_far < names.index(near + "_B") < len(names) - 1
+            else:
+                assert nears == [near]
