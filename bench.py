@@ -28,23 +28,25 @@ PEAK_HBM = 8.0e12  # bytes/s
 
 
 def kernel_source_hash():
+    """Hash of the sources that decide what the leaf-stage launches do: the kernels and the
+    plan and scheduling code that cut the work into launches."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.hpp"):
+    for f in ("kernels.hip", "device.hpp", "plan.cpp", "api.cpp"):
         with open(os.path.join(ROOT, "paper_2501_17967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_launch_flops):
+def traffic_from_profile(shape):
     """HBM bytes per launch of the leaf-stage kernel from the committed counter summary, or
-    None when the summary is missing or was taken on a different kernel source."""
+    None when the summary is missing or was taken on other sources or another launch shape."""
     path = os.path.join(ROOT, "profiles", "leaf_stage_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_source_hash():
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("launch_shape") != shape:
         return None
     return d.get("bytes_per_launch")
 
@@ -106,8 +108,10 @@ def main():
     if args.overlap is not None:
         shape["overlap"] = args.overlap
     print("bench: launch shape %s (autotuner %.1fs)" % (shape, t_tune), file=sys.stderr, flush=True)
+    plan_shape = {"tile_leaf": 32, "tile_box": 64, "split_min": 0, "overlap": 0}
+    plan_shape.update(shape)
     t0 = time.perf_counter()
-    plan = Plan(w.centres, w.levels, **shape)
+    plan = Plan(w.centres, w.levels, **plan_shape)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
@@ -155,16 +159,19 @@ def main():
 
     # roofline of the dominant kernel: the near-field stage (forward) and its transpose
     # (adjoint) -- the same kernel instantiation, one launch each per step
+    # (with the overlap option the near field of each apply runs as two launches)
     leaf_ms = st["near"][0] + st["adj_near"][0]
     leaf_n = st["near"][1] + st["adj_near"][1]
-    flops_per_launch = (info["flops_kind"]["near"] + info["flops_kind"]["adj_near"]) / 2.0
+    launches_per_step = leaf_n / args.steps
+    flops_per_launch = (info["flops_kind"]["near"] + info["flops_kind"]["adj_near"]) / launches_per_step
     avg_ms = leaf_ms / max(leaf_n, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3)
-    traffic = traffic_from_profile(flops_per_launch)
+    traffic = traffic_from_profile(plan_shape)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
                 "kernel": "grg_kernel, 256-row tiles: near-field stage (forward) and its transpose (adjoint)",
-                "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms, "launches": leaf_n}
+                "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms, "launches": leaf_n,
+                "launches_per_step": launches_per_step}
     # per-stage breakdown: a separate pass with every launch timed (events perturb the overlap)
     plan.set_timing(True)
     plan.stage_times()
@@ -192,7 +199,7 @@ def main():
         "config": {"workload": w.name + " (adaptive 20-Gaussian source, size-matched quadtree, seed %d)" % args.seed,
                    "n_leaves": int(w.n_leaves), "unknowns": int(N), "max_level": int(info["max_level"]), "p": 16,
                    "expansion_order": int(info["order"]), "step": "forward + adjoint",
-                   "launch_shape": shape, "autotune_s": t_tune},
+                   "launch_shape": plan_shape, "autotune_s": t_tune},
         "roofline": roofline,
         "fwd_unknowns_per_s": N / t_fwd,
         "adj_unknowns_per_s": N / t_adj,

@@ -176,9 +176,44 @@ int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centr
 struct Entry { int32_t rel; int8_t fam; int32_t src; };
 struct R1 { int8_t fam; int32_t idx; double coef; };
 
-static void make_tiles(Stage& st, const std::vector<int32_t>& targets,
-                       const std::vector<std::vector<Entry>>& entries,
+static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
+                               const std::vector<std::vector<Entry>>& entries,
+                               const std::vector<std::vector<R1>>& r1, const Matrices& mats);
+
+// Targets grouped by the set of relations they take, classes in lexicographic order of their
+// sorted relation lists (neighbouring classes share most relations), the given order within a
+// class. Every segment of a tile costs the same whatever its occupancy, so a tile should hold
+// targets that take the same relations: in adaptive trees, targets near refinement boundaries
+// take neighbours in many patterns.
+static void make_tiles(Stage& st, const std::vector<int32_t>& targets, const std::vector<std::vector<Entry>>& entries,
                        const std::vector<std::vector<R1>>& r1, const Matrices& mats) {
+  const size_t n = targets.size();
+  std::vector<std::vector<int32_t>> sigs(n);
+  std::map<std::vector<int32_t>, int32_t> cls;
+  for (size_t i = 0; i < n; ++i) {
+    for (const Entry& e : entries[i]) sigs[i].push_back(e.rel);
+    std::sort(sigs[i].begin(), sigs[i].end());
+    cls.emplace(sigs[i], 0);
+  }
+  int32_t rank = 0;
+  for (auto& kv : cls) kv.second = rank++;
+  std::vector<int32_t> c(n), perm(n);
+  for (size_t i = 0; i < n; ++i) { c[i] = cls[sigs[i]]; perm[i] = int32_t(i); }
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return c[size_t(x)] < c[size_t(y)]; });
+  std::vector<int32_t> t2(n);
+  std::vector<std::vector<Entry>> e2(n);
+  std::vector<std::vector<R1>> r2(n);
+  for (size_t i = 0; i < n; ++i) {
+    t2[i] = targets[size_t(perm[i])];
+    e2[i] = entries[size_t(perm[i])];
+    r2[i] = r1[size_t(perm[i])];
+  }
+  make_tiles_ordered(st, t2, e2, r2, mats);
+}
+
+static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
+                               const std::vector<std::vector<Entry>>& entries,
+                               const std::vector<std::vector<R1>>& r1, const Matrices& mats) {
   const int NT = st.NT;
   st.n_tiles = int((targets.size() + NT - 1) / NT);
   st.tile_tgt.assign(size_t(st.n_tiles) * NT, -1);
@@ -633,6 +668,29 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     make_tiles(st, tg, E, R, mats);
     P.fwd.push_back(std::move(st));
   }
+  // Near-field targets grouped by the set of relations they take (in an adaptive tree, leaves at
+  // a refinement boundary take fine or coarse neighbours in many patterns; interior leaves all
+  // take the same nine), classes in lexicographic order of their relation lists (neighbouring
+  // classes share most relations), box order within a class. A tile then holds
+  // few relations whose slots are mostly empty: each segment costs the same whatever its
+  // occupancy.
+  auto by_signature = [&](const std::vector<std::vector<std::pair<int32_t, int32_t>>>& lists) {
+    std::map<std::vector<int32_t>, int32_t> cls;  // signature -> rank in lexicographic order
+    std::vector<std::vector<int32_t>> sigs(size_t(P.n_leaves));
+    for (int32_t a : leaf_order) {
+      for (auto& e : lists[size_t(a)]) sigs[size_t(a)].push_back(e.first);
+      std::sort(sigs[size_t(a)].begin(), sigs[size_t(a)].end());
+      cls.emplace(sigs[size_t(a)], 0);
+    }
+    int32_t rank = 0;
+    for (auto& kv : cls) kv.second = rank++;
+    std::vector<int32_t> c(size_t(P.n_leaves));
+    for (int32_t a : leaf_order) c[size_t(a)] = cls[sigs[size_t(a)]];
+    std::vector<int32_t> o(leaf_order);
+    std::stable_sort(o.begin(), o.end(), [&](int32_t x, int32_t y) { return c[size_t(x)] < c[size_t(y)]; });
+    return o;
+  };
+  const std::vector<int32_t> near_order = by_signature(Ulist), anear_order = by_signature(Uinv);
   // with overlap the leaf stages' targets are cut in two halves (at a tile boundary): the near
   // field then runs as two launches, each beside one far-field chain
   std::vector<std::pair<size_t, size_t>> halves;
@@ -643,7 +701,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     halves = {{0, leaf_order.size()}};
   }
   for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
-    const std::vector<int32_t> part(leaf_order.begin() + long(halves[h].first), leaf_order.begin() + long(halves[h].second));
+    const std::vector<int32_t> part(near_order.begin() + long(halves[h].first), near_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
     st.fam[0] = {A_INS, kNP, 0};
     std::vector<std::vector<Entry>> E(part.size());
@@ -753,7 +811,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     P.adj.push_back(std::move(st));
   }
   for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
-    const std::vector<int32_t> part(leaf_order.begin() + long(halves[h].first), leaf_order.begin() + long(halves[h].second));
+    const std::vector<int32_t> part(anear_order.begin() + long(halves[h].first), anear_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
     st.out_scaled = 1;
     st.fam[0] = {A_IN, kNP, 0};
