@@ -120,6 +120,7 @@ struct volpot_plan_s {
   DeviceTables* tables = nullptr;
   char* d_block = nullptr;
   double *d_mp = nullptr, *d_loc = nullptr, *d_lb = nullptr, *d_ab = nullptr, *d_usum = nullptr, *d_leaf_s2 = nullptr;
+  double *d_far = nullptr, *d_afar = nullptr;  // far-field parts before the downward chains
   double* d_fs = nullptr;  // prescaled input s^2 f
   double* d_part[2] = {nullptr, nullptr};  // partial sums of split tiles: helper-stream, caller-stream stages
   int split_min = 0;
@@ -178,8 +179,11 @@ int schedule_all(volpot_plan_s* p, int nominal) {
           it = resident.emplace(key, nominal > 0 ? nominal : grg_resident_blocks(s.M, s.NT, s.KC)).first;
         if (it->second <= 0) return VOLPOT_ERR_HIP;
         // a stage that runs beside the helper stream leaves `overlap` compute units' share free
+        // (helper-stream stages get that share only)
         int blocks = it->second;
-        if (s.concurrent && p->overlap > 0) blocks = std::max(1, blocks - (blocks / std::max(cus, 1)) * p->overlap);
+        const int per_cu = blocks / std::max(cus, 1);
+        if (p->overlap > 0 && s.concurrent) blocks = std::max(1, blocks - per_cu * p->overlap);
+        if (p->overlap > 0 && s.helper) blocks = std::max(1, std::min(blocks, per_cu * p->overlap));
         // default: a block gets at least one whole segment (K / KC chunks)
         build_schedule(s, blocks, p->split_min != 0 ? p->split_min : s.K / s.KC);
       }
@@ -222,6 +226,8 @@ int upload(volpot_plan_s* p) {
   size_t o_loc = (total + 255) & ~size_t(255); total = o_loc + nb;
   size_t o_lb = (total + 255) & ~size_t(255); total = o_lb + nb;
   size_t o_ab = (total + 255) & ~size_t(255); total = o_ab + nb;
+  size_t o_far = (total + 255) & ~size_t(255); total = o_far + nb;
+  size_t o_afar = (total + 255) & ~size_t(255); total = o_afar + nb;
   size_t o_us = (total + 255) & ~size_t(255); total = o_us + size_t(P.n_leaves) * sizeof(double);
   size_t o_fs = (total + 255) & ~size_t(255); total = o_fs + size_t(P.n_leaves) * kNP * sizeof(double);
   std::vector<double> s2(P.leaf_s2);
@@ -262,6 +268,8 @@ int upload(volpot_plan_s* p) {
   p->d_loc = reinterpret_cast<double*>(b + o_loc);
   p->d_lb = reinterpret_cast<double*>(b + o_lb);
   p->d_ab = reinterpret_cast<double*>(b + o_ab);
+  p->d_far = reinterpret_cast<double*>(b + o_far);
+  p->d_afar = reinterpret_cast<double*>(b + o_afar);
   p->d_usum = reinterpret_cast<double*>(b + o_us);
   p->d_fs = reinterpret_cast<double*>(b + o_fs);
   p->d_leaf_s2 = reinterpret_cast<double*>(b + o_s2);
@@ -294,6 +302,8 @@ const double* arr_ptr(volpot_plan_s* p, int8_t a, const double* in, double* out)
     case A_LB: return p->d_lb;
     case A_AB: return p->d_ab;
     case A_USUM: return p->d_usum;
+    case A_FAR: return p->d_far;
+    case A_AFAR: return p->d_afar;
     default: return nullptr;
   }
 }
@@ -381,6 +391,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     g.out_scaled = s.out_scaled;
     g.r1_all_rows = s.r1_all_rows;
     g.accumulate = s.accumulate;
+    g.acc_src = s.acc_arr == A_NONE ? nullptr : arr_ptr(p, s.acc_arr, in, out);
     g.pieces = d.pieces; g.blk_ptr = d.blk_ptr; g.tile_count = d.tile_count;
     g.partial = p->d_part[s.helper ? 0 : 1];  // helper-marked stages never share a buffer with the others
     g.n_blocks = s.n_blocks;

@@ -43,7 +43,8 @@ struct GrgParams {
   int32_t out_stride;
   int32_t out_scaled;           // 1: multiply the output of target t by leaf_s2[t]
   int32_t r1_all_rows;          // 1: rank-one term on every row, else on row 0 only
-  int32_t accumulate;           // 1: add to the existing output, else overwrite
+  int32_t accumulate;           // 1: add to the existing output (or to acc_src), else overwrite
+  const double* acc_src;        // with accumulate: add this array's values (output layout) instead of the output's
   const PieceDesc* pieces;      // balanced schedule: block b runs pieces [blk_ptr[b], blk_ptr[b+1])
   const int32_t* blk_ptr;       // n_blocks + 1
   int32_t* tile_count;          // n_tiles arrival counters of split tiles, zero between launches

@@ -210,10 +210,11 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 #pragma unroll
       for (int r = 0; r < 4; ++r) prev[i][r] = 0.0;
     if (p.accumulate) {
+      const double* __restrict__ a = (p.acc_src ? p.acc_src : p.out) + (size_t)tgt * p.out_stride;
 #pragma unroll
       for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) prev[i][r] = o[(wm * MT + i) * 16 + 4 * r + (lane >> 4)];
+        for (int r = 0; r < 4; ++r) prev[i][r] = a[(wm * MT + i) * 16 + 4 * r + (lane >> 4)];
     }
 #pragma unroll
     for (int i = 0; i < MT; ++i)
@@ -232,8 +233,14 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 // then counts itself in on the tile's counter; the block that arrives last adds the partials
 // in piece order (so the result does not depend on arrival order), writes the output and
 // re-arms the counter. No block ever waits for another.
+// The near-field instantiation (256 rows, 32 slots, 4 waves) is held to two blocks per compute
+// unit (256 registers per lane): the other block works while this one waits at a barrier or
+// for memory. The other instantiations keep the compiler's own register choice.
 template <int MT, int NTT, int WM, int WN, int KC>
-__global__ void __launch_bounds__(64 * WM * WN) grg_kernel(const GrgParams p) {
+constexpr int min_blocks() { return (MT == 4 && NTT == 2 && WM == 4 && WN == 1 && KC == 32) ? 2 : 1; }
+
+template <int MT, int NTT, int WM, int WN, int KC>
+__global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>())) grg_kernel(const GrgParams p) {
   constexpr int M = 16 * MT * WM;
   constexpr int NT = 16 * NTT * WN;
   constexpr int NTHR = 64 * WM * WN;

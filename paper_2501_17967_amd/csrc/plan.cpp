@@ -191,7 +191,7 @@ static void make_tiles(Stage& st, const std::vector<int32_t>& targets, const std
   std::vector<std::vector<int32_t>> sigs(n);
   std::map<std::vector<int32_t>, int32_t> cls;
   for (size_t i = 0; i < n; ++i) {
-    for (const Entry& e : entries[i]) sigs[i].push_back(e.rel);
+    for (const Entry& e : entries[i]) sigs[i].push_back(e.rel * 16 + e.fam);
     std::sort(sigs[i].begin(), sigs[i].end());
     cls.emplace(sigs[i], 0);
   }
@@ -222,43 +222,48 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
   st.seg_rel.clear(); st.seg_fam.clear(); st.seg_src.clear();
   st.r1_idx.clear(); st.r1_fam.clear(); st.r1_coef.clear();
   st.flops = 0; st.n_pairs = 0; st.flops_issued = 0;
+  std::vector<int32_t> seg_of(size_t(kNumRel) * 16, -1), used;
   for (int t = 0; t < st.n_tiles; ++t) {
-    std::map<int32_t, size_t> segs;  // rel -> segment index (ordered by rel id)
-    std::map<int32_t, int8_t> segfam;
+    // segments keyed by (relation, source family), ordered by relation then family
+    used.clear();
     for (int s = 0; s < NT; ++s) {
       size_t ti = size_t(t) * NT + s;
       if (ti >= targets.size()) break;
       st.tile_tgt[ti] = targets[ti];
       for (const Entry& e : entries[ti]) {
         // the kernel reads M x K of the relation's table and K values of each source
+        if (e.rel < 0 || e.rel >= kNumRel || e.fam < 0 || e.fam >= 4) throw std::runtime_error("bad entry");
         if (mats.M[e.rel] != st.M) throw std::runtime_error("relation rows differ from stage rows");
         if (st.fam[e.fam].stride < mats.K[e.rel]) throw std::runtime_error("source shorter than relation");
         // the kernel walks K in full chunks of KC
         if (mats.K[e.rel] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
-        segs.emplace(e.rel, 0);
-        segfam[e.rel] = e.fam;
+        const int32_t key = e.rel * 16 + e.fam;
+        if (seg_of[size_t(key)] < 0) {
+          seg_of[size_t(key)] = 0;
+          used.push_back(key);
+        }
       }
     }
-    size_t base = st.seg_rel.size();
-    size_t n = 0;
-    for (auto& kv : segs) {
-      kv.second = base + n++;
-      st.seg_rel.push_back(kv.first);
-      st.seg_fam.push_back(segfam[kv.first]);
-      st.flops_issued += 2.0 * st.M * mats.K[kv.first] * NT;
+    std::sort(used.begin(), used.end());
+    for (int32_t key : used) {
+      seg_of[size_t(key)] = int32_t(st.seg_rel.size());
+      st.seg_rel.push_back(key / 16);
+      st.seg_fam.push_back(int8_t(key % 16));
+      st.flops_issued += 2.0 * st.M * mats.K[key / 16] * NT;
     }
     st.seg_src.resize(st.seg_rel.size() * NT, -1);
     for (int s = 0; s < NT; ++s) {
       size_t ti = size_t(t) * NT + s;
       if (ti >= targets.size()) break;
       for (const Entry& e : entries[ti]) {
-        int32_t& slot = st.seg_src[segs[e.rel] * NT + s];
+        int32_t& slot = st.seg_src[size_t(seg_of[size_t(e.rel * 16 + e.fam)]) * NT + s];
         if (slot != -1) throw std::runtime_error("duplicate relation for one target");
         slot = e.src;
         st.flops += 2.0 * mats.nnz[e.rel];
         st.n_pairs += 1;
       }
     }
+    for (int32_t key : used) seg_of[size_t(key)] = -1;
     st.tile_seg_ptr[t + 1] = int32_t(st.seg_rel.size());
   }
   for (size_t ti = 0; ti < st.tile_tgt.size(); ++ti) {
@@ -612,22 +617,96 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     make_tiles(st, tg, E, R, mats);
     P.fwd.push_back(std::move(st));
   }
-  for (int l = P.max_level - 1; l >= 2; --l) {  // M2M chain, upward
-    std::vector<int32_t> tg;
-    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
-    if (tg.empty()) continue;
-    Stage st; init_stage(st, K_UP, lvl("M2M", l), l, kNE, kNE, NTB, A_MP, kNE);
-    st.fam[0] = {A_MP, kNE, 0};
-    std::vector<std::vector<Entry>> E(tg.size());
-    std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i)
-      for (int q = 0; q < 4; ++q) { E[i].push_back({kRelM2M + q, 0, P.box_child[tg[i]][q]}); P.n_m2m++; }
-    make_tiles(st, tg, E, R, mats);
-    P.fwd.push_back(std::move(st));
-  }
+  // Upward chain, two levels per launch: boxes of level l from their children (level l + 1,
+  // complete), boxes of level l - 1 from their leaf children (level l) and, through the
+  // composite M2M_qc M2M_qg, from their grandchildren (level l + 1): the launch reads nothing
+  // it writes.
+  auto up_pairs = [&](bool adj) {
+    const int rel1 = adj ? kRelL2L + kNumFwd : kRelM2M, rel2 = adj ? kRelL2L2 + kNumFwd : kRelM2M2;
+    const int8_t arr = adj ? A_LB : A_MP;
+    for (int l = P.max_level - 1; l >= 2; l -= 2) {
+      std::vector<int32_t> tg;
+      std::vector<std::vector<Entry>> E;
+      for (int32_t b : boxes_at[l]) {
+        if (P.box_leaf[b] >= 0) continue;
+        tg.push_back(b);
+        E.emplace_back();
+        for (int q = 0; q < 4; ++q) { E.back().push_back({rel1 + q, 0, P.box_child[b][q]}); P.n_m2m += !adj; }
+      }
+      if (l - 1 >= 2)
+        for (int32_t a : boxes_at[l - 1]) {
+          if (P.box_leaf[a] >= 0) continue;
+          tg.push_back(a);
+          E.emplace_back();
+          for (int qc = 0; qc < 4; ++qc) {
+            const int32_t c = P.box_child[a][qc];
+            if (P.box_leaf[c] >= 0) { E.back().push_back({rel1 + qc, 0, c}); P.n_m2m += !adj; continue; }
+            for (int qg = 0; qg < 4; ++qg) { E.back().push_back({rel2 + 4 * qc + qg, 0, P.box_child[c][qg]}); P.n_m2m += !adj; }
+          }
+        }
+      if (tg.empty()) continue;
+      std::string name = std::string(adj ? "AL2L[" : "M2M[") + std::to_string(l) +
+                         (l - 1 >= 2 ? "," + std::to_string(l - 1) : std::string()) + "]";
+      Stage st; init_stage(st, adj ? K_AUP : K_UP, name, l, kNE, kNE, NTB, arr, kNE);
+      st.fam[0] = {arr, kNE, 0};
+      std::vector<std::vector<R1>> R(tg.size());
+      make_tiles(st, tg, E, R, mats);
+      (adj ? P.adj : P.fwd).push_back(std::move(st));
+    }
+  };
+  // Downward chain, two levels per launch, out-of-place: total = far part (acc_arr) + the
+  // parent's translated total. Boxes of level l take L2L_qc of their parent's total (level
+  // l - 1, complete; at level 2 the total is the far part); boxes of level l + 1 take L2L_qg of
+  // their parent's far part plus the composite L2L_qg L2L_qc of their grandparent's total. The
+  // first launch also copies the far part of leaves at level <= copy_level (their total).
+  auto down_pairs = [&](bool adj) {
+    const int rel1 = adj ? kRelM2M + kNumFwd : kRelL2L, rel2 = adj ? kRelM2M2 + kNumFwd : kRelL2L2;
+    const int8_t tot = adj ? A_AB : A_LOC, farp = adj ? A_AFAR : A_FAR;
+    const int copy_level = adj ? 2 : 2;
+    auto parent_fam = [&](int level) -> int8_t { return level <= 2 ? 1 : 0; };  // fam 0 totals, 1 far parts
+    bool first = true;
+    for (int l = 3;; l += 2) {
+      std::vector<int32_t> tg;
+      std::vector<std::vector<Entry>> E;
+      if (first)
+        for (int lc = adj ? 0 : 2; lc <= std::min(copy_level, P.max_level); ++lc)
+          for (int32_t b : boxes_at[lc])
+            if (P.box_leaf[b] >= 0) { tg.push_back(b); E.emplace_back(); }
+      if (l <= P.max_level)
+        for (int32_t c : boxes_at[l]) {
+          tg.push_back(c);
+          E.emplace_back();
+          E.back().push_back({rel1 + quadrant(c), parent_fam(l - 1), P.box_parent[c]});
+          P.n_l2l += !adj;
+        }
+      if (l + 1 <= P.max_level)
+        for (int32_t g : boxes_at[l + 1]) {
+          const int32_t c = P.box_parent[g];
+          tg.push_back(g);
+          E.emplace_back();
+          E.back().push_back({rel1 + quadrant(g), 1, c});
+          E.back().push_back({rel2 + 4 * quadrant(c) + quadrant(g), parent_fam(l - 1), P.box_parent[c]});
+          P.n_l2l += !adj;
+        }
+      first = false;
+      if (!tg.empty()) {
+        std::string name = std::string(adj ? "AM2M[" : "L2L[") + std::to_string(l) +
+                           (l + 1 <= P.max_level ? "," + std::to_string(l + 1) : std::string()) + "]";
+        Stage st; init_stage(st, adj ? K_ADOWN : K_DOWN, name, l, kNE, kNE, NTB, tot, kNE);
+        st.accumulate = 1;
+        st.acc_arr = farp;
+        st.fam[0] = {tot, kNE, 0}; st.fam[1] = {farp, kNE, 0};
+        std::vector<std::vector<R1>> R(tg.size());
+        make_tiles(st, tg, E, R, mats);
+        (adj ? P.adj : P.fwd).push_back(std::move(st));
+      }
+      if (l + 1 >= P.max_level) break;
+    }
+  };
+  up_pairs(false);
   if (!deep_by_quadrant.empty()) {  // FARV: M2L for every box of every level >= 2, plus all log terms
     const auto& tg = deep_by_quadrant;
-    Stage st; init_stage(st, K_DOWN, "FARV", -1, kNE, kNE, NTB, A_LOC, kNE);
+    Stage st; init_stage(st, K_DOWN, "FARV", -1, kNE, kNE, NTB, A_FAR, kNE);
     st.fam[0] = {A_MP, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -645,7 +724,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg;
     for (int32_t b : deep_by_quadrant) if (!Xlist[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
-      Stage st; init_stage(st, K_DOWN, "FARX", -1, kNE, kNP, NTB, A_LOC, kNE);
+      Stage st; init_stage(st, K_DOWN, "FARX", -1, kNE, kNP, NTB, A_FAR, kNE);
         st.accumulate = 1;
       st.fam[0] = {A_INS, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
@@ -656,18 +735,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       P.fwd.push_back(std::move(st));
     }
   }
-  for (int l = 3; l <= P.max_level; ++l) {  // L2L chain, downward, added onto FAR's locals
-    std::vector<int32_t> tg = boxes_at[l];
-    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
-    Stage st; init_stage(st, K_DOWN, lvl("L2L", l), l, kNE, kNE, NTB, A_LOC, kNE);
-    st.accumulate = 1;
-    st.fam[0] = {A_LOC, kNE, 0};
-    std::vector<std::vector<Entry>> E(tg.size());
-    std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i) { E[i].push_back({kRelL2L + quadrant(tg[i]), 0, P.box_parent[tg[i]]}); P.n_l2l++; }
-    make_tiles(st, tg, E, R, mats);
-    P.fwd.push_back(std::move(st));
-  }
+  down_pairs(false);
   // Near-field targets grouped by the set of relations they take (in an adaptive tree, leaves at
   // a refinement boundary take fine or coarse neighbours in many patterns; interior leaves all
   // take the same nine), classes in lexicographic order of their relation lists (neighbouring
@@ -744,19 +812,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       P.adj.push_back(std::move(st));
     }
   }
-  for (int l = P.max_level - 1; l >= 2; --l) {  // AL2L chain, upward (transpose of L2L)
-    std::vector<int32_t> tg;
-    for (int32_t b : boxes_at[l]) if (P.box_leaf[b] < 0) tg.push_back(b);
-    if (tg.empty()) continue;
-    Stage st; init_stage(st, K_AUP, lvl("AL2L", l), l, kNE, kNE, NTB, A_LB, kNE);
-    st.fam[0] = {A_LB, kNE, 0};
-    std::vector<std::vector<Entry>> E(tg.size());
-    std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i)
-      for (int q = 0; q < 4; ++q) E[i].push_back({kRelL2L + q + kNumFwd, 0, P.box_child[tg[i]][q]});
-    make_tiles(st, tg, E, R, mats);
-    P.adj.push_back(std::move(st));
-  }
+  up_pairs(true);
   // abar is needed for every box whose multipole is used: all leaves and boxes of level >= 2
   std::vector<int32_t> afar_tg;
   for (int l = 0; l < 2 && l <= P.max_level; ++l)
@@ -764,7 +820,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   afar_tg.insert(afar_tg.end(), deep_by_quadrant.begin(), deep_by_quadrant.end());
   {  // AFARV: M2L^T plus every log term
     const auto& tg = afar_tg;
-    Stage st; init_stage(st, K_ADOWN, "AFARV", -1, kNE, kNE, NTB, A_AB, kNE);
+    Stage st; init_stage(st, K_ADOWN, "AFARV", -1, kNE, kNE, NTB, A_AFAR, kNE);
     st.fam[0] = {A_LB, kNE, 0};
     st.r1fam[0] = {A_LB, kNE, 0}; st.r1fam[1] = {A_USUM, 1, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -787,7 +843,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg;
     for (int32_t b : afar_tg) if (!Winv[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
-      Stage st; init_stage(st, K_ADOWN, "AFARW", -1, kNE, kNP, NTB, A_AB, kNE);
+      Stage st; init_stage(st, K_ADOWN, "AFARW", -1, kNE, kNP, NTB, A_AFAR, kNE);
         st.accumulate = 1;
       st.fam[0] = {A_IN, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
@@ -798,18 +854,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       P.adj.push_back(std::move(st));
     }
   }
-  for (int l = 3; l <= P.max_level; ++l) {  // AM2M chain, downward (transpose of M2M)
-    std::vector<int32_t> tg = boxes_at[l];
-    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return quadrant(x) < quadrant(y); });
-    Stage st; init_stage(st, K_ADOWN, lvl("AM2M", l), l, kNE, kNE, NTB, A_AB, kNE);
-    st.accumulate = 1;
-    st.fam[0] = {A_AB, kNE, 0};
-    std::vector<std::vector<Entry>> E(tg.size());
-    std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i) E[i].push_back({kRelM2M + quadrant(tg[i]) + kNumFwd, 0, P.box_parent[tg[i]]});
-    make_tiles(st, tg, E, R, mats);
-    P.adj.push_back(std::move(st));
-  }
+  down_pairs(true);
   for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
     const std::vector<int32_t> part(anear_order.begin() + long(halves[h].first), anear_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);

@@ -54,7 +54,9 @@ constexpr int kRelS2L = 49;   // +20 offsets
 constexpr int kRelNear = 69;  // +33 relations
 constexpr int kRelM2T = 102;  // +20 offsets
 constexpr int kRelL2T = 122;
-constexpr int kNumFwd = 123;
+constexpr int kRelM2M2 = 123; // +4 qc + qg: M2M_qc M2M_qg, grandchild (quadrant qg of child qc) to box
+constexpr int kRelL2L2 = 139; // +4 qc + qg: L2L_qg L2L_qc, box to grandchild
+constexpr int kNumFwd = 155;
 constexpr int kNumRel = 2 * kNumFwd;
 
 struct Offset { double dx, dy, rho; };
@@ -76,7 +78,9 @@ void set_table_cache_dir(const char* dir);
 
 // ---------------------------------------------------------------- plan
 // A_INS: the input with each leaf scaled by its s^2 (forward only; written by a prescale pass)
-enum Arr : int8_t { A_IN = 0, A_INS, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_NONE };
+// A_FAR / A_AFAR: the far-field parts (M2L + S2L, and their transposes) before the downward
+// chains add the parents' contributions into A_LOC / A_AB
+enum Arr : int8_t { A_IN = 0, A_INS, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_FAR, A_AFAR, A_NONE };
 // timing / accounting kinds: 0 upward (S2M, M2M), 1 downward (FARV/X, L2L), 2 NEAR, 3 LOCT,
 // 4 adjoint upward (AL2T, AL2L), 5 adjoint downward (AFARV/W, AM2M), 6 ANEAR, 7 ALOCT,
 // 8 adjoint row sums
@@ -111,6 +115,7 @@ struct Stage {
   int8_t out_scaled = 0;   // multiply output by s^2 of the target leaf
   int8_t r1_all_rows = 0;  // rank-one term added to all rows (else row 0 only)
   int8_t accumulate = 0;   // add to the output (else overwrite)
+  int8_t acc_arr = A_NONE; // with accumulate: add the values of this array (same layout) instead of the output's
   int8_t helper = 0;       // runs on the helper stream (far-field chain)
   int8_t join_before = 0;  // waits for the helper stream's work before launching
   int8_t fork_before = 0;  // the helper stream waits for the caller's stream before this stage

@@ -468,6 +468,25 @@ static Matrices build_matrices() {
     set(kRelM2M + q, kNE, kNE, std::move(R1));
     set(kRelL2L + q, kNE, kNE, std::move(R2));
   }
+  // two-level translations: M2M_qc M2M_qg (grandchild to box) and L2L_qg L2L_qc (box to grandchild)
+  for (int qc = 0; qc < 4; ++qc)
+    for (int qg = 0; qg < 4; ++qg) {
+      std::vector<double> Pm(size_t(kNE) * kNE, 0.0), Pl(size_t(kNE) * kNE, 0.0);
+      const std::vector<double>& Mc = M.a[kRelM2M + qc];
+      const std::vector<double>& Mg = M.a[kRelM2M + qg];
+      const std::vector<double>& Lc = M.a[kRelL2L + qc];
+      const std::vector<double>& Lg = M.a[kRelL2L + qg];
+      for (int i = 0; i < kNE; ++i)
+        for (int k = 0; k < kNE; ++k) {
+          const double mc = Mc[size_t(i) * kNE + k], lg = Lg[size_t(i) * kNE + k];
+          for (int j = 0; j < kNE; ++j) {
+            Pm[size_t(i) * kNE + j] += mc * Mg[size_t(k) * kNE + j];
+            Pl[size_t(i) * kNE + j] += lg * Lc[size_t(k) * kNE + j];
+          }
+        }
+      set(kRelM2M2 + 4 * qc + qg, kNE, kNE, std::move(Pm));
+      set(kRelL2L2 + 4 * qc + qg, kNE, kNE, std::move(Pl));
+    }
   // M2L_r: d = (source - target centre) / s
   const auto& VO = v_offsets();
   for (size_t r = 0; r < VO.size(); ++r) {
