@@ -281,7 +281,7 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
 // Launch order and stream flags. Built order: [S2M] [M2M chain] [FARV] [FARX] [L2L chain]
 // [NEAR or NEAR_A NEAR_B] [LOCT] (adjoint: [AL2T] [AL2L chain] [AFARV] [AFARW] [AM2M chain]
 // [ANEAR...] [ALOCT]). Launch order:
-//   S2M, M2M chain (helper), NEAR_A, FARV (join), FARX, L2L chain (helper), NEAR_B, LOCT (join)
+//   S2M, M2M chain (helper), NEAR_A, FARV (join), FARX + L2L chain (helper), NEAR_B, LOCT (join)
 // so that, with the overlap option, each latency-bound chain runs beside half of the near
 // field, which does not depend on the far field. Without overlap everything runs in this
 // order on one stream, which is also a valid order.
@@ -316,11 +316,19 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   for (Stage& s : head) v.push_back(std::move(s));
   chain(up_chain);
   put_near(0);
+  // M2L (FARV / AFARV) on the caller's stream; the small S2L / M2T^T stage (FARX / AFARW),
+  // which only the downward chain reads, opens that chain on the helper stream
+  std::vector<Stage> down;
   for (size_t i = 0; i < far.size(); ++i) {
-    far[i].join_before = i == 0;
-    v.push_back(std::move(far[i]));
+    if (i == 0) {
+      far[i].join_before = 1;
+      v.push_back(std::move(far[i]));
+    } else {
+      down.push_back(std::move(far[i]));
+    }
   }
-  chain(down_chain);
+  for (Stage& s : down_chain) down.push_back(std::move(s));
+  chain(down);
   put_near(1);
   for (size_t i = 0; i < tail.size(); ++i) {
     tail[i].join_before = i == 0;

@@ -181,10 +181,12 @@ def test_overlap_launch_order(vp):
             names = [s["name"] for s in plan.stages(adj)]
             helper = [s["name"] for s in plan.stages(adj) if s["helper"]]
             assert names[0] == head and names[-1] == tail
-            assert helper == [n for n in names if n.startswith(up + "[") or n.startswith(down + "[")]
+            assert helper == [n for n in names if n.startswith(up + "[") or n.startswith(down + "[") or n == far[1]]
             i_far = names.index(far[0])
             assert all(names.index(n) < i_far for n in names if n.startswith(up + "["))
+            # the small far stage (S2L / M2T^T) opens the downward chain
             assert all(names.index(n) > names.index(far[-1]) for n in names if n.startswith(down + "["))
+            assert names.index(far[-1]) == names.index(far[0]) + 1
             nears = [n for n in names if n.startswith(near)]
             if overlap:
                 assert nears == [near + "_A", near + "_B"]
