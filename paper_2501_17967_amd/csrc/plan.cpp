@@ -9,10 +9,13 @@
 // 2:1 balance over edges and corners (Sec. 4.2.1) bounds adjacent levels to l-1..l+1, which
 // is what makes the 33 near relations and the 20 W / X offsets exhaustive.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <stdexcept>
+#include <thread>
 
 #include "../../include/volpot.h"
 #include "plan.hpp"
@@ -613,6 +616,21 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     deep_by_quadrant.insert(deep_by_quadrant.end(), tg.begin(), tg.end());
   }
 
+  // Tiling (make_tiles) is the costly part of a stage; the stages are tiled concurrently once
+  // all have been described, and kept in the order they were described.
+  struct Job {
+    Stage st;
+    std::vector<int32_t> tg;
+    std::vector<std::vector<Entry>> E;
+    std::vector<std::vector<R1>> R;
+    bool adj;
+  };
+  std::vector<Job> jobs;
+  auto defer = [&](Stage&& st, const std::vector<int32_t>& tg, std::vector<std::vector<Entry>>&& E,
+                   std::vector<std::vector<R1>>&& R, bool adj) {
+    jobs.push_back(Job{std::move(st), tg, std::move(E), std::move(R), adj});
+  };
+
   // ================================================================ forward
   {  // S2M: every leaf's multipole
     std::vector<int32_t> tg;
@@ -622,8 +640,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
     for (size_t i = 0; i < tg.size(); ++i) { E[i].push_back({kRelS2M, 0, P.box_leaf[tg[i]]}); P.n_s2m++; }
-    make_tiles(st, tg, E, R, mats);
-    P.fwd.push_back(std::move(st));
+    defer(std::move(st), tg, std::move(E), std::move(R), false);
   }
   // Upward chain, two levels per launch: boxes of level l from their children (level l + 1,
   // complete), boxes of level l - 1 from their leaf children (level l) and, through the
@@ -658,8 +675,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       Stage st; init_stage(st, adj ? K_AUP : K_UP, name, l, kNE, kNE, NTB, arr, kNE);
       st.fam[0] = {arr, kNE, 0};
       std::vector<std::vector<R1>> R(tg.size());
-      make_tiles(st, tg, E, R, mats);
-      (adj ? P.adj : P.fwd).push_back(std::move(st));
+      defer(std::move(st), tg, std::move(E), std::move(R), adj);
     }
   };
   // Downward chain, two levels per launch, out-of-place: total = far part (acc_arr) + the
@@ -705,8 +721,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         st.acc_arr = farp;
         st.fam[0] = {tot, kNE, 0}; st.fam[1] = {farp, kNE, 0};
         std::vector<std::vector<R1>> R(tg.size());
-        make_tiles(st, tg, E, R, mats);
-        (adj ? P.adj : P.fwd).push_back(std::move(st));
+        defer(std::move(st), tg, std::move(E), std::move(R), adj);
       }
       if (l + 1 >= P.max_level) break;
     }
@@ -725,8 +740,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (auto& e : Vlist[b]) { E[i].push_back({kRelM2L + e.first, 0, e.second}); R[i].push_back({0, e.second, ls}); }
       for (auto& e : Xlist[b]) R[i].push_back({0, P.leaf_box[e.second], ls});
     }
-    make_tiles(st, tg, E, R, mats);
-    P.fwd.push_back(std::move(st));
+    defer(std::move(st), tg, std::move(E), std::move(R), false);
   }
   {  // FARX: S2L, added onto FARV for the boxes that have an X list
     std::vector<int32_t> tg;
@@ -739,8 +753,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       std::vector<std::vector<R1>> R(tg.size());
       for (size_t i = 0; i < tg.size(); ++i)
         for (auto& e : Xlist[tg[i]]) E[i].push_back({kRelS2L + e.first, 0, e.second});
-      make_tiles(st, tg, E, R, mats);
-      P.fwd.push_back(std::move(st));
+      defer(std::move(st), tg, std::move(E), std::move(R), false);
     }
   }
   down_pairs(false);
@@ -784,8 +797,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<std::vector<R1>> R(part.size());
     for (size_t i = 0; i < part.size(); ++i)
       for (auto& e : Ulist[part[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
-    make_tiles(st, part, E, R, mats);
-    P.fwd.push_back(std::move(st));
+    defer(std::move(st), part, std::move(E), std::move(R), false);
   }
   {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
     Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
@@ -802,8 +814,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (auto& e : Wlist[a]) { E[i].push_back({kRelM2T + e.first, 0, e.second}); R[i].push_back({0, e.second, kap}); }
       if (levels[a] >= 2) { E[i].push_back({kRelL2T, 1, P.leaf_box[a]}); P.n_l2t++; }
     }
-    make_tiles(st, leaf_order, E, R, mats);
-    P.fwd.push_back(std::move(st));
+    defer(std::move(st), leaf_order, std::move(E), std::move(R), false);
   }
 
   // ================================================================ adjoint
@@ -816,8 +827,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
       for (size_t i = 0; i < tg.size(); ++i) E[i].push_back({kRelL2T + kNumFwd, 0, P.box_leaf[tg[i]]});
-      make_tiles(st, tg, E, R, mats);
-      P.adj.push_back(std::move(st));
+      defer(std::move(st), tg, std::move(E), std::move(R), true);
     }
   }
   up_pairs(true);
@@ -844,8 +854,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         for (auto& e : Xinv[leaf]) R[i].push_back({0, e.second, lnS(P.box_level[e.second])});
       }
     }
-    make_tiles(st, tg, E, R, mats);
-    P.adj.push_back(std::move(st));
+    defer(std::move(st), tg, std::move(E), std::move(R), true);
   }
   {  // AFARW: M2T^T, added onto AFARV for the boxes that have a W^-1 list
     std::vector<int32_t> tg;
@@ -858,8 +867,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       std::vector<std::vector<R1>> R(tg.size());
       for (size_t i = 0; i < tg.size(); ++i)
         for (auto& e : Winv[tg[i]]) E[i].push_back({kRelM2T + e.first + kNumFwd, 0, e.second});
-      make_tiles(st, tg, E, R, mats);
-      P.adj.push_back(std::move(st));
+      defer(std::move(st), tg, std::move(E), std::move(R), true);
     }
   }
   down_pairs(true);
@@ -872,8 +880,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<std::vector<R1>> R(part.size());
     for (size_t i = 0; i < part.size(); ++i)
       for (auto& e : Uinv[part[i]]) E[i].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
-    make_tiles(st, part, E, R, mats);
-    P.adj.push_back(std::move(st));
+    defer(std::move(st), part, std::move(E), std::move(R), true);
   }
   {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
     Stage st; init_stage(st, K_ALOCT, "ALOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
@@ -887,8 +894,31 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       E[i].push_back({kRelS2M + kNumFwd, 0, P.leaf_box[b]});
       for (auto& e : Xinv[b]) E[i].push_back({kRelS2L + e.first + kNumFwd, 1, e.second});
     }
-    make_tiles(st, leaf_order, E, R, mats);
-    P.adj.push_back(std::move(st));
+    defer(std::move(st), leaf_order, std::move(E), std::move(R), true);
+  }
+  {
+    std::vector<std::exception_ptr> err(jobs.size());
+    std::atomic<size_t> next(0);
+    auto work = [&]() {
+      for (size_t j; (j = next.fetch_add(1)) < jobs.size();) {
+        try {
+          make_tiles(jobs[j].st, jobs[j].tg, jobs[j].E, jobs[j].R, mats);
+        } catch (...) {
+          err[j] = std::current_exception();
+        }
+        // the descriptions are not needed once tiled
+        std::vector<std::vector<Entry>>().swap(jobs[j].E);
+        std::vector<std::vector<R1>>().swap(jobs[j].R);
+      }
+    };
+    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned i = 1; i < nt; ++i) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+    for (auto& e : err)
+      if (e) std::rethrow_exception(e);
+    for (Job& j : jobs) (j.adj ? P.adj : P.fwd).push_back(std::move(j.st));
   }
   arrange_stages(P.fwd, false);
   arrange_stages(P.adj, true);
