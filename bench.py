@@ -112,7 +112,7 @@ def main():
     if args.overlap is not None:
         shape["overlap"] = args.overlap
     print("bench: launch shape %s (autotuner %.1fs)" % (shape, t_tune), file=sys.stderr, flush=True)
-    plan_shape = {"tile_leaf": 32, "tile_box": 64, "split_min": 0, "overlap": 0}
+    plan_shape = {"tile_leaf": 32, "tile_box": 32, "split_min": 0, "overlap": 0}
     plan_shape.update(shape)
     t0 = time.perf_counter()
     plan = Plan(w.centres, w.levels, **plan_shape)
@@ -274,7 +274,11 @@ def main():
         reps = max(3, args.steps // 2)
         tb_f = timed(lambda: forest.apply(F, out=Ub), reps)
         tb_a = timed(lambda: forest.apply_adjoint(F, out=Fb), reps)
-        singles = [Plan(t.centres, t.levels) for t in trees]
+        # sequential applies: one plan per tree, each with the shape the autotuner picks for
+        # the median-size tree (tuning all 256 separately would take minutes)
+        med = trees[int(np.argsort([t.n_leaves for t in trees])[len(trees) // 2])]
+        sshape, _ = autotune(med.centres, med.levels)
+        singles = [Plan(t.centres, t.levels, **sshape) for t in trees]
         views = [F[off[i]:off[i + 1]] for i in range(len(trees))]
         outs = [Ub[off[i]:off[i + 1]].clone() for i in range(len(trees))]
         outa = [o.clone() for o in outs]
@@ -300,7 +304,7 @@ def main():
                           "batched_fwd_adj_unknowns_per_s": Nb / (tb_f + tb_a),
                           "sequential_fwd_adj_unknowns_per_s": Nb / (ts_f + ts_a),
                           "speedup_fwd_adj": (ts_f + ts_a) / (tb_f + tb_a),
-                          "launch_shape": fshape, "autotune_s": t_ftune,
+                          "launch_shape": fshape, "autotune_s": t_ftune, "sequential_launch_shape": sshape,
                           "max_rel_diff_batched_vs_sequential": dev_max}
         for p_ in singles:
             p_.close()

@@ -64,7 +64,7 @@ typedef struct {
   int32_t tile_leaf;       /* slots per tile of the 256-row (leaf-output) stages: 32 or 64;
                               0 = default (32) */
   int32_t tile_box;        /* slots per tile of the 80-row (expansion) stages: 16, 32 or 64;
-                              0 = default (64) */
+                              0 = default (32) */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
   int32_t split_min;       /* each stage is cut into as many equal shares of its k-chunks as the
                               device runs blocks at once; a share has at least this many chunks

@@ -572,7 +572,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   // ---------------------------------------------------------------- stages
   const Matrices& mats = matrices();
   const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
-  const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 64;
+  const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 32;
   auto quadrant = [&](int32_t b) { return int(P.box_x[b] & 1) + 2 * int(P.box_y[b] & 1); };
   std::vector<std::vector<int32_t>> boxes_at(P.max_level + 1);
   for (int32_t b = 0; b < NB; ++b) boxes_at[P.box_level[b]].push_back(b);

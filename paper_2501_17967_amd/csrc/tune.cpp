@@ -142,7 +142,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     return r;
   };
   // coordinate descent over the three knobs, one at a time, from the defaults
-  Candidate cur{32, 64, 0, 0};
+  Candidate cur{32, 32, 0, 0};
   double best_t = 1e30;
   auto try_axis = [&](int axis, std::initializer_list<int32_t> values) {
     Candidate keep = cur;
@@ -173,13 +173,13 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     try_axis(2, {0, 1, -1});
     try_axis(3, {0, 16, 24, 32, 48});
   }
-  if (rc == VOLPOT_OK && !(cur.tile_leaf == 32 && cur.tile_box == 64 && cur.split_min == 0 && cur.overlap == 0)) {
+  if (rc == VOLPOT_OK && !(cur.tile_leaf == 32 && cur.tile_box == 32 && cur.split_min == 0 && cur.overlap == 0)) {
     // confirm against the defaults, timed again now, so that a noisy reading cannot win
     double t_best = 0, t_def = 0;
     rc = time_it(cur, &t_best);
-    if (rc == VOLPOT_OK) rc = time_it(Candidate{32, 64, 0, 0}, &t_def);
+    if (rc == VOLPOT_OK) rc = time_it(Candidate{32, 32, 0, 0}, &t_def);
     if (rc == VOLPOT_OK) {
-      if (t_def < t_best) cur = Candidate{32, 64, 0, 0};
+      if (t_def < t_best) cur = Candidate{32, 32, 0, 0};
       best_t = std::min(t_best, t_def);
     }
   }
