@@ -385,3 +385,24 @@ def test_overlapped_streams_match_single_stream(vp, torch_mod, overlap):
     plan.close()
     assert rel(u2, u1) <= 1e-14 and rel(f2, f1) <= 1e-14
     assert np.array_equal(u2, u3) and np.array_equal(f2, f3)
+
+
+def test_graph_replays_with_overlap_match_eager(vp, torch_mod):
+    # captured applies that fork to and join from the helper stream, replayed with other work
+    # in between, against eager applies of a single-stream plan
+    w = gen.config2(0)
+    _say("case graph replay with overlap")
+    f = _gpu(torch_mod, w.f)
+    eager = vp.Plan(w.centres, w.levels)
+    ref, refa = eager.apply(f).cpu().numpy(), eager.apply_adjoint(f).cpu().numpy()
+    graph = vp.Plan(w.centres, w.levels, use_graph=True, overlap=32)
+    out, outa = torch_mod.empty_like(f), torch_mod.empty_like(f)
+    for rep in range(3):
+        graph.apply(f, out=out)
+        graph.apply_adjoint(f, out=outa)
+        torch_mod.cuda.synchronize()
+        assert rel(out.cpu().numpy(), ref) <= 1e-14 and rel(outa.cpu().numpy(), refa) <= 1e-14
+        eager.apply(f)
+        torch_mod.cuda.synchronize()
+    eager.close()
+    graph.close()
