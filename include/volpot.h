@@ -61,8 +61,9 @@ typedef struct {
                               apply calls return VOLPOT_ERR_STATE). Default 0. */
   int32_t use_graph;       /* 1: capture each apply once per (input, output) pointer pair into
                               a hipGraph and replay it. Default 0. */
-  int32_t tile_leaf;       /* slots per tile of the 256-row (leaf-output) stages: 32 or 64;
-                              0 = default (32) */
+  int32_t tile_leaf;       /* slots per tile of the near-field stages (256 rows): 32 or 64;
+                              0 = default (32). The 256-row stages with K = 80 (L2T + M2T and
+                              S2M^T + S2L^T) always use 16-slot tiles. */
   int32_t tile_box;        /* slots per tile of the 80-row (expansion) stages: 16, 32 or 64;
                               0 = default (32) */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
@@ -162,8 +163,10 @@ int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* o
  * the launch shapes tile_box 16|32|64, tile_leaf 32|64, split_min 0|1|-1 and overlap 0|16|24|32|48
  * one knob at a time from the defaults (the other fields are taken from base, nullable),
  * building a plan for each candidate and timing one forward plus one adjoint apply on internal
- * device buffers after a warm-up (HIP events, private stream); writes the fastest options to
- * *best and their time in milliseconds to *best_ms (nullable). With cache_path (nullable) the result is looked up in, and appended to, that text file,
+ * device buffers after a warm-up (HIP events, private stream, best of 5); writes the fastest
+ * options to *best and their time in milliseconds to *best_ms (nullable). A candidate must beat
+ * the current choice by more than 1.5%, and the result must beat the defaults by as much when
+ * both are timed again, so that differences within timing noise keep the defaults. With cache_path (nullable) the result is looked up in, and appended to, that text file,
  * keyed by a signature of the trees' level histogram and sizes and of the device, so that a
  * shape is timed once. Allocates and synchronises; not for use inside a timed region.
  * Arguments as volpot_plan_forest (a single tree: n_trees = 1, offsets {0, n_leaves}). */

@@ -573,6 +573,10 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   const Matrices& mats = matrices();
   const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
   const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 32;
+  // The leaf stages with K = 80 (L2T, M2T and their transposes' counterparts S2M^T, S2L^T) do
+  // little work per tile and are bound by the latency of their few dependent k-chunks; 16-slot
+  // tiles give twice as many independent workgroups to hide it.
+  constexpr int kNTK80 = 16;
   auto quadrant = [&](int32_t b) { return int(P.box_x[b] & 1) + 2 * int(P.box_y[b] & 1); };
   std::vector<std::vector<int32_t>> boxes_at(P.max_level + 1);
   for (int32_t b = 0; b < NB; ++b) boxes_at[P.box_level[b]].push_back(b);
@@ -800,7 +804,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     defer(std::move(st), part, std::move(E), std::move(R), false);
   }
   {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
-    Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
+    Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
     st.accumulate = 1;
     st.r1_all_rows = 1;
     st.fam[0] = {A_MP, kNE, 0}; st.fam[1] = {A_LOC, kNE, 0};
@@ -883,7 +887,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     defer(std::move(st), part, std::move(E), std::move(R), true);
   }
   {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
-    Stage st; init_stage(st, K_ALOCT, "ALOCT", -1, kNP, kNE, NTL, A_OUT, kNP);
+    Stage st; init_stage(st, K_ALOCT, "ALOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
     st.accumulate = 1;
     st.out_scaled = 1;
     st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_LB, kNE, 0};
