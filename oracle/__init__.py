@@ -26,6 +26,9 @@ tree          integer box keys, tiling and 2:1-balance checks, the U/V/W/X inter
               lists of the adaptive FMM by key arithmetic
 fmm           a CPU machine code with complex scaled expansions (Greengard-Rokhlin), its
               exact transpose, used for full-size parity and as the CPU baseline
+layer         the glue layer potentials S[sigma] - D[tau] of Sec. 4.4 on a panel-discretised
+              curve, by direct summation at arbitrary targets (the plain definition that
+              the FMM evaluation at the quadtree nodes approximates)
 
 Parity pins: see tests/test_oracle_*.py. Every function here is pinned by a closed form,
 a library routine, brute force or an invariant, except where its docstring says

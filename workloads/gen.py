@@ -316,3 +316,52 @@ def random_small_tree(seed, max_level=4, n_splits=6):
         leaves = balance(leaves)
     g = sample_gaussians(rng, 3, -0.8, 0.8, 0.05, 0.4, log_sigma=True)
     return make_workload("random-small-%d" % seed, g, leaves, shuffle_seed=seed, meta={"seed": seed})
+
+
+@dataclass
+class Curve:
+    """A closed curve cut into panels, each carrying Gauss-Legendre nodes: node positions,
+    quadrature weights (arc length included), outward unit normals, and two seeded smooth
+    densities (sigma, tau) on the nodes."""
+    name: str
+    nodes: np.ndarray    # (m, 2)
+    weights: np.ndarray  # (m,)
+    normals: np.ndarray  # (m, 2)
+    sigma: np.ndarray    # (m,)
+    tau: np.ndarray      # (m,)
+    theta: np.ndarray    # (m,) curve parameter of each node
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self):
+        return self.nodes.shape[0]
+
+
+def star_curve(n_panels=128, order=24, scale=0.95, seed=0, n_modes=8):
+    """The star r(theta) = scale * 0.7 (1 + 0.3 cos 5 theta) (the truncation curve of the
+    200-Gaussian workload, pulled inwards by ``scale``), cut into n_panels equal parameter
+    intervals with ``order`` Gauss-Legendre nodes each (counter-clockwise, outward normals).
+    sigma and tau are random trigonometric series in theta with n_modes modes and
+    coefficients decaying like 1/(1 + k), drawn from default_rng(seed): sigma first, then tau."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    edges = np.linspace(0.0, 2.0 * np.pi, n_panels + 1)
+    half = 0.5 * (edges[1:] - edges[:-1])
+    mid = 0.5 * (edges[1:] + edges[:-1])
+    th = (mid[:, None] + half[:, None] * xg[None, :]).reshape(-1)
+    wq = (half[:, None] * wg[None, :]).reshape(-1)
+    R0, a, k = 0.7 * scale, 0.3, 5
+    r = R0 * (1.0 + a * np.cos(k * th))
+    dr = -R0 * a * k * np.sin(k * th)
+    x, y = r * np.cos(th), r * np.sin(th)
+    dx = dr * np.cos(th) - r * np.sin(th)
+    dy = dr * np.sin(th) + r * np.cos(th)
+    speed = np.hypot(dx, dy)
+    normals = np.stack([dy / speed, -dx / speed], axis=1)
+    rng = np.random.default_rng(seed)
+    dens = []
+    for _ in range(2):
+        c = rng.standard_normal((2, n_modes + 1)) / (1.0 + np.arange(n_modes + 1))[None, :]
+        kk = np.arange(n_modes + 1)[:, None]
+        dens.append(c[0] @ np.cos(kk * th[None, :]) + c[1] @ np.sin(kk * th[None, :]))
+    return Curve("star-curve-%dx%d" % (n_panels, order), np.stack([x, y], axis=1), wq * speed, normals,
+                 dens[0], dens[1], th, meta={"n_panels": n_panels, "order": order, "scale": scale, "seed": seed})
