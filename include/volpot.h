@@ -97,6 +97,12 @@ typedef struct {
   double flops_issued_kind[9]; /* matrix-core work the kernels issue per stage kind: every tile
                                   multiplies each of its relation tables by all of its slots,
                                   occupied or not (>= flops_kind) */
+  /* layer-potential plans (volpot_layer_plan; zero otherwise) */
+  int64_t n_layer_nodes;    /* curve quadrature nodes */
+  int64_t n_source_leaves;  /* leaves holding at least one node */
+  int64_t n_active_boxes;   /* boxes whose subtree holds nodes (the only multipole sources) */
+  int64_t pairs_p2p;        /* (leaf node, curve node) pairs summed directly */
+  int64_t pairs_p2l;        /* (box, curve node) pairs expanded directly into local expansions */
 } volpot_info;
 
 /* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
@@ -124,6 +130,36 @@ int volpot_apply(volpot_plan_t plan, const double* f_dev, double* u_dev, void* h
  * (the gradient of <ubar, A f> with respect to f). Same layout and stream rules. */
 int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fbar_dev,
                          void* hip_stream);
+
+/* Glue layer potentials (Sec. 4.4): a plan that evaluates
+ *
+ *     V(x) = S[sigma](x) - D[tau](x)
+ *          = -(1/2 pi) sum_j w_j [ sigma_j log|x - y_j| + tau_j n_j . (x - y_j) / |x - y_j|^2 ]
+ *
+ * (S, D the single- and double-layer potentials of the fundamental solution of -Lap on the
+ * fictitious curve, discretised by quadrature nodes y_j with weights w_j and unit normals n_j)
+ * at every leaf node of one tree, with the box code's far-field machinery: multipoles of the
+ * leaves holding nodes, the same M2M / M2L / L2L / L2T / M2T translations, local expansions
+ * from the nodes of X-list leaves, and direct sums over the nodes of adjacent leaves.
+ *   centres, levels, n_leaves, p   the tree, as volpot_plan
+ *   nodes    host, n_nodes x 2; every node must lie in the root box [-1,1]^2
+ *   weights  host, n_nodes quadrature weights (arc length included)
+ *   normals  host, n_nodes x 2 unit normals
+ *   opt      nullable; host_only, use_graph, tile_box, split_min, table_cache and overlap apply
+ * The plan copies the node geometry. Returns VOLPOT_ERR_ARG for a node outside the root box or
+ * non-finite node data, the tree errors of volpot_plan otherwise. n_nodes may be 0 (V = 0).
+ * volpot_apply and volpot_apply_adjoint reject a layer plan (VOLPOT_ERR_STATE); every other
+ * call taking a plan works on it. */
+int volpot_layer_plan(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p,
+                      int64_t n_nodes, const double* nodes, const double* weights, const double* normals,
+                      const volpot_options* opt, volpot_plan_t* out);
+
+/* u = V at every leaf node, [n_leaves][16][16] as volpot_apply's output (overwritten).
+ * sigma_dev, tau_dev: device FP64 densities at the nodes, in the order given to the plan.
+ * A leaf node that coincides with a curve node gets a non-finite value. Asynchronous on the
+ * stream; returns VOLPOT_ERR_STATE for a volume plan. */
+int volpot_layer_apply(volpot_plan_t plan, const double* sigma_dev, const double* tau_dev, double* u_dev,
+                       void* hip_stream);
 
 /* Sizes and algorithmic flop/byte counts of the plan. */
 int volpot_plan_info(volpot_plan_t plan, volpot_info* out);

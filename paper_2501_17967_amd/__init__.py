@@ -5,6 +5,7 @@ a C ABI (include/volpot.h); this package holds the HIP sources (csrc/), the in-t
 (build.py) and the ctypes binding (volpot.py).
 """
 from .volpot import (  # noqa: F401
+    LayerPlan,
     EXPORTED,
     Plan,
     VolpotError,

@@ -30,9 +30,10 @@ def build(verbose=False):
         cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         jobs.append(cmd)
         objs.append(obj)
-    kobj = os.path.join(BUILD, "kernels.hip.o")
-    jobs.append([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", kobj])
-    objs.append(kobj)
+    for src in ("kernels.hip", "layer.hip"):
+        kobj = os.path.join(BUILD, src + ".o")
+        jobs.append([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", kobj])
+        objs.append(kobj)
     procs = [(cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)) for cmd in jobs]
     failed = False
     for cmd, p in procs:

@@ -99,10 +99,12 @@ struct DevStage {
   double* r1_coef = nullptr;
   PieceDesc* pieces = nullptr;
   int32_t *blk_ptr = nullptr, *tile_count = nullptr;
+  int32_t *c_tgt = nullptr, *c_ptr = nullptr, *c_idx = nullptr;  // custom (layer) stages
 };
 
 struct GraphEntry {
   const void* in;
+  const void* in2;
   void* out;
   bool adjoint;
   hipGraphExec_t exec;
@@ -136,6 +138,10 @@ struct volpot_plan_s {
   std::vector<GraphEntry> graphs;
   hipStream_t helper = nullptr;  // far-field chain runs here, forked from the caller's stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // layer potentials: sorted curve nodes and their per-apply charges / dipoles
+  int32_t *d_order = nullptr, *d_bptr = nullptr, *d_leaf_box = nullptr;
+  double *d_sxy = nullptr, *d_sw = nullptr, *d_sn = nullptr, *d_geo = nullptr, *d_sq = nullptr, *d_smu = nullptr;
+  LeafNodes nodes{};
 };
 
 namespace {
@@ -173,6 +179,7 @@ int schedule_all(volpot_plan_s* p, int nominal) {
   try {
     for (auto* v : {&p->host.fwd, &p->host.adj})
       for (Stage& s : *v) {
+        if (s.custom != C_NONE) continue;  // own kernels, one block per target
         auto key = std::array<int, 3>{s.M, s.NT, s.KC};
         auto it = resident.find(key);
         if (it == resident.end())
@@ -201,7 +208,7 @@ int upload(volpot_plan_s* p) {
   if (rc != VOLPOT_OK) return rc;
   size_t total = 0;
   const size_t nb = size_t(P.n_boxes) * kNE * sizeof(double);
-  struct Off { size_t tt, tsp, sd, ss, rp, ri, rf, rc, pc, bp, tc; };
+  struct Off { size_t tt, tsp, sd, ss, rp, ri, rf, rc, pc, bp, tc, ct, cp, ci; };
   std::vector<std::vector<int32_t>> zeros;  // arrival counters start at zero
   std::vector<std::vector<SegDesc>> segd;   // segment descriptors (table pointers of this device)
   auto plan_stage = [&](const Stage& s) {
@@ -217,21 +224,29 @@ int upload(volpot_plan_s* p) {
     o.pc = add_bytes(total, s.pieces); o.bp = add_bytes(total, s.blk_ptr);
     zeros.emplace_back(size_t(std::max(s.n_tiles, 1)), 0);
     o.tc = add_bytes(total, zeros.back());
+    o.ct = add_bytes(total, s.c_tgt); o.cp = add_bytes(total, s.c_ptr); o.ci = add_bytes(total, s.c_idx);
     return o;
   };
   std::vector<Off> ofw, oad;
   for (auto& s : P.fwd) ofw.push_back(plan_stage(s));
   for (auto& s : P.adj) oad.push_back(plan_stage(s));
+  const bool vol = !P.layer;  // the adjoint's and the prescaled input's arrays are for volume plans only
   size_t o_mp = (total + 255) & ~size_t(255); total = o_mp + nb;
   size_t o_loc = (total + 255) & ~size_t(255); total = o_loc + nb;
-  size_t o_lb = (total + 255) & ~size_t(255); total = o_lb + nb;
-  size_t o_ab = (total + 255) & ~size_t(255); total = o_ab + nb;
+  size_t o_lb = (total + 255) & ~size_t(255); total = o_lb + (vol ? nb : 0);
+  size_t o_ab = (total + 255) & ~size_t(255); total = o_ab + (vol ? nb : 0);
   size_t o_far = (total + 255) & ~size_t(255); total = o_far + nb;
-  size_t o_afar = (total + 255) & ~size_t(255); total = o_afar + nb;
-  size_t o_us = (total + 255) & ~size_t(255); total = o_us + size_t(P.n_leaves) * sizeof(double);
-  size_t o_fs = (total + 255) & ~size_t(255); total = o_fs + size_t(P.n_leaves) * kNP * sizeof(double);
+  size_t o_afar = (total + 255) & ~size_t(255); total = o_afar + (vol ? nb : 0);
+  size_t o_us = (total + 255) & ~size_t(255); total = o_us + (vol ? size_t(P.n_leaves) * sizeof(double) : 0);
+  size_t o_fs = (total + 255) & ~size_t(255); total = o_fs + (vol ? size_t(P.n_leaves) * kNP * sizeof(double) : 0);
   std::vector<double> s2(P.leaf_s2);
   size_t o_s2 = add_bytes(total, s2);
+  std::vector<int32_t> leaf_box(P.layer ? P.leaf_box : std::vector<int32_t>());
+  size_t o_order = add_bytes(total, P.src_order), o_sxy = add_bytes(total, P.src_xy), o_sw = add_bytes(total, P.src_w);
+  size_t o_sn = add_bytes(total, P.src_n), o_bptr = add_bytes(total, P.box_src_ptr), o_geo = add_bytes(total, P.box_geo);
+  size_t o_lbox = add_bytes(total, leaf_box);
+  size_t o_sq = (total + 255) & ~size_t(255); total = o_sq + std::max<size_t>(size_t(P.n_src), 1) * sizeof(double);
+  size_t o_smu = (total + 255) & ~size_t(255); total = o_smu + std::max<size_t>(size_t(P.n_src), 1) * 2 * sizeof(double);
   std::vector<char> host(total, 0);
   auto put = [&](size_t o, const auto& v) {
     if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(v[0]));
@@ -241,11 +256,14 @@ int upload(volpot_plan_s* p) {
     put(o.tt, s.tile_tgt); put(o.tsp, s.tile_seg_ptr); put(o.sd, segd[si_++]); put(o.ss, s.seg_src);
     put(o.rp, s.r1_ptr); put(o.ri, s.r1_idx); put(o.rf, s.r1_fam); put(o.rc, s.r1_coef);
     put(o.pc, s.pieces); put(o.bp, s.blk_ptr);
+    put(o.ct, s.c_tgt); put(o.cp, s.c_ptr); put(o.ci, s.c_idx);
   };
   for (size_t i = 0; i < P.fwd.size(); ++i) put_stage(P.fwd[i], ofw[i]);
   for (size_t i = 0; i < P.adj.size(); ++i) put_stage(P.adj[i], oad[i]);
   static_assert(sizeof(Piece) == sizeof(PieceDesc), "piece layouts differ");
   put(o_s2, s2);
+  put(o_order, P.src_order); put(o_sxy, P.src_xy); put(o_sw, P.src_w); put(o_sn, P.src_n);
+  put(o_bptr, P.box_src_ptr); put(o_geo, P.box_geo); put(o_lbox, leaf_box);
   if (hipMalloc(&p->d_block, total) != hipSuccess) return VOLPOT_ERR_OOM;
   p->device_bytes = int64_t(total);
   if (hipMemcpy(p->d_block, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return VOLPOT_ERR_HIP;
@@ -260,6 +278,8 @@ int upload(volpot_plan_s* p) {
     d.r1_coef = reinterpret_cast<double*>(b + o.rc);
     d.pieces = reinterpret_cast<PieceDesc*>(b + o.pc); d.blk_ptr = reinterpret_cast<int32_t*>(b + o.bp);
     d.tile_count = reinterpret_cast<int32_t*>(b + o.tc);
+    d.c_tgt = reinterpret_cast<int32_t*>(b + o.ct); d.c_ptr = reinterpret_cast<int32_t*>(b + o.cp);
+    d.c_idx = reinterpret_cast<int32_t*>(b + o.ci);
     return d;
   };
   for (size_t i = 0; i < P.fwd.size(); ++i) p->dfwd.push_back(mk(P.fwd[i], ofw[i]));
@@ -273,6 +293,19 @@ int upload(volpot_plan_s* p) {
   p->d_usum = reinterpret_cast<double*>(b + o_us);
   p->d_fs = reinterpret_cast<double*>(b + o_fs);
   p->d_leaf_s2 = reinterpret_cast<double*>(b + o_s2);
+  p->d_order = reinterpret_cast<int32_t*>(b + o_order);
+  p->d_sxy = reinterpret_cast<double*>(b + o_sxy);
+  p->d_sw = reinterpret_cast<double*>(b + o_sw);
+  p->d_sn = reinterpret_cast<double*>(b + o_sn);
+  p->d_bptr = reinterpret_cast<int32_t*>(b + o_bptr);
+  p->d_geo = reinterpret_cast<double*>(b + o_geo);
+  p->d_leaf_box = reinterpret_cast<int32_t*>(b + o_lbox);
+  p->d_sq = reinterpret_cast<double*>(b + o_sq);
+  p->d_smu = reinterpret_cast<double*>(b + o_smu);
+  {
+    double w[kP];
+    volpot_nodes(kP, p->nodes.t, w);
+  }
   // partial-sum buffers, one per stream (stages on one stream run one after another)
   size_t part[2] = {0, 0};
   for (auto* v : {&P.fwd, &P.adj})
@@ -338,7 +371,8 @@ void timed_end(volpot_plan_s* p, int kind, hipStream_t st, hipEvent_t ea, hipEve
 // stages marked helper then run on it (the far-field chains) while the caller's stream goes on
 // (the near field), and a stage marked join_before, and the end of the apply, make the
 // caller's stream wait for the helper's work, so that the caller's stream orders everything.
-int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t main, int32_t timing) {
+int run(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, double* out, hipStream_t main,
+        int32_t timing) {
   std::vector<DevStage>& stages = adjoint ? p->dadj : p->dfwd;
   const bool two = p->overlap > 0;
   bool forked = false;  // the helper stream holds work not yet joined
@@ -357,7 +391,12 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
   };
   {
     hipEvent_t ea, eb;
-    if (!adjoint) {  // every forward source read uses s^2 f: scale once
+    if (p->host.layer) {  // charges and dipoles of the sorted curve nodes
+      timed_begin(p, timing, K_UP, main, &ea, &eb);
+      if (launch_layer_prep(p->host.n_src, p->d_order, p->d_sw, p->d_sn, in, in2, p->d_sq, p->d_smu, main) != hipSuccess)
+        return VOLPOT_ERR_HIP;
+      timed_end(p, K_UP, main, ea, eb);
+    } else if (!adjoint) {  // every forward source read uses s^2 f: scale once
       timed_begin(p, timing, K_UP, main, &ea, &eb);
       if (launch_prescale(in, p->d_leaf_s2, p->d_fs, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
       timed_end(p, K_UP, main, ea, eb);
@@ -373,6 +412,21 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
     if (two && s.join_before && !join()) return VOLPOT_ERR_HIP;
     if (s.n_tiles == 0) continue;
     hipStream_t st = (two && s.helper && forked) ? p->helper : main;
+    if (s.custom != C_NONE) {
+      hipEvent_t ea, eb;
+      timed_begin(p, timing, s.kind, st, &ea, &eb);
+      hipError_t e = hipSuccess;
+      if (s.custom == C_P2M)
+        e = launch_p2m(s.n_tiles, d.c_tgt, p->d_bptr, p->d_geo, p->d_sxy, p->d_sq, p->d_smu, p->d_mp, st);
+      else if (s.custom == C_P2L)
+        e = launch_p2l(s.n_tiles, d.c_tgt, d.c_ptr, d.c_idx, p->d_bptr, p->d_geo, p->d_sxy, p->d_sq, p->d_smu, p->d_far, st);
+      else
+        e = launch_p2p(s.n_tiles, d.c_tgt, d.c_ptr, d.c_idx, p->d_leaf_box, p->d_bptr, p->d_geo, p->d_sxy, p->d_sq,
+                       p->d_smu, p->nodes, out, st);
+      timed_end(p, s.kind, st, ea, eb);
+      if (e != hipSuccess) return VOLPOT_ERR_HIP;
+      continue;
+    }
     GrgParams g;
     std::memset(&g, 0, sizeof(g));
     g.tile_tgt = d.tile_tgt; g.tile_seg_ptr = d.tile_seg_ptr; g.segs = d.segs; g.seg_src = d.seg_src;
@@ -405,14 +459,14 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream
   return VOLPOT_OK;
 }
 
-int run_graph(volpot_plan_s* p, bool adjoint, const double* in, double* out, hipStream_t stream) {
+int run_graph(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, double* out, hipStream_t stream) {
   for (auto& g : p->graphs)
-    if (g.in == in && g.out == out && g.adjoint == adjoint)
+    if (g.in == in && g.in2 == in2 && g.out == out && g.adjoint == adjoint)
       return hipGraphLaunch(g.exec, stream) == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
   if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) return VOLPOT_ERR_HIP;
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return VOLPOT_ERR_HIP;
-  int rc = run(p, adjoint, in, out, p->cap_stream, 0);
+  int rc = run(p, adjoint, in, in2, out, p->cap_stream, 0);
   hipError_t ec = hipStreamEndCapture(p->cap_stream, &graph);
   if (rc != VOLPOT_OK || ec != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -422,7 +476,7 @@ int run_graph(volpot_plan_s* p, bool adjoint, const double* in, double* out, hip
   ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ec != hipSuccess) return VOLPOT_ERR_HIP;
-  p->graphs.push_back({in, out, adjoint, exec});
+  p->graphs.push_back({in, in2, out, adjoint, exec});
   return hipGraphLaunch(exec, stream) == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
 }
 
@@ -446,7 +500,7 @@ void free_plan(volpot_plan_s* p) {
 }
 
 int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels, int32_t p,
-              const volpot_options* opt, volpot_plan_t* out) {
+              const volpot_options* opt, volpot_plan_t* out, const LayerSources* layer = nullptr) {
   if (!out || !offsets || !centres || !levels || n_trees <= 0) return VOLPOT_ERR_ARG;
   if (p != kP) return VOLPOT_ERR_UNSUPPORTED;
   if (offsets[0] != 0) return VOLPOT_ERR_ARG;
@@ -462,7 +516,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   int rc;
   try {
     rc = build_plan(n_trees, offsets, centres, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr);
+                    nullptr, layer);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {
@@ -506,21 +560,42 @@ int volpot_plan_forest(int32_t n_trees, const int64_t* tree_offsets, const doubl
 
 int volpot_apply(volpot_plan_t plan, const double* f_dev, double* u_dev, void* hip_stream) {
   if (!plan || !f_dev || !u_dev || !aligned16(f_dev) || !aligned16(u_dev) || f_dev == u_dev) return VOLPOT_ERR_ARG;
-  if (plan->host_only) return VOLPOT_ERR_STATE;
+  if (plan->host_only || plan->host.layer) return VOLPOT_ERR_STATE;
   DeviceGuard dg(plan->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  if (plan->use_graph) return run_graph(plan, false, f_dev, u_dev, s);
-  return run(plan, false, f_dev, u_dev, s, plan->timing);
+  if (plan->use_graph) return run_graph(plan, false, f_dev, nullptr, u_dev, s);
+  return run(plan, false, f_dev, nullptr, u_dev, s, plan->timing);
 }
 
 int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fbar_dev, void* hip_stream) {
   if (!plan || !ubar_dev || !fbar_dev || !aligned16(ubar_dev) || !aligned16(fbar_dev) || ubar_dev == fbar_dev)
     return VOLPOT_ERR_ARG;
-  if (plan->host_only) return VOLPOT_ERR_STATE;
+  if (plan->host_only || plan->host.layer) return VOLPOT_ERR_STATE;
   DeviceGuard dg(plan->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  if (plan->use_graph) return run_graph(plan, true, ubar_dev, fbar_dev, s);
-  return run(plan, true, ubar_dev, fbar_dev, s, plan->timing);
+  if (plan->use_graph) return run_graph(plan, true, ubar_dev, nullptr, fbar_dev, s);
+  return run(plan, true, ubar_dev, nullptr, fbar_dev, s, plan->timing);
+}
+
+int volpot_layer_plan(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p, int64_t n_nodes,
+                      const double* nodes, const double* weights, const double* normals, const volpot_options* opt,
+                      volpot_plan_t* out) {
+  if (n_leaves <= 0 || n_nodes < 0 || n_nodes > (int64_t(1) << 31) - 1) return VOLPOT_ERR_ARG;
+  if (n_nodes > 0 && (!nodes || !weights || !normals)) return VOLPOT_ERR_ARG;
+  int64_t off[2] = {0, n_leaves};
+  LayerSources ls{n_nodes, nodes, weights, normals};
+  return make_plan(1, off, centres, levels, p, opt, out, &ls);
+}
+
+int volpot_layer_apply(volpot_plan_t plan, const double* sigma_dev, const double* tau_dev, double* u_dev,
+                       void* hip_stream) {
+  if (!plan || !u_dev || !aligned16(u_dev)) return VOLPOT_ERR_ARG;
+  if (plan->host.n_src > 0 && (!sigma_dev || !tau_dev)) return VOLPOT_ERR_ARG;
+  if (plan->host_only || !plan->host.layer) return VOLPOT_ERR_STATE;
+  DeviceGuard dg(plan->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (plan->use_graph) return run_graph(plan, false, sigma_dev, tau_dev, u_dev, s);
+  return run(plan, false, sigma_dev, tau_dev, u_dev, s, plan->timing);
 }
 
 int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
@@ -552,6 +627,17 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   out->flops_adjoint += out->flops_kind[K_ASUM];
   out->launches_kind[K_ASUM] = 1;
   out->bytes_min = 16.0 * double(P.n_leaves) * kNP;
+  if (P.layer) {
+    out->flops_kind[K_ASUM] = 0.0;
+    out->launches_kind[K_ASUM] = 0;
+    out->flops_adjoint = 0.0;
+    out->bytes_min = 8.0 * double(P.n_leaves) * kNP + 16.0 * double(P.n_src);
+  }
+  out->n_layer_nodes = P.n_src;
+  out->n_source_leaves = P.n_src_leaves;
+  out->n_active_boxes = P.n_active;
+  out->pairs_p2p = P.pairs_p2p;
+  out->pairs_p2l = P.pairs_p2l;
   out->device_bytes = plan->device_bytes + (plan->tables ? int64_t(plan->tables->bytes) : 0);
   return VOLPOT_OK;
 }

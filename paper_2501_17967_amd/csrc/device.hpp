@@ -62,4 +62,24 @@ hipError_t launch_prescale(const double* x, const double* s2, double* out, int64
 // usum[a] = sum of the 256 values of leaf a
 hipError_t launch_rowsum(const double* x, double* usum, int64_t n_leaves, hipStream_t stream);
 
+// ---------------------------------------------------------------- layer potentials (layer.hip)
+// Nodes of a leaf on [-1,1] (first-kind Chebyshev, ascending); passed by value.
+struct LeafNodes {
+  double t[16];
+};
+// Sorted curve nodes j: q[j] = w[j] sigma[order[j]], mu[j] = w[j] tau[order[j]] n[j] (complex).
+hipError_t launch_layer_prep(int64_t n, const int32_t* order, const double* w, const double* nrm, const double* sigma,
+                             const double* tau, double* q, double* mu, hipStream_t stream);
+// Multipoles (80 reals) of the leaf boxes tgt[0 .. n_tgt) from their sorted nodes bptr[b] .. bptr[b+1].
+hipError_t launch_p2m(int32_t n_tgt, const int32_t* tgt, const int32_t* bptr, const double* geo, const double* sxy,
+                      const double* q, const double* mu, double* mp, hipStream_t stream);
+// far[tgt[i]] += local expansion of the nodes of the leaf boxes idx[ptr[i] .. ptr[i+1]).
+hipError_t launch_p2l(int32_t n_tgt, const int32_t* tgt, const int32_t* ptr, const int32_t* idx, const int32_t* bptr,
+                      const double* geo, const double* sxy, const double* q, const double* mu, double* far,
+                      hipStream_t stream);
+// u[tgt[i]] (256 values) = direct sum over the nodes of the leaf boxes idx[ptr[i] .. ptr[i+1]).
+hipError_t launch_p2p(int32_t n_tgt, const int32_t* tgt, const int32_t* ptr, const int32_t* idx, const int32_t* leaf_box,
+                      const int32_t* bptr, const double* geo, const double* sxy, const double* q, const double* mu,
+                      const LeafNodes& nodes, double* u, hipStream_t stream);
+
 }  // namespace vp

@@ -425,7 +425,9 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
 }
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
-               int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad) {
+               int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer) {
+  if (layer && (n_trees != 1 || layer->n < 0 || (layer->n > 0 && (!layer->xy || !layer->weights || !layer->normals))))
+    return VOLPOT_ERR_ARG;
   const double kLn2 = std::log(2.0);
   const double kInv2Pi = 1.0 / (2.0 * M_PI);
   P = Plan();
@@ -569,6 +571,59 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       Xlist[c].push_back({r, int32_t(a)});
     }
 
+  // ---------------------------------------------------------------- layer sources
+  // Each curve node belongs to the leaf that holds it (a node on an edge between boxes goes to
+  // the box on its right / upper side, one on the root's right or top edge to the box inside);
+  // nodes are sorted by that leaf's box. A box is active when its subtree holds nodes: only
+  // active boxes have multipoles, and only they are sources of M2M, M2L and M2T.
+  std::vector<char> active;
+  if (layer) {
+    const int64_t n = layer->n;
+    P.layer = true;
+    P.n_src = n;
+    P.box_geo.assign(size_t(NB) * 4, 0.0);
+    for (int32_t b = 0; b < NB; ++b) {
+      P.box_geo[4 * size_t(b)] = cx(b);
+      P.box_geo[4 * size_t(b) + 1] = cy(b);
+      P.box_geo[4 * size_t(b) + 2] = hw(b);
+    }
+    const int32_t root = find_box(0, pack(0, 0, 0));
+    std::vector<int32_t> src_box(static_cast<size_t>(n));
+    for (int64_t j = 0; j < n; ++j) {
+      const double x = layer->xy[2 * j], y = layer->xy[2 * j + 1];
+      const double nx = layer->normals[2 * j], ny = layer->normals[2 * j + 1];
+      if (!(x >= -1.0 && x <= 1.0 && y >= -1.0 && y <= 1.0) || !std::isfinite(layer->weights[j]) || !std::isfinite(nx) ||
+          !std::isfinite(ny)) {
+        if (bad) *bad = j;
+        return VOLPOT_ERR_ARG;
+      }
+      int32_t b = root;
+      while (P.box_leaf[b] < 0) b = P.box_child[b][int(x >= cx(b)) + 2 * int(y >= cy(b))];
+      src_box[size_t(j)] = b;
+    }
+    P.src_order.resize(size_t(n));
+    for (int64_t j = 0; j < n; ++j) P.src_order[size_t(j)] = int32_t(j);
+    std::stable_sort(P.src_order.begin(), P.src_order.end(),
+                     [&](int32_t a, int32_t b) { return src_box[size_t(a)] < src_box[size_t(b)]; });
+    P.src_xy.resize(size_t(2 * n)); P.src_w.resize(size_t(n)); P.src_n.resize(size_t(2 * n));
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t j = P.src_order[size_t(i)];
+      P.src_xy[2 * i] = layer->xy[2 * j]; P.src_xy[2 * i + 1] = layer->xy[2 * j + 1];
+      P.src_w[i] = layer->weights[j];
+      P.src_n[2 * i] = layer->normals[2 * j]; P.src_n[2 * i + 1] = layer->normals[2 * j + 1];
+    }
+    std::vector<int64_t> cnt(size_t(NB), 0);
+    for (int64_t j = 0; j < n; ++j) cnt[size_t(src_box[size_t(j)])]++;
+    P.box_src_ptr.assign(size_t(NB) + 1, 0);
+    for (int32_t b = 0; b < NB; ++b) P.box_src_ptr[size_t(b) + 1] = P.box_src_ptr[size_t(b)] + int32_t(cnt[size_t(b)]);
+    for (int32_t b = 0; b < NB; ++b) P.n_src_leaves += (P.box_leaf[b] >= 0 && cnt[size_t(b)] > 0);
+    for (int32_t b = int32_t(NB) - 1; b >= 0; --b)  // children follow their parents in box order
+      if (P.box_parent[b] >= 0) cnt[size_t(P.box_parent[b])] += cnt[size_t(b)];
+    active.resize(size_t(NB));
+    for (int32_t b = 0; b < NB; ++b) { active[size_t(b)] = cnt[size_t(b)] > 0; P.n_active += active[size_t(b)]; }
+  }
+  auto use = [&](int32_t b) { return !layer || active[size_t(b)]; };
+
   // ---------------------------------------------------------------- stages
   const Matrices& mats = matrices();
   const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
@@ -610,7 +665,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (auto& f : st.fam) f = {A_NONE, 0, 0};
     for (auto& f : st.r1fam) f = {A_NONE, 0, 0};
   };
-  auto lvl = [](const char* n, int l) { return std::string(n) + "[" + std::to_string(l) + "]"; };
   // boxes at levels >= 2 ordered by (level, quadrant, tree, morton): targets of one tile then
   // share their V-list offset pattern
   std::vector<int32_t> deep_by_quadrant;
@@ -636,7 +690,15 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   };
 
   // ================================================================ forward
-  {  // S2M: every leaf's multipole
+  if (layer) {  // P2M: multipoles of the leaves that hold curve nodes
+    Stage st; init_stage(st, K_UP, "P2M", -1, kNE, kNE, 1, A_MP, kNE);
+    st.custom = C_P2M;
+    for (int32_t b = 0; b < NB; ++b)
+      if (P.box_leaf[b] >= 0 && P.box_src_ptr[size_t(b) + 1] > P.box_src_ptr[size_t(b)]) st.c_tgt.push_back(b);
+    st.n_tiles = int(st.c_tgt.size());
+    defer(std::move(st), {}, {}, {}, false);
+  }
+  if (!layer) {  // S2M: every leaf's multipole
     std::vector<int32_t> tg;
     for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0) tg.push_back(b);
     Stage st; init_stage(st, K_UP, "S2M", -1, kNE, kNP, NTB, A_MP, kNE);
@@ -657,20 +719,26 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       std::vector<int32_t> tg;
       std::vector<std::vector<Entry>> E;
       for (int32_t b : boxes_at[l]) {
-        if (P.box_leaf[b] >= 0) continue;
+        if (P.box_leaf[b] >= 0 || !use(b)) continue;
         tg.push_back(b);
         E.emplace_back();
-        for (int q = 0; q < 4; ++q) { E.back().push_back({rel1 + q, 0, P.box_child[b][q]}); P.n_m2m += !adj; }
+        for (int q = 0; q < 4; ++q)
+          if (use(P.box_child[b][q])) { E.back().push_back({rel1 + q, 0, P.box_child[b][q]}); P.n_m2m += !adj; }
       }
       if (l - 1 >= 2)
         for (int32_t a : boxes_at[l - 1]) {
-          if (P.box_leaf[a] >= 0) continue;
+          if (P.box_leaf[a] >= 0 || !use(a)) continue;
           tg.push_back(a);
           E.emplace_back();
           for (int qc = 0; qc < 4; ++qc) {
             const int32_t c = P.box_child[a][qc];
+            if (!use(c)) continue;
             if (P.box_leaf[c] >= 0) { E.back().push_back({rel1 + qc, 0, c}); P.n_m2m += !adj; continue; }
-            for (int qg = 0; qg < 4; ++qg) { E.back().push_back({rel2 + 4 * qc + qg, 0, P.box_child[c][qg]}); P.n_m2m += !adj; }
+            for (int qg = 0; qg < 4; ++qg)
+              if (use(P.box_child[c][qg])) {
+                E.back().push_back({rel2 + 4 * qc + qg, 0, P.box_child[c][qg]});
+                P.n_m2m += !adj;
+              }
           }
         }
       if (tg.empty()) continue;
@@ -732,7 +800,19 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   };
   up_pairs(false);
   if (!deep_by_quadrant.empty()) {  // FARV: M2L for every box of every level >= 2, plus all log terms
-    const auto& tg = deep_by_quadrant;
+    std::vector<int32_t> tg = deep_by_quadrant;
+    if (layer) {  // most boxes have few active sources: group boxes with the same V relations
+      std::map<std::vector<int32_t>, int32_t> cls;
+      std::vector<std::vector<int32_t>> sig(static_cast<size_t>(NB));
+      for (int32_t b : tg) {
+        for (auto& e : Vlist[b]) if (use(e.second)) sig[size_t(b)].push_back(e.first);
+        std::sort(sig[size_t(b)].begin(), sig[size_t(b)].end());
+        cls.emplace(sig[size_t(b)], 0);
+      }
+      int32_t rank = 0;
+      for (auto& kv : cls) kv.second = rank++;
+      std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return cls[sig[size_t(x)]] < cls[sig[size_t(y)]]; });
+    }
     Stage st; init_stage(st, K_DOWN, "FARV", -1, kNE, kNE, NTB, A_FAR, kNE);
     st.fam[0] = {A_MP, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
@@ -741,12 +821,33 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (size_t i = 0; i < tg.size(); ++i) {
       int32_t b = tg[i];
       double ls = lnS(P.box_level[b]);
-      for (auto& e : Vlist[b]) { E[i].push_back({kRelM2L + e.first, 0, e.second}); R[i].push_back({0, e.second, ls}); }
-      for (auto& e : Xlist[b]) R[i].push_back({0, P.leaf_box[e.second], ls});
+      for (auto& e : Vlist[b])
+        if (use(e.second)) { E[i].push_back({kRelM2L + e.first, 0, e.second}); R[i].push_back({0, e.second, ls}); }
+      if (!layer)
+        for (auto& e : Xlist[b]) R[i].push_back({0, P.leaf_box[e.second], ls});
     }
     defer(std::move(st), tg, std::move(E), std::move(R), false);
   }
-  {  // FARX: S2L, added onto FARV for the boxes that have an X list
+  if (layer) {  // P2L: the nodes of X-list leaves, added onto FARV
+    Stage st; init_stage(st, K_DOWN, "P2L", -1, kNE, kNE, 1, A_FAR, kNE);
+    st.custom = C_P2L;
+    st.c_ptr.push_back(0);
+    for (int32_t b : deep_by_quadrant) {
+      bool any = false;
+      for (auto& e : Xlist[b]) {
+        const int32_t lb = P.leaf_box[e.second];
+        const int32_t ns = P.box_src_ptr[size_t(lb) + 1] - P.box_src_ptr[size_t(lb)];
+        if (ns == 0) continue;
+        st.c_idx.push_back(lb);
+        P.pairs_p2l += ns;
+        any = true;
+      }
+      if (any) { st.c_tgt.push_back(b); st.c_ptr.push_back(int32_t(st.c_idx.size())); }
+    }
+    st.n_tiles = int(st.c_tgt.size());
+    defer(std::move(st), {}, {}, {}, false);
+  }
+  if (!layer) {  // FARX: S2L, added onto FARV for the boxes that have an X list
     std::vector<int32_t> tg;
     for (int32_t b : deep_by_quadrant) if (!Xlist[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
@@ -793,6 +894,25 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   } else {
     halves = {{0, leaf_order.size()}};
   }
+  if (layer) {  // P2P: every leaf's nodes from the curve nodes in its adjacent leaves (itself included)
+    Stage st; init_stage(st, K_NEAR, "P2P", -1, kNP, kNE, 1, A_OUT, kNP);
+    st.custom = C_P2P;
+    st.c_ptr.push_back(0);
+    for (int32_t a : leaf_order) {
+      for (auto& e : Ulist[size_t(a)]) {
+        const int32_t lb = P.leaf_box[e.second];
+        const int32_t ns = P.box_src_ptr[size_t(lb) + 1] - P.box_src_ptr[size_t(lb)];
+        if (ns == 0) continue;
+        st.c_idx.push_back(lb);
+        P.pairs_p2p += int64_t(ns) * kNP;
+      }
+      st.c_tgt.push_back(a);
+      st.c_ptr.push_back(int32_t(st.c_idx.size()));
+    }
+    st.n_tiles = int(st.c_tgt.size());
+    defer(std::move(st), {}, {}, {}, false);
+  }
+  if (layer) halves.clear();
   for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
     const std::vector<int32_t> part(near_order.begin() + long(halves[h].first), near_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
@@ -803,7 +923,24 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (auto& e : Ulist[part[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
     defer(std::move(st), part, std::move(E), std::move(R), false);
   }
-  {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
+  if (layer) {  // LOCT: L2T + M2T of active W boxes and their kappa(s_a) * mass terms, added onto P2P
+    Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
+    st.accumulate = 1;
+    st.r1_all_rows = 1;
+    st.fam[0] = {A_MP, kNE, 0}; st.fam[1] = {A_LOC, kNE, 0};
+    st.r1fam[0] = {A_MP, kNE, 0};
+    std::vector<std::vector<Entry>> E(P.n_leaves);
+    std::vector<std::vector<R1>> R(P.n_leaves);
+    for (size_t i = 0; i < leaf_order.size(); ++i) {
+      int32_t a = leaf_order[i];
+      double kap = P.leaf_kappa[a];
+      for (auto& e : Wlist[a])
+        if (use(e.second)) { E[i].push_back({kRelM2T + e.first, 0, e.second}); R[i].push_back({0, e.second, kap}); }
+      if (levels[a] >= 2) { E[i].push_back({kRelL2T, 1, P.leaf_box[a]}); P.n_l2t++; }
+    }
+    defer(std::move(st), leaf_order, std::move(E), std::move(R), false);
+  }
+  if (!layer) {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
     Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
     st.accumulate = 1;
     st.r1_all_rows = 1;
@@ -822,6 +959,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   }
 
   // ================================================================ adjoint
+  if (!layer) {
   {  // AL2T: lbar of leaves at level >= 2
     std::vector<int32_t> tg;
     for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0 && P.box_level[b] >= 2) tg.push_back(b);
@@ -900,13 +1038,14 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     }
     defer(std::move(st), leaf_order, std::move(E), std::move(R), true);
   }
+  }  // adjoint
   {
     std::vector<std::exception_ptr> err(jobs.size());
     std::atomic<size_t> next(0);
     auto work = [&]() {
       for (size_t j; (j = next.fetch_add(1)) < jobs.size();) {
         try {
-          make_tiles(jobs[j].st, jobs[j].tg, jobs[j].E, jobs[j].R, mats);
+          if (jobs[j].st.custom == C_NONE) make_tiles(jobs[j].st, jobs[j].tg, jobs[j].E, jobs[j].R, mats);
         } catch (...) {
           err[j] = std::current_exception();
         }

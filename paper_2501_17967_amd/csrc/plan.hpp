@@ -88,6 +88,10 @@ enum StageKind : int { K_UP = 0, K_DOWN, K_NEAR, K_LOCT, K_AUP, K_ADOWN, K_ANEAR
 
 struct FamDesc { int8_t arr; int32_t stride; int8_t unused; };
 
+// Stages of the layer-potential evaluation that are not grouped products: per-point
+// expansions and direct sums over the curve's quadrature nodes (their own kernels).
+enum Custom : int8_t { C_NONE = 0, C_P2M, C_P2L, C_P2P };
+
 // One piece of a stage's work as run by one block: n_chunks consecutive k-chunks of one tile,
 // starting at chunk k0 / KC of segment seg. A tile cut over several blocks ("split") has its
 // pieces' partial sums added, in piece order, by whichever of those blocks finishes last.
@@ -120,6 +124,7 @@ struct Stage {
   int8_t join_before = 0;  // waits for the helper stream's work before launching
   int8_t fork_before = 0;  // the helper stream waits for the caller's stream before this stage
   int8_t concurrent = 0;   // runs while helper-stream stages may run: leaves compute units free
+  int8_t custom = C_NONE;  // not a grouped product: c_tgt / c_ptr / c_idx describe the work
   std::string name;        // stage name for reports, e.g. NEAR or M2M[5]
   FamDesc fam[4];
   FamDesc r1fam[3];
@@ -132,6 +137,8 @@ struct Stage {
   std::vector<int32_t> r1_idx;
   std::vector<int8_t> r1_fam;
   std::vector<double> r1_coef;
+  // custom stages: target c_tgt[i] takes the source leaves (boxes) c_idx[c_ptr[i] .. c_ptr[i+1])
+  std::vector<int32_t> c_tgt, c_ptr, c_idx;
   double flops = 0.0;
   int64_t n_pairs = 0;
   // balanced schedule (build_schedule): block b runs pieces [blk_ptr[b], blk_ptr[b+1])
@@ -155,6 +162,21 @@ struct Plan {
   // pair counts
   int64_t pairs_near = 0, pairs_v = 0, pairs_w = 0, pairs_x = 0, n_m2m = 0, n_l2l = 0, n_s2m = 0,
           n_l2t = 0;
+  // layer potentials (point sources on a curve; empty for the volume potential)
+  bool layer = false;
+  int64_t n_src = 0, n_src_leaves = 0, n_active = 0, pairs_p2p = 0, pairs_p2l = 0;
+  std::vector<int32_t> src_order;    // sorted position -> caller node index (sorted by leaf box)
+  std::vector<double> src_xy, src_w, src_n;  // sorted positions (x, y), weights, normals (x, y)
+  std::vector<int32_t> box_src_ptr;  // n_boxes + 1: the sorted nodes inside each leaf box
+  std::vector<double> box_geo;       // per box: centre x, centre y, half-width, 0
+};
+
+// Quadrature nodes of a curve carrying the layer densities (host arrays, caller order).
+struct LayerSources {
+  int64_t n;
+  const double* xy;       // n x 2
+  const double* weights;  // n
+  const double* normals;  // n x 2, unit
 };
 
 // Validates trees only (tiling, level grid, 2:1 balance); no tables are built.
@@ -170,7 +192,10 @@ void build_schedule(Stage& st, int max_blocks, int min_units);
 
 // overlap > 0: near field split in two launches, each concurrent with one chain of the far
 // field on the helper stream (stage order and flags below); 0: one stream, plan order.
+// layer != nullptr: plan the evaluation of the layer potentials of those nodes at every leaf
+// node of one tree instead (no adjoint stages).
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
-               const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf);
+               const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
+               const LayerSources* layer = nullptr);
 
 }  // namespace vp

@@ -8,6 +8,8 @@ Every step of the volume potential runs in the HIP library; PyTorch supplies dev
     u = plan.apply(f)                       # f: cuda float64 (n_leaves, 16, 16) or (n, 256)
     fbar = plan.apply_adjoint(ubar)         # exact transpose
     u = volume_potential(f, plan)           # autograd: backward runs apply_adjoint
+    lp = LayerPlan(centres, levels, nodes, weights, normals)   # glue layer potentials
+    v = lp.apply(sigma, tau)                # S[sigma] - D[tau] at every leaf node
 
 Sign convention: u = int G f with G = -(1/2pi) log|x - y| (so -Lap u = f); the paper's v_bulk
 (Sec. 4.2, eq. (vbulk)) is -u.
@@ -27,7 +29,7 @@ EXPORTED = [
     "volpot_plan", "volpot_plan_forest", "volpot_apply", "volpot_apply_adjoint", "volpot_plan_info",
     "volpot_validate_tree", "volpot_nodes", "volpot_plan_destroy", "volpot_status_string",
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
-    "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune",
+    "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune", "volpot_layer_plan", "volpot_layer_apply",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -55,7 +57,9 @@ class Info(ctypes.Structure):
                 ("flops_total", ctypes.c_double), ("flops_adjoint", ctypes.c_double),
                 ("flops_kind", ctypes.c_double * 9), ("launches_kind", ctypes.c_int64 * 9),
                 ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64),
-                ("flops_issued_kind", ctypes.c_double * 9)]
+                ("flops_issued_kind", ctypes.c_double * 9), ("n_layer_nodes", ctypes.c_int64),
+                ("n_source_leaves", ctypes.c_int64), ("n_active_boxes", ctypes.c_int64), ("pairs_p2p", ctypes.c_int64),
+                ("pairs_p2l", ctypes.c_int64)]
 
 
 class StageInfo(ctypes.Structure):
@@ -107,6 +111,9 @@ def lib():
         L.volpot_autotune.argtypes = [ctypes.c_int32, _lp, _dp, _ip, ctypes.c_int32, ctypes.POINTER(Options),
                                       ctypes.c_char_p, ctypes.POINTER(Options), _dp]
         L.volpot_plan_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(StageInfo)]
+        L.volpot_layer_plan.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp,
+                                        ctypes.POINTER(Options), ctypes.POINTER(_vp)]
+        L.volpot_layer_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
         _lib = L
     return _lib
 
@@ -279,6 +286,55 @@ class Plan:
         _check(lib().volpot_apply_adjoint(self._h, ctypes.c_void_p(ubar.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                           _stream_handle(stream)), "volpot_apply_adjoint")
         return out
+
+
+class LayerPlan(Plan):
+    """Evaluation of the glue layer potentials V = S[sigma] - D[tau] (Sec. 4.4) at every leaf node
+    of one tree; the curve is given by quadrature nodes (m, 2), weights (m,) and unit normals (m, 2).
+    Inspection (info, stages, timing) as for Plan; apply / apply_adjoint do not apply."""
+
+    def __init__(self, centres, levels, nodes, weights, normals, p=16, *, host_only=False, use_graph=False,
+                 tile_box=0, table_cache=None, split_min=0, overlap=0):
+        c, l = _host_tree(centres, levels)
+        y = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, 2))
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        n = np.ascontiguousarray(np.asarray(normals, dtype=np.float64).reshape(-1, 2))
+        if not (y.shape[0] == w.shape[0] == n.shape[0]):
+            raise ValueError("nodes, weights and normals differ in length")
+        self.n_leaves = c.shape[0]
+        self.n_nodes = y.shape[0]
+        self.n_trees = 1
+        opt = Options(int(host_only), int(use_graph), 0, int(tile_box), table_cache.encode() if table_cache else None,
+                      int(split_min), int(overlap))
+        h = _vp()
+        _check(lib().volpot_layer_plan(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), self.n_leaves, p, self.n_nodes,
+                                       y.ctypes.data_as(_dp), w.ctypes.data_as(_dp), n.ctypes.data_as(_dp),
+                                       ctypes.byref(opt), ctypes.byref(h)), "volpot_layer_plan")
+        self._h = h
+        self.host_only = host_only
+
+    def apply(self, sigma, tau, out=None, stream=None):
+        """V at every leaf node, (n_leaves, 256) float64 (asynchronous on ``stream``)."""
+        import torch
+
+        dens = []
+        for x in (sigma, tau):
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
+                raise TypeError("expected CUDA float64 densities")
+            if x.numel() != self.n_nodes:
+                raise ValueError("expected %d node values" % self.n_nodes)
+            dens.append(x.contiguous())
+        if out is None:
+            out = torch.empty((self.n_leaves, 256), dtype=torch.float64, device=dens[0].device)
+        elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.n_leaves * 256):
+            raise ValueError("bad output tensor")
+        ptr = [ctypes.c_void_p(d.data_ptr() if d.numel() else 0) for d in dens]
+        _check(lib().volpot_layer_apply(self._h, ptr[0], ptr[1], ctypes.c_void_p(out.data_ptr()),
+                                        _stream_handle(stream)), "volpot_layer_apply")
+        return out
+
+    def apply_adjoint(self, *args, **kwargs):
+        raise VolpotError(ERR_STATE, "volpot_apply_adjoint")
 
 
 def _autograd_cls():

@@ -193,3 +193,97 @@ def test_overlap_launch_order(vp):
                 assert names.index(near + "_A") < i_far < names.index(near + "_B") < len(names) - 1
             else:
                 assert nears == [near]
+
+
+# ---------------------------------------------------------------- layer potentials (host side)
+def _circle_nodes(R, m, c=(0.0, 0.0)):
+    th = 2 * np.pi * np.arange(m) / m
+    y = np.stack([c[0] + R * np.cos(th), c[1] + R * np.sin(th)], axis=1)
+    return y, np.full(m, 2 * np.pi * R / m), np.stack([np.cos(th), np.sin(th)], axis=1)
+
+
+def _leaf_of_point(T, x, y):
+    """The leaf holding (x, y): half-open boxes [lo, hi), the root's right / top edge included."""
+    for l in range(T.max_level + 1):
+        n = 1 << l
+        ix = min(int(np.floor((x + 1.0) * n / 2.0)), n - 1)
+        iy = min(int(np.floor((y + 1.0) * n / 2.0)), n - 1)
+        if (l, ix, iy) in T.leaf_of:
+            return (l, ix, iy)
+    raise AssertionError("point not covered")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_layer_plan_counts_match_oracle_lists(vp, seed):
+    w = gen.random_small_tree(seed, max_level=5, n_splits=9)
+    # a circle through box edges and corners (nodes at angles k pi / 2 sit on x = 0.5 or y = 0.5)
+    y, wt, nrm = _circle_nodes(0.5, 64)
+    c = gen.star_curve(n_panels=8, order=6, scale=0.6, seed=seed)
+    y = np.vstack([y, c.nodes]); wt = np.concatenate([wt, c.weights]); nrm = np.vstack([nrm, c.normals])
+    plan = vp.LayerPlan(w.centres, w.levels, y, wt, nrm, host_only=True)
+    inf = plan.info()
+    T = tree.Tree(w.centres, w.levels)
+    U, V, W, X = T.lists()
+    count = {}
+    for (px, py) in y:
+        k = _leaf_of_point(T, px, py)
+        count[k] = count.get(k, 0) + 1
+    active = set()
+    for k in count:
+        l, x, yy = k
+        while True:
+            active.add((l, x, yy))
+            if l == 0:
+                break
+            l, x, yy = l - 1, x >> 1, yy >> 1
+    assert inf["n_layer_nodes"] == len(y)
+    assert inf["n_source_leaves"] == len(count)
+    assert inf["n_active_boxes"] == len(active)
+    assert inf["pairs_p2p"] == 256 * sum(count.get(b, 0) for a in U for b in U[a])
+    assert inf["pairs_p2l"] == sum(count.get(a, 0) for cbox in X for a in X[cbox])
+    names = [s["name"] for s in plan.stages(False)]
+    assert plan.stages(True) == []
+    assert names[0] == "P2M" and names[-1] == "LOCT"
+    assert not any(n in ("S2M", "NEAR", "FARX") for n in names)
+    i_far = names.index("FARV")
+    assert names.index("P2P") < i_far and names.index("P2L") == i_far + 1
+    assert all(names.index(n) < i_far for n in names if n.startswith("M2M["))
+    assert all(names.index(n) > i_far + 1 for n in names if n.startswith("L2L["))
+    # only active boxes are multipole sources: M2L work is that of the active V pairs (each a
+    # real 80 x 80 matrix with at least half its entries non-zero, plus one log term)
+    farv = [s for s in plan.stages(False) if s["name"] == "FARV"]
+    n_v_active = sum(1 for b in V for s in V[b] if s in active)
+    if farv:
+        assert 2 * 3200 * n_v_active <= farv[0]["flops"] <= 2 * (6400 + 1) * n_v_active
+
+
+def test_layer_plan_errors(vp):
+    w = gen.config1(0)
+    y, wt, nrm = _circle_nodes(0.5, 16)
+    for bad in ((1.5, 0.0), (np.nan, 0.0), (0.0, -1.000001)):
+        yb = y.copy()
+        yb[3] = bad
+        with pytest.raises(vp.VolpotError) as e:
+            vp.LayerPlan(w.centres, w.levels, yb, wt, nrm, host_only=True)
+        assert e.value.code == vp.ERR_ARG
+    nb = nrm.copy()
+    nb[5, 1] = np.inf
+    with pytest.raises(vp.VolpotError):
+        vp.LayerPlan(w.centres, w.levels, y, wt, nb, host_only=True)
+    with pytest.raises(ValueError):
+        vp.LayerPlan(w.centres, w.levels, y, wt[:-1], nrm, host_only=True)
+    # nodes on the root's edges and corners belong to the boxes inside; no nodes at all is valid
+    edge = np.array([[1.0, 1.0], [-1.0, -1.0], [1.0, 0.0], [0.0, -1.0]])
+    p = vp.LayerPlan(w.centres, w.levels, edge, np.ones(4), np.tile([[1.0, 0.0]], (4, 1)), host_only=True)
+    assert p.info()["n_source_leaves"] == 4
+    p0 = vp.LayerPlan(w.centres, w.levels, np.zeros((0, 2)), np.zeros(0), np.zeros((0, 2)), host_only=True)
+    assert p0.info()["n_active_boxes"] == 0 and p0.info()["pairs_p2p"] == 0
+    # host-only plans refuse to apply; the arguments are checked first (pointers never dereferenced)
+    import ctypes
+    L = vp.lib()
+    a16, b16 = ctypes.c_void_p(256), ctypes.c_void_p(512)
+    assert L.volpot_layer_apply(p._h, a16, a16, b16, None) == vp.ERR_STATE
+    assert L.volpot_layer_apply(p._h, None, a16, b16, None) == vp.ERR_ARG
+    assert L.volpot_layer_apply(p._h, a16, a16, ctypes.c_void_p(520 + 4), None) == vp.ERR_ARG
+    assert L.volpot_apply(p._h, a16, b16, None) == vp.ERR_STATE
+    assert L.volpot_layer_apply(p0._h, None, None, b16, None) == vp.ERR_STATE  # no nodes: no densities needed
