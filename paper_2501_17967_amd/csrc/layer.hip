@@ -12,7 +12,8 @@
 //        b_0 = sum [ q log|zeta - c| - (mu / s) / w ],
 //        b_l = sum [ -(q / l) w^-l - (mu / s) w^-(l+1) ]                           (l >= 1)
 //        (only real parts reach V, so the log keeps its modulus only)
-//   P2P  direct sum at the 256 nodes of a leaf over the curve nodes in its adjacent leaves.
+//   P2P  direct sum at the 256 nodes of a leaf over the curve nodes in its adjacent leaves,
+//        added onto the far field (only leaves with curve nodes nearby are launched).
 // Each output has one owner and a fixed summation order: deterministic, no atomics.
 #include <hip/hip_runtime.h>
 
@@ -59,120 +60,185 @@ __global__ void layer_prep_kernel(int64_t n, const int32_t* __restrict__ order, 
   mu[2 * j + 1] = d * nrm[2 * j + 1];
 }
 
-// one wave per target leaf box; lane n < 40 owns term n
-__global__ void __launch_bounds__(64) p2m_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ bptr,
-                                                 const double* __restrict__ geo, const double* __restrict__ sxy,
-                                                 const double* __restrict__ q, const double* __restrict__ mu,
-                                                 double* __restrict__ mp) {
-  const int32_t b = tgt[blockIdx.x];
-  const int n = threadIdx.x;
-  if (n >= kTerms) return;
-  const double cx = geo[4 * size_t(b)], cy = geo[4 * size_t(b) + 1], is = 1.0 / geo[4 * size_t(b) + 2];
-  const double inv_n = n > 0 ? 1.0 / double(n) : 0.0;
-  double ar = 0.0, ai = 0.0;
-  const int32_t j1 = bptr[b + 1];
-  for (int32_t j = bptr[b]; j < j1; ++j) {
-    const double qj = q[j];
-    if (n == 0) {
-      ar += qj;
-      continue;
-    }
-    const double ex = (sxy[2 * size_t(j)] - cx) * is, ey = (sxy[2 * size_t(j) + 1] - cy) * is;
-    double pr, pi;
-    cpow(ex, ey, n - 1, pr, pi);
-    // eta^(n-1) [ -(q/n) eta + mu/s ]
-    const double cr = -qj * inv_n * ex + mu[2 * size_t(j)] * is;
-    const double ci = -qj * inv_n * ey + mu[2 * size_t(j) + 1] * is;
-    ar += pr * cr - pi * ci;
-    ai += pr * ci + pi * cr;
+// The curve nodes a target reads: the sorted nodes of the leaf boxes idx[e0 .. e1) (at most
+// kMaxRanges of them; the plan checks), numbered 0 .. total-1 in list order; list_node() maps a
+// position of that numbering to its sorted node. Kernels stage CH of them at a time in LDS.
+constexpr int kMaxRanges = 64;
+constexpr int CH = 256;
+
+struct NodeList {
+  int32_t start[kMaxRanges];  // first sorted node of each range
+  int32_t pre[kMaxRanges + 1];  // prefix of the range lengths
+  int n_ranges;
+};
+
+__device__ __forceinline__ int list_init(NodeList& L, const int32_t* __restrict__ idx, int32_t e0, int32_t e1,
+                                         const int32_t* __restrict__ bptr, int tid) {
+  const int nr = e1 - e0;
+  if (tid < nr) {
+    const int32_t b = idx[e0 + tid];
+    L.start[tid] = bptr[b];
+    L.pre[tid + 1] = bptr[b + 1] - bptr[b];
   }
-  mp[size_t(b) * kReals + 2 * n] = ar;
-  mp[size_t(b) * kReals + 2 * n + 1] = ai;
+  __syncthreads();
+  if (tid == 0) {
+    L.pre[0] = 0;
+    for (int r = 0; r < nr; ++r) L.pre[r + 1] += L.pre[r];
+    L.n_ranges = nr;
+  }
+  __syncthreads();
+  return L.pre[nr];
 }
 
-// one wave per target box; lane l < 40 owns term l; adds onto the far part written by M2L
-__global__ void __launch_bounds__(64) p2l_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ ptr,
-                                                 const int32_t* __restrict__ idx, const int32_t* __restrict__ bptr,
-                                                 const double* __restrict__ geo, const double* __restrict__ sxy,
-                                                 const double* __restrict__ q, const double* __restrict__ mu,
-                                                 double* __restrict__ far) {
-  const int i = blockIdx.x;
-  const int32_t b = tgt[i];
-  const int l = threadIdx.x;
-  if (l >= kTerms) return;
+// sorted node index of list position k < total
+__device__ __forceinline__ int32_t list_node(const NodeList& L, int k) {
+  int r = 0;
+  while (k >= L.pre[r + 1]) ++r;
+  return L.start[r] + (k - L.pre[r]);
+}
+
+// Multipole / local expansion of one target from its nodes: thread t < 240 owns term l = t % 40
+// and the nodes k = g (mod 6) of each staged chunk, g = t / 40; the six partial sums of a term
+// are added in g order at the end (fixed order: deterministic).
+constexpr int kGroups = 6;
+
+// P2M (local == false): terms of eta = (zeta - c) / s; P2L (local == true): terms of 1 / w,
+// w = (zeta - c) / s, added onto the output.
+template <bool local>
+__device__ __forceinline__ void expand(int32_t b, const NodeList& L, int total, const double* __restrict__ geo,
+                                       const double* __restrict__ sxy, const double* __restrict__ q,
+                                       const double* __restrict__ mu, double* __restrict__ out, int tid) {
+  __shared__ double zr[CH], zi[CH], cq[CH], dr[CH], di[CH], lg[CH];
+  __shared__ double red[kGroups][2 * kTerms];
   const double cx = geo[4 * size_t(b)], cy = geo[4 * size_t(b) + 1], s = geo[4 * size_t(b) + 2], is = 1.0 / s;
-  const double log_s = log(s);
+  const int l = tid % kTerms, g = tid / kTerms;
   const double inv_l = l > 0 ? 1.0 / double(l) : 0.0;
   double br = 0.0, bi = 0.0;
-  const int32_t e1 = ptr[i + 1];
-  for (int32_t e = ptr[i]; e < e1; ++e) {
-    const int32_t lb = idx[e];
-    const int32_t j1 = bptr[lb + 1];
-    for (int32_t j = bptr[lb]; j < j1; ++j) {
-      const double wx = (sxy[2 * size_t(j)] - cx) * is, wy = (sxy[2 * size_t(j) + 1] - cy) * is;
-      const double d = wx * wx + wy * wy;
-      const double vx = wx / d, vy = -wy / d;  // 1 / w
-      const double qj = q[j];
-      const double mx = mu[2 * size_t(j)] * is, my = mu[2 * size_t(j) + 1] * is;
-      const double mvx = mx * vx - my * vy, mvy = mx * vy + my * vx;  // (mu / s) / w
-      if (l == 0) {
-        br += qj * (0.5 * log(d) + log_s) - mvx;
-        bi -= mvy;
+  for (int c0 = 0; c0 < total; c0 += CH) {
+    const int nn = min(CH, total - c0);
+    __syncthreads();  // the previous chunk is no longer read
+    if (tid < nn) {
+      const size_t j = size_t(list_node(L, c0 + tid));
+      const double wx = (sxy[2 * j] - cx) * is, wy = (sxy[2 * j + 1] - cy) * is;
+      const double mx = mu[2 * j] * is, my = mu[2 * j + 1] * is;  // mu / s
+      cq[tid] = q[j];
+      if (local) {
+        const double d = wx * wx + wy * wy;
+        const double vx = wx / d, vy = -wy / d;  // 1 / w
+        zr[tid] = vx;
+        zi[tid] = vy;
+        dr[tid] = mx * vx - my * vy;  // (mu / s) / w
+        di[tid] = mx * vy + my * vx;
+        lg[tid] = q[j] * (0.5 * log(d) + log(s));  // q log|zeta - c|
       } else {
-        double pr, pi;
-        cpow(vx, vy, l, pr, pi);
-        // w^-l [ -(q/l) - (mu/s) / w ]
-        const double cr = -qj * inv_l - mvx, ci = -mvy;
-        br += pr * cr - pi * ci;
-        bi += pr * ci + pi * cr;
+        zr[tid] = wx;
+        zi[tid] = wy;
+        dr[tid] = mx;
+        di[tid] = my;
       }
     }
+    __syncthreads();
+    if (g < kGroups) {
+      for (int k = g; k < nn; k += kGroups) {
+        const double qk = cq[k];
+        if (local) {
+          // b_0 += q log|zeta - c| - (mu/s)/w;  b_l += w^-l [ -(q/l) - (mu/s)/w ]
+          if (l == 0) {
+            br += lg[k] - dr[k];
+            bi -= di[k];
+          } else {
+            double pr, pi;
+            cpow(zr[k], zi[k], l, pr, pi);
+            const double cr = -qk * inv_l - dr[k], ci = -di[k];
+            br += pr * cr - pi * ci;
+            bi += pr * ci + pi * cr;
+          }
+        } else {
+          // a_0 += q;  a_n += eta^(n-1) [ -(q/n) eta + mu/s ]
+          if (l == 0) {
+            br += qk;
+          } else {
+            double pr, pi;
+            cpow(zr[k], zi[k], l - 1, pr, pi);
+            const double cr = -qk * inv_l * zr[k] + dr[k], ci = -qk * inv_l * zi[k] + di[k];
+            br += pr * cr - pi * ci;
+            bi += pr * ci + pi * cr;
+          }
+        }
+      }
+      red[g][2 * l] = br;
+      red[g][2 * l + 1] = bi;
+    }
+    br = bi = 0.0;
+    __syncthreads();
+    if (tid < 2 * kTerms) {  // add this chunk's group sums in group order
+      double v = 0.0;
+      for (int gg = 0; gg < kGroups; ++gg) v += red[gg][tid];
+      double* o = out + size_t(b) * kReals + tid;
+      *o = (local || c0 > 0) ? *o + v : v;
+    }
   }
-  far[size_t(b) * kReals + 2 * l] += br;
-  far[size_t(b) * kReals + 2 * l + 1] += bi;
 }
 
-// one block per target leaf, one thread per node; the curve nodes of each adjacent leaf pass
-// through LDS in chunks of 256
+__global__ void __launch_bounds__(256) p2m_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ bptr,
+                                                  const double* __restrict__ geo, const double* __restrict__ sxy,
+                                                  const double* __restrict__ q, const double* __restrict__ mu,
+                                                  double* __restrict__ mp) {
+  __shared__ NodeList L;
+  const int32_t b = tgt[blockIdx.x];
+  const int total = list_init(L, tgt, blockIdx.x, blockIdx.x + 1, bptr, threadIdx.x);
+  expand<false>(b, L, total, geo, sxy, q, mu, mp, threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) p2l_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ idx, const int32_t* __restrict__ bptr,
+                                                  const double* __restrict__ geo, const double* __restrict__ sxy,
+                                                  const double* __restrict__ q, const double* __restrict__ mu,
+                                                  double* __restrict__ far) {
+  __shared__ NodeList L;
+  const int i = blockIdx.x;
+  const int total = list_init(L, idx, ptr[i], ptr[i + 1], bptr, threadIdx.x);
+  expand<true>(tgt[i], L, total, geo, sxy, q, mu, far, threadIdx.x);
+}
+
+// one block per target leaf, one thread per node; u += direct sum over the curve nodes of its
+// adjacent leaves, staged through LDS 256 at a time
 __global__ void __launch_bounds__(256) p2p_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ idx, const int32_t* __restrict__ leaf_box,
                                                   const int32_t* __restrict__ bptr, const double* __restrict__ geo,
                                                   const double* __restrict__ sxy, const double* __restrict__ q,
                                                   const double* __restrict__ mu, LeafNodes nodes, double* __restrict__ u) {
-  __shared__ double sx[256], sy[256], sq[256], smx[256], smy[256];
+  __shared__ double sx[CH], sy[CH], sq[CH], smx[CH], smy[CH];
+  __shared__ NodeList L;
   const int i = blockIdx.x;
   const int32_t a = tgt[i];
   const int m = threadIdx.x;
+  const int total = list_init(L, idx, ptr[i], ptr[i + 1], bptr, m);
   const int32_t b = leaf_box[a];
   const double s = geo[4 * size_t(b) + 2];
   const double x = geo[4 * size_t(b)] + s * nodes.t[m & 15];
   const double y = geo[4 * size_t(b) + 1] + s * nodes.t[m >> 4];
   double vs = 0.0, vd = 0.0;
-  const int32_t e1 = ptr[i + 1];
-  for (int32_t e = ptr[i]; e < e1; ++e) {
-    const int32_t lb = idx[e];
-    const int32_t j0 = bptr[lb], j1 = bptr[lb + 1];
-    for (int32_t c = j0; c < j1; c += 256) {
-      const int nn = min(256, j1 - c);
-      __syncthreads();  // the previous chunk is no longer read
-      if (m < nn) {
-        const size_t j = size_t(c + m);
-        sx[m] = sxy[2 * j];
-        sy[m] = sxy[2 * j + 1];
-        sq[m] = q[j];
-        smx[m] = mu[2 * j];
-        smy[m] = mu[2 * j + 1];
-      }
-      __syncthreads();
-      for (int k = 0; k < nn; ++k) {
-        const double dx = x - sx[k], dy = y - sy[k];
-        const double r2 = dx * dx + dy * dy;
-        vs += sq[k] * log(r2);
-        vd += (smx[k] * dx + smy[k] * dy) / r2;
-      }
+  for (int c0 = 0; c0 < total; c0 += CH) {
+    const int nn = min(CH, total - c0);
+    __syncthreads();  // the previous chunk is no longer read
+    if (m < nn) {
+      const size_t j = size_t(list_node(L, c0 + m));
+      sx[m] = sxy[2 * j];
+      sy[m] = sxy[2 * j + 1];
+      sq[m] = q[j];
+      smx[m] = mu[2 * j];
+      smy[m] = mu[2 * j + 1];
+    }
+    __syncthreads();
+    for (int k = 0; k < nn; ++k) {
+      const double dx = x - sx[k], dy = y - sy[k];
+      const double r2 = dx * dx + dy * dy;
+      vs += sq[k] * log(r2);
+      vd += (smx[k] * dx + smy[k] * dy) / r2;
     }
   }
-  u[size_t(a) * 256 + m] = -kInv2Pi * (0.5 * vs + vd);
+  u[size_t(a) * 256 + m] += -kInv2Pi * (0.5 * vs + vd);
 }
 
 }  // namespace
@@ -188,7 +254,7 @@ hipError_t launch_layer_prep(int64_t n, const int32_t* order, const double* w, c
 hipError_t launch_p2m(int32_t n_tgt, const int32_t* tgt, const int32_t* bptr, const double* geo, const double* sxy,
                       const double* q, const double* mu, double* mp, hipStream_t stream) {
   if (n_tgt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(p2m_kernel, dim3(unsigned(n_tgt)), dim3(64), 0, stream, tgt, bptr, geo, sxy, q, mu, mp);
+  hipLaunchKernelGGL(p2m_kernel, dim3(unsigned(n_tgt)), dim3(256), 0, stream, tgt, bptr, geo, sxy, q, mu, mp);
   return hipGetLastError();
 }
 
@@ -196,7 +262,7 @@ hipError_t launch_p2l(int32_t n_tgt, const int32_t* tgt, const int32_t* ptr, con
                       const double* geo, const double* sxy, const double* q, const double* mu, double* far,
                       hipStream_t stream) {
   if (n_tgt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(p2l_kernel, dim3(unsigned(n_tgt)), dim3(64), 0, stream, tgt, ptr, idx, bptr, geo, sxy, q, mu, far);
+  hipLaunchKernelGGL(p2l_kernel, dim3(unsigned(n_tgt)), dim3(256), 0, stream, tgt, ptr, idx, bptr, geo, sxy, q, mu, far);
   return hipGetLastError();
 }
 

@@ -287,7 +287,8 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
 //   S2M, M2M chain (helper), NEAR_A, FARV (join), FARX + L2L chain (helper), NEAR_B, LOCT (join)
 // so that, with the overlap option, each latency-bound chain runs beside half of the near
 // field, which does not depend on the far field. Without overlap everything runs in this
-// order on one stream, which is also a valid order.
+// order on one stream, which is also a valid order. A layer plan has P2M in S2M's place, P2L in
+// FARX's, and its direct sum P2P, which adds onto LOCT's output, last.
 static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   const int k_up = adjoint ? K_AUP : K_UP, k_down = adjoint ? K_ADOWN : K_DOWN;
   const int k_near = adjoint ? K_ANEAR : K_NEAR, k_loct = adjoint ? K_ALOCT : K_LOCT;
@@ -316,6 +317,9 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
       v.push_back(std::move(near[i]));
     }
   };
+  // layer plans: the direct sum (P2P) adds onto LOCT's output, so it runs last
+  std::vector<Stage> last;
+  if (near.size() == 1 && near[0].custom == C_P2P) last.push_back(std::move(near[0])), near.clear();
   for (Stage& s : head) v.push_back(std::move(s));
   chain(up_chain);
   put_near(0);
@@ -337,6 +341,7 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
     tail[i].join_before = i == 0;
     v.push_back(std::move(tail[i]));
   }
+  for (Stage& s : last) v.push_back(std::move(s));
 }
 
 void build_schedule(Stage& st, int max_blocks, int min_units) {
@@ -894,20 +899,21 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   } else {
     halves = {{0, leaf_order.size()}};
   }
-  if (layer) {  // P2P: every leaf's nodes from the curve nodes in its adjacent leaves (itself included)
+  if (layer) {  // P2P: the leaves with curve nodes in an adjacent leaf (itself included), added onto LOCT
     Stage st; init_stage(st, K_NEAR, "P2P", -1, kNP, kNE, 1, A_OUT, kNP);
     st.custom = C_P2P;
     st.c_ptr.push_back(0);
     for (int32_t a : leaf_order) {
+      bool any = false;
       for (auto& e : Ulist[size_t(a)]) {
         const int32_t lb = P.leaf_box[e.second];
         const int32_t ns = P.box_src_ptr[size_t(lb) + 1] - P.box_src_ptr[size_t(lb)];
         if (ns == 0) continue;
         st.c_idx.push_back(lb);
         P.pairs_p2p += int64_t(ns) * kNP;
+        any = true;
       }
-      st.c_tgt.push_back(a);
-      st.c_ptr.push_back(int32_t(st.c_idx.size()));
+      if (any) { st.c_tgt.push_back(a); st.c_ptr.push_back(int32_t(st.c_idx.size())); }
     }
     st.n_tiles = int(st.c_tgt.size());
     defer(std::move(st), {}, {}, {}, false);
@@ -923,9 +929,8 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (auto& e : Ulist[part[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
     defer(std::move(st), part, std::move(E), std::move(R), false);
   }
-  if (layer) {  // LOCT: L2T + M2T of active W boxes and their kappa(s_a) * mass terms, added onto P2P
+  if (layer) {  // LOCT: L2T + M2T of active W boxes and their kappa(s_a) * mass terms (P2P adds on)
     Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
-    st.accumulate = 1;
     st.r1_all_rows = 1;
     st.fam[0] = {A_MP, kNE, 0}; st.fam[1] = {A_LOC, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
@@ -1061,7 +1066,11 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (auto& th : pool) th.join();
     for (auto& e : err)
       if (e) std::rethrow_exception(e);
-    for (Job& j : jobs) (j.adj ? P.adj : P.fwd).push_back(std::move(j.st));
+    for (Job& j : jobs) {
+      for (size_t i = 0; i + 1 < j.st.c_ptr.size(); ++i)  // the layer kernels stage at most 64 leaves per target
+        if (j.st.c_ptr[i + 1] - j.st.c_ptr[i] > 64) throw std::runtime_error("layer list longer than 64 leaves");
+      (j.adj ? P.adj : P.fwd).push_back(std::move(j.st));
+    }
   }
   arrange_stages(P.fwd, false);
   arrange_stages(P.adj, true);

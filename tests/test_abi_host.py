@@ -243,10 +243,12 @@ def test_layer_plan_counts_match_oracle_lists(vp, seed):
     assert inf["pairs_p2l"] == sum(count.get(a, 0) for cbox in X for a in X[cbox])
     names = [s["name"] for s in plan.stages(False)]
     assert plan.stages(True) == []
-    assert names[0] == "P2M" and names[-1] == "LOCT"
+    assert names[0] == "P2M" and names[-2:] == ["LOCT", "P2P"]  # the direct sum adds onto LOCT
     assert not any(n in ("S2M", "NEAR", "FARX") for n in names)
     i_far = names.index("FARV")
-    assert names.index("P2P") < i_far and names.index("P2L") == i_far + 1
+    assert names.index("P2L") == i_far + 1
+    p2p = [s for s in plan.stages(False) if s["name"] == "P2P"][0]
+    assert p2p["n_tiles"] == sum(1 for a in U if any(count.get(b, 0) for b in U[a]))
     assert all(names.index(n) < i_far for n in names if n.startswith("M2M["))
     assert all(names.index(n) > i_far + 1 for n in names if n.startswith("L2L["))
     # only active boxes are multipole sources: M2L work is that of the active V pairs (each a
