@@ -201,6 +201,44 @@ __global__ void __launch_bounds__(256) p2l_kernel(const int32_t* __restrict__ tg
   expand<true>(tgt[i], L, total, geo, sxy, q, mu, far, threadIdx.x);
 }
 
+// log x for finite x > 0, table-driven after P. T. P. Tang (ACM TOMS 16, 1990): x = 2^e m with
+// m in [1, 2); c = m with all but its 7 leading fraction bits cleared (so m - c is exact and
+// 0 <= r = (m - c) / c < 2^-7); log x = e log 2 + log c + log1p(r), the last by its Taylor
+// series to r^8 (truncation below 2^-60 relative). lc[i] = log(1 + i/128) and ic[i] = 1 / (1 + i/128)
+// come from the block's table. The absolute error is a few units in the last place of
+// max(|e log 2|, 1); just below x = 1 the two leading terms cancel and the relative error of the
+// (small) result grows, which a weighted sum of logarithms does not notice.
+__device__ __forceinline__ double table_log(double x, const double* __restrict__ lc, const double* __restrict__ ic) {
+  int e;
+  double m = frexp(x, &e);  // m in [0.5, 1)
+  m *= 2.0;
+  e -= 1;
+  const unsigned long long bits = __double_as_longlong(m);
+  const int i = int((bits >> 45) & 127);
+  const double c = __longlong_as_double(bits & ~((1ull << 45) - 1));
+  const double r = (m - c) * ic[i];
+  // log1p(r) = r - r^2/2 + r^3/3 - ... + (-1)^7 r^8/8  (Horner)
+  double p = -1.0 / 8.0;
+  p = fma(p, r, 1.0 / 7.0);
+  p = fma(p, r, -1.0 / 6.0);
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -1.0 / 4.0);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  p = fma(p, r * r, r);
+  return fma(double(e), 0.69314718055994530941723212145817657, lc[i] + p);
+}
+
+// 1 / x for finite x > 0: the hardware estimate refined by two Newton-Raphson steps
+// (y <- y + y (1 - x y)), each of which squares the relative error.
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double t = fma(-x, y, 1.0);
+  y = fma(y, t, y);
+  t = fma(-x, y, 1.0);
+  return fma(y, t, y);
+}
+
 // one block per target leaf, one thread per node; u += direct sum over the curve nodes of its
 // adjacent leaves, staged through LDS 256 at a time
 __global__ void __launch_bounds__(256) p2p_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ ptr,
@@ -209,10 +247,16 @@ __global__ void __launch_bounds__(256) p2p_kernel(const int32_t* __restrict__ tg
                                                   const double* __restrict__ sxy, const double* __restrict__ q,
                                                   const double* __restrict__ mu, LeafNodes nodes, double* __restrict__ u) {
   __shared__ double sx[CH], sy[CH], sq[CH], smx[CH], smy[CH];
+  __shared__ double lc[128], ic[128];
   __shared__ NodeList L;
   const int i = blockIdx.x;
   const int32_t a = tgt[i];
   const int m = threadIdx.x;
+  if (m < 128) {  // the logarithm's table (list_init's barrier publishes it)
+    const double c = 1.0 + double(m) / 128.0;
+    lc[m] = log(c);
+    ic[m] = 1.0 / c;
+  }
   const int total = list_init(L, idx, ptr[i], ptr[i + 1], bptr, m);
   const int32_t b = leaf_box[a];
   const double s = geo[4 * size_t(b) + 2];
@@ -234,8 +278,8 @@ __global__ void __launch_bounds__(256) p2p_kernel(const int32_t* __restrict__ tg
     for (int k = 0; k < nn; ++k) {
       const double dx = x - sx[k], dy = y - sy[k];
       const double r2 = dx * dx + dy * dy;
-      vs += sq[k] * log(r2);
-      vd += (smx[k] * dx + smy[k] * dy) / r2;
+      vs = fma(sq[k], table_log(r2, lc, ic), vs);
+      vd = fma(smx[k] * dx + smy[k] * dy, recip(r2), vd);
     }
   }
   u[size_t(a) * 256 + m] += -kInv2Pi * (0.5 * vs + vd);
