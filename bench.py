@@ -55,6 +55,87 @@ def traffic_from_profile(shape):
     return d.get("bytes_per_launch")
 
 
+def _timed(fn, reps):
+    import torch
+
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - a) / reps
+
+
+def _oracle_cores():
+    try:
+        from threadpoolctl import threadpool_info
+
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+    except Exception:
+        return len(os.sched_getaffinity(0))
+
+
+def layer_leg(args, dev):
+    """The glue layer potentials S[sigma] - D[tau] (Sec. 4.4) at every node of the star-cut
+    adaptive tree, from 512 panels of 24 nodes on the star pulled inwards."""
+    import numpy as np
+    import torch
+
+    from workloads import gen
+
+    from paper_2501_17967_amd import LayerPlan
+
+    timed = _timed
+    cores = _oracle_cores()
+
+    print("bench: layer potentials", file=sys.stderr, flush=True)
+    lw = gen.config3(0, lcut=10)
+    curve = gen.star_curve(n_panels=512, order=24, scale=0.95, seed=1)
+    t0 = time.perf_counter()
+    lp = LayerPlan(lw.centres, lw.levels, curve.nodes, curve.weights, curve.normals)
+    torch.cuda.synchronize()
+    t_lplan = time.perf_counter() - t0
+    sig = torch.from_numpy(curve.sigma).to(dev)
+    tau = torch.from_numpy(curve.tau).to(dev)
+    V = torch.empty((lw.n_leaves, 256), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        lp.apply(sig, tau, out=V)
+    t_lay = timed(lambda: lp.apply(sig, tau, out=V), max(5, args.steps))
+    lp.set_timing(True)
+    lp.stage_times()
+    for _ in range(3):
+        lp.apply(sig, tau, out=V)
+    lst = lp.stage_times()
+    lp.set_timing(False)
+    linf = lp.info()
+    n_t = lw.n_leaves * 256
+    names = {"up": "prep+P2M+M2M", "down": "M2L+P2L+L2L", "near": "P2P", "loct": "L2T+M2T"}
+    lay = {"workload": "star-cut adaptive tree (200 Gaussians, lcut 10) x star curve 512 panels x 24 nodes",
+           "targets": n_t, "curve_nodes": curve.n_nodes, "ms": 1e3 * t_lay, "targets_per_s": n_t / t_lay,
+           "plan_s": t_lplan, "source_leaves": linf["n_source_leaves"], "active_boxes": linf["n_active_boxes"],
+           "pairs_direct": linf["pairs_p2p"],
+           "stage_ms": {names[k]: round(v[0] / 3, 4) for k, v in lst.items() if v[1]}}
+    if lst["near"][1]:
+        lay["direct_pairs_per_s"] = linf["pairs_p2p"] / (lst["near"][0] / 3 * 1e-3)
+    if not args.no_cpu_baseline:
+        # the oracle (direct sum over all curve nodes) on a bounded sample of the targets,
+        # which also checks the sampled values
+        from oracle import layer as olayer
+
+        tg = olayer.leaf_targets(lw.centres, lw.levels)
+        idx = np.random.default_rng(args.seed + 2).choice(n_t, 50000, replace=False)
+        t0 = time.perf_counter()
+        ref = olayer.layer_potential(tg[idx], curve.nodes, curve.weights, curve.normals, curve.sigma, curve.tau)
+        t_cpu = time.perf_counter() - t0
+        got = V.reshape(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        lay["rel_err_vs_oracle_sampled"] = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        lay["cpu_baseline"] = {"value": idx.size / t_cpu, "unit": "targets/s", "cores": int(cores), "kind": "oracle",
+                               "sample": "%d random leaf nodes, direct sum over all %d curve nodes: %.1f s"
+                                         % (idx.size, curve.n_nodes, t_cpu)}
+    lp.close()
+    return lay
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +145,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-layer", action="store_true", help="skip the layer-potential evaluation leg")
+    ap.add_argument("--layer-only", action="store_true",
+                    help="run only the layer-potential leg and print its object (for profiling)")
     ap.add_argument("--batched-trees", type=int, default=256)
     ap.add_argument("--tile-leaf", type=int, default=0, help="0: chosen by the autotuner")
     ap.add_argument("--tile-box", type=int, default=0, help="0: chosen by the autotuner")
@@ -88,6 +171,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.calibrate_copy_mib, "copies": 5}))
+        return
+
+    if args.layer_only:
+        print(json.dumps({"layer_potential": layer_leg(args, torch.device("cuda:0"))}), flush=True)
         return
 
     from paper_2501_17967_amd import Plan, autotune
@@ -312,53 +399,7 @@ def main():
         forest.close()
 
     if not args.no_layer:
-        # glue layer potentials S[sigma] - D[tau] (Sec. 4.4) at every node of the star-cut
-        # adaptive tree, from 512 panels of 24 nodes on the star pulled inwards
-        from paper_2501_17967_amd import LayerPlan
-
-        print("bench: layer potentials", file=sys.stderr, flush=True)
-        lw = gen.config3(0, lcut=10)
-        curve = gen.star_curve(n_panels=512, order=24, scale=0.95, seed=1)
-        t0 = time.perf_counter()
-        lp = LayerPlan(lw.centres, lw.levels, curve.nodes, curve.weights, curve.normals)
-        torch.cuda.synchronize()
-        t_lplan = time.perf_counter() - t0
-        sig = torch.from_numpy(curve.sigma).to(dev)
-        tau = torch.from_numpy(curve.tau).to(dev)
-        V = torch.empty((lw.n_leaves, 256), dtype=torch.float64, device=dev)
-        for _ in range(3):
-            lp.apply(sig, tau, out=V)
-        t_lay = timed(lambda: lp.apply(sig, tau, out=V), max(5, args.steps))
-        lp.set_timing(True)
-        lp.stage_times()
-        for _ in range(3):
-            lp.apply(sig, tau, out=V)
-        lst = lp.stage_times()
-        lp.set_timing(False)
-        linf = lp.info()
-        n_t = lw.n_leaves * 256
-        lay = {"workload": "star-cut adaptive tree (200 Gaussians, lcut 10) x star curve 512 panels x 24 nodes",
-               "targets": n_t, "curve_nodes": curve.n_nodes, "ms": 1e3 * t_lay, "targets_per_s": n_t / t_lay,
-               "plan_s": t_lplan, "source_leaves": linf["n_source_leaves"], "active_boxes": linf["n_active_boxes"],
-               "pairs_direct": linf["pairs_p2p"],
-               "stage_ms": {k: round(v[0] / 3, 4) for k, v in lst.items() if v[1]}}
-        if not args.no_cpu_baseline:
-            # the oracle (direct sum over all curve nodes) on a bounded sample of the targets,
-            # which also checks the sampled values
-            from oracle import layer as olayer
-
-            tg = olayer.leaf_targets(lw.centres, lw.levels)
-            idx = np.random.default_rng(args.seed + 2).choice(n_t, 50000, replace=False)
-            t0 = time.perf_counter()
-            ref = olayer.layer_potential(tg[idx], curve.nodes, curve.weights, curve.normals, curve.sigma, curve.tau)
-            t_cpu = time.perf_counter() - t0
-            got = V.reshape(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
-            lay["rel_err_vs_oracle_sampled"] = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-            lay["cpu_baseline"] = {"value": idx.size / t_cpu, "unit": "targets/s", "cores": int(cores), "kind": "oracle",
-                                   "sample": "%d random leaf nodes, direct sum over all %d curve nodes: %.1f s"
-                                             % (idx.size, curve.n_nodes, t_cpu)}
-        out["layer_potential"] = lay
-        lp.close()
+        out["layer_potential"] = layer_leg(args, dev)
 
     plan.close()
     print(json.dumps(out), flush=True)
