@@ -21,7 +21,8 @@ nodes         node/weight convention of a leaf (first-kind Chebyshev, Fejer-1 we
 closed_forms  uniform-square and Gaussian potentials in closed form, exterior tail
 quad          the log-kernel integral of one Lagrange basis over a box (adaptive
               subdivision, plain C in ``_quad.c``), the near tables built from it, and
-              the direct sum u = sum_b int_{B_b} G f_h  (the plain definition)
+              the direct sum u = sum_b int_{B_b} G f_h  (the plain definition), also at
+              arbitrary points and with its gradient
 tree          integer box keys, tiling and 2:1-balance checks, the U/V/W/X interaction
               lists of the adaptive FMM by key arithmetic
 fmm           a CPU machine code with complex scaled expansions (Greengard-Rokhlin), its

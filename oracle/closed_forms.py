@@ -6,7 +6,7 @@ introduction (Sec. 1, the convolution approach), with the sign that makes -Lap u
 * ``square_potential``: u(x) = int_{[a1,b1]x[a2,b2]} G(x - y) dy for a uniform unit
   density. With F(X,Y) = XY log(X^2+Y^2) - 3XY + X^2 atan(Y/X) + Y^2 atan(X/Y) one has
   d^2F/dXdY = log(X^2+Y^2), so the integral is -(1/4pi) times the signed corner sum
-  of F at (x - corner).
+  of F at (x - corner). ``square_gradient`` differentiates that sum term by term.
 * ``gaussian_potential``: whole-plane potential of f = A exp(-|y-c|^2/(2 sigma^2)).
   Circle averages of log|x-y| give u(r) = -int_0^inf rho f(rho) log max(r, rho) d rho,
   which integrates to u(r) = -(A sigma^2/2) [log(2 sigma^2) - gamma + Ein(r^2/(2 sigma^2))],
@@ -40,6 +40,31 @@ def square_potential(x, y, a1, b1, a2, b2):
     Y1, Y2 = y - b2, y - a2
     s = _F(X2, Y2) - _F(X1, Y2) - _F(X2, Y1) + _F(X1, Y1)
     return -s / (4.0 * np.pi)
+
+
+def _dF(X, Y):
+    """(dF/dX, dF/dY) of F above: dF/dX = Y log(X^2+Y^2) - 2Y + 2X atan(Y/X) (symmetric in Y)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    r2 = X * X + Y * Y
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lg = np.where(r2 > 0, np.log(np.where(r2 > 0, r2, 1.0)), 0.0)
+        ax = np.where(X != 0, np.arctan(Y / np.where(X != 0, X, 1.0)), 0.0)
+        ay = np.where(Y != 0, np.arctan(X / np.where(Y != 0, Y, 1.0)), 0.0)
+    return Y * lg - 2.0 * Y + 2.0 * X * ax, X * lg - 2.0 * X + 2.0 * Y * ay
+
+
+def square_gradient(x, y, a1, b1, a2, b2):
+    """Gradient of ``square_potential`` in (x, y): the same signed corner sum of dF."""
+    X1, X2 = x - b1, x - a1
+    Y1, Y2 = y - b2, y - a2
+    gx = np.zeros(np.broadcast(x, y).shape)
+    gy = np.zeros_like(gx)
+    for (X, Y, sgn) in ((X2, Y2, 1.0), (X1, Y2, -1.0), (X2, Y1, -1.0), (X1, Y1, 1.0)):
+        dx, dy = _dF(X, Y)
+        gx = gx + sgn * dx
+        gy = gy + sgn * dy
+    return -gx / (4.0 * np.pi), -gy / (4.0 * np.pi)
 
 
 def ein(t):

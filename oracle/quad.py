@@ -60,6 +60,7 @@ def _load(p=nodes.P_DEFAULT):
         lib.oq_init.restype = ctypes.c_int
         lib.oq_logint.argtypes = [ctypes.c_int, dp, dp]
         lib.oq_direct_far.argtypes = [ctypes.c_int, dp, lp, lp, ctypes.c_int, dp, dp, dp, dp]
+        lib.oq_direct_grad.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp]
         t = np.ascontiguousarray(nodes.cheb1_points(p))
         lam = np.ascontiguousarray(nodes.barycentric_weights(p))
         wt = np.ascontiguousarray(nodes.tensor_weights(p))
@@ -209,3 +210,20 @@ def direct_potential(tree, f, samples=None):
     far = direct_far(xy, excl, tree.centres, tree.halfw, f)
     u = near + far
     return u.reshape(tree.n_leaves, 256) if full else u
+
+
+def potential_at_points(centres, halfw, f, xy, grad=False):
+    """u(x) = sum_b int_{B_b} G(x - y) f_h(y) dy at arbitrary points x (n, 2) by the plain
+    definition (adaptive quadrature over every leaf, no tables), and with grad=True also its
+    gradient (n, 2) (the same sum with grad_x G = -(1/2pi) (x - y)/|x - y|^2)."""
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+    u = direct_far(xy, [[] for _ in range(xy.shape[0])], centres, halfw, f)
+    if not grad:
+        return u
+    lib = _load()
+    c = np.ascontiguousarray(centres, dtype=np.float64)
+    h = np.ascontiguousarray(halfw, dtype=np.float64)
+    ff = np.ascontiguousarray(f, dtype=np.float64).reshape(-1, nodes.P_DEFAULT ** 2)
+    g = np.zeros((xy.shape[0], 2))
+    lib.oq_direct_grad(xy.shape[0], _dp(xy), c.shape[0], _dp(c), _dp(h), _dp(ff), _dp(g))
+    return u, g
