@@ -103,6 +103,9 @@ typedef struct {
   int64_t n_active_boxes;   /* boxes whose subtree holds nodes (the only multipole sources) */
   int64_t pairs_p2p;        /* (leaf node, curve node) pairs summed directly */
   int64_t pairs_p2l;        /* (box, curve node) pairs expanded directly into local expansions */
+  /* plans with evaluation points (volpot_plan_points; zero otherwise) */
+  int64_t n_points;         /* evaluation points */
+  int64_t pairs_points;     /* (point, adjacent leaf) pairs, each a precomputed 3 x 256 moment block */
 } volpot_info;
 
 /* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
@@ -130,6 +133,25 @@ int volpot_apply(volpot_plan_t plan, const double* f_dev, double* u_dev, void* h
  * (the gradient of <ubar, A f> with respect to f). Same layout and stream rules. */
 int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fbar_dev,
                          void* hip_stream);
+
+/* Off-grid evaluation (the glue step of Sec. 4.4 needs v_bulk and its normal derivative on the
+ * fictitious curve, away from the leaf nodes): a volume plan that can also evaluate
+ *     u(x) = int_{Omega_B} G(x - y) f_h(y) dy  and  grad u(x)
+ * at n_points fixed points x (host, n_points x 2, inside the root box [-1,1]^2). The box code's
+ * own decomposition is used at each point: the local expansion of the leaf holding it, the
+ * multipoles of that leaf's W list, and the integrals over its adjacent leaves, whose moments
+ * against the leaf basis are computed at plan time (adaptive quadrature, a few milliseconds
+ * per point on the host). A point on an edge between leaves belongs to the leaf on its
+ * right / upper side. Returns VOLPOT_ERR_ARG for a point outside the root box; the tree errors
+ * of volpot_plan otherwise. The plan is a full volume plan (volpot_apply and the adjoint work). */
+int volpot_plan_points(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p,
+                       int64_t n_points, const double* points, const volpot_options* opt, volpot_plan_t* out);
+
+/* One forward apply (as volpot_apply: u_dev at the leaf nodes) that also writes u at the plan's
+ * points to u_pts_dev (device, n_points) and, when grad_pts_dev is not NULL, its gradient
+ * (device, n_points x 2: d/dx, d/dy). Asynchronous on the stream. */
+int volpot_apply_points(volpot_plan_t plan, const double* f_dev, double* u_dev, double* u_pts_dev,
+                        double* grad_pts_dev, void* hip_stream);
 
 /* Glue layer potentials (Sec. 4.4): a plan that evaluates
  *

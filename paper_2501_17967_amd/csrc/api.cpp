@@ -142,6 +142,8 @@ struct volpot_plan_s {
   int32_t *d_order = nullptr, *d_bptr = nullptr, *d_leaf_box = nullptr;
   double *d_sxy = nullptr, *d_sw = nullptr, *d_sn = nullptr, *d_geo = nullptr, *d_sq = nullptr, *d_smu = nullptr;
   LeafNodes nodes{};
+  // evaluation points (volpot_plan_points)
+  PointParams pts{};
 };
 
 namespace {
@@ -245,6 +247,9 @@ int upload(volpot_plan_s* p) {
   size_t o_order = add_bytes(total, P.src_order), o_sxy = add_bytes(total, P.src_xy), o_sw = add_bytes(total, P.src_w);
   size_t o_sn = add_bytes(total, P.src_n), o_bptr = add_bytes(total, P.box_src_ptr), o_geo = add_bytes(total, P.box_geo);
   size_t o_lbox = add_bytes(total, leaf_box);
+  size_t o_pxy = add_bytes(total, P.pt_xy), o_ploc = add_bytes(total, P.pt_loc), o_pnp = add_bytes(total, P.pt_near_ptr);
+  size_t o_pnl = add_bytes(total, P.pt_near_leaf), o_pmom = add_bytes(total, P.pt_mom), o_pwp = add_bytes(total, P.pt_w_ptr);
+  size_t o_pwb = add_bytes(total, P.pt_w_box);
   size_t o_sq = (total + 255) & ~size_t(255); total = o_sq + std::max<size_t>(size_t(P.n_src), 1) * sizeof(double);
   size_t o_smu = (total + 255) & ~size_t(255); total = o_smu + std::max<size_t>(size_t(P.n_src), 1) * 2 * sizeof(double);
   std::vector<char> host(total, 0);
@@ -264,6 +269,8 @@ int upload(volpot_plan_s* p) {
   put(o_s2, s2);
   put(o_order, P.src_order); put(o_sxy, P.src_xy); put(o_sw, P.src_w); put(o_sn, P.src_n);
   put(o_bptr, P.box_src_ptr); put(o_geo, P.box_geo); put(o_lbox, leaf_box);
+  put(o_pxy, P.pt_xy); put(o_ploc, P.pt_loc); put(o_pnp, P.pt_near_ptr); put(o_pnl, P.pt_near_leaf);
+  put(o_pmom, P.pt_mom); put(o_pwp, P.pt_w_ptr); put(o_pwb, P.pt_w_box);
   if (hipMalloc(&p->d_block, total) != hipSuccess) return VOLPOT_ERR_OOM;
   p->device_bytes = int64_t(total);
   if (hipMemcpy(p->d_block, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return VOLPOT_ERR_HIP;
@@ -302,6 +309,16 @@ int upload(volpot_plan_s* p) {
   p->d_leaf_box = reinterpret_cast<int32_t*>(b + o_lbox);
   p->d_sq = reinterpret_cast<double*>(b + o_sq);
   p->d_smu = reinterpret_cast<double*>(b + o_smu);
+  p->pts.xy = reinterpret_cast<const double*>(b + o_pxy);
+  p->pts.loc_box = reinterpret_cast<const int32_t*>(b + o_ploc);
+  p->pts.near_ptr = reinterpret_cast<const int32_t*>(b + o_pnp);
+  p->pts.near_leaf = reinterpret_cast<const int32_t*>(b + o_pnl);
+  p->pts.mom = reinterpret_cast<const double*>(b + o_pmom);
+  p->pts.w_ptr = reinterpret_cast<const int32_t*>(b + o_pwp);
+  p->pts.w_box = reinterpret_cast<const int32_t*>(b + o_pwb);
+  p->pts.geo = p->d_geo;
+  p->pts.loc = p->d_loc;
+  p->pts.mp = p->d_mp;
   {
     double w[kP];
     volpot_nodes(kP, p->nodes.t, w);
@@ -500,7 +517,8 @@ void free_plan(volpot_plan_s* p) {
 }
 
 int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels, int32_t p,
-              const volpot_options* opt, volpot_plan_t* out, const LayerSources* layer = nullptr) {
+              const volpot_options* opt, volpot_plan_t* out, const LayerSources* layer = nullptr,
+              const PointTargets* points = nullptr) {
   if (!out || !offsets || !centres || !levels || n_trees <= 0) return VOLPOT_ERR_ARG;
   if (p != kP) return VOLPOT_ERR_UNSUPPORTED;
   if (offsets[0] != 0) return VOLPOT_ERR_ARG;
@@ -516,7 +534,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   int rc;
   try {
     rc = build_plan(n_trees, offsets, centres, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr, layer);
+                    nullptr, layer, points);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {
@@ -575,6 +593,36 @@ int volpot_apply_adjoint(volpot_plan_t plan, const double* ubar_dev, double* fba
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   if (plan->use_graph) return run_graph(plan, true, ubar_dev, nullptr, fbar_dev, s);
   return run(plan, true, ubar_dev, nullptr, fbar_dev, s, plan->timing);
+}
+
+int volpot_plan_points(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p, int64_t n_points,
+                       const double* points, const volpot_options* opt, volpot_plan_t* out) {
+  if (n_leaves <= 0 || n_points < 0 || n_points > (int64_t(1) << 31) - 1 || (n_points > 0 && !points))
+    return VOLPOT_ERR_ARG;
+  int64_t off[2] = {0, n_leaves};
+  PointTargets pt{n_points, points};
+  return make_plan(1, off, centres, levels, p, opt, out, nullptr, &pt);
+}
+
+int volpot_apply_points(volpot_plan_t plan, const double* f_dev, double* u_dev, double* u_pts_dev, double* grad_pts_dev,
+                        void* hip_stream) {
+  if (!plan || !f_dev || !u_dev || !aligned16(f_dev) || !aligned16(u_dev) || f_dev == u_dev) return VOLPOT_ERR_ARG;
+  if (plan->host.n_pts > 0 && !u_pts_dev) return VOLPOT_ERR_ARG;
+  if (plan->host_only || plan->host.layer) return VOLPOT_ERR_STATE;
+  DeviceGuard dg(plan->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  int rc = plan->use_graph ? run_graph(plan, false, f_dev, nullptr, u_dev, s)
+                           : run(plan, false, f_dev, nullptr, u_dev, s, plan->timing);
+  if (rc != VOLPOT_OK) return rc;
+  PointParams pp = plan->pts;
+  pp.f = f_dev;
+  pp.u = u_pts_dev;
+  pp.grad = grad_pts_dev;
+  hipEvent_t ea, eb;
+  timed_begin(plan, plan->timing, K_LOCT, s, &ea, &eb);
+  hipError_t e = launch_points(pp, plan->host.n_pts, s);
+  timed_end(plan, K_LOCT, s, ea, eb);
+  return e == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
 }
 
 int volpot_layer_plan(const double* centres, const int32_t* levels, int64_t n_leaves, int32_t p, int64_t n_nodes,
@@ -638,6 +686,8 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   out->n_active_boxes = P.n_active;
   out->pairs_p2p = P.pairs_p2p;
   out->pairs_p2l = P.pairs_p2l;
+  out->n_points = P.n_pts;
+  out->pairs_points = int64_t(P.pt_near_leaf.size());
   out->device_bytes = plan->device_bytes + (plan->tables ? int64_t(plan->tables->bytes) : 0);
   return VOLPOT_OK;
 }

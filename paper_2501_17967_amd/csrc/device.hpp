@@ -82,4 +82,23 @@ hipError_t launch_p2p(int32_t n_tgt, const int32_t* tgt, const int32_t* ptr, con
                       const int32_t* bptr, const double* geo, const double* sxy, const double* q, const double* mu,
                       const LeafNodes& nodes, double* u, hipStream_t stream);
 
+// ---------------------------------------------------------------- evaluation points (points.hip)
+struct PointParams {
+  const double* xy;         // n x 2
+  const int32_t* loc_box;   // box whose local expansion applies, -1 for leaves above level 2
+  const int32_t* near_ptr;  // n + 1
+  const int32_t* near_leaf;
+  const double* mom;        // per pair 3 x 256
+  const int32_t* w_ptr;     // n + 1
+  const int32_t* w_box;
+  const double* geo;        // per box: centre x, centre y, half-width, 0
+  const double* f;          // the apply's input, [n_leaves][256]
+  const double* loc;        // local expansions, [n_boxes][80]
+  const double* mp;         // multipoles, [n_boxes][80]
+  double* u;                // n
+  double* grad;             // n x 2, or null
+};
+// u (and grad) at the n points, after a forward apply that filled loc and mp
+hipError_t launch_points(const PointParams& p, int64_t n, hipStream_t stream);
+
 }  // namespace vp

@@ -430,9 +430,11 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
 }
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
-               int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer) {
+               int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer,
+               const PointTargets* points) {
   if (layer && (n_trees != 1 || layer->n < 0 || (layer->n > 0 && (!layer->xy || !layer->weights || !layer->normals))))
     return VOLPOT_ERR_ARG;
+  if (points && (layer || n_trees != 1 || points->n < 0 || (points->n > 0 && !points->xy))) return VOLPOT_ERR_ARG;
   const double kLn2 = std::log(2.0);
   const double kInv2Pi = 1.0 / (2.0 * M_PI);
   P = Plan();
@@ -628,6 +630,71 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t b = 0; b < NB; ++b) { active[size_t(b)] = cnt[size_t(b)] > 0; P.n_active += active[size_t(b)]; }
   }
   auto use = [&](int32_t b) { return !layer || active[size_t(b)]; };
+
+  // ---------------------------------------------------------------- evaluation points
+  // Each point belongs to a leaf a (the rule of the layer nodes). At the point, u is a's local
+  // expansion (level >= 2), the multipoles of a's W list, and the integrals over a's U list,
+  // which take precomputed moment vectors: for leaf b with half-width s and reference point
+  // xi = (x - c_b) / s, int_{B_b} G(x - y) l_k dy = s^2 (-1/2pi) (log s W_k + I_k(xi)) and its
+  // x-gradient s (-1/2pi) grad I_k(xi) (point_moments). Moments are computed in parallel.
+  if (points) {
+    const int64_t n = points->n;
+    P.n_pts = n;
+    P.box_geo.assign(size_t(NB) * 4, 0.0);
+    for (int32_t b = 0; b < NB; ++b) {
+      P.box_geo[4 * size_t(b)] = cx(b);
+      P.box_geo[4 * size_t(b) + 1] = cy(b);
+      P.box_geo[4 * size_t(b) + 2] = hw(b);
+    }
+    const int32_t root = find_box(0, pack(0, 0, 0));
+    P.pt_xy.assign(points->xy, points->xy + 2 * n);
+    P.pt_box.resize(size_t(n));
+    P.pt_loc.resize(size_t(n));
+    P.pt_near_ptr.assign(1, 0);
+    P.pt_w_ptr.assign(1, 0);
+    for (int64_t j = 0; j < n; ++j) {
+      const double x = points->xy[2 * j], y = points->xy[2 * j + 1];
+      if (!(x >= -1.0 && x <= 1.0 && y >= -1.0 && y <= 1.0)) {
+        if (bad) *bad = j;
+        return VOLPOT_ERR_ARG;
+      }
+      int32_t b = root;
+      while (P.box_leaf[b] < 0) b = P.box_child[b][int(x >= cx(b)) + 2 * int(y >= cy(b))];
+      const int32_t a = P.box_leaf[b];
+      P.pt_box[size_t(j)] = b;
+      P.pt_loc[size_t(j)] = levels[a] >= 2 ? b : -1;
+      for (auto& e : Ulist[size_t(a)]) P.pt_near_leaf.push_back(e.second);
+      P.pt_near_ptr.push_back(int32_t(P.pt_near_leaf.size()));
+      for (auto& e : Wlist[size_t(a)]) P.pt_w_box.push_back(e.second);
+      P.pt_w_ptr.push_back(int32_t(P.pt_w_box.size()));
+    }
+    const size_t n_pairs = P.pt_near_leaf.size();
+    P.pt_mom.assign(n_pairs * 3 * kNP, 0.0);
+    std::vector<int32_t> pair_pt(n_pairs);
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t e = P.pt_near_ptr[size_t(j)]; e < P.pt_near_ptr[size_t(j) + 1]; ++e) pair_pt[size_t(e)] = int32_t(j);
+    std::atomic<size_t> next(0);
+    auto work = [&]() {
+      double I[kNP], Ix[kNP], Iy[kNP];
+      for (size_t e; (e = next.fetch_add(1)) < n_pairs;) {
+        const int32_t j = pair_pt[e], bl = P.pt_near_leaf[e], bb = P.leaf_box[bl];
+        const double s = hw(bb);
+        point_moments((P.pt_xy[2 * size_t(j)] - cx(bb)) / s, (P.pt_xy[2 * size_t(j) + 1] - cy(bb)) / s, I, Ix, Iy);
+        double* m = P.pt_mom.data() + e * 3 * kNP;
+        const double ls = std::log(s);
+        for (int k = 0; k < kNP; ++k) {
+          m[k] = -kInv2Pi * s * s * (ls * tensor_weight(k) + I[k]);
+          m[kNP + k] = -kInv2Pi * s * Ix[k];
+          m[2 * kNP + k] = -kInv2Pi * s * Iy[k];
+        }
+      }
+    };
+    const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned i = 1; i < nt && i < n_pairs; ++i) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+  }
 
   // ---------------------------------------------------------------- stages
   const Matrices& mats = matrices();

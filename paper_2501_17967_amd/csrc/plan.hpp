@@ -74,6 +74,10 @@ struct Matrices {
   std::vector<double> nnz;  // non-zero count of each
 };
 const Matrices& matrices();  // built once per process (near tables by polar quadrature)
+// Moments at an arbitrary xi over the reference square [-1,1]^2, for each tensor basis l_k:
+// I_k = int log|xi - eta| l_k(eta) d eta and the xi-gradient (Ix_k, Iy_k) of it (256 each).
+void point_moments(double x0, double y0, double* I, double* Ix, double* Iy);
+double tensor_weight(int k);  // int l_k over the reference square
 void set_table_cache_dir(const char* dir);
 
 // ---------------------------------------------------------------- plan
@@ -169,6 +173,22 @@ struct Plan {
   std::vector<double> src_xy, src_w, src_n;  // sorted positions (x, y), weights, normals (x, y)
   std::vector<int32_t> box_src_ptr;  // n_boxes + 1: the sorted nodes inside each leaf box
   std::vector<double> box_geo;       // per box: centre x, centre y, half-width, 0
+  // evaluation points (volume plans with points; empty otherwise)
+  int64_t n_pts = 0;
+  std::vector<double> pt_xy;            // n_pts x 2
+  std::vector<int32_t> pt_box;          // box of the leaf holding each point
+  std::vector<int32_t> pt_loc;          // that box if its level >= 2 (it has a local expansion), else -1
+  std::vector<int32_t> pt_near_ptr;     // n_pts + 1: pairs (point, adjacent leaf)
+  std::vector<int32_t> pt_near_leaf;    // caller leaf of each pair
+  std::vector<double> pt_mom;           // per pair 3 x 256: weights of u, d/dx, d/dy on that leaf's values
+  std::vector<int32_t> pt_w_ptr;        // n_pts + 1
+  std::vector<int32_t> pt_w_box;        // W-list boxes of each point's leaf
+};
+
+// Points at which a volume plan also evaluates u and its gradient (host, caller order).
+struct PointTargets {
+  int64_t n;
+  const double* xy;  // n x 2
 };
 
 // Quadrature nodes of a curve carrying the layer densities (host arrays, caller order).
@@ -193,9 +213,10 @@ void build_schedule(Stage& st, int max_blocks, int min_units);
 // overlap > 0: near field split in two launches, each concurrent with one chain of the far
 // field on the helper stream (stage order and flags below); 0: one stream, plan order.
 // layer != nullptr: plan the evaluation of the layer potentials of those nodes at every leaf
-// node of one tree instead (no adjoint stages).
+// node of one tree instead (no adjoint stages). points != nullptr (one tree): also prepare the
+// evaluation of u and its gradient at those points (near-field moments, lists).
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
-               const LayerSources* layer = nullptr);
+               const LayerSources* layer = nullptr, const PointTargets* points = nullptr);
 
 }  // namespace vp

@@ -10,6 +10,8 @@ Every step of the volume potential runs in the HIP library; PyTorch supplies dev
     u = volume_potential(f, plan)           # autograd: backward runs apply_adjoint
     lp = LayerPlan(centres, levels, nodes, weights, normals)   # glue layer potentials
     v = lp.apply(sigma, tau)                # S[sigma] - D[tau] at every leaf node
+    pp = PointPlan(centres, levels, points) # u and grad u also at arbitrary points
+    u, u_pts, grad = pp.apply_points(f)
 
 Sign convention: u = int G f with G = -(1/2pi) log|x - y| (so -Lap u = f); the paper's v_bulk
 (Sec. 4.2, eq. (vbulk)) is -u.
@@ -30,6 +32,7 @@ EXPORTED = [
     "volpot_validate_tree", "volpot_nodes", "volpot_plan_destroy", "volpot_status_string",
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
     "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune", "volpot_layer_plan", "volpot_layer_apply",
+    "volpot_plan_points", "volpot_apply_points",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -59,7 +62,7 @@ class Info(ctypes.Structure):
                 ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("flops_issued_kind", ctypes.c_double * 9), ("n_layer_nodes", ctypes.c_int64),
                 ("n_source_leaves", ctypes.c_int64), ("n_active_boxes", ctypes.c_int64), ("pairs_p2p", ctypes.c_int64),
-                ("pairs_p2l", ctypes.c_int64)]
+                ("pairs_p2l", ctypes.c_int64), ("n_points", ctypes.c_int64), ("pairs_points", ctypes.c_int64)]
 
 
 class StageInfo(ctypes.Structure):
@@ -114,6 +117,9 @@ def lib():
         L.volpot_layer_plan.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp,
                                         ctypes.POINTER(Options), ctypes.POINTER(_vp)]
         L.volpot_layer_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.volpot_plan_points.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _dp,
+                                         ctypes.POINTER(Options), ctypes.POINTER(_vp)]
+        L.volpot_apply_points.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         _lib = L
     return _lib
 
@@ -286,6 +292,39 @@ class Plan:
         _check(lib().volpot_apply_adjoint(self._h, ctypes.c_void_p(ubar.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                           _stream_handle(stream)), "volpot_apply_adjoint")
         return out
+
+
+class PointPlan(Plan):
+    """A volume plan for one tree that also evaluates u and grad u at fixed points (m, 2); all of
+    Plan's calls work on it."""
+
+    def __init__(self, centres, levels, points, p=16, *, host_only=False, use_graph=False, tile_leaf=0, tile_box=0,
+                 table_cache=None, split_min=0, overlap=0):
+        c, l = _host_tree(centres, levels)
+        x = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 2))
+        self.n_leaves = c.shape[0]
+        self.n_points = x.shape[0]
+        self.n_trees = 1
+        opt = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
+                      table_cache.encode() if table_cache else None, int(split_min), int(overlap))
+        h = _vp()
+        _check(lib().volpot_plan_points(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), self.n_leaves, p, self.n_points,
+                                        x.ctypes.data_as(_dp), ctypes.byref(opt), ctypes.byref(h)), "volpot_plan_points")
+        self._h = h
+        self.host_only = host_only
+
+    def apply_points(self, f, out=None, grad=True, stream=None):
+        """(u at the leaf nodes, u at the points (m,), grad u at the points (m, 2) or None)."""
+        import torch
+
+        f, out = self._prep(f, out)
+        up = torch.empty(self.n_points, dtype=torch.float64, device=f.device)
+        gp = torch.empty((self.n_points, 2), dtype=torch.float64, device=f.device) if grad else None
+        _check(lib().volpot_apply_points(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(up.data_ptr() if self.n_points else 0),
+                                         ctypes.c_void_p(gp.data_ptr()) if gp is not None and self.n_points else None,
+                                         _stream_handle(stream)), "volpot_apply_points")
+        return out, up, gp
 
 
 class LayerPlan(Plan):

@@ -289,3 +289,23 @@ def test_layer_plan_errors(vp):
     assert L.volpot_layer_apply(p._h, a16, a16, ctypes.c_void_p(520 + 4), None) == vp.ERR_ARG
     assert L.volpot_apply(p._h, a16, b16, None) == vp.ERR_STATE
     assert L.volpot_layer_apply(p0._h, None, None, b16, None) == vp.ERR_STATE  # no nodes: no densities needed
+
+
+# ---------------------------------------------------------------- evaluation points (host side)
+def test_point_plan_counts_and_errors(vp):
+    w = gen.random_small_tree(4, max_level=5, n_splits=8)
+    rng = np.random.default_rng(0)
+    pts = np.vstack([rng.uniform(-1, 1, (30, 2)), [[0.5, 0.5], [1.0, 1.0], [-1.0, 0.25], [0.0, 0.0]]])
+    plan = vp.PointPlan(w.centres, w.levels, pts, host_only=True)
+    inf = plan.info()
+    T = tree.Tree(w.centres, w.levels)
+    U, V, W, X = T.lists()
+    assert inf["n_points"] == len(pts)
+    assert inf["pairs_points"] == sum(len(U[_leaf_of_point(T, x, y)]) for x, y in pts)
+    # it is a full volume plan
+    assert [s["name"] for s in plan.stages(False)][0] == "S2M" and plan.stages(True)
+    for bad in ((1.0000001, 0.0), (np.nan, 0.2)):
+        with pytest.raises(vp.VolpotError) as e:
+            vp.PointPlan(w.centres, w.levels, np.vstack([pts, [bad]]), host_only=True)
+        assert e.value.code == vp.ERR_ARG
+    assert vp.PointPlan(w.centres, w.levels, np.zeros((0, 2)), host_only=True).info()["pairs_points"] == 0
