@@ -136,6 +136,56 @@ def layer_leg(args, dev):
     return lay
 
 
+def points_leg(args, dev):
+    """u and grad u at the nodes of a curve inside the star-cut adaptive tree (the values the
+    glue step needs on the fictitious curve), in one forward apply of the volume potential."""
+    import numpy as np
+    import torch
+
+    from paper_2501_17967_amd import PointPlan
+    from workloads import gen
+
+    print("bench: off-grid points", file=sys.stderr, flush=True)
+    pw = gen.config3(0, lcut=10)
+    curve = gen.star_curve(n_panels=128, order=24, scale=0.95, seed=1)
+    t0 = time.perf_counter()
+    pp = PointPlan(pw.centres, pw.levels, curve.nodes, overlap=32)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    f = torch.from_numpy(pw.f).to(dev)
+    u = torch.empty_like(f)
+    for _ in range(3):
+        pp.apply_points(f, out=u)
+        pp.apply(f, out=u)
+    reps = max(10, args.steps)
+    t_pts = _timed(lambda: pp.apply_points(f, out=u), reps)
+    t_app = _timed(lambda: pp.apply(f, out=u), reps)
+    _, up, gp = pp.apply_points(f, out=u)
+    torch.cuda.synchronize()
+    inf = pp.info()
+    res = {"workload": "star-cut adaptive tree (200 Gaussians, lcut 10), u and grad u at the 3,072 nodes of a "
+                       "128-panel star curve", "points": curve.n_nodes, "pairs": inf["pairs_points"],
+           "plan_s": t_plan, "ms_apply": 1e3 * t_app, "ms_apply_points": 1e3 * t_pts,
+           "points_per_s": curve.n_nodes / max(t_pts - t_app, 1e-9)}
+    if not args.no_cpu_baseline:
+        from oracle import quad, tree
+
+        idx = np.random.default_rng(args.seed + 3).choice(curve.n_nodes, 60, replace=False)
+        T = tree.Tree(pw.centres, pw.levels)
+        t0 = time.perf_counter()
+        u_o, g_o = quad.potential_at_points(pw.centres, T.halfw, pw.f, curve.nodes[idx], grad=True)
+        t_cpu = time.perf_counter() - t0
+        ug = up.cpu().numpy()[idx]
+        gg = gp.cpu().numpy()[idx]
+        res["rel_err_vs_oracle_sampled"] = {"u": float(np.max(np.abs(ug - u_o)) / np.max(np.abs(u_o))),
+                                            "grad": float(np.max(np.abs(gg - g_o)) / np.max(np.abs(g_o)))}
+        res["cpu_baseline"] = {"value": idx.size / t_cpu, "unit": "points/s", "cores": _oracle_cores(), "kind": "oracle",
+                               "sample": "%d random curve nodes, u and grad u by adaptive quadrature over all %d "
+                                         "leaves: %.1f s" % (idx.size, pw.n_leaves, t_cpu)}
+    pp.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +197,7 @@ def main():
     ap.add_argument("--no-layer", action="store_true", help="skip the layer-potential evaluation leg")
     ap.add_argument("--layer-only", action="store_true",
                     help="run only the layer-potential leg and print its object (for profiling)")
+    ap.add_argument("--no-points", action="store_true", help="skip the off-grid evaluation leg")
     ap.add_argument("--batched-trees", type=int, default=256)
     ap.add_argument("--tile-leaf", type=int, default=0, help="0: chosen by the autotuner")
     ap.add_argument("--tile-box", type=int, default=0, help="0: chosen by the autotuner")
@@ -400,6 +451,8 @@ def main():
 
     if not args.no_layer:
         out["layer_potential"] = layer_leg(args, dev)
+    if not args.no_points:
+        out["points"] = points_leg(args, dev)
 
     plan.close()
     print(json.dumps(out), flush=True)
