@@ -25,6 +25,8 @@ quad          the log-kernel integral of one Lagrange basis over a box (adaptive
               arbitrary points and with its gradient
 tree          integer box keys, tiling and 2:1-balance checks, the U/V/W/X interaction
               lists of the adaptive FMM by key arithmetic
+quadtree      adaptive construction of the quadtree from samples of f (Chebyshev tail test)
+              and the 2:1 balance, plain loops
 fmm           a CPU machine code with complex scaled expansions (Greengard-Rokhlin), its
               exact transpose, used for full-size parity and as the CPU baseline
 layer         the glue layer potentials S[sigma] - D[tau] of Sec. 4.4 on a panel-discretised
