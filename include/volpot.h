@@ -183,6 +183,36 @@ int volpot_layer_plan(const double* centres, const int32_t* levels, int64_t n_le
 int volpot_layer_apply(volpot_plan_t plan, const double* sigma_dev, const double* tau_dev, double* u_dev,
                        void* hip_stream);
 
+/* Adaptive quadtree construction (Sec. 4.2.1, Alg. 2: the function-resolution criterion)
+ * followed by the 2:1 balance over edges and corners, with the per-box work on the GPU. The
+ * library hands out the nodes of the boxes to test; the caller samples f there (any way it
+ * likes, e.g. a kernel of its own) and submits the samples; the library computes each box's
+ * Chebyshev coefficients c_nm (n in y, m in x) and splits the boxes whose tail
+ * max { |c_nm| : n >= p-2 or m >= p-2 } exceeds eps * scale; one level per round.
+ *   p           16 only (VOLPOT_ERR_UNSUPPORTED otherwise)
+ *   eps, scale  tolerance (> 0) and a global magnitude of f (>= 0), e.g. its maximum
+ *   min_level   boxes above this level are split without samples (0..12)
+ *   max_level   boxes at this level are leaves (min_level..29)
+ * The builder allocates device memory for the round's nodes and tails (not for use inside
+ * graph capture). */
+typedef struct volpot_tree_s* volpot_tree_t;
+int volpot_tree_create(int32_t p, double eps, double scale, int32_t min_level, int32_t max_level,
+                       volpot_tree_t* out);
+/* Number of boxes in the round (0 when the construction is finished). */
+int volpot_tree_pending(volpot_tree_t tree, int64_t* n);
+/* Writes the round's node coordinates to nodes_dev (device, caller-owned, [n][16][16][2] as
+ * (x, y), the leaf-data layout) asynchronously on hip_stream. */
+int volpot_tree_nodes(volpot_tree_t tree, double* nodes_dev, void* hip_stream);
+/* values_dev: device [n][16][16] samples of f at the round's nodes (same stream). Decides every
+ * box of the round (synchronises the stream). A non-finite sample splits its box (down to
+ * max_level). */
+int volpot_tree_submit(volpot_tree_t tree, const double* values_dev, void* hip_stream);
+/* After the last round: the balanced leaves, ordered by level, then y, then x. *n receives their
+ * number; centres (n x 2) and levels (n) are host arrays, each nullable (ask for n first).
+ * VOLPOT_ERR_STATE while boxes are pending. The result is a valid input of volpot_plan. */
+int volpot_tree_leaves(volpot_tree_t tree, int64_t* n, double* centres, int32_t* levels);
+void volpot_tree_destroy(volpot_tree_t tree);
+
 /* Sizes and algorithmic flop/byte counts of the plan. */
 int volpot_plan_info(volpot_plan_t plan, volpot_info* out);
 

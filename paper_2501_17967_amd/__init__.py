@@ -11,6 +11,7 @@ from .volpot import (  # noqa: F401
     Plan,
     VolpotError,
     autotune,
+    build_tree,
     lib,
     near_relation,
     nodes,

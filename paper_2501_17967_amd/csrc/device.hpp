@@ -101,4 +101,15 @@ struct PointParams {
 // u (and grad) at the n points, after a forward apply that filled loc and mp
 hipError_t launch_points(const PointParams& p, int64_t n, hipStream_t stream);
 
+// ---------------------------------------------------------------- quadtree construction (tree.hip)
+// First-kind points t (ascending) and the values-to-coefficients transform D[m][i]; by value.
+struct TreeRule {
+  double t[16];
+  double D[256];
+};
+// Node coordinates [n][256][2] of the boxes with packed keys (level << 58 | ix << 29 | iy).
+hipError_t launch_tree_nodes(const int64_t* keys, int64_t n, const TreeRule& r, double* nodes, hipStream_t stream);
+// Chebyshev tail of each box's 256 samples.
+hipError_t launch_tree_tail(const double* values, int64_t n, const TreeRule& r, double* tails, hipStream_t stream);
+
 }  // namespace vp

@@ -12,6 +12,7 @@ Every step of the volume potential runs in the HIP library; PyTorch supplies dev
     v = lp.apply(sigma, tau)                # S[sigma] - D[tau] at every leaf node
     pp = PointPlan(centres, levels, points) # u and grad u also at arbitrary points
     u, u_pts, grad = pp.apply_points(f)
+    centres, levels = build_tree(f_of_points, eps, scale)   # adaptive quadtree on the GPU
 
 Sign convention: u = int G f with G = -(1/2pi) log|x - y| (so -Lap u = f); the paper's v_bulk
 (Sec. 4.2, eq. (vbulk)) is -u.
@@ -32,7 +33,8 @@ EXPORTED = [
     "volpot_validate_tree", "volpot_nodes", "volpot_plan_destroy", "volpot_status_string",
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
     "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune", "volpot_layer_plan", "volpot_layer_apply",
-    "volpot_plan_points", "volpot_apply_points",
+    "volpot_plan_points", "volpot_apply_points", "volpot_tree_create", "volpot_tree_pending", "volpot_tree_nodes",
+    "volpot_tree_submit", "volpot_tree_leaves", "volpot_tree_destroy",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -120,6 +122,14 @@ def lib():
         L.volpot_plan_points.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _dp,
                                          ctypes.POINTER(Options), ctypes.POINTER(_vp)]
         L.volpot_apply_points.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.volpot_tree_create.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.POINTER(_vp)]
+        L.volpot_tree_pending.argtypes = [_vp, _lp]
+        L.volpot_tree_nodes.argtypes = [_vp, _vp, _vp]
+        L.volpot_tree_submit.argtypes = [_vp, _vp, _vp]
+        L.volpot_tree_leaves.argtypes = [_vp, _lp, _dp, _ip]
+        L.volpot_tree_destroy.argtypes = [_vp]
+        L.volpot_tree_destroy.restype = None
         _lib = L
     return _lib
 
@@ -150,6 +160,39 @@ def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
            "volpot_autotune")
     return ({"tile_leaf": best.tile_leaf, "tile_box": best.tile_box, "split_min": best.split_min,
              "overlap": best.overlap}, ms.value)
+
+
+def build_tree(f, eps, scale, min_level=0, max_level=24, p=16, stream=None):
+    """Adaptive quadtree of f (Sec. 4.2.1) with 2:1 balance, built with the library's GPU tail
+    test (volpot_tree_*). f maps a CUDA float64 tensor of points (n, 2) to n values (a CUDA
+    tensor). Returns (centres (n, 2), levels (n,)) as NumPy arrays, ready for Plan."""
+    import torch
+
+    L = lib()
+    h = _vp()
+    _check(L.volpot_tree_create(p, float(eps), float(scale), int(min_level), int(max_level), ctypes.byref(h)),
+           "volpot_tree_create")
+    try:
+        sh = _stream_handle(stream)
+        n = ctypes.c_int64(0)
+        while True:
+            _check(L.volpot_tree_pending(h, ctypes.byref(n)), "volpot_tree_pending")
+            if n.value == 0:
+                break
+            nodes = torch.empty((n.value * 256, 2), dtype=torch.float64, device="cuda")
+            _check(L.volpot_tree_nodes(h, ctypes.c_void_p(nodes.data_ptr()), sh), "volpot_tree_nodes")
+            vals = f(nodes)
+            if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.numel() == nodes.shape[0]):
+                raise ValueError("f must return one CUDA value per point")
+            vals = vals.to(torch.float64).contiguous()
+            _check(L.volpot_tree_submit(h, ctypes.c_void_p(vals.data_ptr()), sh), "volpot_tree_submit")
+        _check(L.volpot_tree_leaves(h, ctypes.byref(n), None, None), "volpot_tree_leaves")
+        c = np.zeros((n.value, 2))
+        lv = np.zeros(n.value, dtype=np.int32)
+        _check(L.volpot_tree_leaves(h, ctypes.byref(n), c.ctypes.data_as(_dp), lv.ctypes.data_as(_ip)), "volpot_tree_leaves")
+        return c, lv
+    finally:
+        L.volpot_tree_destroy(h)
 
 
 def validate_tree(centres, levels, p=16):

@@ -309,3 +309,19 @@ def test_point_plan_counts_and_errors(vp):
             vp.PointPlan(w.centres, w.levels, np.vstack([pts, [bad]]), host_only=True)
         assert e.value.code == vp.ERR_ARG
     assert vp.PointPlan(w.centres, w.levels, np.zeros((0, 2)), host_only=True).info()["pairs_points"] == 0
+
+
+# ---------------------------------------------------------------- quadtree builder (host side)
+def test_tree_builder_arguments(vp):
+    import ctypes
+    L = vp.lib()
+    h = ctypes.c_void_p()
+    assert L.volpot_tree_create(16, 0.0, 1.0, 0, 10, ctypes.byref(h)) == vp.ERR_ARG
+    assert L.volpot_tree_create(16, 1e-10, 1.0, 5, 4, ctypes.byref(h)) == vp.ERR_ARG
+    assert L.volpot_tree_create(12, 1e-10, 1.0, 0, 10, ctypes.byref(h)) == vp.ERR_UNSUPPORTED
+    assert L.volpot_tree_create(16, 1e-10, 1.0, 13, 20, ctypes.byref(h)) == vp.ERR_UNSUPPORTED
+    assert L.volpot_tree_create(16, 1e-10, 1.0, 3, 10, ctypes.byref(h)) == vp.OK
+    n = ctypes.c_int64(0)
+    assert L.volpot_tree_pending(h, ctypes.byref(n)) == vp.OK and n.value == 64  # the level-3 boxes
+    assert L.volpot_tree_leaves(h, ctypes.byref(n), None, None) == vp.ERR_STATE  # boxes still pending
+    L.volpot_tree_destroy(h)
