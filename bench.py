@@ -186,6 +186,54 @@ def points_leg(args, dev):
     return res
 
 
+def tree_leg(args, dev):
+    """Adaptive quadtree construction (Sec. 4.2.1) of the size-matched 20-Gaussian workload on
+    the GPU: the source is sampled by a torch expression on the device, the tail tests run in
+    the library; against the oracle builder (NumPy) on the host, whose leaves must be the same."""
+    import numpy as np
+    import torch
+
+    from paper_2501_17967_amd import build_tree
+    from workloads import gen
+
+    print("bench: quadtree construction", file=sys.stderr, flush=True)
+    g = gen.sample_gaussians(np.random.default_rng(args.seed), 20, -0.9, 0.9, 1e-3, 1e-1)
+    C = torch.tensor(g.centres, device=dev)
+    S2 = torch.tensor(2.0 * g.sigmas ** 2, device=dev)
+    A = torch.tensor(g.amps, device=dev)
+
+    def f_dev(p):
+        d2 = (p[:, None, 0] - C[None, :, 0]) ** 2 + (p[:, None, 1] - C[None, :, 1]) ** 2
+        return (A[None, :] * torch.exp(-d2 / S2[None, :])).sum(dim=1)
+
+    build_tree(f_dev, 1e-11, g.scale, 7, 24)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, lv = build_tree(f_dev, 1e-11, g.scale, 7, 24)
+    t_gpu = time.perf_counter() - t0
+    res = {"workload": "20 Gaussians (sigma log-U[1e-3, 1e-1]), eps 1e-11, min level 7: the size-matched tree",
+           "leaves": int(lv.size), "max_level": int(lv.max()), "s": t_gpu, "leaves_per_s": lv.size / t_gpu}
+    if not args.no_cpu_baseline:
+        from oracle import quadtree as qt
+
+        def f_np(p):
+            out = np.zeros(p.shape[0])
+            for cc, s, a in zip(g.centres, g.sigmas, g.amps):
+                out += a * np.exp(-((p[:, 0] - cc[0]) ** 2 + (p[:, 1] - cc[1]) ** 2) / (2 * s * s))
+            return out
+
+        t0 = time.perf_counter()
+        ref = qt.build(f_np, 1e-11, g.scale, 7, 24)
+        t_cpu = time.perf_counter() - t0
+        s = 2.0 ** (-lv.astype(float))
+        got = {(int(a), int(x), int(y)) for a, x, y in zip(lv, np.round((c[:, 0] + 1) / (2 * s) - 0.5),
+                                                             np.round((c[:, 1] + 1) / (2 * s) - 0.5))}
+        res["same_leaves_as_oracle"] = got == set(ref)
+        res["cpu_baseline"] = {"value": len(ref) / t_cpu, "unit": "leaves/s", "cores": 1, "kind": "oracle",
+                               "sample": "the whole construction by the oracle builder: %.1f s" % t_cpu}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +246,7 @@ def main():
     ap.add_argument("--layer-only", action="store_true",
                     help="run only the layer-potential leg and print its object (for profiling)")
     ap.add_argument("--no-points", action="store_true", help="skip the off-grid evaluation leg")
+    ap.add_argument("--no-tree", action="store_true", help="skip the quadtree construction leg")
     ap.add_argument("--batched-trees", type=int, default=256)
     ap.add_argument("--tile-leaf", type=int, default=0, help="0: chosen by the autotuner")
     ap.add_argument("--tile-box", type=int, default=0, help="0: chosen by the autotuner")
@@ -453,6 +502,8 @@ def main():
         out["layer_potential"] = layer_leg(args, dev)
     if not args.no_points:
         out["points"] = points_leg(args, dev)
+    if not args.no_tree:
+        out["tree"] = tree_leg(args, dev)
 
     plan.close()
     print(json.dumps(out), flush=True)
