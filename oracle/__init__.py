@@ -27,6 +27,8 @@ tree          integer box keys, tiling and 2:1-balance checks, the U/V/W/X inter
               lists of the adaptive FMM by key arithmetic
 quadtree      adaptive construction of the quadtree from samples of f (Chebyshev tail test)
               and the 2:1 balance, plain loops
+strip         the strip solve of Sec. 4.3 (multidomain spectral collocation between the boundary
+              and the fictitious curve), assembled densely and solved directly
 fmm           a CPU machine code with complex scaled expansions (Greengard-Rokhlin), its
               exact transpose, used for full-size parity and as the CPU baseline
 layer         the glue layer potentials S[sigma] - D[tau] of Sec. 4.4 on a panel-discretised
