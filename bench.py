@@ -234,6 +234,54 @@ def tree_leg(args, dev):
     return res
 
 
+def strip_leg(args, dev):
+    """Strip solve (Sec. 4.3) at the size of the paper's raindrop strip: 56 elements of 24 nodes
+    along the panel by 16 across (21,504 unknowns), here between the star (56 panels of 16
+    Gauss-Legendre nodes) and the star pulled inwards by 7 %. Plan (host factorization) outside
+    the timed apply; against the oracle's dense row-equilibrated solve of the same system."""
+    import numpy as np
+    import torch
+
+    from paper_2501_17967_amd import StripPlan
+    from workloads import gen
+
+    print("bench: strip solve", file=sys.stderr, flush=True)
+    n, q, n_r = 56, 24, 16
+    g = gen.star_curve(n_panels=n, order=16, scale=1.0).nodes.reshape(n, 16, 2)
+    gt = gen.star_curve(n_panels=n, order=16, scale=0.93).nodes.reshape(n, 16, 2)
+    f_np = lambda p: np.sin(3 * p[:, 0]) * np.exp(p[:, 1]) + 0.5
+    t0 = time.perf_counter()
+    sp = StripPlan(g, gt, q, n_r)
+    t_plan = time.perf_counter() - t0
+    f = torch.from_numpy(f_np(sp.nodes.reshape(-1, 2))).to(dev)
+    v = torch.empty(sp.shape, dtype=torch.float64, device=dev)
+    for _ in range(5):
+        sp.apply(f, out=v)
+    t_app = _timed(lambda: sp.apply(f, out=v), max(50, args.steps))
+    N = n * q * n_r
+    B, m = q * n_r, n_r - 2
+    # algorithmic HBM bytes of one apply: the block inverses (n B^2), their value and derivative
+    # columns (2 n B m), the couplings (n m B), the corner columns (N 2m), f, rs, v and the work
+    # vectors c, y (read and written once each)
+    bytes_apply = 8 * (n * B * B + 3 * n * B * m + N * 2 * m + 7 * N)
+    res = {"workload": "strip of 56 elements at 24 x 16 (21,504 unknowns) between the star and the star pulled "
+                       "inwards by 7 %", "unknowns": N, "plan_s": t_plan, "ms_apply": 1e3 * t_app,
+           "unknowns_per_s": N / t_app, "bytes_per_apply": bytes_apply,
+           "hbm_frac_whole_apply": bytes_apply / t_app / PEAK_HBM}
+    if not args.no_cpu_baseline:
+        from oracle import strip
+
+        t0 = time.perf_counter()
+        ref, _ = strip.solve(g, gt, f_np, q=q, n_r=n_r)
+        t_cpu = time.perf_counter() - t0
+        vv = v.cpu().numpy()
+        res["rel_err_vs_oracle"] = float(np.max(np.abs(vv - ref)) / np.max(np.abs(ref)))
+        res["cpu_baseline"] = {"value": N / t_cpu, "unit": "unknowns/s", "cores": _oracle_cores(), "kind": "oracle",
+                               "sample": "the whole strip by the oracle (assembly and dense solve): %.1f s" % t_cpu}
+    sp.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +295,9 @@ def main():
                     help="run only the layer-potential leg and print its object (for profiling)")
     ap.add_argument("--no-points", action="store_true", help="skip the off-grid evaluation leg")
     ap.add_argument("--no-tree", action="store_true", help="skip the quadtree construction leg")
+    ap.add_argument("--no-strip", action="store_true", help="skip the strip-solve leg")
+    ap.add_argument("--strip-only", action="store_true",
+                    help="run only the strip-solve leg and print its object (for profiling)")
     ap.add_argument("--batched-trees", type=int, default=256)
     ap.add_argument("--tile-leaf", type=int, default=0, help="0: chosen by the autotuner")
     ap.add_argument("--tile-box", type=int, default=0, help="0: chosen by the autotuner")
@@ -275,6 +326,9 @@ def main():
 
     if args.layer_only:
         print(json.dumps({"layer_potential": layer_leg(args, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.strip_only:
+        print(json.dumps({"strip": strip_leg(args, torch.device("cuda:0"))}), flush=True)
         return
 
     from paper_2501_17967_amd import Plan, autotune
@@ -504,6 +558,8 @@ def main():
         out["points"] = points_leg(args, dev)
     if not args.no_tree:
         out["tree"] = tree_leg(args, dev)
+    if not args.no_strip:
+        out["strip"] = strip_leg(args, dev)
 
     plan.close()
     print(json.dumps(out), flush=True)

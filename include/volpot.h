@@ -213,6 +213,31 @@ int volpot_tree_submit(volpot_tree_t tree, const double* values_dev, void* hip_s
 int volpot_tree_leaves(volpot_tree_t tree, int64_t* n, double* centres, int32_t* levels);
 void volpot_tree_destroy(volpot_tree_t tree);
 
+/* Strip solve (Sec. 4.3): Lap v = f in the strip between the boundary Gamma and the fictitious
+ * curve Gamma~, v = 0 on both, by multidomain spectral collocation. Element k spans panel k of
+ * Gamma and panel k of Gamma~ (the panels correspond one to one, in the same direction around the
+ * closed curves); its nodes are the curvilinear tensor grid of second-kind Chebyshev points,
+ * q along the panel (the panel's points interpolated from its Gauss-Legendre nodes) and n_r
+ * across the strip (r = -1 on Gamma). The plan assembles and factors the block-tridiagonal
+ * periodic system on the host (block inverses in parallel, rank-(n_r - 2) couplings, Woodbury
+ * for the periodic corner); the apply solves it on the GPU.
+ *   n_panel        panels per curve (>= 3)
+ *   n_gl           Gauss-Legendre nodes per panel (2..64)
+ *   gamma, gamma_t host, n_panel x n_gl x 2: the nodes of each panel, in the panel's direction
+ *   q, n_r         4..32 each, q * n_r <= 1024
+ * Node order: element, then radial index i (0 on Gamma), then along-panel index j (fastest).
+ * Returns VOLPOT_ERR_ARG for bad sizes, non-finite nodes or a singular (degenerate) element. */
+typedef struct volpot_strip_s* volpot_strip_t;
+int volpot_strip_plan(int32_t n_panel, int32_t n_gl, const double* gamma, const double* gamma_t, int32_t q,
+                      int32_t n_r, volpot_strip_t* out);
+/* The element nodes (host, n_panel x n_r x q x 2), where the caller samples f. */
+int volpot_strip_nodes(volpot_strip_t strip, double* xy);
+/* v_dev (device, n_panel x n_r x q) from f_dev (device, f at the nodes; values at the nodes on
+ * Gamma, Gamma~ and the element edges are ignored). Asynchronous on the stream; one solve at a
+ * time per plan (shared workspace). */
+int volpot_strip_apply(volpot_strip_t strip, const double* f_dev, double* v_dev, void* hip_stream);
+void volpot_strip_destroy(volpot_strip_t strip);
+
 /* Sizes and algorithmic flop/byte counts of the plan. */
 int volpot_plan_info(volpot_plan_t plan, volpot_info* out);
 

@@ -7,6 +7,7 @@ a C ABI (include/volpot.h); this package holds the HIP sources (csrc/), the in-t
 from .volpot import (  # noqa: F401
     LayerPlan,
     PointPlan,
+    StripPlan,
     EXPORTED,
     Plan,
     VolpotError,

@@ -25,12 +25,12 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     objs = []
-    for src in ("plan.cpp", "tables.cpp", "api.cpp", "tune.cpp", "tree.cpp"):
+    for src in ("plan.cpp", "tables.cpp", "api.cpp", "tune.cpp", "tree.cpp", "strip.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         jobs.append(cmd)
         objs.append(obj)
-    for src in ("kernels.hip", "layer.hip", "points.hip", "tree.hip"):
+    for src in ("kernels.hip", "layer.hip", "points.hip", "tree.hip", "strip.hip"):
         kobj = os.path.join(BUILD, src + ".o")
         jobs.append([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", kobj])
         objs.append(kobj)

@@ -13,6 +13,8 @@ Every step of the volume potential runs in the HIP library; PyTorch supplies dev
     pp = PointPlan(centres, levels, points) # u and grad u also at arbitrary points
     u, u_pts, grad = pp.apply_points(f)
     centres, levels = build_tree(f_of_points, eps, scale)   # adaptive quadtree on the GPU
+    sp = StripPlan(gamma, gamma_t, q, n_r)  # strip solve (Sec. 4.3)
+    v = sp.apply(f_at_sp_nodes)
 
 Sign convention: u = int G f with G = -(1/2pi) log|x - y| (so -Lap u = f); the paper's v_bulk
 (Sec. 4.2, eq. (vbulk)) is -u.
@@ -34,7 +36,8 @@ EXPORTED = [
     "volpot_set_timing", "volpot_stage_times", "volpot_plan_table", "volpot_near_relation",
     "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune", "volpot_layer_plan", "volpot_layer_apply",
     "volpot_plan_points", "volpot_apply_points", "volpot_tree_create", "volpot_tree_pending", "volpot_tree_nodes",
-    "volpot_tree_submit", "volpot_tree_leaves", "volpot_tree_destroy",
+    "volpot_tree_submit", "volpot_tree_leaves", "volpot_tree_destroy", "volpot_strip_plan", "volpot_strip_nodes",
+    "volpot_strip_apply", "volpot_strip_destroy",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -130,6 +133,12 @@ def lib():
         L.volpot_tree_leaves.argtypes = [_vp, _lp, _dp, _ip]
         L.volpot_tree_destroy.argtypes = [_vp]
         L.volpot_tree_destroy.restype = None
+        L.volpot_strip_plan.argtypes = [ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(_vp)]
+        L.volpot_strip_nodes.argtypes = [_vp, _dp]
+        L.volpot_strip_apply.argtypes = [_vp, _vp, _vp, _vp]
+        L.volpot_strip_destroy.argtypes = [_vp]
+        L.volpot_strip_destroy.restype = None
         _lib = L
     return _lib
 
@@ -193,6 +202,49 @@ def build_tree(f, eps, scale, min_level=0, max_level=24, p=16, stream=None):
         return c, lv
     finally:
         L.volpot_tree_destroy(h)
+
+
+class StripPlan:
+    """Strip solve of Sec. 4.3 (volpot_strip_*): gamma and gamma_t are (n_panel, n_gl, 2) Gauss-Legendre
+    nodes of corresponding panels of the boundary and of the fictitious curve; q and n_r the
+    Chebyshev resolution along and across the strip. ``nodes`` (n_panel, n_r, q, 2) are where f is
+    sampled; apply(f) returns v at those nodes."""
+
+    def __init__(self, gamma, gamma_t, q=16, n_r=16):
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+        gt = np.ascontiguousarray(np.asarray(gamma_t, dtype=np.float64))
+        if g.ndim != 3 or g.shape[2] != 2 or g.shape != gt.shape:
+            raise ValueError("gamma and gamma_t must both be (n_panel, n_gl, 2)")
+        self.shape = (g.shape[0], int(n_r), int(q))
+        h = _vp()
+        _check(lib().volpot_strip_plan(g.shape[0], g.shape[1], g.ctypes.data_as(_dp), gt.ctypes.data_as(_dp), int(q),
+                                       int(n_r), ctypes.byref(h)), "volpot_strip_plan")
+        self._h = h
+        self.nodes = np.zeros(self.shape + (2,))
+        _check(lib().volpot_strip_nodes(h, self.nodes.ctypes.data_as(_dp)), "volpot_strip_nodes")
+
+    def apply(self, f, out=None, stream=None):
+        import torch
+
+        if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64 and f.numel() == np.prod(self.shape)):
+            raise TypeError("expected a CUDA float64 tensor of %d node values" % int(np.prod(self.shape)))
+        f = f.contiguous()
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=f.device)
+        _check(lib().volpot_strip_apply(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        _stream_handle(stream)), "volpot_strip_apply")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().volpot_strip_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def validate_tree(centres, levels, p=16):

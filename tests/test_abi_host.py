@@ -325,3 +325,16 @@ def test_tree_builder_arguments(vp):
     assert L.volpot_tree_pending(h, ctypes.byref(n)) == vp.OK and n.value == 64  # the level-3 boxes
     assert L.volpot_tree_leaves(h, ctypes.byref(n), None, None) == vp.ERR_STATE  # boxes still pending
     L.volpot_tree_destroy(h)
+
+
+def test_strip_plan_arguments(vp):
+    import ctypes
+    L = vp.lib()
+    h = ctypes.c_void_p()
+    g = np.zeros((4, 8, 2))
+    p = g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.volpot_strip_plan(2, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG   # too few panels
+    assert L.volpot_strip_plan(4, 8, p, p, 3, 10, ctypes.byref(h)) == vp.ERR_ARG    # q too small
+    assert L.volpot_strip_plan(4, 8, p, p, 32, 33, ctypes.byref(h)) == vp.ERR_ARG   # n_r too large
+    g[1, 2, 0] = np.nan
+    assert L.volpot_strip_plan(4, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG   # non-finite node
