@@ -21,8 +21,11 @@ start; element unknowns ordered (i, j) with j fastest; the interface normal is t
 of the segment from Gamma's to Gamma~'s shared endpoint, oriented along increasing j.
 
 Everything is written out plainly (barycentric weights and differentiation matrices from their
-definitions, a dense global matrix, numpy.linalg.solve / scipy sparse). Pinned by
-tests/test_oracle_strip.py.
+definitions, a dense global matrix, numpy.linalg.solve). Before the solve every row is divided by
+its 1-norm: this changes no solution of the system, but without it the spread of row norms (1
+for boundary rows, up to about 1e7 for Laplacian rows on thin elements) costs the dense LU up to
+five digits (4e-9 against a manufactured solution at 56 panels, 24 x 16; 4e-14 with the
+scaling). Pinned by tests/test_oracle_strip.py.
 """
 import numpy as np
 
@@ -150,4 +153,5 @@ def solve(gamma, gamma_t, f, q=16, n_r=16):
     X = element_grids(gamma, gamma_t, q, n_r)
     A, pde = assemble(X)
     b = np.where(pde, f(X.reshape(-1, 2)), 0.0)
-    return np.linalg.solve(A, b).reshape(X.shape[:3]), X
+    s = 1.0 / np.abs(A).sum(axis=1)  # row equilibration
+    return np.linalg.solve(A * s[:, None], b * s).reshape(X.shape[:3]), X

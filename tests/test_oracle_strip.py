@@ -64,7 +64,7 @@ def test_manufactured_solution_on_annulus():
         ve = v(X.reshape(-1, 2))
         errs.append(np.max(np.abs(sol.reshape(-1) - ve)) / np.max(np.abs(ve)))
     assert errs[0] > errs[1] > errs[2]  # spectral convergence across the strip
-    assert errs[-1] < 5e-11  # saturates near 2e-11 (along-panel resolution and conditioning)
+    assert errs[-1] < 1e-12  # saturates near 1.5e-14 (rounding of the row-equilibrated solve)
 
 
 def test_zero_and_linearity():
@@ -77,4 +77,16 @@ def test_zero_and_linearity():
     s1, _ = strip.solve(gam, gamt, f1, q=12, n_r=10)
     s2, _ = strip.solve(gam, gamt, f2, q=12, n_r=10)
     s12, _ = strip.solve(gam, gamt, lambda p: 2 * f1(p) - f2(p), q=12, n_r=10)
-    assert np.max(np.abs(s12 - (2 * s1 - s2))) < 1e-10 * np.max(np.abs(s12))  # condition number about 2e4
+    assert np.max(np.abs(s12 - (2 * s1 - s2))) < 1e-13 * np.max(np.abs(s12))  # row-scaled condition number about 1e2
+
+
+def test_full_size_manufactured_and_zero_boundary():
+    # 56 thin elements at 24 x 16 (the size of the benchmark strip): the row norms span seven
+    # decades here, and the solve must still hold the boundary rows at zero and the manufactured
+    # solution to near rounding
+    a, b = 0.85, 0.9
+    v, f = _manufactured(a, b)
+    sol, X = strip.solve(_annulus(56, 16, b), _annulus(56, 16, a), f, q=24, n_r=16)
+    ve = v(X.reshape(-1, 2)).reshape(sol.shape)
+    assert np.max(np.abs(sol - ve)) < 1e-12 * np.max(np.abs(ve))
+    assert np.max(np.abs(sol[:, 0])) < 1e-15 and np.max(np.abs(sol[:, -1])) < 1e-15
