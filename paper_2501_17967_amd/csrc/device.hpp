@@ -116,24 +116,21 @@ hipError_t launch_tree_tail(const double* values, int64_t n, const TreeRule& r, 
 // Device data of the factored strip system (strip.cpp): n elements of B = q n_r unknowns,
 // m = n_r - 2 interface rows per side.
 struct StripDevice {
-  int32_t n, B, m;
-  const double* Et;        // n x B x B: E_k transposed (column c of E_k contiguous)
-  const double* Ut;        // n x m x B: derivative rows of element k acting on element k + 1
-  const double* F;         // n x m x m: forward recurrence E_k[last column, value rows]
-  const double* H;         // n x m x m: backward recurrence U~_{k-1} E_k[:, derivative rows]
-  const int32_t* pvrow;    // m value rows (first column)
-  const int32_t* prow;     // m derivative rows (last column)
-  const int32_t* scol;     // m last-column unknowns
-  const int8_t* pde;       // B: PDE rows
-  const double* Z;         // n B x 2m: T^-1 of the corner columns
-  const double* K;         // 2m x 2m: (I + V^T Z)^-1
-  const double* rs;        // n x B: row scale of each PDE row (the right-hand side is f * rs)
-  double* c;               // n x B work
-  double* y;               // n x B work
-  double* z;               // (n + 1) x m work
-  double* g;               // n x m work
-  double* t;               // (n + 1) x m work
-  double* h;               // 2m work
+  int32_t n, q, B, m, Bi, chunk;  // elements, nodes along, nodes per element, m = n_r - 2, Bi = m q
+  const double* EiT;  // n x Bi x Bi: interior block of E_k = D_k^-1, column c contiguous
+  const double* W;    // n x 2m x Bi: [E_k[last column, :]; U~_{k-1} E_k] on the interior columns
+  const double* F;    // n x m x m: E_k[last column, value rows]
+  const double* G;    // n x m x m: U~_{k-1} E_k[:, value rows]
+  const double* H;    // n x m x m: U~_{k-1} E_k[:, derivative rows] (k = 0: the corner term)
+  const double* Pz;   // n x m x m: response of z_k to the corner values h_lo
+  const double* Pt;   // (n + 1) x m x 2m: response of t_k to h
+  const double* K;    // 2m x 2m: the Woodbury capacitance inverse of the periodic corner
+  const double* rs;   // n x B: row scale of each PDE row (the right-hand side is f * rs)
+  double* s;          // n x m work: E_k[last column, :] b_k
+  double* w;          // n x m work: U~_{k-1} E_k b_k
+  double* z;          // (n + 1) x m work: forward sweep
+  double* t;          // (n + 1) x m work: backward sweep
+  double* h;          // 2m work: corner values
 };
 // v (n x B) from the node samples f (n x B): Lap v = f inside, the boundary and interface rows zero
 hipError_t launch_strip_solve(const StripDevice& d, const double* f, double* v, hipStream_t stream);

@@ -381,51 +381,107 @@ void host_tsolve(const StripHost& S, const double* b, double* x) {
   }
 }
 
-}  // namespace
-
-struct volpot_strip_s;
-static int strip_upload(volpot_strip_s* s);
-
-struct volpot_strip_s {
-  StripHost H;
-  int device = -1;
-  StripDevice d{};
-  char* block = nullptr;
+// Arrays of the three-launch apply. With Bi = m q the interior rows (1 <= i <= n_r - 2, a
+// contiguous range q .. B - q - 1 of each element), the Dirichlet rows of D_k are identity rows,
+// so x is zero there and only the interior block of E_k = D_k^-1 is ever applied.
+//   rhs pass:  s_k = E_k[S, :] b_k,  w_k = U~_{k-1} E_k b_k         (W_k, 2m x Bi; U~_{-1} = U~_{n-1})
+//   sweep:     z_0 = 0, z_{k+1} = s_k + F_k z_k;  g_k = w_k + G_k z_k;
+//              t_n = 0, t_k = g_k - H_k t_{k+1} (k = n-1 .. 1);
+//              h = K [z_n; w_0 - H_0 t_1]                          (the periodic corner, Woodbury)
+//   solution:  z*_k = z_k + Pz_k h_lo,  t*_{k+1} = t_{k+1} + Pt_{k+1} h,
+//              x_k = E_k (b_k + P' z*_k - P t*_{k+1})             (interior block, Bi x Bi)
+// The corrected solution T^-1 (b - U_c h) is the non-periodic sweep started from z_0 = h_lo and
+// t_n = h_hi (U_c injects exactly there), and the sweep is linear in those two boundary values:
+// Pz_k, Pt_k are its responses, precomputed here.
+struct StripArrays {
+  int n = 0, q = 0, B = 0, m = 0, Bi = 0;
+  std::vector<double> EiT, W, F, G, Hm, Pz, Pt, K, rs;
 };
 
-// Recurrence matrices, corner columns and the device copy of everything the apply reads.
-static int strip_upload(volpot_strip_s* s) {
-  StripHost& H = s->H;
-  const int n = H.n, B = H.B, m = H.m;
-  const size_t N = size_t(n) * B;
-  std::vector<double> F(static_cast<size_t>(n) * m * m), Hm(size_t(n) * m * m, 0.0), Et(size_t(n) * B * B);
-  for (int k = 0; k < n; ++k) {
+template <class Fn>
+void parallel_for(int n, Fn fn) {
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    for (int k; (k = next.fetch_add(1)) < n;) fn(k);
+  };
+  const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned i = 1; i < nt && i < unsigned(n); ++i) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+}
+
+void apply_arrays(const StripHost& H, StripArrays& R) {
+  const int n = H.n, B = H.B, m = H.m, q = H.q, Bi = B - 2 * q;
+  R.n = n; R.q = q; R.B = B; R.m = m; R.Bi = Bi;
+  const size_t mm = size_t(m) * m;
+  R.EiT.assign(size_t(n) * Bi * Bi, 0.0);
+  R.W.assign(size_t(n) * 2 * m * Bi, 0.0);
+  R.F.assign(size_t(n) * mm, 0.0);
+  R.G.assign(size_t(n) * mm, 0.0);
+  R.Hm.assign(size_t(n) * mm, 0.0);
+  parallel_for(n, [&](int k) {
     const Mat& E = H.E[size_t(k)];
+    const Mat& U = H.Ut[size_t((k + n - 1) % n)];  // derivative rows of element k - 1 acting on k
+    for (int c = 0; c < Bi; ++c)
+      for (int p = 0; p < Bi; ++p) R.EiT[(size_t(k) * Bi + c) * Bi + p] = E[size_t(q + p) * B + q + c];
+    std::vector<double> UE(size_t(m) * B, 0.0);  // U~ E_k (m x B)
     for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) F[(size_t(k) * m + a) * m + b] = E[size_t(H.Scol[size_t(a)]) * B + H.Pvrow[size_t(b)]];
-    if (k > 0)
-      for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) {
-          double acc = 0.0;
-          for (int r = 0; r < B; ++r) acc += H.Ut[size_t(k - 1)][size_t(a) * B + r] * E[size_t(r) * B + H.Prow[size_t(b)]];
-          Hm[(size_t(k) * m + a) * m + b] = acc;
-        }
-    for (int r = 0; r < B; ++r)
-      for (int c = 0; c < B; ++c) Et[(size_t(k) * B + c) * B + r] = E[size_t(r) * B + c];
-  }
-  // corner: Z = T^-1 U_c (columns: -e at element 0's value rows, +e at element n-1's derivative rows)
+      for (int r = 0; r < B; ++r) {
+        const double u = U[size_t(a) * B + r];
+        if (u == 0.0) continue;
+        for (int c = 0; c < B; ++c) UE[size_t(a) * B + c] += u * E[size_t(r) * B + c];
+      }
+    double* W = R.W.data() + size_t(k) * 2 * m * Bi;
+    for (int a = 0; a < m; ++a)
+      for (int c = 0; c < Bi; ++c) {
+        W[size_t(a) * Bi + c] = E[size_t(H.Scol[size_t(a)]) * B + q + c];
+        W[size_t(m + a) * Bi + c] = UE[size_t(a) * B + q + c];
+      }
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        R.F[size_t(k) * mm + size_t(a) * m + b] = E[size_t(H.Scol[size_t(a)]) * B + H.Pvrow[size_t(b)]];
+        R.G[size_t(k) * mm + size_t(a) * m + b] = UE[size_t(a) * B + H.Pvrow[size_t(b)]];
+        R.Hm[size_t(k) * mm + size_t(a) * m + b] = UE[size_t(a) * B + H.Prow[size_t(b)]];
+      }
+  });
+  // responses of the sweep to its boundary values
   const int m2 = 2 * m;
-  std::vector<double> Z(N * m2), col(N), sol(N);
-  for (int j = 0; j < m2; ++j) {
-    std::fill(col.begin(), col.end(), 0.0);
+  R.Pz.assign(size_t(n) * mm, 0.0);
+  for (int a = 0; a < m; ++a) R.Pz[size_t(a) * m + a] = 1.0;
+  for (int k = 0; k + 1 < n; ++k)
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        double acc = 0.0;
+        for (int c = 0; c < m; ++c) acc += R.F[size_t(k) * mm + size_t(a) * m + c] * R.Pz[size_t(k) * mm + size_t(c) * m + b];
+        R.Pz[size_t(k + 1) * mm + size_t(a) * m + b] = acc;
+      }
+  R.Pt.assign(size_t(n + 1) * m * m2, 0.0);
+  for (int a = 0; a < m; ++a) R.Pt[size_t(n) * m * m2 + size_t(a) * m2 + m + a] = 1.0;
+  for (int k = n - 1; k >= 1; --k)
+    for (int a = 0; a < m; ++a)
+      for (int j = 0; j < m2; ++j) {
+        double acc = 0.0;
+        if (j < m)
+          for (int c = 0; c < m; ++c) acc += R.G[size_t(k) * mm + size_t(a) * m + c] * R.Pz[size_t(k) * mm + size_t(c) * m + j];
+        for (int c = 0; c < m; ++c)
+          acc -= R.Hm[size_t(k) * mm + size_t(a) * m + c] * R.Pt[size_t(k + 1) * m * m2 + size_t(c) * m2 + j];
+        R.Pt[size_t(k) * m * m2 + size_t(a) * m2 + j] = acc;
+      }
+  // the corner: Z = T^-1 U_c (columns -e at element 0's value rows, +e at element n-1's
+  // derivative rows), K = (I + V^T Z)^-1 with V^T = [element n-1's last column; U~_{n-1} on element 0]
+  const size_t N = size_t(n) * B;
+  std::vector<double> Z(N * m2);
+  parallel_for(m2, [&](int j) {
+    std::vector<double> col(N, 0.0), sol(N);
     if (j < m) col[size_t(H.Pvrow[size_t(j)])] = -1.0;
     else col[size_t(n - 1) * B + H.Prow[size_t(j - m)]] = 1.0;
     host_tsolve(H, col.data(), sol.data());
     for (size_t r = 0; r < N; ++r) Z[r * m2 + j] = sol[r];
-  }
-  Mat G(size_t(m2) * m2, 0.0);  // I + V^T Z, V^T = [element n-1's last column; U~_{n-1} on element 0]
+  });
+  Mat Gc(size_t(m2) * m2, 0.0);
   for (int a = 0; a < m2; ++a) {
-    G[size_t(a) * m2 + a] = 1.0;
+    Gc[size_t(a) * m2 + a] = 1.0;
     for (int j = 0; j < m2; ++j) {
       double v;
       if (a < m) {
@@ -434,75 +490,51 @@ static int strip_upload(volpot_strip_s* s) {
         v = 0.0;
         for (int r = 0; r < B; ++r) v += H.Ut[size_t(n - 1)][size_t(a - m) * B + r] * Z[size_t(r) * m2 + j];
       }
-      G[size_t(a) * m2 + j] += v;
+      Gc[size_t(a) * m2 + j] += v;
     }
   }
-  Mat Kinv;
-  try {
-    Kinv = inverse(G, m2);
-  } catch (...) {
-    return VOLPOT_ERR_ARG;
-  }
-  std::vector<double> Ut(static_cast<size_t>(n) * m * B);
-  for (int k = 0; k < n; ++k) std::memcpy(Ut.data() + size_t(k) * m * B, H.Ut[size_t(k)].data(), size_t(m) * B * sizeof(double));
-  std::vector<int32_t> idx(static_cast<size_t>(3 * m));
-  for (int a = 0; a < m; ++a) {
-    idx[size_t(a)] = H.Pvrow[size_t(a)];
-    idx[size_t(m + a)] = H.Prow[size_t(a)];
-    idx[size_t(2 * m + a)] = H.Scol[size_t(a)];
-  }
-  if (hipGetDevice(&s->device) != hipSuccess) return VOLPOT_ERR_HIP;
+  R.K = inverse(Gc, m2);  // throws on a singular corner system
+  R.rs = H.rs;
+}
+
+}  // namespace
+
+struct volpot_strip_s {
+  StripHost H;
+  int device = -1;
+  StripDevice d{};
+  char* block = nullptr;
+};
+
+// Device copy of everything the apply reads, and its work vectors, in one allocation.
+static int strip_upload(volpot_strip_s* s, const StripArrays& R) {
+  const int n = R.n, m = R.m;
+  const size_t N = size_t(n) * R.B;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  size_t o = 0;
-  const size_t oEt = o; o += al(Et.size() * 8);
-  const size_t oUt = o; o += al(Ut.size() * 8);
-  const size_t oF = o; o += al(F.size() * 8);
-  const size_t oH = o; o += al(Hm.size() * 8);
-  const size_t oI = o; o += al(idx.size() * 4);
-  const size_t oP = o; o += al(size_t(B));
-  const size_t oZ = o; o += al(Z.size() * 8);
-  const size_t oK = o; o += al(Kinv.size() * 8);
-  const size_t oR = o; o += al(N * 8);
-  const size_t oc = o; o += al(N * 8);
-  const size_t oy = o; o += al(N * 8);
+  const std::vector<double>* in[] = {&R.EiT, &R.W, &R.F, &R.G, &R.Hm, &R.Pz, &R.Pt, &R.K, &R.rs};
+  size_t off[9], o = 0;
+  for (int i = 0; i < 9; ++i) { off[i] = o; o += al(in[i]->size() * 8); }
+  const size_t os = o; o += al(size_t(n) * m * 8);
+  const size_t ow = o; o += al(size_t(n) * m * 8);
   const size_t oz = o; o += al(size_t(n + 1) * m * 8);
-  const size_t og = o; o += al(size_t(n) * m * 8);
   const size_t ot = o; o += al(size_t(n + 1) * m * 8);
-  const size_t oh = o; o += al(size_t(m2) * 8);
-  if (hipMalloc(&s->block, o) != hipSuccess) return VOLPOT_ERR_OOM;
+  const size_t oh = o; o += al(size_t(2 * m) * 8);
+  (void)N;
+  if (hipGetDevice(&s->device) != hipSuccess) return VOLPOT_ERR_HIP;
+  if (hipMalloc(&s->block, o) != hipSuccess) { s->block = nullptr; return VOLPOT_ERR_OOM; }
   char* b = s->block;
-  if (hipMemcpy(b + oEt, Et.data(), Et.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oUt, Ut.data(), Ut.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oF, F.data(), F.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oH, Hm.data(), Hm.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oI, idx.data(), idx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oP, H.pde.data(), size_t(B), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oZ, Z.data(), Z.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oK, Kinv.data(), Kinv.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b + oR, H.rs.data(), N * 8, hipMemcpyHostToDevice) != hipSuccess)
-    return VOLPOT_ERR_HIP;
+  for (int i = 0; i < 9; ++i)
+    if (hipMemcpy(b + off[i], in[i]->data(), in[i]->size() * 8, hipMemcpyHostToDevice) != hipSuccess) return VOLPOT_ERR_HIP;
   StripDevice& d = s->d;
-  d.n = n; d.B = B; d.m = m;
-  d.Et = reinterpret_cast<const double*>(b + oEt);
-  d.Ut = reinterpret_cast<const double*>(b + oUt);
-  d.F = reinterpret_cast<const double*>(b + oF);
-  d.H = reinterpret_cast<const double*>(b + oH);
-  d.pvrow = reinterpret_cast<const int32_t*>(b + oI);
-  d.prow = d.pvrow + m;
-  d.scol = d.pvrow + 2 * m;
-  d.pde = reinterpret_cast<const int8_t*>(b + oP);
-  d.Z = reinterpret_cast<const double*>(b + oZ);
-  d.K = reinterpret_cast<const double*>(b + oK);
-  d.rs = reinterpret_cast<const double*>(b + oR);
-  d.c = reinterpret_cast<double*>(b + oc);
-  d.y = reinterpret_cast<double*>(b + oy);
+  d.n = n; d.q = R.q; d.B = R.B; d.m = m; d.Bi = R.Bi;
+  auto cd = [&](int i) { return reinterpret_cast<const double*>(b + off[i]); };
+  d.EiT = cd(0); d.W = cd(1); d.F = cd(2); d.G = cd(3); d.H = cd(4); d.Pz = cd(5); d.Pt = cd(6); d.K = cd(7); d.rs = cd(8);
+  d.s = reinterpret_cast<double*>(b + os);
+  d.w = reinterpret_cast<double*>(b + ow);
   d.z = reinterpret_cast<double*>(b + oz);
-  d.g = reinterpret_cast<double*>(b + og);
   d.t = reinterpret_cast<double*>(b + ot);
   d.h = reinterpret_cast<double*>(b + oh);
-  // the host copies of the blocks are no longer needed
-  std::vector<Mat>().swap(H.A);
-  std::vector<Mat>().swap(H.E);
+  d.chunk = std::max(1, 3072 / (m * m + m));  // two buffers of at most 24 KiB
   return VOLPOT_OK;
 }
 
@@ -557,7 +589,20 @@ int volpot_strip_plan(int32_t n_panel, int32_t n_gl, const double* gamma, const 
     delete s;
     return VOLPOT_ERR_ARG;  // a singular block: degenerate element geometry
   }
-  int rc = strip_upload(s);
+  StripArrays R;
+  try {
+    apply_arrays(H, R);
+  } catch (const std::bad_alloc&) {
+    delete s;
+    return VOLPOT_ERR_OOM;
+  } catch (...) {
+    delete s;
+    return VOLPOT_ERR_ARG;  // a singular corner system
+  }
+  std::vector<Mat>().swap(H.A);  // the host blocks are no longer needed
+  std::vector<Mat>().swap(H.E);
+  std::vector<Mat>().swap(H.Ut);
+  int rc = strip_upload(s, R);
   if (rc != VOLPOT_OK) { volpot_strip_destroy(s); return rc; }
   *out = s;
   return VOLPOT_OK;

@@ -55,7 +55,7 @@ def test_annulus_manufactured_and_oracle(device):
     assert rel_max_err(v, ve) < 1e-11
 
 
-@pytest.mark.parametrize("n_panel,q,n_r", [(16, 12, 8), (7, 16, 12), (24, 10, 16)])
+@pytest.mark.parametrize("n_panel,q,n_r", [(16, 12, 8), (7, 16, 12), (24, 10, 16), (5, 8, 32), (9, 20, 4)])
 def test_star_strip_vs_oracle(device, n_panel, q, n_r):
     # strip between the star and the star pulled inwards, a smooth f
     c_out = gen.star_curve(n_panels=n_panel, order=16, scale=1.0)
