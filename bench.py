@@ -260,10 +260,11 @@ def strip_leg(args, dev):
     t_app = _timed(lambda: sp.apply(f, out=v), max(50, args.steps))
     N = n * q * n_r
     B, m = q * n_r, n_r - 2
-    # algorithmic HBM bytes of one apply: the block inverses (n B^2), their value and derivative
-    # columns (2 n B m), the couplings (n m B), the corner columns (N 2m), f, rs, v and the work
-    # vectors c, y (read and written once each)
-    bytes_apply = 8 * (n * B * B + 3 * n * B * m + N * 2 * m + 7 * N)
+    Bi = m * q
+    # algorithmic HBM bytes of one apply: the interior blocks of the inverses (n Bi^2), the
+    # right-hand-side functionals (n 2m Bi), the sweep and response matrices F, G, H, Pz, Pt
+    # (6 n m^2), f and the row scales read twice (4 n Bi), v written (N), the sweep vectors
+    bytes_apply = 8 * (n * Bi * Bi + 2 * m * n * Bi + 6 * n * m * m + 4 * n * Bi + N + 8 * n * m)
     res = {"workload": "strip of 56 elements at 24 x 16 (21,504 unknowns) between the star and the star pulled "
                        "inwards by 7 %", "unknowns": N, "plan_s": t_plan, "ms_apply": 1e3 * t_app,
            "unknowns_per_s": N / t_app, "bytes_per_apply": bytes_apply,

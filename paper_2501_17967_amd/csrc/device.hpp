@@ -135,4 +135,22 @@ struct StripDevice {
 // v (n x B) from the node samples f (n x B): Lap v = f inside, the boundary and interface rows zero
 hipError_t launch_strip_solve(const StripDevice& d, const double* f, double* v, hipStream_t stream);
 
+// Plan-time factorization on the GPU (strip_factor.hip).
+struct StripFactorDevice {
+  int32_t n, N, Bi, m, q;  // elements, padded interior size (multiple of 16), Bi = m q, m, q
+  double* A;               // n x N x N: interior blocks, column-major (destroyed)
+  double* Rb;              // n x 16 x N work: a panel's exchanged rows
+  int32_t* flag;           // n: 1 where a block is singular
+  double* Ainv;            // n x N x N: the inverses, column-major
+  const double* U;         // n x m x Bi: U~_k (element k's derivative rows on element k + 1)
+  double* R;               // n x m x Bi: R_k = U~_{k-1} A_k^-1
+  double* pieces;          // n x 4 x m x m: A^-1[S, P], A^-1[S, V], R[:, P], R[:, V]
+  const double* MG;        // n x m x m: the chain's M_k G_k^-1 (host)
+  double* Q;               // n x m x Bi: MG_k R_k
+  double* W;               // n x 2m x Bi: the apply's right-hand-side functionals
+  double* EiT;             // n x Bi x Bi: the apply's interior blocks of E_k, column c contiguous
+};
+// stage 0: inverses, R and the pieces; stage 1 (after the host chain): Q, W and EiT
+hipError_t launch_strip_factor(const StripFactorDevice& f, int stage, hipStream_t stream);
+
 }  // namespace vp

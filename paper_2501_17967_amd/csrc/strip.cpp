@@ -10,13 +10,18 @@
 //
 // The matrix is block tridiagonal with a periodic corner. Block k couples to k - 1 only through
 // the value rows (a selection of m = n_r - 2 entries) and to k + 1 only through the m derivative
-// rows, so every coupling has rank m. Plan time (host): each diagonal block's inverse A_k^-1 (in
-// parallel); the block elimination of the non-periodic part, D_k = A_k + P'_k M_k U~_{k-1} with
-// the m x m matrix M_k = S_{k-1}^T D_{k-1}^-1 P_{k-1}, whose inverse follows from A_k^-1 by the
-// Woodbury identity (sequential, O(B^2 m) per block); the periodic corner is a rank-2m term,
-// removed by the Woodbury identity at the global level. Apply (GPU, strip.hip): batched block
-// products and two m-dimensional recurrences (forward and backward sweeps), then the corner
-// correction.
+// rows, so every coupling has rank m. The Dirichlet unknowns are zero, so only the interior rows
+// and columns of a block (Bi = m q of them, a contiguous range) enter. The factorization:
+//   host   assembly of the interior blocks A_k (row-equilibrated) and couplings U~_k
+//   GPU    A_k^-1 for all elements (batched blocked Gauss-Jordan on FP64 MFMA) and
+//          R_k = U~_{k-1} A_k^-1 (strip_factor.hip)
+//   host   the block elimination of the non-periodic part on m x m pieces only:
+//          D_k = A_k + P'_k M_k U~_{k-1}, M_k = E_{k-1}[S, P], E_k = D_k^-1 = A_k^-1 - C_k MG_k R_k
+//          (Woodbury, MG_k = M_k (I + R_k[:, V] M_k)^-1, C_k = A_k^-1[:, V]); the sweep matrices
+//          F, G, H, their responses to the corner values, and the corner's capacitance matrix
+//   GPU    E_k on the interior (the apply's blocks) and the right-hand-side functionals W_k
+// Apply (GPU, strip.hip): per-element functionals, the two m-dimensional sweeps, the per-element
+// solution product.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -120,19 +125,30 @@ Mat inverse(Mat A, int n) {
   return X;
 }
 
+template <class Fn>
+void parallel_for(int n, Fn fn) {
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    for (int k; (k = next.fetch_add(1)) < n;) fn(k);
+  };
+  const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned i = 1; i < nt && i < unsigned(n); ++i) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+}
+
 struct StripHost {
-  int n = 0, q = 0, nr = 0, B = 0, m = 0;
-  std::vector<double> X;     // n * B * 2 node coordinates
-  std::vector<int8_t> pde;   // B: PDE row flags (same in every element)
-  std::vector<Mat> A;        // diagonal blocks (B x B)
-  std::vector<Mat> Ut;       // m x B: derivative rows of block k acting on block k+1
-  std::vector<int> Prow, Pvrow, Scol, Lcol;  // m each: derivative rows, value rows, last column, first column
-  std::vector<Mat> E;        // D_k^-1 (B x B)
-  std::vector<double> rs;    // n * B row scales of the PDE rows (1 elsewhere)
+  int n = 0, q = 0, nr = 0, B = 0, m = 0, Bi = 0, N = 0;  // N: Bi rounded up to a multiple of 16
+  std::vector<double> X;   // n * B * 2 node coordinates
+  std::vector<double> A;   // n * N * N: interior blocks, column-major, identity beyond Bi
+  std::vector<double> U;   // n * m * Bi: derivative rows of element k on element k + 1's interior
+  std::vector<double> rs;  // n * B: row scale of each PDE row (1 elsewhere)
 };
 
-void build_blocks(StripHost& S, const double* gamma, const double* gamma_t, int n_gl) {
-  const int n = S.n, q = S.q, nr = S.nr, B = S.B;
+// Nodes, operators and the row-equilibrated interior blocks.
+void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl) {
+  const int n = S.n, q = S.q, nr = S.nr, B = S.B, m = S.m, Bi = S.Bi, N = S.N;
   std::vector<double> sg;
   gauss_legendre(n_gl, sg);
   const auto tq = cheb2(q), tr = cheb2(nr);
@@ -168,20 +184,10 @@ void build_blocks(StripHost& S, const double* gamma, const double* gamma_t, int 
       }
     }
   const Mat Dq = diff_matrix(tq), Dr = diff_matrix(tr);
-  S.pde.assign(size_t(B), 0);
-  S.m = nr - 2;
-  S.Prow.clear(); S.Pvrow.clear(); S.Scol.clear(); S.Lcol.clear();
-  for (int i = 1; i < nr - 1; ++i) {
-    S.Pvrow.push_back(i * q);             // value rows (first column)
-    S.Prow.push_back(i * q + q - 1);      // derivative rows (last column)
-    S.Scol.push_back(i * q + q - 1);      // last-column unknowns (read by the next element's value rows)
-    S.Lcol.push_back(i * q);              // first-column unknowns (read by the previous element's derivative rows)
-    for (int j = 1; j < q - 1; ++j) S.pde[size_t(i) * q + j] = 1;
-  }
-  // per element: DX, DY as sparse rows (nonzeros in the same grid row and column)
+  // per element: DX, DY (dense B x B; the nonzeros of a row lie in its grid row and column)
   struct Ops { Mat DX, DY; std::vector<double> xxi, yxi; };
   std::vector<Ops> ops(static_cast<size_t>(n));
-  auto make_ops = [&](int k) {
+  parallel_for(n, [&](int k) {
     Ops o;
     o.DX.assign(size_t(B) * B, 0.0);
     o.DY.assign(size_t(B) * B, 0.0);
@@ -214,321 +220,261 @@ void build_blocks(StripHost& S, const double* gamma, const double* gamma_t, int 
         }
       }
     ops[size_t(k)] = std::move(o);
-  };
-  for (int k = 0; k < n; ++k) make_ops(k);
-  S.A.assign(size_t(n), Mat());
-  S.Ut.assign(size_t(n), Mat());
+  });
+  S.A.assign(size_t(n) * N * N, 0.0);
+  S.U.assign(size_t(n) * m * Bi, 0.0);
   S.rs.assign(size_t(n) * B, 1.0);
-  for (int k = 0; k < n; ++k) {
+  parallel_for(n, [&](int k) {
     const Ops& o = ops[size_t(k)];
     const Ops& on = ops[size_t((k + 1) % n)];
-    Mat A(size_t(B) * B, 0.0);
+    double* Ak = S.A.data() + size_t(k) * N * N;  // column-major: (p, c) at c N + p
     // interface normal between element k and k + 1: the segment from Gamma's to Gamma~'s shared point
     const double* Xk = S.X.data() + size_t(k) * B * 2;
     const double px = Xk[size_t(q - 1) * 2], py = Xk[size_t(q - 1) * 2 + 1];
     const double ptx = Xk[(size_t(nr - 1) * q + q - 1) * 2], pty = Xk[(size_t(nr - 1) * q + q - 1) * 2 + 1];
     const double len = std::hypot(ptx - px, pty - py);
-    double nx = (pty - py) / len, ny = -(ptx - px) / len;
-    Mat Ut(size_t(S.m) * B, 0.0);
-    for (int i = 0; i < nr; ++i)
+    const double nx = (pty - py) / len, ny = -(ptx - px) / len;
+    std::vector<double> rowv(static_cast<size_t>(B)), uvec(static_cast<size_t>(B));
+    for (int i = 1; i < nr - 1; ++i)
       for (int j = 0; j < q; ++j) {
-        const int row = i * q + j;
-        if (i == 0 || i == nr - 1 || j == 0) {
-          A[size_t(row) * B + row] = 1.0;  // Dirichlet, or the value row (its coupling is a selection)
-        } else if (j == q - 1) {
+        const int row = i * q + j, p = row - q;  // p: interior index
+        if (j == 0) {  // value row: unit coefficient here, -1 on the previous element's last column
+          Ak[size_t(p) * N + p] = 1.0;
+          continue;
+        }
+        std::fill(rowv.begin(), rowv.end(), 0.0);
+        double nrm = 0.0;
+        if (j == q - 1) {  // derivative along the interface normal, oriented along increasing j
           double sx = nx, sy = ny;
           if (sx * o.xxi[size_t(row)] + sy * o.yxi[size_t(row)] < 0) { sx = -sx; sy = -sy; }
-          for (int c = 0; c < B; ++c) A[size_t(row) * B + c] = sx * o.DX[size_t(row) * B + c] + sy * o.DY[size_t(row) * B + c];
           const int nrow = i * q;  // the next element's first-column node on this interface
-          for (int c = 0; c < B; ++c)
-            Ut[size_t(i - 1) * B + c] = -(sx * on.DX[size_t(nrow) * B + c] + sy * on.DY[size_t(nrow) * B + c]);
-        } else {  // Laplacian row: (DX DX + DY DY)[row], through the sparse rows of DX, DY
+          for (int c = 0; c < B; ++c) {
+            rowv[size_t(c)] = sx * o.DX[size_t(row) * B + c] + sy * o.DY[size_t(row) * B + c];
+            uvec[size_t(c)] = -(sx * on.DX[size_t(nrow) * B + c] + sy * on.DY[size_t(nrow) * B + c]);
+            nrm += std::fabs(rowv[size_t(c)]) + std::fabs(uvec[size_t(c)]);
+          }
+        } else {  // Laplacian row (DX DX + DY DY)[row], through the sparse rows of DX, DY
           for (int c = 0; c < B; ++c) {
             const double ax = o.DX[size_t(row) * B + c], ay = o.DY[size_t(row) * B + c];
             if (ax == 0.0 && ay == 0.0) continue;
-            for (int d = 0; d < B; ++d)
-              A[size_t(row) * B + d] += ax * o.DX[size_t(c) * B + d] + ay * o.DY[size_t(c) * B + d];
+            for (int d = 0; d < B; ++d) rowv[size_t(d)] += ax * o.DX[size_t(c) * B + d] + ay * o.DY[size_t(c) * B + d];
           }
+          for (int c = 0; c < B; ++c) nrm += std::fabs(rowv[size_t(c)]);
+        }
+        // Row equilibration: the Laplacian rows have 1-norms up to ~1e7 (spectral second
+        // derivatives on thin elements), the value rows 2. Scaling the PDE and derivative rows
+        // (with their coupling to element k + 1) to unit 1-norm leaves the solution unchanged and
+        // keeps the block inverses and the sweeps well conditioned; the right-hand side of a PDE
+        // row is scaled with it (rs, applied on the GPU). The Dirichlet columns are dropped (the
+        // unknowns there are zero).
+        const double sc = 1.0 / nrm;
+        for (int c = 0; c < Bi; ++c) Ak[size_t(c) * N + p] = sc * rowv[size_t(q + c)];
+        if (j == q - 1) {
+          for (int c = 0; c < Bi; ++c) S.U[(size_t(k) * m + (i - 1)) * Bi + c] = sc * uvec[size_t(q + c)];
+        } else {
+          S.rs[size_t(k) * B + row] = sc;
         }
       }
-    // Row equilibration: the Laplacian rows have 1-norms up to ~1e7 (spectral second derivatives
-    // on thin elements), the Dirichlet and value rows 1 or 2. Scaling the PDE and derivative rows
-    // to unit 1-norm (the derivative rows together with their coupling to element k + 1) leaves
-    // the solution unchanged and keeps the block inverses and the recurrences well conditioned.
-    // The value rows keep their unit coefficients (norm 2), so the coupling to k - 1 stays a
-    // selection; the right-hand side of a PDE row is scaled with it (rs, applied on the GPU).
-    for (int i = 1; i < nr - 1; ++i)
-      for (int j = 1; j < q; ++j) {
-        const int row = i * q + j;
-        double nrm = 0.0;
-        for (int c = 0; c < B; ++c) nrm += std::fabs(A[size_t(row) * B + c]);
-        if (j == q - 1)
-          for (int c = 0; c < B; ++c) nrm += std::fabs(Ut[size_t(i - 1) * B + c]);
-        const double sc = 1.0 / nrm;
-        for (int c = 0; c < B; ++c) A[size_t(row) * B + c] *= sc;
-        if (j == q - 1)
-          for (int c = 0; c < B; ++c) Ut[size_t(i - 1) * B + c] *= sc;
-        else
-          S.rs[size_t(k) * B + row] = sc;
-      }
-    S.A[size_t(k)] = std::move(A);
-    S.Ut[size_t(k)] = std::move(Ut);
-  }
+    for (int p = Bi; p < N; ++p) Ak[size_t(p) * N + p] = 1.0;  // padding
+  });
 }
 
-// E_k = D_k^-1 for the non-periodic block-tridiagonal part, from A_k^-1 (parallel) and the
-// rank-m chain M_k = S^T E_{k-1} P (sequential).
-void factor(StripHost& S) {
-  const int n = S.n, B = S.B, m = S.m;
-  std::vector<Mat> Ainv(static_cast<size_t>(n));
-  std::atomic<int> next(0);
-  std::vector<std::exception_ptr> err(static_cast<size_t>(n));
-  auto work = [&]() {
-    for (int k; (k = next.fetch_add(1)) < n;) {
-      try {
-        Ainv[size_t(k)] = inverse(S.A[size_t(k)], B);
-      } catch (...) {
-        err[size_t(k)] = std::current_exception();
-      }
-    }
-  };
-  const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-  std::vector<std::thread> pool;
-  for (unsigned i = 1; i < nt; ++i) pool.emplace_back(work);
-  work();
-  for (auto& t : pool) t.join();
-  for (auto& e : err)
-    if (e) std::rethrow_exception(e);
-  S.E.assign(size_t(n), Mat());
-  S.E[0] = Ainv[0];
-  for (int k = 1; k < n; ++k) {
-    const Mat& Ep = S.E[size_t(k - 1)];
-    const Mat& Ai = Ainv[size_t(k)];
-    const Mat& Up = S.Ut[size_t(k - 1)];  // m x B, acting on block k
-    // M = S^T E_{k-1} P: E_{k-1}[last-column node, derivative row]   (m x m)
-    Mat M(size_t(m) * m);
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) M[size_t(a) * m + b] = Ep[size_t(S.Scol[size_t(a)]) * B + S.Prow[size_t(b)]];
-    // D_k = A_k + P'_k M U~_{k-1}; D_k^-1 = Ai - C M G^-1 R, C = Ai P' (B x m), R = U~ Ai (m x B),
-    // G = I + (R P') M
-    Mat C(size_t(B) * m), R(size_t(m) * B, 0.0);
-    for (int r = 0; r < B; ++r)
-      for (int b = 0; b < m; ++b) C[size_t(r) * m + b] = Ai[size_t(r) * B + S.Pvrow[size_t(b)]];
-    for (int a = 0; a < m; ++a)
-      for (int c = 0; c < B; ++c) {
-        const double u = Up[size_t(a) * B + c];
-        if (u == 0.0) continue;
-        for (int d = 0; d < B; ++d) R[size_t(a) * B + d] += u * Ai[size_t(c) * B + d];
-      }
-    Mat G(size_t(m) * m, 0.0);
-    for (int a = 0; a < m; ++a) {
-      G[size_t(a) * m + a] = 1.0;
-      for (int b = 0; b < m; ++b) {
-        double s = 0.0;
-        for (int c = 0; c < m; ++c) s += R[size_t(a) * B + S.Pvrow[size_t(c)]] * M[size_t(c) * m + b];
-        G[size_t(a) * m + b] += s;
-      }
-    }
-    const Mat Gi = inverse(G, m);
-    Mat MG(size_t(m) * m, 0.0);  // M G^-1
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) {
-        double s = 0.0;
-        for (int c = 0; c < m; ++c) s += M[size_t(a) * m + c] * Gi[size_t(c) * m + b];
-        MG[size_t(a) * m + b] = s;
-      }
-    Mat CMG(size_t(B) * m, 0.0);
-    for (int r = 0; r < B; ++r)
-      for (int b = 0; b < m; ++b) {
-        double s = 0.0;
-        for (int c = 0; c < m; ++c) s += C[size_t(r) * m + c] * MG[size_t(c) * m + b];
-        CMG[size_t(r) * m + b] = s;
-      }
-    Mat Ek = Ai;
-    for (int r = 0; r < B; ++r)
-      for (int b = 0; b < m; ++b) {
-        const double cmg = CMG[size_t(r) * m + b];
-        for (int d = 0; d < B; ++d) Ek[size_t(r) * B + d] -= cmg * R[size_t(b) * B + d];
-      }
-    S.E[size_t(k)] = std::move(Ek);
-  }
-}
-
-// x = T^-1 b for the non-periodic part on the host (plan time: the corner columns)
-void host_tsolve(const StripHost& S, const double* b, double* x) {
-  const int n = S.n, B = S.B, m = S.m;
-  std::vector<double> y(static_cast<size_t>(n) * B), rhs(static_cast<size_t>(B));
-  for (int k = 0; k < n; ++k) {
-    for (int r = 0; r < B; ++r) rhs[size_t(r)] = b[size_t(k) * B + r];
-    if (k > 0)  // b_k - L_k y_{k-1}: the value rows add the previous element's last column
-      for (int a = 0; a < m; ++a) rhs[size_t(S.Pvrow[size_t(a)])] += y[size_t(k - 1) * B + S.Scol[size_t(a)]];
-    for (int r = 0; r < B; ++r) {
-      double s = 0.0;
-      for (int c = 0; c < B; ++c) s += S.E[size_t(k)][size_t(r) * B + c] * rhs[size_t(c)];
-      y[size_t(k) * B + r] = s;
-    }
-  }
-  for (int r = 0; r < B; ++r) x[size_t(n - 1) * B + r] = y[size_t(n - 1) * B + r];
-  for (int k = n - 2; k >= 0; --k) {
-    std::vector<double> t(size_t(m), 0.0);  // U~_k x_{k+1}
-    for (int a = 0; a < m; ++a)
-      for (int c = 0; c < B; ++c) t[size_t(a)] += S.Ut[size_t(k)][size_t(a) * B + c] * x[size_t(k + 1) * B + c];
-    for (int r = 0; r < B; ++r) {
-      double s = 0.0;  // E_k P t
-      for (int a = 0; a < m; ++a) s += S.E[size_t(k)][size_t(r) * B + S.Prow[size_t(a)]] * t[size_t(a)];
-      x[size_t(k) * B + r] = y[size_t(k) * B + r] - s;
-    }
-  }
-}
-
-// Arrays of the three-launch apply. With Bi = m q the interior rows (1 <= i <= n_r - 2, a
-// contiguous range q .. B - q - 1 of each element), the Dirichlet rows of D_k are identity rows,
-// so x is zero there and only the interior block of E_k = D_k^-1 is ever applied.
-//   rhs pass:  s_k = E_k[S, :] b_k,  w_k = U~_{k-1} E_k b_k         (W_k, 2m x Bi; U~_{-1} = U~_{n-1})
-//   sweep:     z_0 = 0, z_{k+1} = s_k + F_k z_k;  g_k = w_k + G_k z_k;
-//              t_n = 0, t_k = g_k - H_k t_{k+1} (k = n-1 .. 1);
-//              h = K [z_n; w_0 - H_0 t_1]                          (the periodic corner, Woodbury)
-//   solution:  z*_k = z_k + Pz_k h_lo,  t*_{k+1} = t_{k+1} + Pt_{k+1} h,
-//              x_k = E_k (b_k + P' z*_k - P t*_{k+1})             (interior block, Bi x Bi)
-// The corrected solution T^-1 (b - U_c h) is the non-periodic sweep started from z_0 = h_lo and
-// t_n = h_hi (U_c injects exactly there), and the sweep is linear in those two boundary values:
-// Pz_k, Pt_k are its responses, precomputed here.
-struct StripArrays {
-  int n = 0, q = 0, B = 0, m = 0, Bi = 0;
-  std::vector<double> EiT, W, F, G, Hm, Pz, Pt, K, rs;
+// The chain on m x m pieces (row-major), after the GPU has formed A_k^-1 and R_k.
+struct Chain {
+  std::vector<double> MG, F, G, H, Pz, Pt, K;
 };
 
-template <class Fn>
-void parallel_for(int n, Fn fn) {
-  std::atomic<int> next(0);
-  auto work = [&]() {
-    for (int k; (k = next.fetch_add(1)) < n;) fn(k);
-  };
-  const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-  std::vector<std::thread> pool;
-  for (unsigned i = 1; i < nt && i < unsigned(n); ++i) pool.emplace_back(work);
-  work();
-  for (auto& t : pool) t.join();
+Mat mul(const Mat& X, const Mat& Y, int r, int s, int t) {  // (r x s)(s x t)
+  Mat Z(size_t(r) * t, 0.0);
+  for (int i = 0; i < r; ++i)
+    for (int l = 0; l < s; ++l) {
+      const double x = X[size_t(i) * s + l];
+      for (int j = 0; j < t; ++j) Z[size_t(i) * t + j] += x * Y[size_t(l) * t + j];
+    }
+  return Z;
 }
 
-void apply_arrays(const StripHost& H, StripArrays& R) {
-  const int n = H.n, B = H.B, m = H.m, q = H.q, Bi = B - 2 * q;
-  R.n = n; R.q = q; R.B = B; R.m = m; R.Bi = Bi;
+void chain(int n, int m, const std::vector<double>& pieces, Chain& C) {
   const size_t mm = size_t(m) * m;
-  R.EiT.assign(size_t(n) * Bi * Bi, 0.0);
-  R.W.assign(size_t(n) * 2 * m * Bi, 0.0);
-  R.F.assign(size_t(n) * mm, 0.0);
-  R.G.assign(size_t(n) * mm, 0.0);
-  R.Hm.assign(size_t(n) * mm, 0.0);
-  parallel_for(n, [&](int k) {
-    const Mat& E = H.E[size_t(k)];
-    const Mat& U = H.Ut[size_t((k + n - 1) % n)];  // derivative rows of element k - 1 acting on k
-    for (int c = 0; c < Bi; ++c)
-      for (int p = 0; p < Bi; ++p) R.EiT[(size_t(k) * Bi + c) * Bi + p] = E[size_t(q + p) * B + q + c];
-    std::vector<double> UE(size_t(m) * B, 0.0);  // U~ E_k (m x B)
-    for (int a = 0; a < m; ++a)
-      for (int r = 0; r < B; ++r) {
-        const double u = U[size_t(a) * B + r];
-        if (u == 0.0) continue;
-        for (int c = 0; c < B; ++c) UE[size_t(a) * B + c] += u * E[size_t(r) * B + c];
-      }
-    double* W = R.W.data() + size_t(k) * 2 * m * Bi;
-    for (int a = 0; a < m; ++a)
-      for (int c = 0; c < Bi; ++c) {
-        W[size_t(a) * Bi + c] = E[size_t(H.Scol[size_t(a)]) * B + q + c];
-        W[size_t(m + a) * Bi + c] = UE[size_t(a) * B + q + c];
-      }
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) {
-        R.F[size_t(k) * mm + size_t(a) * m + b] = E[size_t(H.Scol[size_t(a)]) * B + H.Pvrow[size_t(b)]];
-        R.G[size_t(k) * mm + size_t(a) * m + b] = UE[size_t(a) * B + H.Pvrow[size_t(b)]];
-        R.Hm[size_t(k) * mm + size_t(a) * m + b] = UE[size_t(a) * B + H.Prow[size_t(b)]];
-      }
-  });
-  // responses of the sweep to its boundary values
+  auto piece = [&](int k, int which) {
+    return Mat(pieces.begin() + long(size_t(k) * 4 * mm + which * mm), pieces.begin() + long(size_t(k) * 4 * mm + (which + 1) * mm));
+  };
+  Mat I(mm, 0.0);
+  for (int a = 0; a < m; ++a) I[size_t(a) * m + a] = 1.0;
+  C.MG.assign(size_t(n) * mm, 0.0);
+  C.F.assign(size_t(n) * mm, 0.0);
+  C.G.assign(size_t(n) * mm, 0.0);
+  C.H.assign(size_t(n) * mm, 0.0);
+  auto put = [&](std::vector<double>& dst, int k, const Mat& v) { std::copy(v.begin(), v.end(), dst.begin() + long(size_t(k) * mm)); };
+  // element 0: E_0 = A_0^-1 (no elimination yet); G_0, H_0 use U~_{n-1} (the corner's terms)
+  Mat ESP = piece(0, 0);
+  put(C.F, 0, piece(0, 1));
+  put(C.G, 0, piece(0, 3));
+  put(C.H, 0, piece(0, 2));
+  for (int k = 1; k < n; ++k) {
+    const Mat aSP = piece(k, 0), aSV = piece(k, 1), rP = piece(k, 2), rV = piece(k, 3);
+    Mat Gm = mul(rV, ESP, m, m, m);
+    for (size_t e = 0; e < mm; ++e) Gm[e] += I[e];
+    const Mat MG = mul(ESP, inverse(Gm, m), m, m, m);
+    const Mat T1 = mul(aSV, MG, m, m, m);
+    const Mat T1P = mul(T1, rP, m, m, m), T1V = mul(T1, rV, m, m, m);
+    Mat Y = mul(rV, MG, m, m, m);
+    for (size_t e = 0; e < mm; ++e) Y[e] = I[e] - Y[e];
+    Mat Fk(mm);
+    for (size_t e = 0; e < mm; ++e) {
+      ESP[e] = aSP[e] - T1P[e];
+      Fk[e] = aSV[e] - T1V[e];
+    }
+    put(C.MG, k, MG);
+    put(C.F, k, Fk);
+    put(C.G, k, mul(Y, rV, m, m, m));
+    put(C.H, k, mul(Y, rP, m, m, m));
+  }
+  // ESP = E_{n-1}[S, P]
   const int m2 = 2 * m;
-  R.Pz.assign(size_t(n) * mm, 0.0);
-  for (int a = 0; a < m; ++a) R.Pz[size_t(a) * m + a] = 1.0;
-  for (int k = 0; k + 1 < n; ++k)
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) {
-        double acc = 0.0;
-        for (int c = 0; c < m; ++c) acc += R.F[size_t(k) * mm + size_t(a) * m + c] * R.Pz[size_t(k) * mm + size_t(c) * m + b];
-        R.Pz[size_t(k + 1) * mm + size_t(a) * m + b] = acc;
-      }
-  R.Pt.assign(size_t(n + 1) * m * m2, 0.0);
-  for (int a = 0; a < m; ++a) R.Pt[size_t(n) * m * m2 + size_t(a) * m2 + m + a] = 1.0;
+  // responses of the sweep to its boundary values z_0 = h_lo, t_n = h_hi
+  C.Pz.assign(size_t(n) * mm, 0.0);
+  for (int a = 0; a < m; ++a) C.Pz[size_t(a) * m + a] = 1.0;
+  for (int k = 0; k + 1 < n; ++k) {
+    const Mat Fk(C.F.begin() + long(size_t(k) * mm), C.F.begin() + long(size_t(k + 1) * mm));
+    const Mat Pk(C.Pz.begin() + long(size_t(k) * mm), C.Pz.begin() + long(size_t(k + 1) * mm));
+    put(C.Pz, k + 1, mul(Fk, Pk, m, m, m));
+  }
+  C.Pt.assign(size_t(n + 1) * m * m2, 0.0);
+  for (int a = 0; a < m; ++a) C.Pt[size_t(n) * m * m2 + size_t(a) * m2 + m + a] = 1.0;
   for (int k = n - 1; k >= 1; --k)
     for (int a = 0; a < m; ++a)
       for (int j = 0; j < m2; ++j) {
         double acc = 0.0;
         if (j < m)
-          for (int c = 0; c < m; ++c) acc += R.G[size_t(k) * mm + size_t(a) * m + c] * R.Pz[size_t(k) * mm + size_t(c) * m + j];
+          for (int c = 0; c < m; ++c) acc += C.G[size_t(k) * mm + size_t(a) * m + c] * C.Pz[size_t(k) * mm + size_t(c) * m + j];
         for (int c = 0; c < m; ++c)
-          acc -= R.Hm[size_t(k) * mm + size_t(a) * m + c] * R.Pt[size_t(k + 1) * m * m2 + size_t(c) * m2 + j];
-        R.Pt[size_t(k) * m * m2 + size_t(a) * m2 + j] = acc;
+          acc -= C.H[size_t(k) * mm + size_t(a) * m + c] * C.Pt[size_t(k + 1) * m * m2 + size_t(c) * m2 + j];
+        C.Pt[size_t(k) * m * m2 + size_t(a) * m2 + j] = acc;
       }
-  // the corner: Z = T^-1 U_c (columns -e at element 0's value rows, +e at element n-1's
-  // derivative rows), K = (I + V^T Z)^-1 with V^T = [element n-1's last column; U~_{n-1} on element 0]
-  const size_t N = size_t(n) * B;
-  std::vector<double> Z(N * m2);
-  parallel_for(m2, [&](int j) {
-    std::vector<double> col(N, 0.0), sol(N);
-    if (j < m) col[size_t(H.Pvrow[size_t(j)])] = -1.0;
-    else col[size_t(n - 1) * B + H.Prow[size_t(j - m)]] = 1.0;
-    host_tsolve(H, col.data(), sol.data());
-    for (size_t r = 0; r < N; ++r) Z[r * m2 + j] = sol[r];
-  });
+  // the corner: K = (I + V^T Z)^-1, Z = T^-1 U_c. A column of U_c enters the sweep as a boundary
+  // value (-e_j at z_0, or -e_j at t_n), so V^T Z follows from the responses:
+  //   j < m:  [-(F_{n-1} Pz_{n-1})[:, j];  -G_0[:, j] + (H_0 Pt_1)[:, j]]
+  //   j >= m: [E_{n-1}[S, P][:, j - m];    (H_0 Pt_1)[:, j]]
+  const Mat Fl(C.F.begin() + long(size_t(n - 1) * mm), C.F.end());
+  const Mat Pl(C.Pz.begin() + long(size_t(n - 1) * mm), C.Pz.end());
+  const Mat FP = mul(Fl, Pl, m, m, m);
+  const Mat H0(C.H.begin(), C.H.begin() + long(mm));
+  const Mat Pt1(C.Pt.begin() + long(size_t(m) * m2), C.Pt.begin() + long(size_t(2) * m * m2));
+  const Mat HP = mul(H0, Pt1, m, m, m2);
   Mat Gc(size_t(m2) * m2, 0.0);
-  for (int a = 0; a < m2; ++a) {
-    Gc[size_t(a) * m2 + a] = 1.0;
+  for (int a = 0; a < m; ++a)
     for (int j = 0; j < m2; ++j) {
-      double v;
-      if (a < m) {
-        v = Z[(size_t(n - 1) * B + H.Scol[size_t(a)]) * m2 + j];
-      } else {
-        v = 0.0;
-        for (int r = 0; r < B; ++r) v += H.Ut[size_t(n - 1)][size_t(a - m) * B + r] * Z[size_t(r) * m2 + j];
-      }
-      Gc[size_t(a) * m2 + j] += v;
+      Gc[size_t(a) * m2 + j] = j < m ? -FP[size_t(a) * m + j] : ESP[size_t(a) * m + (j - m)];
+      Gc[size_t(m + a) * m2 + j] = (j < m ? -C.G[size_t(a) * m + j] : 0.0) + HP[size_t(a) * m2 + j];
     }
-  }
-  R.K = inverse(Gc, m2);  // throws on a singular corner system
-  R.rs = H.rs;
+  for (int a = 0; a < m2; ++a) Gc[size_t(a) * m2 + a] += 1.0;
+  C.K = inverse(Gc, m2);  // throws on a singular corner system
 }
 
 }  // namespace
 
 struct volpot_strip_s {
-  StripHost H;
+  int n = 0, q = 0, nr = 0;
+  std::vector<double> X;  // node coordinates
   int device = -1;
   StripDevice d{};
   char* block = nullptr;
 };
 
-// Device copy of everything the apply reads, and its work vectors, in one allocation.
-static int strip_upload(volpot_strip_s* s, const StripArrays& R) {
-  const int n = R.n, m = R.m;
-  const size_t N = size_t(n) * R.B;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const std::vector<double>* in[] = {&R.EiT, &R.W, &R.F, &R.G, &R.Hm, &R.Pz, &R.Pt, &R.K, &R.rs};
-  size_t off[9], o = 0;
-  for (int i = 0; i < 9; ++i) { off[i] = o; o += al(in[i]->size() * 8); }
-  const size_t os = o; o += al(size_t(n) * m * 8);
-  const size_t ow = o; o += al(size_t(n) * m * 8);
-  const size_t oz = o; o += al(size_t(n + 1) * m * 8);
-  const size_t ot = o; o += al(size_t(n + 1) * m * 8);
-  const size_t oh = o; o += al(size_t(2 * m) * 8);
-  (void)N;
+namespace {
+
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// The factorization: host assembly, GPU inverses, host chain, GPU blocks; the apply's arrays
+// in one allocation (s->block).
+int strip_factor(volpot_strip_s* s, StripHost& H) {
+  const int n = H.n, m = H.m, Bi = H.Bi, N = H.N, B = H.B, q = H.q;
+  const size_t mm = size_t(m) * m, m2 = size_t(2) * m;
   if (hipGetDevice(&s->device) != hipSuccess) return VOLPOT_ERR_HIP;
+  // the apply's block
+  const size_t nEiT = size_t(n) * Bi * Bi, nW = size_t(n) * m2 * Bi, nmm = size_t(n) * mm;
+  size_t o = 0;
+  const size_t oEiT = o; o += al256(nEiT * 8);
+  const size_t oW = o; o += al256(nW * 8);
+  const size_t oF = o; o += al256(nmm * 8);
+  const size_t oG = o; o += al256(nmm * 8);
+  const size_t oH = o; o += al256(nmm * 8);
+  const size_t oPz = o; o += al256(nmm * 8);
+  const size_t oPt = o; o += al256(size_t(n + 1) * m * m2 * 8);
+  const size_t oK = o; o += al256(m2 * m2 * 8);
+  const size_t oR = o; o += al256(size_t(n) * B * 8);
+  const size_t os = o; o += al256(size_t(n) * m * 8);
+  const size_t ow = o; o += al256(size_t(n) * m * 8);
+  const size_t oz = o; o += al256(size_t(n + 1) * m * 8);
+  const size_t ot = o; o += al256(size_t(n + 1) * m * 8);
+  const size_t oh = o; o += al256(m2 * 8);
   if (hipMalloc(&s->block, o) != hipSuccess) { s->block = nullptr; return VOLPOT_ERR_OOM; }
   char* b = s->block;
-  for (int i = 0; i < 9; ++i)
-    if (hipMemcpy(b + off[i], in[i]->data(), in[i]->size() * 8, hipMemcpyHostToDevice) != hipSuccess) return VOLPOT_ERR_HIP;
+  // plan-time work memory
+  size_t w = 0;
+  const size_t wA = w; w += al256(size_t(n) * N * N * 8);
+  const size_t wAi = w; w += al256(size_t(n) * N * N * 8);
+  const size_t wRb = w; w += al256(size_t(n) * 16 * N * 8);
+  const size_t wFl = w; w += al256(size_t(n) * 4);
+  const size_t wU = w; w += al256(size_t(n) * m * Bi * 8);
+  const size_t wRm = w; w += al256(size_t(n) * m * Bi * 8);
+  const size_t wPc = w; w += al256(size_t(n) * 4 * mm * 8);
+  const size_t wMG = w; w += al256(nmm * 8);
+  const size_t wQ = w; w += al256(size_t(n) * m * Bi * 8);
+  char* work = nullptr;
+  if (hipMalloc(&work, w) != hipSuccess) return VOLPOT_ERR_OOM;
+  int rc = VOLPOT_OK;
+  auto fail = [&](int e) { rc = e; return e; };
+  do {
+    StripFactorDevice f{};
+    f.n = n; f.N = N; f.Bi = Bi; f.m = m; f.q = q;
+    f.A = reinterpret_cast<double*>(work + wA);
+    f.Ainv = reinterpret_cast<double*>(work + wAi);
+    f.Rb = reinterpret_cast<double*>(work + wRb);
+    f.flag = reinterpret_cast<int32_t*>(work + wFl);
+    f.U = reinterpret_cast<const double*>(work + wU);
+    f.R = reinterpret_cast<double*>(work + wRm);
+    f.pieces = reinterpret_cast<double*>(work + wPc);
+    f.MG = reinterpret_cast<const double*>(work + wMG);
+    f.Q = reinterpret_cast<double*>(work + wQ);
+    f.W = reinterpret_cast<double*>(b + oW);
+    f.EiT = reinterpret_cast<double*>(b + oEiT);
+    if (hipMemcpy(f.A, H.A.data(), H.A.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(work + wU, H.U.data(), H.U.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+    if (launch_strip_factor(f, 0, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+    std::vector<int32_t> flag(static_cast<size_t>(n));
+    std::vector<double> pieces(size_t(n) * 4 * mm);
+    if (hipMemcpy(flag.data(), f.flag, size_t(n) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(pieces.data(), f.pieces, pieces.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+    if (std::any_of(flag.begin(), flag.end(), [](int32_t v) { return v != 0; })) { fail(VOLPOT_ERR_ARG); break; }
+    Chain C;
+    try {
+      chain(n, m, pieces, C);
+    } catch (const std::bad_alloc&) {
+      fail(VOLPOT_ERR_OOM);
+      break;
+    } catch (...) {
+      fail(VOLPOT_ERR_ARG);  // a singular m x m system: degenerate geometry
+      break;
+    }
+    if (hipMemcpy(work + wMG, C.MG.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oF, C.F.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oG, C.G.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oH, C.H.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oPz, C.Pz.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oPt, C.Pt.data(), C.Pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oK, C.K.data(), C.K.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + oR, H.rs.data(), H.rs.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+    if (launch_strip_factor(f, 1, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+  } while (false);
+  (void)hipFree(work);
+  if (rc != VOLPOT_OK) return rc;
   StripDevice& d = s->d;
-  d.n = n; d.q = R.q; d.B = R.B; d.m = m; d.Bi = R.Bi;
-  auto cd = [&](int i) { return reinterpret_cast<const double*>(b + off[i]); };
-  d.EiT = cd(0); d.W = cd(1); d.F = cd(2); d.G = cd(3); d.H = cd(4); d.Pz = cd(5); d.Pt = cd(6); d.K = cd(7); d.rs = cd(8);
+  d.n = n; d.q = q; d.B = B; d.m = m; d.Bi = Bi;
+  auto cd = [&](size_t off) { return reinterpret_cast<const double*>(b + off); };
+  d.EiT = cd(oEiT); d.W = cd(oW); d.F = cd(oF); d.G = cd(oG); d.H = cd(oH); d.Pz = cd(oPz); d.Pt = cd(oPt);
+  d.K = cd(oK); d.rs = cd(oR);
   d.s = reinterpret_cast<double*>(b + os);
   d.w = reinterpret_cast<double*>(b + ow);
   d.z = reinterpret_cast<double*>(b + oz);
@@ -538,11 +484,13 @@ static int strip_upload(volpot_strip_s* s, const StripArrays& R) {
   return VOLPOT_OK;
 }
 
+}  // namespace
+
 extern "C" {
 
 int volpot_strip_nodes(volpot_strip_t s, double* xy) {
   if (!s || !xy) return VOLPOT_ERR_ARG;
-  std::memcpy(xy, s->H.X.data(), s->H.X.size() * sizeof(double));
+  std::memcpy(xy, s->X.data(), s->X.size() * sizeof(double));
   return VOLPOT_OK;
 }
 
@@ -577,32 +525,17 @@ int volpot_strip_plan(int32_t n_panel, int32_t n_gl, const double* gamma, const 
     if (!std::isfinite(gamma[i]) || !std::isfinite(gamma_t[i])) return VOLPOT_ERR_ARG;
   auto* s = new (std::nothrow) volpot_strip_s();
   if (!s) return VOLPOT_ERR_OOM;
-  StripHost& H = s->H;
-  H.n = n_panel; H.q = q; H.nr = n_r; H.B = q * n_r;
+  s->n = n_panel; s->q = q; s->nr = n_r;
+  StripHost H;
+  H.n = n_panel; H.q = q; H.nr = n_r; H.B = q * n_r; H.m = n_r - 2; H.Bi = H.m * q; H.N = (H.Bi + 15) / 16 * 16;
   try {
-    build_blocks(H, gamma, gamma_t, n_gl);
-    factor(H);
+    assemble(H, gamma, gamma_t, n_gl);
   } catch (const std::bad_alloc&) {
     delete s;
     return VOLPOT_ERR_OOM;
-  } catch (...) {
-    delete s;
-    return VOLPOT_ERR_ARG;  // a singular block: degenerate element geometry
   }
-  StripArrays R;
-  try {
-    apply_arrays(H, R);
-  } catch (const std::bad_alloc&) {
-    delete s;
-    return VOLPOT_ERR_OOM;
-  } catch (...) {
-    delete s;
-    return VOLPOT_ERR_ARG;  // a singular corner system
-  }
-  std::vector<Mat>().swap(H.A);  // the host blocks are no longer needed
-  std::vector<Mat>().swap(H.E);
-  std::vector<Mat>().swap(H.Ut);
-  int rc = strip_upload(s, R);
+  s->X = H.X;
+  const int rc = strip_factor(s, H);
   if (rc != VOLPOT_OK) { volpot_strip_destroy(s); return rc; }
   *out = s;
   return VOLPOT_OK;

@@ -8,10 +8,10 @@
 //   strip_solution_kernel  per element and 64-row tile: z*_k = z_k + Pz_k h_lo,
 //                          t*_{k+1} = t_{k+1} + Pt_{k+1} h, x_k = E_k (b_k + P' z*_k - P t*_{k+1})
 //                          on the interior rows; the Dirichlet rows are zero
-// In the sweep, wave 0 runs the recurrence with lane a holding component a of the vector (the
-// other components come by lane broadcast), reading its m x m matrices from LDS, while waves
-// 1-3 stage the next chunk of matrices (double buffer, one barrier per chunk). All sums have a
-// fixed order, so repeated applies are bitwise identical.
+// In the sweep, wave 0 runs the recurrence with lane a holding component a of the vector (each
+// step writes the vector to a wave-private LDS slot and reads it back as a broadcast), reading
+// its m x m matrices from LDS, while waves 1-3 stage the next chunk of matrices (double buffer,
+// one barrier per chunk). All sums have a fixed order, so repeated applies are bitwise identical.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -67,6 +67,34 @@ __device__ __forceinline__ void load_row(const double* A, int lane, double (&row
   for (int b = 0; b < m; ++b) row[b] = A[a * m + b];
 }
 
+__device__ __forceinline__ void wave_sync() {
+  // orders this wavefront's LDS accesses around the point (the LDS executes a wave's accesses in
+  // issue order; the fences keep the compiler from moving them across)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// As apply_row, with x broadcast through a wave-private LDS vector xb (m doubles, 16-byte
+// aligned): one write and m/2 broadcast reads instead of 2m lane reads.
+template <int m>
+__device__ __forceinline__ double apply_row_lds(const double (&row)[m], double c, double x, double sgn, double* xb,
+                                                int lane) {
+  if (lane < m) xb[lane] = x;
+  wave_sync();
+  double xv[m];
+#pragma unroll
+  for (int b = 0; b < m; ++b) xv[b] = xb[b];
+  wave_sync();
+  double v0 = c, v1 = 0.0;
+#pragma unroll
+  for (int b = 0; b < m; b += 2) {
+    v0 = fma(sgn * row[b], xv[b], v0);
+    if (b + 1 < m) v1 = fma(sgn * row[b + 1], xv[b + 1], v1);
+  }
+  return v0 + v1;
+}
+
 template <int m>
 __device__ __forceinline__ double apply_row(const double (&row)[m], double c, double x, double sgn) {
   double v0 = c, v1 = 0.0;
@@ -104,6 +132,7 @@ __global__ void __launch_bounds__(kStripThreads) strip_sweep_kernel(StripDevice 
   // buffer i of the double buffer, computed from the LDS base so that the accesses stay LDS
   // accesses (a pointer taken through a private array would become a generic one)
   auto buf = [&](int i) { return sm + size_t(i & 1) * C * st; };
+  double* xb = sm + size_t(2) * C * st;  // wave 0's broadcast vector (32 doubles)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int loader = tid - 64, nload = kStripThreads - 64;
   const int nfc = (n + C - 1) / C;        // forward chunks: buffers 0 .. nfc - 1
@@ -148,7 +177,7 @@ __global__ void __launch_bounds__(kStripThreads) strip_sweep_kernel(StripDevice 
       for (int kk = 0; kk < ns; ++kk) {
         double row[m];
         load_row<m>(cb + size_t(kk) * mm, lane, row);
-        z = apply_row<m>(row, cb[size_t(C) * mm + size_t(kk) * m + ml], z, 1.0);
+        z = apply_row_lds<m>(row, cb[size_t(C) * mm + size_t(kk) * m + ml], z, 1.0, xb, lane);
         if (lane < m) d.z[size_t(k0 + kk + 1) * m + lane] = z;
       }
     } else if (ci + 1 < nfc) {
@@ -173,7 +202,7 @@ __global__ void __launch_bounds__(kStripThreads) strip_sweep_kernel(StripDevice 
       for (int uu = 0; uu < ns; ++uu) {
         double row[m];
         load_row<m>(cb + size_t(ns - 1 - uu) * mm, lane, row);
-        t = apply_row<m>(row, cb[size_t(C) * mm + size_t(uu) * m + ml], t, -1.0);
+        t = apply_row_lds<m>(row, cb[size_t(C) * mm + size_t(uu) * m + ml], t, -1.0, xb, lane);
         if (lane < m) d.t[size_t(n - 1 - (u0 + uu)) * m + lane] = t;
       }
     } else if (ci + 1 < nbc) {
@@ -248,7 +277,7 @@ __global__ void __launch_bounds__(kSolThreads)
 
 hipError_t launch_strip_solve(const StripDevice& d, const double* f, double* v, hipStream_t stream) {
   if (d.m < 2 || d.m > kMaxM) return hipErrorInvalidValue;  // the plan keeps 4 <= n_r <= 32
-  const size_t lds_sweep = size_t(2) * d.chunk * (d.m * d.m + d.m) * sizeof(double);
+  const size_t lds_sweep = (size_t(2) * d.chunk * (d.m * d.m + d.m) + 32) * sizeof(double);
   hipLaunchKernelGGL(strip_rhs_kernel, dim3(unsigned(d.n), unsigned((2 * d.m + 3) / 4)), dim3(kStripThreads),
                      size_t(d.Bi) * sizeof(double), stream, d, f);
   using Sweep = void (*)(StripDevice);
