@@ -184,15 +184,14 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
       }
     }
   const Mat Dq = diff_matrix(tq), Dr = diff_matrix(tr);
-  // per element: DX, DY (dense B x B; the nonzeros of a row lie in its grid row and column)
-  struct Ops { Mat DX, DY; std::vector<double> xxi, yxi; };
-  std::vector<Ops> ops(static_cast<size_t>(n));
+  // per element and node: the inverse-map factors of D_X = M[xi_x] D_xi + M[eta_x] D_eta (and
+  // D_Y), and x_xi, y_xi (the orientation of the interface normal). Row (i, j) of D_X has its
+  // nonzeros in grid row i (xi_x Dq[j][.]) and grid column j (eta_x Dr[i][.]).
+  struct Metric { std::vector<double> xix, xiy, etx, ety, xxi, yxi; };
+  std::vector<Metric> met(static_cast<size_t>(n));
   parallel_for(n, [&](int k) {
-    Ops o;
-    o.DX.assign(size_t(B) * B, 0.0);
-    o.DY.assign(size_t(B) * B, 0.0);
-    o.xxi.assign(size_t(B), 0.0);
-    o.yxi.assign(size_t(B), 0.0);
+    Metric& o = met[size_t(k)];
+    for (auto* v : {&o.xix, &o.xiy, &o.etx, &o.ety, &o.xxi, &o.yxi}) v->assign(size_t(B), 0.0);
     const double* Xk = S.X.data() + size_t(k) * B * 2;
     for (int i = 0; i < nr; ++i)
       for (int j = 0; j < q; ++j) {
@@ -206,27 +205,29 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
           yeta += Dr[size_t(i) * nr + c] * Xk[(size_t(c) * q + j) * 2 + 1];
         }
         const double J = xxi * yeta - xeta * yxi;
-        const double xi_x = yeta / J, xi_y = -xeta / J, eta_x = -yxi / J, eta_y = xxi / J;
-        const int row = i * q + j;
-        o.xxi[size_t(row)] = xxi;
-        o.yxi[size_t(row)] = yxi;
-        for (int c = 0; c < q; ++c) {
-          o.DX[size_t(row) * B + i * q + c] += xi_x * Dq[size_t(j) * q + c];
-          o.DY[size_t(row) * B + i * q + c] += xi_y * Dq[size_t(j) * q + c];
-        }
-        for (int c = 0; c < nr; ++c) {
-          o.DX[size_t(row) * B + c * q + j] += eta_x * Dr[size_t(i) * nr + c];
-          o.DY[size_t(row) * B + c * q + j] += eta_y * Dr[size_t(i) * nr + c];
-        }
+        const size_t r = size_t(i) * q + j;
+        o.xix[r] = yeta / J;
+        o.xiy[r] = -xeta / J;
+        o.etx[r] = -yxi / J;
+        o.ety[r] = xxi / J;
+        o.xxi[r] = xxi;
+        o.yxi[r] = yxi;
       }
-    ops[size_t(k)] = std::move(o);
   });
+  // v += sx D_X[row] + sy D_Y[row] of element o (dense B vector)
+  auto add_grad = [&](const Metric& o, int row, double sx, double sy, double* v) {
+    const int i = row / q, j = row % q;
+    const double a = sx * o.xix[size_t(row)] + sy * o.xiy[size_t(row)];
+    const double e = sx * o.etx[size_t(row)] + sy * o.ety[size_t(row)];
+    for (int c = 0; c < q; ++c) v[size_t(i) * q + c] += a * Dq[size_t(j) * q + c];
+    for (int c = 0; c < nr; ++c) v[size_t(c) * q + j] += e * Dr[size_t(i) * nr + c];
+  };
   S.A.assign(size_t(n) * N * N, 0.0);
   S.U.assign(size_t(n) * m * Bi, 0.0);
   S.rs.assign(size_t(n) * B, 1.0);
   parallel_for(n, [&](int k) {
-    const Ops& o = ops[size_t(k)];
-    const Ops& on = ops[size_t((k + 1) % n)];
+    const Metric& o = met[size_t(k)];
+    const Metric& on = met[size_t((k + 1) % n)];
     double* Ak = S.A.data() + size_t(k) * N * N;  // column-major: (p, c) at c N + p
     // interface normal between element k and k + 1: the segment from Gamma's to Gamma~'s shared point
     const double* Xk = S.X.data() + size_t(k) * B * 2;
@@ -234,7 +235,8 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
     const double ptx = Xk[(size_t(nr - 1) * q + q - 1) * 2], pty = Xk[(size_t(nr - 1) * q + q - 1) * 2 + 1];
     const double len = std::hypot(ptx - px, pty - py);
     const double nx = (pty - py) / len, ny = -(ptx - px) / len;
-    std::vector<double> rowv(static_cast<size_t>(B)), uvec(static_cast<size_t>(B));
+    std::vector<double> rowv(static_cast<size_t>(B)), uvec(static_cast<size_t>(B)), dx(static_cast<size_t>(B)),
+        dy(static_cast<size_t>(B));
     for (int i = 1; i < nr - 1; ++i)
       for (int j = 0; j < q; ++j) {
         const int row = i * q + j, p = row - q;  // p: interior index
@@ -247,18 +249,21 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
         if (j == q - 1) {  // derivative along the interface normal, oriented along increasing j
           double sx = nx, sy = ny;
           if (sx * o.xxi[size_t(row)] + sy * o.yxi[size_t(row)] < 0) { sx = -sx; sy = -sy; }
-          const int nrow = i * q;  // the next element's first-column node on this interface
-          for (int c = 0; c < B; ++c) {
-            rowv[size_t(c)] = sx * o.DX[size_t(row) * B + c] + sy * o.DY[size_t(row) * B + c];
-            uvec[size_t(c)] = -(sx * on.DX[size_t(nrow) * B + c] + sy * on.DY[size_t(nrow) * B + c]);
-            nrm += std::fabs(rowv[size_t(c)]) + std::fabs(uvec[size_t(c)]);
-          }
-        } else {  // Laplacian row (DX DX + DY DY)[row], through the sparse rows of DX, DY
-          for (int c = 0; c < B; ++c) {
-            const double ax = o.DX[size_t(row) * B + c], ay = o.DY[size_t(row) * B + c];
-            if (ax == 0.0 && ay == 0.0) continue;
-            for (int d = 0; d < B; ++d) rowv[size_t(d)] += ax * o.DX[size_t(c) * B + d] + ay * o.DY[size_t(c) * B + d];
-          }
+          std::fill(uvec.begin(), uvec.end(), 0.0);
+          add_grad(o, row, sx, sy, rowv.data());
+          add_grad(on, i * q, -sx, -sy, uvec.data());  // the next element's first-column node
+          for (int c = 0; c < B; ++c) nrm += std::fabs(rowv[size_t(c)]) + std::fabs(uvec[size_t(c)]);
+        } else {  // Laplacian row (D_X D_X + D_Y D_Y)[row] = sum_c D_X[row][c] D_X[c] + D_Y[row][c] D_Y[c]
+          std::fill(dx.begin(), dx.end(), 0.0);
+          std::fill(dy.begin(), dy.end(), 0.0);
+          add_grad(o, row, 1.0, 0.0, dx.data());
+          add_grad(o, row, 0.0, 1.0, dy.data());
+          auto term = [&](int c) {
+            if (dx[size_t(c)] != 0.0 || dy[size_t(c)] != 0.0) add_grad(o, c, dx[size_t(c)], dy[size_t(c)], rowv.data());
+          };
+          for (int c = 0; c < q; ++c) term(i * q + c);            // grid row i
+          for (int c = 0; c < nr; ++c)
+            if (c != i) term(c * q + j);                           // grid column j
           for (int c = 0; c < B; ++c) nrm += std::fabs(rowv[size_t(c)]);
         }
         // Row equilibration: the Laplacian rows have 1-norms up to ~1e7 (spectral second
