@@ -112,45 +112,4 @@ hipError_t launch_tree_nodes(const int64_t* keys, int64_t n, const TreeRule& r, 
 // Chebyshev tail of each box's 256 samples.
 hipError_t launch_tree_tail(const double* values, int64_t n, const TreeRule& r, double* tails, hipStream_t stream);
 
-// ---------------------------------------------------------------- strip solve (strip.hip)
-// Device data of the factored strip system (strip.cpp): n elements of B = q n_r unknowns,
-// m = n_r - 2 interface rows per side.
-struct StripDevice {
-  int32_t n, q, B, m, Bi, chunk;  // elements, nodes along, nodes per element, m = n_r - 2, Bi = m q
-  const double* EiT;  // n x Bi x Bi: interior block of E_k = D_k^-1, column c contiguous
-  const double* W;    // n x 2m x Bi: [E_k[last column, :]; U~_{k-1} E_k] on the interior columns
-  const double* F;    // n x m x m: E_k[last column, value rows]
-  const double* G;    // n x m x m: U~_{k-1} E_k[:, value rows]
-  const double* H;    // n x m x m: U~_{k-1} E_k[:, derivative rows] (k = 0: the corner term)
-  const double* Pz;   // n x m x m: response of z_k to the corner values h_lo
-  const double* Pt;   // (n + 1) x m x 2m: response of t_k to h
-  const double* K;    // 2m x 2m: the Woodbury capacitance inverse of the periodic corner
-  const double* rs;   // n x B: row scale of each PDE row (the right-hand side is f * rs)
-  double* s;          // n x m work: E_k[last column, :] b_k
-  double* w;          // n x m work: U~_{k-1} E_k b_k
-  double* z;          // (n + 1) x m work: forward sweep
-  double* t;          // (n + 1) x m work: backward sweep
-  double* h;          // 2m work: corner values
-};
-// v (n x B) from the node samples f (n x B): Lap v = f inside, the boundary and interface rows zero
-hipError_t launch_strip_solve(const StripDevice& d, const double* f, double* v, hipStream_t stream);
-
-// Plan-time factorization on the GPU (strip_factor.hip).
-struct StripFactorDevice {
-  int32_t n, N, Bi, m, q;  // elements, padded interior size (multiple of 16), Bi = m q, m, q
-  double* A;               // n x N x N: interior blocks, column-major (destroyed)
-  double* Rb;              // n x 16 x N work: a panel's exchanged rows
-  int32_t* flag;           // n: 1 where a block is singular
-  double* Ainv;            // n x N x N: the inverses, column-major
-  const double* U;         // n x m x Bi: U~_k (element k's derivative rows on element k + 1)
-  double* R;               // n x m x Bi: R_k = U~_{k-1} A_k^-1
-  double* pieces;          // n x 4 x m x m: A^-1[S, P], A^-1[S, V], R[:, P], R[:, V]
-  const double* MG;        // n x m x m: the chain's M_k G_k^-1 (host)
-  double* Q;               // n x m x Bi: MG_k R_k
-  double* W;               // n x 2m x Bi: the apply's right-hand-side functionals
-  double* EiT;             // n x Bi x Bi: the apply's interior blocks of E_k, column c contiguous
-};
-// stage 0: inverses, R and the pieces; stage 1 (after the host chain): Q, W and EiT
-hipError_t launch_strip_factor(const StripFactorDevice& f, int stage, hipStream_t stream);
-
 }  // namespace vp

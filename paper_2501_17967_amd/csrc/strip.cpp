@@ -34,7 +34,7 @@
 #include <vector>
 
 #include "../../include/volpot.h"
-#include "device.hpp"
+#include "strip.hpp"
 
 using namespace vp;
 

@@ -14,7 +14,7 @@
 // one barrier per chunk). All sums have a fixed order, so repeated applies are bitwise identical.
 #include <hip/hip_runtime.h>
 
-#include "device.hpp"
+#include "strip.hpp"
 
 namespace vp {
 

@@ -21,7 +21,7 @@
 // rows (a q), a = 0 .. m - 1.
 #include <hip/hip_runtime.h>
 
-#include "device.hpp"
+#include "strip.hpp"
 
 namespace vp {
 
