@@ -28,6 +28,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <stdexcept>
 #include <thread>
@@ -126,16 +127,25 @@ Mat inverse(Mat A, int n) {
 }
 
 template <class Fn>
-void parallel_for(int n, Fn fn) {
+void parallel_for(int n, Fn fn) {  // rethrows the first exception a task threw
   std::atomic<int> next(0);
+  std::vector<std::exception_ptr> err(static_cast<size_t>(n));
   auto work = [&]() {
-    for (int k; (k = next.fetch_add(1)) < n;) fn(k);
+    for (int k; (k = next.fetch_add(1)) < n;) {
+      try {
+        fn(k);
+      } catch (...) {
+        err[size_t(k)] = std::current_exception();
+      }
+    }
   };
   const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
   std::vector<std::thread> pool;
   for (unsigned i = 1; i < nt && i < unsigned(n); ++i) pool.emplace_back(work);
   work();
   for (auto& t : pool) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 struct StripHost {
@@ -205,6 +215,7 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
           yeta += Dr[size_t(i) * nr + c] * Xk[(size_t(c) * q + j) * 2 + 1];
         }
         const double J = xxi * yeta - xeta * yxi;
+        if (!(std::fabs(J) > 0.0) || !std::isfinite(J)) throw std::invalid_argument("degenerate element map");
         const size_t r = size_t(i) * q + j;
         o.xix[r] = yeta / J;
         o.xiy[r] = -xeta / J;
@@ -234,6 +245,7 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
     const double px = Xk[size_t(q - 1) * 2], py = Xk[size_t(q - 1) * 2 + 1];
     const double ptx = Xk[(size_t(nr - 1) * q + q - 1) * 2], pty = Xk[(size_t(nr - 1) * q + q - 1) * 2 + 1];
     const double len = std::hypot(ptx - px, pty - py);
+    if (!(len > 0.0) || !std::isfinite(len)) throw std::invalid_argument("degenerate interface");
     const double nx = (pty - py) / len, ny = -(ptx - px) / len;
     std::vector<double> rowv(static_cast<size_t>(B)), uvec(static_cast<size_t>(B)), dx(static_cast<size_t>(B)),
         dy(static_cast<size_t>(B));
@@ -538,6 +550,9 @@ int volpot_strip_plan(int32_t n_panel, int32_t n_gl, const double* gamma, const 
   } catch (const std::bad_alloc&) {
     delete s;
     return VOLPOT_ERR_OOM;
+  } catch (...) {
+    delete s;
+    return VOLPOT_ERR_ARG;  // degenerate geometry (a zero-length interface or a singular element map)
   }
   s->X = H.X;
   const int rc = strip_factor(s, H);

@@ -86,7 +86,9 @@ __global__ void __launch_bounds__(kInvThreads)
 #pragma unroll
       for (int w = 1; w < kInvThreads / 64; ++w)
         if (better(redv[w], redi[w], bv, bi)) { bv = redv[w]; bi = redi[w]; }
-      const int pr = bi;  // the pivot row (the same in every thread)
+      // the pivot row (the same in every thread); no usable candidate (a zero or non-finite
+      // column): no exchange, and the block is reported singular
+      const int pr = bi < N ? bi : j;
       if (tid == 0) {
         pivs[jj] = pr;
         pivall[j] = pr;

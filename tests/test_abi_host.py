@@ -336,5 +336,9 @@ def test_strip_plan_arguments(vp):
     assert L.volpot_strip_plan(2, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG   # too few panels
     assert L.volpot_strip_plan(4, 8, p, p, 3, 10, ctypes.byref(h)) == vp.ERR_ARG    # q too small
     assert L.volpot_strip_plan(4, 8, p, p, 32, 33, ctypes.byref(h)) == vp.ERR_ARG   # n_r too large
+    # a strip of zero width (Gamma~ = Gamma): the interfaces have zero length, rejected on the host
+    th = np.linspace(0, 2 * np.pi, 33)[:32].reshape(4, 8)
+    g[...] = np.stack([np.cos(th), np.sin(th)], axis=2)
+    assert L.volpot_strip_plan(4, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG
     g[1, 2, 0] = np.nan
     assert L.volpot_strip_plan(4, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG   # non-finite node
