@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <new>
 #include <stdexcept>
 #include <thread>
@@ -151,7 +152,8 @@ void parallel_for(int n, Fn fn) {  // rethrows the first exception a task threw
 struct StripHost {
   int n = 0, q = 0, nr = 0, B = 0, m = 0, Bi = 0, N = 0;  // N: Bi rounded up to a multiple of 16
   std::vector<double> X;   // n * B * 2 node coordinates
-  std::vector<double> A;   // n * N * N: interior blocks, column-major, identity beyond Bi
+  std::unique_ptr<double[]> A;  // n * N * N: interior blocks, column-major, identity beyond Bi
+                                // (zeroed per element, in parallel, by assemble)
   std::vector<double> U;   // n * m * Bi: derivative rows of element k on element k + 1's interior
   std::vector<double> rs;  // n * B: row scale of each PDE row (1 elsewhere)
 };
@@ -233,13 +235,14 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
     for (int c = 0; c < q; ++c) v[size_t(i) * q + c] += a * Dq[size_t(j) * q + c];
     for (int c = 0; c < nr; ++c) v[size_t(c) * q + j] += e * Dr[size_t(i) * nr + c];
   };
-  S.A.assign(size_t(n) * N * N, 0.0);
+  S.A.reset(new double[size_t(n) * N * N]);
   S.U.assign(size_t(n) * m * Bi, 0.0);
   S.rs.assign(size_t(n) * B, 1.0);
   parallel_for(n, [&](int k) {
     const Metric& o = met[size_t(k)];
     const Metric& on = met[size_t((k + 1) % n)];
-    double* Ak = S.A.data() + size_t(k) * N * N;  // column-major: (p, c) at c N + p
+    double* Ak = S.A.get() + size_t(k) * N * N;  // column-major: (p, c) at c N + p
+    std::fill(Ak, Ak + size_t(N) * N, 0.0);
     // interface normal between element k and k + 1: the segment from Gamma's to Gamma~'s shared point
     const double* Xk = S.X.data() + size_t(k) * B * 2;
     const double px = Xk[size_t(q - 1) * 2], py = Xk[size_t(q - 1) * 2 + 1];
@@ -457,7 +460,7 @@ int strip_factor(volpot_strip_s* s, StripHost& H) {
     f.Q = reinterpret_cast<double*>(work + wQ);
     f.W = reinterpret_cast<double*>(b + oW);
     f.EiT = reinterpret_cast<double*>(b + oEiT);
-    if (hipMemcpy(f.A, H.A.data(), H.A.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(f.A, H.A.get(), size_t(n) * N * N * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(work + wU, H.U.data(), H.U.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
     if (launch_strip_factor(f, 0, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
     std::vector<int32_t> flag(static_cast<size_t>(n));
