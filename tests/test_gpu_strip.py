@@ -106,3 +106,16 @@ def test_full_size_annulus_manufactured(device):
     sp, v = _run(device, g, gt, f, 24, 16)
     ve = v_exact(sp.nodes.reshape(-1, 2)).reshape(v.shape)
     assert rel_max_err(v, ve) < 1e-11
+
+
+def test_maximum_size_annulus(device):
+    # the largest element the library takes: q = n_r = 32 (interior block 960 x 960, m = 30)
+    from tests.test_oracle_strip import _manufactured
+
+    a, b = 0.8, 0.9
+    v_exact, f = _manufactured(a, b)
+    g, gt = _annulus(4, 16, b), _annulus(4, 16, a)
+    sp, v = _run(device, g, gt, f, 32, 32)
+    ref, X = strip.solve(g, gt, f, q=32, n_r=32)
+    assert rel_max_err(v, ref) < 1e-11
+    assert rel_max_err(v, v_exact(X.reshape(-1, 2)).reshape(v.shape)) < 1e-11
