@@ -314,8 +314,8 @@ def main():
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the box code has no multi-GPU path); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py: the box code runs on one GPU only (it has no multi-GPU path); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
