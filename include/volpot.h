@@ -218,15 +218,19 @@ void volpot_tree_destroy(volpot_tree_t tree);
  * Gamma and panel k of Gamma~ (the panels correspond one to one, in the same direction around the
  * closed curves); its nodes are the curvilinear tensor grid of second-kind Chebyshev points,
  * q along the panel (the panel's points interpolated from its Gauss-Legendre nodes) and n_r
- * across the strip (r = -1 on Gamma). The plan assembles and factors the block-tridiagonal
- * periodic system on the host (block inverses in parallel, rank-(n_r - 2) couplings, Woodbury
- * for the periodic corner); the apply solves it on the GPU.
+ * across the strip (r = -1 on Gamma). The plan assembles the block-tridiagonal periodic system
+ * on the host, inverts every element's block on the current device (batched, one launch), and
+ * eliminates the rank-(n_r - 2) couplings and the periodic corner (Woodbury) on m x m pieces;
+ * it synchronises the device and keeps the factors in device memory until destroy. The apply
+ * solves on the GPU.
  *   n_panel        panels per curve (>= 3)
  *   n_gl           Gauss-Legendre nodes per panel (2..64)
  *   gamma, gamma_t host, n_panel x n_gl x 2: the nodes of each panel, in the panel's direction
  *   q, n_r         4..32 each, q * n_r <= 1024
  * Node order: element, then radial index i (0 on Gamma), then along-panel index j (fastest).
- * Returns VOLPOT_ERR_ARG for bad sizes, non-finite nodes or a singular (degenerate) element. */
+ * Returns VOLPOT_ERR_ARG for bad sizes, non-finite nodes, degenerate geometry (a zero-length
+ * element edge between the curves, a singular element map) or a singular block;
+ * VOLPOT_ERR_OOM / VOLPOT_ERR_HIP when device memory or a HIP call fails. */
 typedef struct volpot_strip_s* volpot_strip_t;
 int volpot_strip_plan(int32_t n_panel, int32_t n_gl, const double* gamma, const double* gamma_t, int32_t q,
                       int32_t n_r, volpot_strip_t* out);
