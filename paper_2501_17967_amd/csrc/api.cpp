@@ -13,6 +13,7 @@
 
 #include "../../include/volpot.h"
 #include "device.hpp"
+#include "moments.hpp"
 #include "plan.hpp"
 
 using namespace vp;
@@ -248,7 +249,10 @@ int upload(volpot_plan_s* p) {
   size_t o_sn = add_bytes(total, P.src_n), o_bptr = add_bytes(total, P.box_src_ptr), o_geo = add_bytes(total, P.box_geo);
   size_t o_lbox = add_bytes(total, leaf_box);
   size_t o_pxy = add_bytes(total, P.pt_xy), o_ploc = add_bytes(total, P.pt_loc), o_pnp = add_bytes(total, P.pt_near_ptr);
-  size_t o_pnl = add_bytes(total, P.pt_near_leaf), o_pmom = add_bytes(total, P.pt_mom), o_pwp = add_bytes(total, P.pt_w_ptr);
+  const size_t n_pairs = P.pt_xi.size() / 3;
+  size_t o_pnl = add_bytes(total, P.pt_near_leaf), o_pwp = add_bytes(total, P.pt_w_ptr);
+  size_t o_pmom = (total + 255) & ~size_t(255); total = o_pmom + n_pairs * 3 * kNP * sizeof(double);
+  size_t o_pxi = add_bytes(total, P.pt_xi);
   size_t o_pwb = add_bytes(total, P.pt_w_box);
   size_t o_sq = (total + 255) & ~size_t(255); total = o_sq + std::max<size_t>(size_t(P.n_src), 1) * sizeof(double);
   size_t o_smu = (total + 255) & ~size_t(255); total = o_smu + std::max<size_t>(size_t(P.n_src), 1) * 2 * sizeof(double);
@@ -270,7 +274,7 @@ int upload(volpot_plan_s* p) {
   put(o_order, P.src_order); put(o_sxy, P.src_xy); put(o_sw, P.src_w); put(o_sn, P.src_n);
   put(o_bptr, P.box_src_ptr); put(o_geo, P.box_geo); put(o_lbox, leaf_box);
   put(o_pxy, P.pt_xy); put(o_ploc, P.pt_loc); put(o_pnp, P.pt_near_ptr); put(o_pnl, P.pt_near_leaf);
-  put(o_pmom, P.pt_mom); put(o_pwp, P.pt_w_ptr); put(o_pwb, P.pt_w_box);
+  put(o_pxi, P.pt_xi); put(o_pwp, P.pt_w_ptr); put(o_pwb, P.pt_w_box);
   if (hipMalloc(&p->d_block, total) != hipSuccess) return VOLPOT_ERR_OOM;
   p->device_bytes = int64_t(total);
   if (hipMemcpy(p->d_block, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return VOLPOT_ERR_HIP;
@@ -314,6 +318,37 @@ int upload(volpot_plan_s* p) {
   p->pts.near_ptr = reinterpret_cast<const int32_t*>(b + o_pnp);
   p->pts.near_leaf = reinterpret_cast<const int32_t*>(b + o_pnl);
   p->pts.mom = reinterpret_cast<const double*>(b + o_pmom);
+  if (n_pairs > 0) {  // the near moments of the points' adjacent leaves, on the device
+    MomentRules R;
+    moment_rules(&R);
+    int32_t* d_flag = nullptr;
+    if (hipMalloc(&d_flag, n_pairs * sizeof(int32_t)) != hipSuccess) return VOLPOT_ERR_OOM;
+    std::vector<int32_t> flag(n_pairs);
+    const bool ok = launch_point_moments(R, int64_t(n_pairs), reinterpret_cast<const double*>(b + o_pxi),
+                                         reinterpret_cast<double*>(b + o_pmom), d_flag, nullptr) == hipSuccess &&
+                    hipDeviceSynchronize() == hipSuccess &&
+                    hipMemcpy(flag.data(), d_flag, n_pairs * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess;
+    (void)hipFree(d_flag);
+    if (!ok) return VOLPOT_ERR_HIP;
+    // a pair whose refinement outgrew the kernel's lists (a point within about 1e-15 of a leaf
+    // edge): its moments from the host quadrature
+    constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+    std::vector<double> m(3 * kNP);
+    double I[kNP], Ix[kNP], Iy[kNP];
+    for (size_t e = 0; e < n_pairs; ++e) {
+      if (!flag[e]) continue;
+      const double s = P.pt_xi[3 * e + 2], ls = std::log(s);
+      point_moments(P.pt_xi[3 * e], P.pt_xi[3 * e + 1], I, Ix, Iy);
+      for (int k = 0; k < kNP; ++k) {
+        m[size_t(k)] = -kInv2Pi * s * s * (ls * tensor_weight(k) + I[k]);
+        m[size_t(kNP + k)] = -kInv2Pi * s * Ix[k];
+        m[size_t(2 * kNP + k)] = -kInv2Pi * s * Iy[k];
+      }
+      if (hipMemcpy(b + o_pmom + e * 3 * kNP * sizeof(double), m.data(), m.size() * sizeof(double),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        return VOLPOT_ERR_HIP;
+    }
+  }
   p->pts.w_ptr = reinterpret_cast<const int32_t*>(b + o_pwp);
   p->pts.w_box = reinterpret_cast<const int32_t*>(b + o_pwb);
   p->pts.geo = p->d_geo;

@@ -636,7 +636,8 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   // expansion (level >= 2), the multipoles of a's W list, and the integrals over a's U list,
   // which take precomputed moment vectors: for leaf b with half-width s and reference point
   // xi = (x - c_b) / s, int_{B_b} G(x - y) l_k dy = s^2 (-1/2pi) (log s W_k + I_k(xi)) and its
-  // x-gradient s (-1/2pi) grad I_k(xi) (point_moments). Moments are computed in parallel.
+  // x-gradient s (-1/2pi) grad I_k(xi). The plan keeps (xi, s) per pair; the moments are computed
+  // on the device when the plan is uploaded (moments.hip).
   if (points) {
     const int64_t n = points->n;
     P.n_pts = n;
@@ -669,31 +670,15 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       P.pt_w_ptr.push_back(int32_t(P.pt_w_box.size()));
     }
     const size_t n_pairs = P.pt_near_leaf.size();
-    P.pt_mom.assign(n_pairs * 3 * kNP, 0.0);
-    std::vector<int32_t> pair_pt(n_pairs);
+    P.pt_xi.assign(n_pairs * 3, 0.0);
     for (int64_t j = 0; j < n; ++j)
-      for (int32_t e = P.pt_near_ptr[size_t(j)]; e < P.pt_near_ptr[size_t(j) + 1]; ++e) pair_pt[size_t(e)] = int32_t(j);
-    std::atomic<size_t> next(0);
-    auto work = [&]() {
-      double I[kNP], Ix[kNP], Iy[kNP];
-      for (size_t e; (e = next.fetch_add(1)) < n_pairs;) {
-        const int32_t j = pair_pt[e], bl = P.pt_near_leaf[e], bb = P.leaf_box[bl];
+      for (int32_t e = P.pt_near_ptr[size_t(j)]; e < P.pt_near_ptr[size_t(j) + 1]; ++e) {
+        const int32_t bb = P.leaf_box[P.pt_near_leaf[size_t(e)]];
         const double s = hw(bb);
-        point_moments((P.pt_xy[2 * size_t(j)] - cx(bb)) / s, (P.pt_xy[2 * size_t(j) + 1] - cy(bb)) / s, I, Ix, Iy);
-        double* m = P.pt_mom.data() + e * 3 * kNP;
-        const double ls = std::log(s);
-        for (int k = 0; k < kNP; ++k) {
-          m[k] = -kInv2Pi * s * s * (ls * tensor_weight(k) + I[k]);
-          m[kNP + k] = -kInv2Pi * s * Ix[k];
-          m[2 * kNP + k] = -kInv2Pi * s * Iy[k];
-        }
+        P.pt_xi[3 * size_t(e)] = (P.pt_xy[2 * size_t(j)] - cx(bb)) / s;
+        P.pt_xi[3 * size_t(e) + 1] = (P.pt_xy[2 * size_t(j) + 1] - cy(bb)) / s;
+        P.pt_xi[3 * size_t(e) + 2] = s;
       }
-    };
-    const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    for (unsigned i = 1; i < nt && i < n_pairs; ++i) pool.emplace_back(work);
-    work();
-    for (auto& th : pool) th.join();
   }
 
   // ---------------------------------------------------------------- stages

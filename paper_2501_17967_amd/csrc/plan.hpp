@@ -77,6 +77,8 @@ const Matrices& matrices();  // built once per process (near tables by polar qua
 // Moments at an arbitrary xi over the reference square [-1,1]^2, for each tensor basis l_k:
 // I_k = int log|xi - eta| l_k(eta) d eta and the xi-gradient (Ix_k, Iy_k) of it (256 each).
 void point_moments(double x0, double y0, double* I, double* Ix, double* Iy);
+struct MomentRules;
+void moment_rules(MomentRules* R);  // the rules point_moments uses, for the device kernel
 double tensor_weight(int k);  // int l_k over the reference square
 void set_table_cache_dir(const char* dir);
 
@@ -180,7 +182,8 @@ struct Plan {
   std::vector<int32_t> pt_loc;          // that box if its level >= 2 (it has a local expansion), else -1
   std::vector<int32_t> pt_near_ptr;     // n_pts + 1: pairs (point, adjacent leaf)
   std::vector<int32_t> pt_near_leaf;    // caller leaf of each pair
-  std::vector<double> pt_mom;           // per pair 3 x 256: weights of u, d/dx, d/dy on that leaf's values
+  std::vector<double> pt_xi;            // per pair: the point in that leaf's reference square (2), its half-width
+                                        // (the device computes the pair's 3 x 256 moments from these)
   std::vector<int32_t> pt_w_ptr;        // n_pts + 1
   std::vector<int32_t> pt_w_box;        // W-list boxes of each point's leaf
 };

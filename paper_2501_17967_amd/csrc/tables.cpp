@@ -33,6 +33,7 @@
 #include <thread>
 
 #include "plan.hpp"
+#include "moments.hpp"
 
 namespace vp {
 
@@ -244,8 +245,8 @@ static void logint(double x0, double y0, double* I) {
 // For xi = (x0, y0) anywhere: I_k = int log|xi - eta| l_k(eta) d eta and (Ix_k, Iy_k) =
 // int (xi - eta) / |xi - eta|^2 l_k(eta) d eta over the reference square (the gradient of I in
 // xi). The square is refined towards xi as a quadtree: a square at distance >= its side from
-// xi takes a 16 x 16 tensor Gauss rule (the kernels are analytic there; the error decays like
-// (2 + sqrt 3)^-32); a square of half-width <= 1/32 whose closure holds xi takes four
+// xi takes a 24 x 24 tensor Gauss rule (the kernels are analytic there); a square of
+// half-width <= 1/32 whose closure holds xi takes four
 // polar-Duffy triangles with apex xi (a 16-point log-product rule in the radial variable, exact
 // to degree 15, which on so small a square leaves terms of relative size 32^-16; adaptive
 // 12-point panels along the far edge, as for the tables). The gradient kernel times the Duffy
@@ -420,6 +421,15 @@ void point_moments(double x0, double y0, double* I, double* Ix, double* Iy) {
 }
 
 double tensor_weight(int k) { return basis().W[k]; }
+
+void moment_rules(MomentRules* R) {
+  static const PointRules Q;
+  const Basis& B = basis();
+  for (int i = 0; i < kP; ++i) { R->t[i] = B.t[i]; R->lam[i] = B.lam[i]; R->w[i] = B.w[i]; }
+  for (int a = 0; a < kNT; ++a) { R->gx[a] = Q.gtx[size_t(a)]; R->gw[a] = Q.gtw[size_t(a)]; }
+  for (int a = 0; a < 12; ++a) { R->px[a] = Q.g12x[size_t(a)]; R->pw[a] = Q.g12w[size_t(a)]; }
+  for (int j = 0; j < 16; ++j) { R->u[j] = Q.R.u[j]; R->uw[j] = Q.R.w[j]; R->ul[j] = Q.R.wl[j]; }
+}
 
 // D4 element g: (x, y) -> (sx * (swap ? y : x), sy * (swap ? x : y))
 struct D4 { int sx, sy, swap; };

@@ -74,3 +74,23 @@ def test_star_tree_at_curve_nodes(device):
     u_o, g_o = _oracle(w, c.nodes[idx])
     assert rel_max_err(up[idx], u_o) < TOL
     assert rel_max_err(gp[idx], g_o) < TOL
+
+
+def test_points_close_to_leaf_edges(device):
+    # points at 1e-6 .. 1e-14 from leaf edges and corners: the moment quadrature refines deep
+    # towards the neighbouring leaves' edges
+    w = gen.random_small_tree(4, max_level=5, n_splits=9)
+    rng = np.random.default_rng(4)
+    s = 2.0 ** (-w.levels.astype(float))
+    pts = []
+    for d in (1e-6, 1e-9, 1e-12, 1e-14):
+        for a in rng.choice(w.n_leaves, 6, replace=False):
+            cx, cy, h = w.centres[a, 0], w.centres[a, 1], s[a]
+            pts.append([cx + h - d, cy + 0.3 * h])       # inside, near the right edge
+            pts.append([cx - 0.7 * h, cy - h + d])       # inside, near the bottom edge
+            pts.append([cx + h - d, cy + h - d])         # inside, near the top-right corner
+    pts = np.clip(np.array(pts), -1.0, 1.0)
+    _, _, up, gp = _run(device, w, pts)
+    u_o, g_o = _oracle(w, pts)
+    assert rel_max_err(up, u_o) < TOL
+    assert rel_max_err(gp, g_o) < TOL
