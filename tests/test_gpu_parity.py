@@ -203,6 +203,24 @@ def test_split_schedules_agree_and_repeat(vp, torch_mod, split_min):
     plan.close()
 
 
+@pytest.mark.parametrize("tile_leaf,tile_box,split_min", [(64, 64, 0), (64, 16, 1)])
+def test_tile_shapes_vs_box_code_oracle(vp, torch_mod, tile_leaf, tile_box, split_min):
+    # 64-slot leaf tiles run the near field in its own instantiation (a k-chunk of 16, four
+    # accumulator columns per wave); every stage against the oracle, and repeat applies bitwise
+    w = gen.config2(0)
+    _say("case tile_leaf=%d tile_box=%d split_min=%d (%d leaves)" % (tile_leaf, tile_box, split_min, w.n_leaves))
+    r = np.random.default_rng(29).standard_normal(w.f.shape)
+    plan = vp.Plan(w.centres, w.levels, tile_leaf=tile_leaf, tile_box=tile_box, split_min=split_min)
+    f, rd = _gpu(torch_mod, w.f), _gpu(torch_mod, r)
+    u, fb = plan.apply(f).cpu().numpy(), plan.apply_adjoint(rd).cpu().numpy()
+    u2, fb2 = plan.apply(f).cpu().numpy(), plan.apply_adjoint(rd).cpu().numpy()
+    plan.close()
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+    assert np.array_equal(u, u2) and np.array_equal(fb, fb2)
+
+
 def test_graph_replays_match_eager(vp, torch_mod):
     w = gen.config2(0)
     _say("case graph replay")
