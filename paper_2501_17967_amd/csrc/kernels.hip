@@ -141,6 +141,38 @@ __device__ __forceinline__ void mfma_step(const double* __restrict__ Aw, const d
     for (int j = 0; j < NTT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
 }
 
+// One k-chunk of the tile product for one wave, with the operands of k-step kk + 1 read from
+// LDS before the products of step kk issue, so that the LDS latency hides behind them. The
+// scheduling barriers keep that order (left to itself, the compiler sinks the reads below the
+// products to reuse the operand registers, and each step then waits for its reads).
+template <int MT, int NTT, int M, int LDB, int KC>
+__device__ __forceinline__ void mfma_chunk(const double* __restrict__ Aw, const double* __restrict__ Bw,
+                                           d4 (&acc)[MT][NTT]) {
+  constexpr int NK = KC / 4;
+  double a[2][MT], b[2][NTT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) a[0][i] = Aw[i * 64];
+#pragma unroll
+  for (int j = 0; j < NTT; ++j) b[0][j] = Bw[j * 16 * LDB];
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    const int cur = kk & 1;
+    if (kk + 1 < NK) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i) a[cur ^ 1][i] = Aw[((kk + 1) * (M / 16) + i) * 64];
+#pragma unroll
+      for (int j = 0; j < NTT; ++j) b[cur ^ 1][j] = Bw[j * 16 * LDB + (kk + 1) * 4];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NTT; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Output of one tile: rank-one terms, optional s^2 scaling, overwrite or accumulate.
 // The rank-one sum of each slot is spread over NTHR / NT threads, each taking every
 // (NTHR / NT)-th entry four at a time (independent loads in flight), and the per-thread sums
@@ -284,8 +316,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
           L.advance(p, tid);
           L.load(tid);
         }
-#pragma unroll
-        for (int kk = 0; kk < KC / 4; ++kk) mfma_step<MT, NTT, M, LDB>(Aw, Bw, kk, acc);
+        mfma_chunk<MT, NTT, M, LDB, KC>(Aw, Bw, acc);
         if (!more) break;
         __syncthreads();  // every wave is done reading the chunk
         L.template store<LDB>(tid, As, Bs);
