@@ -388,6 +388,18 @@ def test_size_matched_config2_forward_and_adjoint_vs_box_code_oracle(vp, torch_m
     assert rel(fb, bc.apply_adjoint(r)) <= TOL
 
 
+def test_size_matched_config2_in_the_benchmark_launch_shape(vp, torch_mod):
+    # the benchmark workload in full, in the shape bench.py times (tiles 32 / 32, two near-field
+    # launches beside the far-field chains with 32 compute units left to them)
+    w = gen.config2(0, size_matched=True)
+    _say("case config2-sm seed 0 full oracle, overlap 32 (%d leaves)" % w.n_leaves)
+    r = np.random.default_rng(31).standard_normal(w.f.shape)
+    u, fb = _run(vp, torch_mod, w, adjoint_input=r, tile_leaf=32, tile_box=32, split_min=0, overlap=32)
+    bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(u, bc.apply(w.f)) <= TOL
+    assert rel(fb, bc.apply_adjoint(r)) <= TOL
+
+
 @pytest.mark.parametrize("overlap", [8, 32])
 def test_overlapped_streams_match_single_stream(vp, torch_mod, overlap):
     # near field in two launches beside the far-field chains on a second stream: the same
