@@ -301,7 +301,11 @@ def main():
     ap.add_argument("--layer-only", action="store_true",
                     help="run only the layer-potential leg and print its object (for profiling)")
     ap.add_argument("--no-points", action="store_true", help="skip the off-grid evaluation leg")
+    ap.add_argument("--points-only", action="store_true",
+                    help="run only the off-grid evaluation leg and print its object (for profiling)")
     ap.add_argument("--no-tree", action="store_true", help="skip the quadtree construction leg")
+    ap.add_argument("--tree-only", action="store_true",
+                    help="run only the quadtree construction leg and print its object (for profiling)")
     ap.add_argument("--no-strip", action="store_true", help="skip the strip-solve leg")
     ap.add_argument("--strip-only", action="store_true",
                     help="run only the strip-solve leg and print its object (for profiling)")
@@ -336,6 +340,12 @@ def main():
         return
     if args.strip_only:
         print(json.dumps({"strip": strip_leg(args, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.points_only:
+        print(json.dumps({"points": points_leg(args, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.tree_only:
+        print(json.dumps({"tree": tree_leg(args, torch.device("cuda:0"))}), flush=True)
         return
 
     from paper_2501_17967_amd import Plan, autotune
