@@ -12,7 +12,8 @@
  * paper's v_bulk equals -u.
  *
  * Conventions
- *   root box      [-1,1]^2 at level 0; a level-l box has half-width s_l = 2^-l; levels 0..29.
+ *   root box      [-1,1]^2 at level 0 by default (volpot_options.root_centre / root_halfwidth
+ *                 move and scale it); a level-l box has half-width s_l = h 2^-l; levels 0..29.
  *   leaf nodes    p = 16 first-kind Chebyshev points per dimension,
  *                 t_i = -cos((2i-1) pi / (2p)), i = 1..p (ascending); see volpot_nodes.
  *   leaf data     FP64, contiguous [n_leaves][p][p]: leaf in the caller's order, then the y
@@ -76,6 +77,14 @@ typedef struct {
                               units' share of blocks free, each beside one latency-bound chain
                               of the far field (upward, downward) on a plan-owned helper
                               stream forked from and joined back into the caller's stream */
+  double root_centre[2];   /* centre (x, y) of the root box in the caller's coordinates
+                              (default 0, 0) */
+  double root_halfwidth;   /* half-width h > 0 of the root box; 0 = default 1. The root box
+                              B_0 = centre + [-h, h]^2 must hold the domain (Sec. 4.2.1); a
+                              level-l leaf has half-width h 2^-l, and every coordinate the plan
+                              takes (leaf centres, curve nodes, evaluation points) and every
+                              output is in the caller's coordinates: u is the potential of the
+                              caller's box sizes, including the log kernel's ln h term. */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -109,7 +118,8 @@ typedef struct {
 } volpot_info;
 
 /* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
- *   centres  host, n_leaves x 2 (x, y) leaf centres; must sit on their level's grid
+ *   centres  host, n_leaves x 2 (x, y) leaf centres; must sit on their level's grid (of the
+ *            root box the options give; a centre may be off it by 1e-6 of its box's width)
  *   levels   host, n_leaves leaf levels (0..29)
  *   opt      nullable; defaults as documented in volpot_options
  *   out      receives the plan; untouched on error
@@ -119,7 +129,7 @@ int volpot_plan(const double* centres, const int32_t* levels, int64_t n_leaves, 
 
 /* Plan for n_trees independent trees applied together (one launch per stage for all trees).
  *   tree_offsets  host, n_trees + 1 ascending offsets into centres/levels (first 0)
- * Each tree has its own root [-1,1]^2; data of tree t occupy leaves
+ * Each tree has its own root box (all of them the one the options give); data of tree t occupy leaves
  * [tree_offsets[t], tree_offsets[t+1]) of f and u. */
 int volpot_plan_forest(int32_t n_trees, const int64_t* tree_offsets, const double* centres,
                        const int32_t* levels, int32_t p, const volpot_options* opt,

@@ -330,24 +330,10 @@ int upload(volpot_plan_s* p) {
                     hipMemcpy(flag.data(), d_flag, n_pairs * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess;
     (void)hipFree(d_flag);
     if (!ok) return VOLPOT_ERR_HIP;
-    // a pair whose refinement outgrew the kernel's lists (a point within about 1e-15 of a leaf
-    // edge): its moments from the host quadrature
-    constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
-    std::vector<double> m(3 * kNP);
-    double I[kNP], Ix[kNP], Iy[kNP];
-    for (size_t e = 0; e < n_pairs; ++e) {
-      if (!flag[e]) continue;
-      const double s = P.pt_xi[3 * e + 2], ls = std::log(s);
-      point_moments(P.pt_xi[3 * e], P.pt_xi[3 * e + 1], I, Ix, Iy);
-      for (int k = 0; k < kNP; ++k) {
-        m[size_t(k)] = -kInv2Pi * s * s * (ls * tensor_weight(k) + I[k]);
-        m[size_t(kNP + k)] = -kInv2Pi * s * Ix[k];
-        m[size_t(2 * kNP + k)] = -kInv2Pi * s * Iy[k];
-      }
-      if (hipMemcpy(b + o_pmom + e * 3 * kNP * sizeof(double), m.data(), m.size() * sizeof(double),
-                    hipMemcpyHostToDevice) != hipSuccess)
-        return VOLPOT_ERR_HIP;
-    }
+    // the kernel's lists are sized so that no pair can outgrow them (bounds in moments.hip);
+    // a flagged pair would mean truncated moments, so the plan fails instead
+    for (size_t e = 0; e < n_pairs; ++e)
+      if (flag[e]) return VOLPOT_ERR_UNSUPPORTED;
   }
   p->pts.w_ptr = reinterpret_cast<const int32_t*>(b + o_pwp);
   p->pts.w_box = reinterpret_cast<const int32_t*>(b + o_pwb);
@@ -564,12 +550,37 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   std::memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
   if (o.table_cache) set_table_cache_dir(o.table_cache);
+  RootBox root;
+  if (o.root_halfwidth != 0.0) {
+    root = RootBox{o.root_centre[0], o.root_centre[1], o.root_halfwidth};
+    if (!(root.h > 0.0) || !std::isfinite(root.h) || !std::isfinite(root.cx) || !std::isfinite(root.cy))
+      return VOLPOT_ERR_ARG;
+  } else if (o.root_centre[0] != 0.0 || o.root_centre[1] != 0.0) {
+    root.cx = o.root_centre[0];
+    root.cy = o.root_centre[1];
+    if (!std::isfinite(root.cx) || !std::isfinite(root.cy)) return VOLPOT_ERR_ARG;
+  }
+  // leaf centres in the reference square [-1,1]^2, where keys and lists are built
+  std::vector<double> ref;
+  const double* cref = centres;
+  if (root.h != 1.0 || root.cx != 0.0 || root.cy != 0.0) {
+    try {
+      ref.resize(size_t(2 * offsets[n_trees]));
+    } catch (const std::bad_alloc&) {
+      return VOLPOT_ERR_OOM;
+    }
+    for (int64_t i = 0; i < offsets[n_trees]; ++i) {
+      ref[size_t(2 * i)] = (centres[2 * i] - root.cx) / root.h;
+      ref[size_t(2 * i + 1)] = (centres[2 * i + 1] - root.cy) / root.h;
+    }
+    cref = ref.data();
+  }
   auto* plan = new (std::nothrow) volpot_plan_s();
   if (!plan) return VOLPOT_ERR_OOM;
   int rc;
   try {
-    rc = build_plan(n_trees, offsets, centres, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr, layer, points);
+    rc = build_plan(n_trees, offsets, cref, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
+                    nullptr, layer, points, root);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {

@@ -328,7 +328,11 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
       // Partial sums go through device-coherent stores and loads (agent scope), so the hand-off
       // needs no device-wide cache write-back or invalidate, which would also evict every other
       // block's table lines: the stores are complete (waitcnt) before the block counts itself
-      // in, and the last block reads the partial sums only after its count has returned.
+      // in, and the last block reads the partial sums only after its count has returned. The
+      // ordering is kept by the hardware's in-order completion at these points (waitcnt, then
+      // the barrier); compiler-only fences keep the compiler from moving any of the atomics
+      // across them. An agent-scope acquire on the counter would invalidate the L2 of the block's
+      // XCD (every other block's table lines with it).
       double* __restrict__ mine = p.partial + (size_t)P.slot * (M * NT) + wave * WPART + lane;
 #pragma unroll
       for (int i = 0; i < MT; ++i)
@@ -338,12 +342,14 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
           for (int r = 0; r < 4; ++r)
             __hip_atomic_store(mine + ((i * NTT + j) * 4 + r) * 64, acc[i][j][r], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (tid == 0)
         last_s = __hip_atomic_fetch_add(p.tile_count + P.tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
                  P.n_pieces - 1;
       __syncthreads();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (!last_s) continue;
       for (int q = 0; q < P.n_pieces; ++q) {
         const double* __restrict__ part = p.partial + (size_t)(P.slot0 + q) * (M * NT) + wave * WPART + lane;

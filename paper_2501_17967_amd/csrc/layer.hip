@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) p2l_kernel(const int32_t* __restrict__ tg
   expand<true>(tgt[i], L, total, geo, sxy, q, mu, far, threadIdx.x);
 }
 
-// log x for finite x > 0, table-driven after P. T. P. Tang (ACM TOMS 16, 1990): x = 2^e m with
+// log x for finite x >= 0 (log 0 = -inf), table-driven after P. T. P. Tang (ACM TOMS 16, 1990): x = 2^e m with
 // m in [1, 2); c = m with all but its 7 leading fraction bits cleared (so m - c is exact and
 // 0 <= r = (m - c) / c < 2^-7); log x = e log 2 + log c + log1p(r), the last by its Taylor
 // series to r^8 (truncation below 2^-60 relative). lc[i] = log(1 + i/128) and ic[i] = 1 / (1 + i/128)
@@ -226,7 +226,8 @@ __device__ __forceinline__ double table_log(double x, const double* __restrict__
   p = fma(p, r, 1.0 / 3.0);
   p = fma(p, r, -0.5);
   p = fma(p, r * r, r);
-  return fma(double(e), 0.69314718055994530941723212145817657, lc[i] + p);
+  const double v = fma(double(e), 0.69314718055994530941723212145817657, lc[i] + p);
+  return x == 0.0 ? -__builtin_inf() : v;  // frexp(0) gives m = 0, which the table would map to -log 2
 }
 
 // 1 / x for finite x > 0: the hardware estimate refined by two Newton-Raphson steps

@@ -9,8 +9,9 @@
 // are analytic on it); a square of half-width <= 1/32 whose closure holds xi is split into four
 // polar-Duffy triangles with apex xi (a 16-point rule with a logarithmic weight in the radial
 // variable; 12-point panels along the far edge, bisected until the edge parameter of xi's
-// projection is far enough in the Bernstein-ellipse sense). Thread 0 builds the lists; the
-// threads then contract the rules with the basis in LDS, in a fixed order.
+// projection is far enough in the Bernstein-ellipse sense). Thread 0 sorts each level's squares;
+// the threads contract the accepted ones with the basis in LDS as each level is sorted, then the
+// triangles, in a fixed order. The flag of a pair is set only if a list capacity were exceeded.
 #include <hip/hip_runtime.h>
 
 #include "moments.hpp"
@@ -21,10 +22,21 @@ namespace {
 
 constexpr int kMT = 256;
 constexpr int kNQ = 24;
-constexpr int kMaxSq = 768;    // accepted squares of one pair
+// List capacities. None can be reached, so the flag the kernel writes stays 0:
+//  * a square is refined only while its distance to xi is below its side 2h, so the refined
+//    squares of one level lie in the disc of radius (2 + sqrt 2) h about xi and number at most
+//    pi (3.42 h)^2 / (2h)^2 < 10 (18 for a loose count): a level has at most 4 * 18 = 72 squares,
+//    of which at most 72 are accepted;
+//  * at most 4 squares of one level hold xi (xi at their shared corner), and holding squares are
+//    not refined further;
+//  * the panel bisection of a triangle edge stops at half-length 1e-12 (depth <= 39); on each
+//    depth at most 3 panels lie within 2.125 half-lengths of xi's projection (the rho = 4
+//    Bernstein ellipse), so at most 6 are examined and 3 refined per depth: <= 3 * 39 + 6 panels,
+//    and the depth-first stack holds at most depth + 2 entries.
+constexpr int kMaxAcc = 256;   // accepted squares of one level
 constexpr int kMaxLvl = 256;   // squares refined on one level
-constexpr int kMaxHold = 16;   // squares of half-width <= 1/32 holding xi (4 when xi is a shared corner)
-constexpr int kMaxPanel = 96;  // panels of one Duffy triangle
+constexpr int kMaxHold = 16;   // squares of half-width <= 1/32 holding xi
+constexpr int kMaxPanel = 160; // panels of one Duffy triangle
 constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
 
 // barycentric Lagrange values of the 16 leaf nodes at x
@@ -68,32 +80,37 @@ __global__ void __launch_bounds__(kMT)
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x, ii = tid & 15, jj = tid >> 4;
   const double x0 = pairs[3 * e], y0 = pairs[3 * e + 1], s = pairs[3 * e + 2];
-  __shared__ double sq[kMaxSq][3];
+  __shared__ double sq[kMaxAcc][2];
   __shared__ double hold[kMaxHold][3];
   __shared__ double lvl[2][kMaxLvl][2];
   __shared__ double pan[kMaxPanel][2];
   __shared__ double pst[64][2];  // bisection stack of the panels
-  __shared__ int nsq, nhold, npan, bad;
+  __shared__ int nsq, nnext, nhold, npan, bad;
   // work area: tensor squares use Lx[24][16], Ly[24][16], G[3][24][24], C[3][16][24];
   // triangles use Lx[64][16], Ly[64][16], wts[3][64]
   __shared__ double work[2 * kNQ * 16 + 3 * kNQ * kNQ + 3 * 16 * kNQ];
   if (tid == 0) {
-    nsq = 0;
     nhold = 0;
     bad = 0;
-    int cur = 0, ncur = 1;
     lvl[0][0][0] = 0.0;
     lvl[0][0][1] = 0.0;
-    double h = 1.0;
-    while (ncur > 0) {
-      int nn = 0;
+  }
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+
+  // level by level: thread 0 sorts the level's squares into accepted ones (tensor rule, contracted
+  // right away by all threads), ones holding xi (triangles, after the loop) and ones to refine
+  int cur = 0, ncur = 1;  // ncur: thread 0 only
+  double h = 1.0;
+  for (;;) {
+    if (tid == 0) {
+      int nn = 0, na = 0;
       for (int c = 0; c < ncur; ++c) {
         const double cx = lvl[cur][c][0], cy = lvl[cur][c][1];
         const double ddx = fmax(fabs(x0 - cx) - h, 0.0), ddy = fmax(fabs(y0 - cy) - h, 0.0);
         if (hypot(ddx, ddy) >= 2.0 * h) {
-          if (nsq < kMaxSq) {
-            sq[nsq][0] = cx; sq[nsq][1] = cy; sq[nsq][2] = h;
-            ++nsq;
+          if (na < kMaxAcc) {
+            sq[na][0] = cx; sq[na][1] = cy;
+            ++na;
           } else {
             bad = 1;
           }
@@ -119,50 +136,53 @@ __global__ void __launch_bounds__(kMT)
           ++nn;
         }
       }
-      cur = 1 - cur;
+      nsq = na;
+      nnext = nn;
       ncur = nn;
-      h *= 0.5;
     }
-  }
-  __syncthreads();
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-
-  // accepted squares: tensor rule, contracted in two stages
-  {
-    double* Lx = work;                 // [24][16]
-    double* Ly = Lx + kNQ * 16;        // [24][16]
-    double* G = Ly + kNQ * 16;         // [3][24][24]
-    double* C = G + 3 * kNQ * kNQ;     // [3][16][24]
-    const int n_sq = nsq;
-    for (int q = 0; q < n_sq; ++q) {
-      const double cx = sq[q][0], cy = sq[q][1], h = sq[q][2];
-      if (tid < kNQ) lagrange16(R, cx + h * R.gx[tid], Lx + tid * 16);
-      else if (tid >= 32 && tid < 32 + kNQ) lagrange16(R, cy + h * R.gx[tid - 32], Ly + (tid - 32) * 16);
-      for (int o = tid; o < kNQ * kNQ; o += kMT) {
-        const int a = o / kNQ, b = o % kNQ;
-        const double dx = x0 - (cx + h * R.gx[a]), dy = y0 - (cy + h * R.gx[b]);
-        const double r2 = dx * dx + dy * dy, wq = R.gw[a] * R.gw[b] * h * h;
-        G[o] = 0.5 * log(r2) * wq;
-        G[kNQ * kNQ + o] = dx / r2 * wq;
-        G[2 * kNQ * kNQ + o] = dy / r2 * wq;
+    __syncthreads();
+    // accepted squares of this level: tensor rule, contracted in two stages
+    {
+      double* Lx = work;                 // [24][16]
+      double* Ly = Lx + kNQ * 16;        // [24][16]
+      double* G = Ly + kNQ * 16;         // [3][24][24]
+      double* C = G + 3 * kNQ * kNQ;     // [3][16][24]
+      const int n_sq = nsq;
+      for (int q = 0; q < n_sq; ++q) {
+        const double cx = sq[q][0], cy = sq[q][1];
+        if (tid < kNQ) lagrange16(R, cx + h * R.gx[tid], Lx + tid * 16);
+        else if (tid >= 32 && tid < 32 + kNQ) lagrange16(R, cy + h * R.gx[tid - 32], Ly + (tid - 32) * 16);
+        for (int o = tid; o < kNQ * kNQ; o += kMT) {
+          const int a = o / kNQ, b = o % kNQ;
+          const double dx = x0 - (cx + h * R.gx[a]), dy = y0 - (cy + h * R.gx[b]);
+          const double r2 = dx * dx + dy * dy, wq = R.gw[a] * R.gw[b] * h * h;
+          G[o] = 0.5 * log(r2) * wq;
+          G[kNQ * kNQ + o] = dx / r2 * wq;
+          G[2 * kNQ * kNQ + o] = dy / r2 * wq;
+        }
+        __syncthreads();
+        for (int o = tid; o < 3 * 16 * kNQ; o += kMT) {  // C[k][i][b] = sum_a Lx[a][i] G[k][a][b]
+          const int k = o / (16 * kNQ), i = (o / kNQ) % 16, b = o % kNQ;
+          const double* g = G + k * kNQ * kNQ + b;
+          double v = 0.0;
+          for (int a = 0; a < kNQ; ++a) v = fma(Lx[a * 16 + i], g[a * kNQ], v);
+          C[o] = v;
+        }
+        __syncthreads();
+        for (int b = 0; b < kNQ; ++b) {
+          const double l = Ly[b * 16 + jj];
+          acc0 = fma(C[(0 * 16 + ii) * kNQ + b], l, acc0);
+          acc1 = fma(C[(1 * 16 + ii) * kNQ + b], l, acc1);
+          acc2 = fma(C[(2 * 16 + ii) * kNQ + b], l, acc2);
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      for (int o = tid; o < 3 * 16 * kNQ; o += kMT) {  // C[k][i][b] = sum_a Lx[a][i] G[k][a][b]
-        const int k = o / (16 * kNQ), i = (o / kNQ) % 16, b = o % kNQ;
-        const double* g = G + k * kNQ * kNQ + b;
-        double v = 0.0;
-        for (int a = 0; a < kNQ; ++a) v = fma(Lx[a * 16 + i], g[a * kNQ], v);
-        C[o] = v;
-      }
-      __syncthreads();
-      for (int b = 0; b < kNQ; ++b) {
-        const double l = Ly[b * 16 + jj];
-        acc0 = fma(C[(0 * 16 + ii) * kNQ + b], l, acc0);
-        acc1 = fma(C[(1 * 16 + ii) * kNQ + b], l, acc1);
-        acc2 = fma(C[(2 * 16 + ii) * kNQ + b], l, acc2);
-      }
-      __syncthreads();
     }
+    const int more = nnext;
+    __syncthreads();  // every thread has read nsq and nnext before thread 0 writes the next level's
+    if (more == 0) break;
+    cur = 1 - cur;
+    h *= 0.5;
   }
 
   // squares holding xi: four polar-Duffy triangles each
@@ -195,7 +215,7 @@ __global__ void __launch_bounds__(kMT)
             const double c = 0.5 * (a + b), hl = 0.5 * (b - a);
             const bool done = bernstein_rho(vf, hv, c, hl) >= 4.0 || hl < 1e-12;
             if (done || top + 2 > 64) {
-              if (!done) bad = 1;  // the stack is full: keep the panel, recompute the pair elsewhere
+              if (!done) bad = 1;  // the stack is full (cannot happen, see the capacities above)
               if (np < kMaxPanel) {
                 pan[np][0] = c;
                 pan[np][1] = hl;

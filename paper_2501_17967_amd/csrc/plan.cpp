@@ -431,7 +431,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
                int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer,
-               const PointTargets* points) {
+               const PointTargets* points, const RootBox& root) {
   if (layer && (n_trees != 1 || layer->n < 0 || (layer->n > 0 && (!layer->xy || !layer->weights || !layer->normals))))
     return VOLPOT_ERR_ARG;
   if (points && (layer || n_trees != 1 || points->n < 0 || (points->n > 0 && !points->xy))) return VOLPOT_ERR_ARG;
@@ -481,11 +481,13 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       P.box_child[p][q] = int32_t(i);
     }
   }
+  // physical half-width of a level-l box: h 2^-l
+  const double lnH = std::log(root.h);
   P.leaf_s2.resize(P.n_leaves); P.leaf_kappa.resize(P.n_leaves);
   for (int64_t a = 0; a < P.n_leaves; ++a) {
     int l = levels[a];
-    P.leaf_s2[a] = std::ldexp(1.0, -2 * l);
-    P.leaf_kappa[a] = l * kLn2 * kInv2Pi;  // -(1/2pi) ln s
+    P.leaf_s2[a] = root.h * root.h * std::ldexp(1.0, -2 * l);
+    P.leaf_kappa[a] = (l * kLn2 - lnH) * kInv2Pi;  // -(1/2pi) ln s
   }
   auto key_of = [&](int32_t b) { return pack(P.box_level[b], P.box_x[b], P.box_y[b]); };
   auto find_box = [&](int32_t tree, uint64_t k) -> int32_t {
@@ -495,6 +497,15 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   auto cx = [&](int32_t b) { return centre_of(P.box_x[b], P.box_level[b]); };
   auto cy = [&](int32_t b) { return centre_of(P.box_y[b], P.box_level[b]); };
   auto hw = [&](int32_t b) { return std::ldexp(1.0, -P.box_level[b]); };
+  // the box geometry the layer and point kernels read: physical centre and half-width
+  auto set_geo = [&]() {
+    P.box_geo.assign(size_t(P.n_boxes) * 4, 0.0);
+    for (int32_t b = 0; b < P.n_boxes; ++b) {
+      P.box_geo[4 * size_t(b)] = root.cx + root.h * cx(b);
+      P.box_geo[4 * size_t(b) + 1] = root.cy + root.h * cy(b);
+      P.box_geo[4 * size_t(b) + 2] = root.h * hw(b);
+    }
+  };
 
   // ---------------------------------------------------------------- lists
   const int64_t NB = P.n_boxes;
@@ -588,23 +599,18 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     const int64_t n = layer->n;
     P.layer = true;
     P.n_src = n;
-    P.box_geo.assign(size_t(NB) * 4, 0.0);
-    for (int32_t b = 0; b < NB; ++b) {
-      P.box_geo[4 * size_t(b)] = cx(b);
-      P.box_geo[4 * size_t(b) + 1] = cy(b);
-      P.box_geo[4 * size_t(b) + 2] = hw(b);
-    }
-    const int32_t root = find_box(0, pack(0, 0, 0));
+    set_geo();
+    const int32_t root_box = find_box(0, pack(0, 0, 0));
     std::vector<int32_t> src_box(static_cast<size_t>(n));
     for (int64_t j = 0; j < n; ++j) {
-      const double x = layer->xy[2 * j], y = layer->xy[2 * j + 1];
+      const double x = (layer->xy[2 * j] - root.cx) / root.h, y = (layer->xy[2 * j + 1] - root.cy) / root.h;
       const double nx = layer->normals[2 * j], ny = layer->normals[2 * j + 1];
       if (!(x >= -1.0 && x <= 1.0 && y >= -1.0 && y <= 1.0) || !std::isfinite(layer->weights[j]) || !std::isfinite(nx) ||
           !std::isfinite(ny)) {
         if (bad) *bad = j;
         return VOLPOT_ERR_ARG;
       }
-      int32_t b = root;
+      int32_t b = root_box;
       while (P.box_leaf[b] < 0) b = P.box_child[b][int(x >= cx(b)) + 2 * int(y >= cy(b))];
       src_box[size_t(j)] = b;
     }
@@ -641,25 +647,25 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   if (points) {
     const int64_t n = points->n;
     P.n_pts = n;
-    P.box_geo.assign(size_t(NB) * 4, 0.0);
-    for (int32_t b = 0; b < NB; ++b) {
-      P.box_geo[4 * size_t(b)] = cx(b);
-      P.box_geo[4 * size_t(b) + 1] = cy(b);
-      P.box_geo[4 * size_t(b) + 2] = hw(b);
+    set_geo();
+    const int32_t root_box = find_box(0, pack(0, 0, 0));
+    P.pt_xy.assign(points->xy, points->xy + 2 * n);  // physical, as the kernel evaluates
+    std::vector<double> ref(size_t(2 * n));          // in the reference square
+    for (int64_t j = 0; j < n; ++j) {
+      ref[size_t(2 * j)] = (points->xy[2 * j] - root.cx) / root.h;
+      ref[size_t(2 * j + 1)] = (points->xy[2 * j + 1] - root.cy) / root.h;
     }
-    const int32_t root = find_box(0, pack(0, 0, 0));
-    P.pt_xy.assign(points->xy, points->xy + 2 * n);
     P.pt_box.resize(size_t(n));
     P.pt_loc.resize(size_t(n));
     P.pt_near_ptr.assign(1, 0);
     P.pt_w_ptr.assign(1, 0);
     for (int64_t j = 0; j < n; ++j) {
-      const double x = points->xy[2 * j], y = points->xy[2 * j + 1];
+      const double x = ref[size_t(2 * j)], y = ref[size_t(2 * j + 1)];
       if (!(x >= -1.0 && x <= 1.0 && y >= -1.0 && y <= 1.0)) {
         if (bad) *bad = j;
         return VOLPOT_ERR_ARG;
       }
-      int32_t b = root;
+      int32_t b = root_box;
       while (P.box_leaf[b] < 0) b = P.box_child[b][int(x >= cx(b)) + 2 * int(y >= cy(b))];
       const int32_t a = P.box_leaf[b];
       P.pt_box[size_t(j)] = b;
@@ -675,9 +681,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (int32_t e = P.pt_near_ptr[size_t(j)]; e < P.pt_near_ptr[size_t(j) + 1]; ++e) {
         const int32_t bb = P.leaf_box[P.pt_near_leaf[size_t(e)]];
         const double s = hw(bb);
-        P.pt_xi[3 * size_t(e)] = (P.pt_xy[2 * size_t(j)] - cx(bb)) / s;
-        P.pt_xi[3 * size_t(e) + 1] = (P.pt_xy[2 * size_t(j) + 1] - cy(bb)) / s;
-        P.pt_xi[3 * size_t(e) + 2] = s;
+        P.pt_xi[3 * size_t(e)] = (ref[2 * size_t(j)] - cx(bb)) / s;
+        P.pt_xi[3 * size_t(e) + 1] = (ref[2 * size_t(j) + 1] - cy(bb)) / s;
+        P.pt_xi[3 * size_t(e) + 2] = root.h * s;  // physical half-width
       }
   }
 
@@ -692,7 +698,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   auto quadrant = [&](int32_t b) { return int(P.box_x[b] & 1) + 2 * int(P.box_y[b] & 1); };
   std::vector<std::vector<int32_t>> boxes_at(P.max_level + 1);
   for (int32_t b = 0; b < NB; ++b) boxes_at[P.box_level[b]].push_back(b);
-  auto lnS = [&](int l) { return -double(l) * kLn2; };
+  auto lnS = [&](int l) { return lnH - double(l) * kLn2; };
   std::vector<int32_t> leaf_order(P.n_leaves);
   for (int64_t a = 0; a < P.n_leaves; ++a) leaf_order[a] = int32_t(a);
   std::sort(leaf_order.begin(), leaf_order.end(), [&](int32_t x, int32_t y) { return P.leaf_box[x] < P.leaf_box[y]; });

@@ -74,12 +74,10 @@ struct Matrices {
   std::vector<double> nnz;  // non-zero count of each
 };
 const Matrices& matrices();  // built once per process (near tables by polar quadrature)
-// Moments at an arbitrary xi over the reference square [-1,1]^2, for each tensor basis l_k:
-// I_k = int log|xi - eta| l_k(eta) d eta and the xi-gradient (Ix_k, Iy_k) of it (256 each).
-void point_moments(double x0, double y0, double* I, double* Ix, double* Iy);
+// The quadrature rules of the point-moment kernel (moments.hip): leaf nodes and barycentric
+// weights, the 24-point tensor rule, the 12-point edge rule and the 16-point log-product rule.
 struct MomentRules;
-void moment_rules(MomentRules* R);  // the rules point_moments uses, for the device kernel
-double tensor_weight(int k);  // int l_k over the reference square
+void moment_rules(MomentRules* R);
 void set_table_cache_dir(const char* dir);
 
 // ---------------------------------------------------------------- plan
@@ -218,8 +216,17 @@ void build_schedule(Stage& st, int max_blocks, int min_units);
 // layer != nullptr: plan the evaluation of the layer potentials of those nodes at every leaf
 // node of one tree instead (no adjoint stages). points != nullptr (one tree): also prepare the
 // evaluation of u and its gradient at those points (near-field moments, lists).
+// The root box in the caller's coordinates: centre (cx, cy) and half-width h. Keys, lists and
+// tables live in the reference square [-1,1]^2 (centres arrive mapped there); every absolute
+// size the kernels see is physical: the leaves' s^2 and -(1/2pi) ln s terms, the ln s terms of
+// the far field, and the box geometry, curve nodes and points of layer and point plans.
+struct RootBox {
+  double cx = 0.0, cy = 0.0, h = 1.0;
+};
+
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
-               const LayerSources* layer = nullptr, const PointTargets* points = nullptr);
+               const LayerSources* layer = nullptr, const PointTargets* points = nullptr,
+               const RootBox& root = RootBox());
 
 }  // namespace vp

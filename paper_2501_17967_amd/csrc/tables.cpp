@@ -270,44 +270,6 @@ struct LogRule16 {
   }
 };
 
-struct MomentAcc {
-  double* I;
-  double* Ix;
-  double* Iy;
-  int n = 0;
-  double Lx[64][kP], Ly[64][kP], w0[64], w1[64], w2[64];
-  void add(const Basis& B, double y1, double y2, double a, double gx, double gy) {
-    B.lagrange(y1, Lx[n]);
-    B.lagrange(y2, Ly[n]);
-    w0[n] = a;
-    w1[n] = gx;
-    w2[n] = gy;
-    if (++n == 64) flush();
-  }
-  void flush() {
-    for (int j = 0; j < kP; ++j) {
-      double a0[64], a1[64], a2[64];
-      for (int q = 0; q < n; ++q) {
-        a0[q] = w0[q] * Ly[q][j];
-        a1[q] = w1[q] * Ly[q][j];
-        a2[q] = w2[q] * Ly[q][j];
-      }
-      for (int i = 0; i < kP; ++i) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int q = 0; q < n; ++q) {
-          s0 += a0[q] * Lx[q][i];
-          s1 += a1[q] * Lx[q][i];
-          s2 += a2[q] * Lx[q][i];
-        }
-        I[j * kP + i] += s0;
-        Ix[j * kP + i] += s1;
-        Iy[j * kP + i] += s2;
-      }
-    }
-    n = 0;
-  }
-};
-
 constexpr int kNT = 24;  // tensor rule of the accepted squares
 struct PointRules {
   std::vector<double> gtx, gtw, g12x, g12w;
@@ -318,109 +280,6 @@ struct PointRules {
   }
 };
 
-// one square (centre c, half-width h) at distance >= 2h from xi: tensor rule, contracted
-static void moment_square(const Basis& B, const PointRules& Q, double x0, double y0, double cx, double cy, double h,
-                          MomentAcc& acc) {
-  double Lx[kNT][kP], Ly[kNT][kP], G[3][kNT][kNT], C[3][kP][kNT];
-  double ya[kNT], yb[kNT];
-  for (int a = 0; a < kNT; ++a) { ya[a] = cx + h * Q.gtx[a]; B.lagrange(ya[a], Lx[a]); }
-  for (int b = 0; b < kNT; ++b) { yb[b] = cy + h * Q.gtx[b]; B.lagrange(yb[b], Ly[b]); }
-  for (int a = 0; a < kNT; ++a) {
-    const double dx = x0 - ya[a];
-    for (int b = 0; b < kNT; ++b) {
-      const double dy = y0 - yb[b], r2 = dx * dx + dy * dy, wq = Q.gtw[a] * Q.gtw[b] * h * h;
-      G[0][a][b] = 0.5 * std::log(r2) * wq;
-      G[1][a][b] = dx / r2 * wq;
-      G[2][a][b] = dy / r2 * wq;
-    }
-  }
-  for (int k = 0; k < 3; ++k)
-    for (int i = 0; i < kP; ++i)
-      for (int b = 0; b < kNT; ++b) {
-        double s = 0.0;
-        for (int a = 0; a < kNT; ++a) s += Lx[a][i] * G[k][a][b];
-        C[k][i][b] = s;
-      }
-  double* out[3] = {acc.I, acc.Ix, acc.Iy};
-  for (int k = 0; k < 3; ++k)
-    for (int j = 0; j < kP; ++j)
-      for (int i = 0; i < kP; ++i) {
-        double s = 0.0;
-        for (int b = 0; b < kNT; ++b) s += C[k][i][b] * Ly[b][j];
-        out[k][j * kP + i] += s;
-      }
-}
-
-// the triangle (xi, p0, p1), xi in the closure of the square the triangle belongs to
-static void moment_triangle(const Basis& B, const PointRules& Q, double x0, double y0, double p0x, double p0y,
-                            double p1x, double p1y, MomentAcc& acc) {
-  double e0x = p0x - x0, e0y = p0y - y0, dx = p1x - p0x, dy = p1y - p0y;
-  double twoA = std::fabs(e0x * dy - e0y * dx);
-  if (twoA < 1e-300) return;
-  double L2 = dx * dx + dy * dy, L = std::sqrt(L2);
-  double vf = -(e0x * dx + e0y * dy) / L2, hv = twoA / L / L;
-  cd zs(vf, hv);
-  std::vector<std::pair<double, double>> stack{{0.0, 1.0}}, panels;
-  while (!stack.empty()) {
-    auto pr = stack.back();
-    stack.pop_back();
-    double c = 0.5 * (pr.first + pr.second), hl = 0.5 * (pr.second - pr.first);
-    if (bernstein_rho(zs, c, hl) >= 4.0 || hl < 1e-12) panels.push_back(pr);
-    else { stack.push_back({pr.first, c}); stack.push_back({c, pr.second}); }
-  }
-  for (auto& pr : panels) {
-    double c = 0.5 * (pr.first + pr.second), hl = 0.5 * (pr.second - pr.first);
-    for (size_t q = 0; q < Q.g12x.size(); ++q) {
-      double v = c + hl * Q.g12x[q], wv = hl * Q.g12w[q];
-      double ex = e0x + v * dx, ey = e0y + v * dy;
-      double e2 = ex * ex + ey * ey;
-      double lnE = 0.5 * std::log(e2);
-      double gxk = -twoA * wv * ex / e2, gyk = -twoA * wv * ey / e2;
-      for (int j = 0; j < 16; ++j) {
-        double u = Q.R.u[j];
-        acc.add(B, x0 + u * ex, y0 + u * ey, twoA * wv * u * (Q.R.wl[j] + lnE * Q.R.w[j]), gxk * Q.R.w[j],
-                gyk * Q.R.w[j]);
-      }
-    }
-  }
-}
-
-static void moment_refine(const Basis& B, const PointRules& Q, double x0, double y0, double cx, double cy, double h,
-                          MomentAcc& acc) {
-  const double ddx = std::max(std::fabs(x0 - cx) - h, 0.0), ddy = std::max(std::fabs(y0 - cy) - h, 0.0);
-  if (std::hypot(ddx, ddy) >= 2.0 * h) {
-    moment_square(B, Q, x0, y0, cx, cy, h, acc);
-    return;
-  }
-  const bool holds = std::fabs(x0 - cx) <= h && std::fabs(y0 - cy) <= h;
-  if (holds && h <= 1.0 / 32.0) {
-    const double P[5][2] = {{cx - h, cy - h}, {cx + h, cy - h}, {cx + h, cy + h}, {cx - h, cy + h}, {cx - h, cy - h}};
-    for (int e = 0; e < 4; ++e) moment_triangle(B, Q, x0, y0, P[e][0], P[e][1], P[e + 1][0], P[e + 1][1], acc);
-    return;
-  }
-  if (h < 1e-15) return;  // only reached beside xi, within 2e-15: below the rounding of the sums
-  const double q = 0.5 * h;
-  moment_refine(B, Q, x0, y0, cx - q, cy - q, q, acc);
-  moment_refine(B, Q, x0, y0, cx + q, cy - q, q, acc);
-  moment_refine(B, Q, x0, y0, cx - q, cy + q, q, acc);
-  moment_refine(B, Q, x0, y0, cx + q, cy + q, q, acc);
-}
-
-void point_moments(double x0, double y0, double* I, double* Ix, double* Iy) {
-  static const PointRules Q;
-  const Basis& B = basis();
-  std::memset(I, 0, sizeof(double) * kNP);
-  std::memset(Ix, 0, sizeof(double) * kNP);
-  std::memset(Iy, 0, sizeof(double) * kNP);
-  MomentAcc acc;
-  acc.I = I;
-  acc.Ix = Ix;
-  acc.Iy = Iy;
-  moment_refine(B, Q, x0, y0, 0.0, 0.0, 1.0, acc);
-  acc.flush();
-}
-
-double tensor_weight(int k) { return basis().W[k]; }
 
 void moment_rules(MomentRules* R) {
   static const PointRules Q;

@@ -53,7 +53,16 @@ class VolpotError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
                 ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
-                ("overlap", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double)]
+
+
+def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0,
+             root_centre=(0.0, 0.0), root_halfwidth=0.0):
+    o = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
+                table_cache.encode() if table_cache else None, int(split_min), int(overlap))
+    o.root_centre[0], o.root_centre[1] = float(root_centre[0]), float(root_centre[1])
+    o.root_halfwidth = float(root_halfwidth)
+    return o
 
 
 class Info(ctypes.Structure):
@@ -280,12 +289,12 @@ class Plan:
     """A plan for one tree or, with ``tree_offsets``, a forest of independent trees."""
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
-                 tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0):
+                 tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0),
+                 root_halfwidth=0.0):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
-        opt = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
-                      table_cache.encode() if table_cache else None, int(split_min),
-                      int(overlap))
+        opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
+                       root_halfwidth)
         h = _vp()
         L = lib()
         if tree_offsets is None:
@@ -394,14 +403,14 @@ class PointPlan(Plan):
     Plan's calls work on it."""
 
     def __init__(self, centres, levels, points, p=16, *, host_only=False, use_graph=False, tile_leaf=0, tile_box=0,
-                 table_cache=None, split_min=0, overlap=0):
+                 table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0), root_halfwidth=0.0):
         c, l = _host_tree(centres, levels)
         x = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 2))
         self.n_leaves = c.shape[0]
         self.n_points = x.shape[0]
         self.n_trees = 1
-        opt = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
-                      table_cache.encode() if table_cache else None, int(split_min), int(overlap))
+        opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
+                       root_halfwidth)
         h = _vp()
         _check(lib().volpot_plan_points(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), self.n_leaves, p, self.n_points,
                                         x.ctypes.data_as(_dp), ctypes.byref(opt), ctypes.byref(h)), "volpot_plan_points")
@@ -428,7 +437,7 @@ class LayerPlan(Plan):
     Inspection (info, stages, timing) as for Plan; apply / apply_adjoint do not apply."""
 
     def __init__(self, centres, levels, nodes, weights, normals, p=16, *, host_only=False, use_graph=False,
-                 tile_box=0, table_cache=None, split_min=0, overlap=0):
+                 tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0), root_halfwidth=0.0):
         c, l = _host_tree(centres, levels)
         y = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, 2))
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
@@ -438,8 +447,7 @@ class LayerPlan(Plan):
         self.n_leaves = c.shape[0]
         self.n_nodes = y.shape[0]
         self.n_trees = 1
-        opt = Options(int(host_only), int(use_graph), 0, int(tile_box), table_cache.encode() if table_cache else None,
-                      int(split_min), int(overlap))
+        opt = _options(host_only, use_graph, 0, tile_box, table_cache, split_min, overlap, root_centre, root_halfwidth)
         h = _vp()
         _check(lib().volpot_layer_plan(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), self.n_leaves, p, self.n_nodes,
                                        y.ctypes.data_as(_dp), w.ctypes.data_as(_dp), n.ctypes.data_as(_dp),

@@ -342,3 +342,22 @@ def test_strip_plan_arguments(vp):
     assert L.volpot_strip_plan(4, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG
     g[1, 2, 0] = np.nan
     assert L.volpot_strip_plan(4, 8, p, p, 12, 10, ctypes.byref(h)) == vp.ERR_ARG   # non-finite node
+
+
+def test_root_box_option_maps_the_tree(vp):
+    # a tree given in the caller's coordinates of a moved and scaled root box plans to the same
+    # lists as the reference tree; an invalid half-width is rejected
+    w = gen.config1(0)
+    c, h = np.array([0.3, -1.7]), 2.5
+    ref = vp.Plan(w.centres, w.levels, host_only=True).info()
+    got = vp.Plan(c + h * w.centres, w.levels, host_only=True, root_centre=c, root_halfwidth=h).info()
+    for k in ("n_leaves", "n_boxes", "pairs_near", "pairs_v", "pairs_w", "pairs_x", "flops_total"):
+        assert got[k] == ref[k], k
+    # the reference centres are off the moved root's grid
+    with pytest.raises(vp.VolpotError) as e:
+        vp.Plan(w.centres, w.levels, host_only=True, root_centre=c, root_halfwidth=h)
+    assert e.value.code == vp.ERR_TREE
+    for bad in (-1.0, float("inf"), float("nan")):
+        with pytest.raises(vp.VolpotError) as e:
+            vp.Plan(w.centres, w.levels, host_only=True, root_halfwidth=bad)
+        assert e.value.code == vp.ERR_ARG

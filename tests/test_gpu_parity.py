@@ -118,11 +118,13 @@ def test_size_matched_config2_sampled_vs_direct_sum(vp, torch_mod):
     assert np.max(np.abs(ug - ud)) / np.max(np.abs(u)) <= TOL
 
 
-def test_config1_against_gaussian_closed_form(vp, torch_mod):
+@pytest.mark.parametrize("seed", [0, 3, 5, 6, 9])
+def test_config1_against_gaussian_closed_form(vp, torch_mod, seed):
     # analysis check: the closed-form whole-plane potential minus the part of each Gaussian
-    # outside the root; differs only by the leaf interpolation error of f (level 3).
-    w = gen.config1(0)
-    _say("case config1 closed form")
+    # outside the root (both pinned on the CPU). Widths 0.11-0.3 are resolved at level 3 to about
+    # 1e-15, so the oracle box code meets the closed form to 2e-15 on these seeds; the GPU adds
+    # its own rounding only.
+    w = gen.config1(seed)
     u, _ = _run(vp, torch_mod, w)
     rng = np.random.default_rng(2)
     g = w.src
@@ -133,7 +135,9 @@ def test_config1_against_gaussian_closed_form(vp, torch_mod):
         for (cx, cy), s, A in zip(g.centres, g.sigmas, g.amps):
             ref += cf.gaussian_potential(x, y, cx, cy, s, A) - cf.gaussian_exterior_tail(x, y, cx, cy, s, A)
         errs.append(abs(u[a, m] - ref))
-    assert max(errs) / np.max(np.abs(u)) < 1e-8
+    err = max(errs) / np.max(np.abs(u))
+    _say("case config1 seed %d closed form: max rel err %.2e (min sigma %.3f)" % (seed, err, g.sigmas.min()))
+    assert err <= 1e-13
 
 
 # ------------------------------------------------------------------------ invariants
@@ -279,11 +283,14 @@ def test_zero_input_gives_zero(vp, torch_mod):
 
 # ------------------------------------------------------------------------ autograd
 def test_autograd_gradient_matches_finite_differences(vp, torch_mod):
-    # J(f) = 1/2 sum W s^2 (A f - u_t)^2 on the config-2 tree; dJ/df through the adjoint kernels
+    # J(f) = 1/2 sum W s^2 (A f - u_t)^2 on the config-2 tree; dJ/df through the adjoint kernels.
+    # J is quadratic, so central differences are exact up to rounding: about 1e-16 |J| / h, which
+    # the oracle measures at 2.3e-8 |dJ.d| at worst over these ten directions.
     from paper_2501_17967_amd import volume_potential
 
-    w, f2, dirs = gen.config5(n_dirs=4)
-    _say("case autograd FD (%d leaves)" % w.n_leaves)
+    w, f2, dirs = gen.config5(n_dirs=10)
+    assert len(dirs) == 10
+    _say("case autograd FD (%d leaves, %d directions)" % (w.n_leaves, len(dirs)))
     plan = vp.Plan(w.centres, w.levels)
     Wq = _gpu(torch_mod, nodes.tensor_weights()[None, :] * (2.0 ** (-2 * w.levels.astype(float)))[:, None])
     ut = plan.apply(_gpu(torch_mod, f2))
@@ -295,17 +302,64 @@ def test_autograd_gradient_matches_finite_differences(vp, torch_mod):
     j = J(f)
     (g,) = torch_mod.autograd.grad(j, f)
     h = 1e-6
+    worst = 0.0
     for d in dirs:
         dt = _gpu(torch_mod, d)
         with torch_mod.no_grad():
-            fd = (J(f + h * dt) - J(f - h * dt)) / (2 * h)
-        an = torch_mod.sum(g * dt)
-        assert abs(float(fd - an)) <= 1e-6 * abs(float(an)) + 1e-9 * abs(float(j))
-    # against the oracle's transpose: grad = A^T (W s^2 (A f - u_t))
+            fd = float((J(f + h * dt) - J(f - h * dt)) / (2 * h))
+        an = float(torch_mod.sum(g * dt))
+        worst = max(worst, abs(fd - an) / abs(an))
+    _say("  FD vs autograd: max rel diff %.2e" % worst)
+    assert worst <= 1e-7
+    # against the oracle's transpose, applied to the GPU's own residual: grad = A^T (W s^2 (A f - u_t))
+    with torch_mod.no_grad():
+        resid_gpu = (Wq * (plan.apply(f.detach()) - ut)).cpu().numpy()
     bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+    assert rel(g.cpu().numpy(), bc.apply_adjoint(resid_gpu)) <= TOL
+    # and with the residual formed by the oracle's forward (the residual is a difference of two
+    # potentials, so its relative rounding is larger than theirs)
     resid = Wq.cpu().numpy() * (bc.apply(w.f) - ut.cpu().numpy())
     assert rel(g.cpu().numpy(), bc.apply_adjoint(resid)) <= 1e-10
     plan.close()
+
+
+def test_autograd_through_a_forest_plan(vp, torch_mod):
+    # the batched adjoint: one objective over a 24-tree slice of the forest workload, dJ/df
+    # through the forest plan's adjoint; each tree's gradient against the oracle's transpose of
+    # that tree, and a forest-wide central difference along a seeded direction
+    from paper_2501_17967_amd import volume_potential
+
+    trees = gen.config4(0, n_trees=24)
+    off = np.cumsum([0] + [t.n_leaves for t in trees])
+    _say("case autograd through a forest of %d trees (%d leaves)" % (len(trees), off[-1]))
+    C = np.vstack([t.centres for t in trees])
+    L = np.concatenate([t.levels for t in trees])
+    forest = vp.Plan(C, L, tree_offsets=off)
+    Wq = _gpu(torch_mod, nodes.tensor_weights()[None, :] * (2.0 ** (-2 * L.astype(float)))[:, None])
+    rng = np.random.default_rng(41)
+    ut = forest.apply(_gpu(torch_mod, np.roll(np.vstack([t.f for t in trees]), 7, axis=0)))
+    f = _gpu(torch_mod, np.vstack([t.f for t in trees])).requires_grad_(True)
+
+    def J(fv):
+        return 0.5 * torch_mod.sum(Wq * (volume_potential(fv, forest) - ut) ** 2)
+
+    (g,) = torch_mod.autograd.grad(J(f), f)
+    with torch_mod.no_grad():
+        resid = (Wq * (forest.apply(f.detach()) - ut)).cpu().numpy()
+    gn = g.cpu().numpy()
+    for i, t in enumerate(trees):
+        bc = fmm.BoxCode(tree.Tree(t.centres, t.levels))
+        assert rel(gn[off[i]:off[i + 1]], bc.apply_adjoint(resid[off[i]:off[i + 1]])) <= TOL, i
+    d = rng.standard_normal(gn.shape)
+    d /= np.max(np.abs(d))
+    dt = _gpu(torch_mod, d)
+    h = 1e-6
+    with torch_mod.no_grad():
+        fd = float((J(f + h * dt) - J(f - h * dt)) / (2 * h))
+    an = float(np.sum(gn * d))
+    _say("  forest FD vs autograd: rel diff %.2e" % (abs(fd - an) / abs(an)))
+    assert abs(fd - an) <= 1e-7 * abs(an)
+    forest.close()
 
 
 def test_autotune_picks_a_valid_shape_and_caches(vp, torch_mod, tmp_path):
@@ -348,32 +402,61 @@ def test_size_matched_config3_sampled_vs_direct_sum(vp, torch_mod):
     assert np.max(np.abs(ug - ud)) / np.max(np.abs(u)) <= TOL
 
 
-def test_config4_forest_graph_trees_vs_oracle(vp, torch_mod):
-    # uneven trees (1-40 Gaussians, min level 3) applied together, graph-captured, forward and
-    # adjoint; per-tree parity against the oracle for the smallest, the largest and two others
-    trees = gen.config4(0, n_trees=32)
+@pytest.mark.timeout(600)
+def test_config4_full_forest_graph_vs_single_trees_and_oracle(vp, torch_mod):
+    # the whole batched workload: 256 uneven trees (1-40 Gaussians, min level 3) in one forest
+    # plan, graph-captured, forward and adjoint, against every tree's own single-tree apply and,
+    # for ten trees (the smallest and the largest among them), against the oracle.
+    # Forest and single-tree plans sum the same terms; they group them differently where the
+    # balanced schedule cuts a tile between blocks (partial sums), and where the two-level chains
+    # pair other levels (a forest pairs levels from its deepest tree down). The difference is
+    # rounding: 1e-14 relative for the forward output, and 1e-13 for the adjoint of a random
+    # cotangent, whose sums cancel (|result| ~ sqrt(terms) |term|).
+    trees = gen.config4(0, n_trees=256)
     off = np.cumsum([0] + [t.n_leaves for t in trees])
-    _say("case config4 forest of %d trees (%d leaves)" % (len(trees), off[-1]))
+    _say("case config4 full forest of %d trees (%d leaves)" % (len(trees), off[-1]))
     F = np.vstack([t.f for t in trees])
-    rng = np.random.default_rng(17)
-    R = rng.standard_normal(F.shape)
-    forest = vp.Plan(np.vstack([t.centres for t in trees]), np.concatenate([t.levels for t in trees]),
-                     tree_offsets=off, use_graph=True)
+    R = np.random.default_rng(17).standard_normal(F.shape)
+    C = np.vstack([t.centres for t in trees])
+    L = np.concatenate([t.levels for t in trees])
     Fd, Rd = _gpu(torch_mod, F), _gpu(torch_mod, R)
-    u, fb = torch_mod.empty_like(Fd), torch_mod.empty_like(Fd)
-    for _ in range(2):  # second call replays the captured graphs
-        forest.apply(Fd, out=u)
-        forest.apply_adjoint(Rd, out=fb)
-    torch_mod.cuda.synchronize()
-    u, fb = u.cpu().numpy(), fb.cpu().numpy()
-    forest.close()
-    sizes = [t.n_leaves for t in trees]
-    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 5, 17})
+
+    def forest_out(**kw):
+        forest = vp.Plan(C, L, tree_offsets=off, **kw)
+        u, fb = torch_mod.empty_like(Fd), torch_mod.empty_like(Fd)
+        for _ in range(3):  # with use_graph the second and third calls replay the captured graphs
+            forest.apply(Fd, out=u)
+            forest.apply_adjoint(Rd, out=fb)
+        torch_mod.cuda.synchronize()
+        forest.close()
+        return u.cpu().numpy(), fb.cpu().numpy()
+
+    def singles_out(**kw):
+        u, fb = np.empty_like(F), np.empty_like(F)
+        for i, t in enumerate(trees):
+            plan = vp.Plan(t.centres, t.levels, **kw)
+            u[off[i]:off[i + 1]] = plan.apply(Fd[off[i]:off[i + 1]]).cpu().numpy()
+            fb[off[i]:off[i + 1]] = plan.apply_adjoint(Rd[off[i]:off[i + 1]]).cpu().numpy()
+            plan.close()
+        return u, fb
+
+    u, fb = forest_out(use_graph=True)
+    us, fs = singles_out()
+    ef = max(rel(u[off[i]:off[i + 1]], us[off[i]:off[i + 1]]) for i in range(len(trees)))
+    ea = max(rel(fb[off[i]:off[i + 1]], fs[off[i]:off[i + 1]]) for i in range(len(trees)))
+    _say("  graph-replayed forest vs single-tree applies: max rel diff forward %.2e adjoint %.2e" % (ef, ea))
+    assert ef <= 1e-14 and ea <= 1e-13
+    sizes = np.array([t.n_leaves for t in trees])
+    order = np.argsort(sizes, kind="stable")
+    pick = sorted({int(order[0]), int(order[-1])} | {int(order[k]) for k in np.linspace(1, 254, 8).astype(int)})
+    assert len(pick) == 10
     for i in pick:
         t = trees[i]
         bc = fmm.BoxCode(tree.Tree(t.centres, t.levels))
-        assert rel(u[off[i]:off[i + 1]], bc.apply(t.f)) <= TOL, i
-        assert rel(fb[off[i]:off[i + 1]], bc.apply_adjoint(R[off[i]:off[i + 1]])) <= TOL, i
+        ef = rel(u[off[i]:off[i + 1]], bc.apply(t.f))
+        ea = rel(fb[off[i]:off[i + 1]], bc.apply_adjoint(R[off[i]:off[i + 1]]))
+        _say("  tree %d (%d leaves): forward %.2e adjoint %.2e vs oracle" % (i, t.n_leaves, ef, ea))
+        assert ef <= TOL and ea <= TOL, i
 
 
 def test_size_matched_config2_forward_and_adjoint_vs_box_code_oracle(vp, torch_mod):

@@ -94,3 +94,27 @@ def test_points_close_to_leaf_edges(device):
     u_o, g_o = _oracle(w, pts)
     assert rel_max_err(up, u_o) < TOL
     assert rel_max_err(gp, g_o) < TOL
+
+
+def test_points_within_rounding_of_edges_and_subsquare_corners(device):
+    # points 1e-16 .. 1e-15 from leaf edges and corners (both sides) and from the corners of the
+    # dyadic sub-squares the moment quadrature refines towards (offsets 1/2, 1/4, 1/32 of a
+    # half-width): the deepest refinements the moment kernel makes, all on the GPU
+    w = gen.random_small_tree(2, max_level=5, n_splits=9)
+    rng = np.random.default_rng(6)
+    s = 2.0 ** (-w.levels.astype(float))
+    pts = []
+    for d in (1e-15, 3e-16, 1e-16):
+        for a in rng.choice(w.n_leaves, 4, replace=False):
+            cx, cy, h = w.centres[a, 0], w.centres[a, 1], s[a]
+            for sgn in (-1.0, 1.0):
+                pts.append([cx + h + sgn * d, cy + 0.3 * h])          # across the right edge
+                pts.append([cx - h + sgn * d, cy - h + sgn * d])      # across the bottom-left corner
+            for frac in (0.5, 0.25, 1.0 / 32.0):
+                pts.append([cx + frac * h - d, cy + frac * h - d])    # beside a sub-square corner
+                pts.append([cx - frac * h + d, cy + 0.6 * h])         # beside a sub-square edge
+    pts = np.clip(np.array(pts), -1.0, 1.0)
+    _, _, up, gp = _run(device, w, pts)
+    u_o, g_o = _oracle(w, pts)
+    assert rel_max_err(up, u_o) < TOL
+    assert rel_max_err(gp, g_o) < TOL

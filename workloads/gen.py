@@ -128,7 +128,7 @@ def _eval_boxes(g, L, IX, IY, cut):
 def _tail(F, p=P):
     D = _cheb_coeff_matrix(p)
     Fb = F.reshape(-1, p, p)  # [box, j, i]
-    C = np.einsum("ni,bij,mj->bnm", D, Fb, D)  # C[b, n(y), m(x)]
+    C = np.matmul(np.matmul(D, Fb), D.T)  # C[b, n(y), m(x)] = sum_ji D[n, j] F[b, j, i] D[m, i]
     mask = np.zeros((p, p), dtype=bool)
     mask[p - 2:, :] = True
     mask[:, p - 2:] = True
@@ -180,43 +180,65 @@ def build_tree(g, eps=1e-11, min_level=0, max_level=24, cut=False, lcut=8):
     return balance(leaves)
 
 
-def _covering_leaf(leaves, key):
-    l, x, y = key
-    while l >= 0:
-        if (l, x, y) in leaves:
-            return (l, x, y)
-        l, x, y = l - 1, x >> 1, y >> 1
-    return None
+def _pack(L, X, Y):
+    return (np.asarray(L, np.int64) << 58) | (np.asarray(X, np.int64) << 29) | np.asarray(Y, np.int64)
 
 
 def balance(leaves):
-    """2:1 balance over edges and corners by splitting coarse leaves (iterated to a fixpoint)."""
-    leaves = set(leaves)
-    changed = True
-    while changed:
-        changed = False
-        for key in sorted(leaves, key=lambda k: -k[0]):
-            if key not in leaves:
-                continue
-            l, x, y = key
-            n = 1 << l
-            for dy in (-1, 0, 1):
-                for dx in (-1, 0, 1):
-                    if not (dx or dy):
-                        continue
-                    q = (l, x + dx, y + dy)
-                    if not (0 <= q[1] < n and 0 <= q[2] < n):
-                        continue
-                    c = _covering_leaf(leaves, q)
-                    while c is not None and c[0] < l - 1:
-                        leaves.remove(c)
-                        cl, cx, cy = c
-                        kids = [(cl + 1, 2 * cx + a, 2 * cy + b) for b in (0, 1) for a in (0, 1)]
-                        leaves.update(kids)
-                        sh = l - (cl + 1)
-                        c = (cl + 1, q[1] >> sh, q[2] >> sh)
-                        changed = True
-    return leaves
+    """2:1 balance over edges and corners: split every leaf that a leaf two or more levels finer
+    touches, until none does (the coarsest balanced refinement, which is unique). Vectorised:
+    a neighbour box q of a level-l leaf is fine when q is a leaf, an internal box, or the child
+    of a leaf; otherwise the leaf covering q is at level <= l - 2 and is split."""
+    keys = np.array(sorted(leaves), dtype=np.int64).reshape(-1, 3)
+    L, X, Y = keys[:, 0], keys[:, 1], keys[:, 2]
+    offs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dx or dy]
+    while True:
+        leaf_k = np.sort(_pack(L, X, Y))
+        # internal boxes: all proper ancestors of leaves
+        anc = []
+        l, x, y = L.copy(), X.copy(), Y.copy()
+        while np.any(l > 0):
+            m = l > 0
+            l, x, y = l[m] - 1, x[m] >> 1, y[m] >> 1
+            anc.append(_pack(l, x, y))
+        inner_k = np.unique(np.concatenate(anc)) if anc else np.zeros(0, np.int64)
+
+        def member(sorted_keys, k):
+            if sorted_keys.size == 0:
+                return np.zeros(k.shape, bool)
+            i = np.minimum(np.searchsorted(sorted_keys, k), sorted_keys.size - 1)
+            return sorted_keys[i] == k
+
+        split = []
+        for dx, dy in offs:
+            qx, qy = X + dx, Y + dy
+            n = np.left_shift(1, L)
+            ok = (qx >= 0) & (qy >= 0) & (qx < n) & (qy < n)
+            ql, qx, qy = L[ok], qx[ok], qy[ok]
+            qk = _pack(ql, qx, qy)
+            fine = member(leaf_k, qk) | member(inner_k, qk)
+            fine |= (ql > 0) & member(leaf_k, _pack(np.maximum(ql - 1, 0), qx >> 1, qy >> 1))
+            ql, qx, qy = ql[~fine], qx[~fine], qy[~fine]
+            # the covering leaf, two or more levels coarser
+            for d in range(2, int(ql.max()) + 1 if ql.size else 0):
+                cl = ql - d
+                live = cl >= 0
+                ck = _pack(np.maximum(cl, 0), qx >> np.minimum(d, ql), qy >> np.minimum(d, ql))
+                hit = live & member(leaf_k, ck)
+                split.append(ck[hit])
+                ql, qx, qy = ql[~hit], qx[~hit], qy[~hit]
+                if ql.size == 0:
+                    break
+        sk = np.unique(np.concatenate(split)) if split else np.zeros(0, np.int64)
+        if sk.size == 0:
+            break
+        k = _pack(L, X, Y)
+        keep = ~member(sk, k)
+        sl, sx, sy = sk >> 58, (sk >> 29) & ((1 << 29) - 1), sk & ((1 << 29) - 1)
+        L = np.concatenate([L[keep], np.repeat(sl + 1, 4)])
+        X = np.concatenate([X[keep], (2 * np.repeat(sx, 4) + np.tile([0, 1, 0, 1], sx.size))])
+        Y = np.concatenate([Y[keep], (2 * np.repeat(sy, 4) + np.tile([0, 0, 1, 1], sy.size))])
+    return {(int(a), int(b), int(c)) for a, b, c in zip(L, X, Y)}
 
 
 def _order(leaves):
