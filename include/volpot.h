@@ -250,6 +250,15 @@ int volpot_strip_nodes(volpot_strip_t strip, double* xy);
  * Gamma, Gamma~ and the element edges are ignored). Asynchronous on the stream; one solve at a
  * time per plan (shared workspace). */
 int volpot_strip_apply(volpot_strip_t strip, const double* f_dev, double* v_dev, void* hip_stream);
+/* As volpot_strip_apply, for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the apply's work vectors live in a
+ * static 1 MiB array of each device the library runs on (held until the process ends) instead of
+ * the plan's memory, and the call allocates nothing. The plan must satisfy
+ * (4 n_panel + 4) (n_r - 2) <= 131072 (e.g. 1,091 panels at n_r = 32); VOLPOT_ERR_ARG otherwise.
+ * All calls on one device share that device's array: calls whose work overlaps on one device
+ * (different streams, or threads) race and give wrong results; serialise them. Same results as
+ * volpot_strip_apply, bit for bit. */
+int volpot_strip_apply_noalloc(volpot_strip_t strip, const double* f_dev, double* v_dev, void* hip_stream);
 void volpot_strip_destroy(volpot_strip_t strip);
 
 /* Sizes and algorithmic flop/byte counts of the plan. */

@@ -524,6 +524,30 @@ int volpot_strip_apply(volpot_strip_t s, const double* f_dev, double* v_dev, voi
   return e == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
 }
 
+int volpot_strip_apply_noalloc(volpot_strip_t s, const double* f_dev, double* v_dev, void* hip_stream) {
+  if (!s || !f_dev || !v_dev || f_dev == v_dev) return VOLPOT_ERR_ARG;
+  const int64_t n = s->d.n, m = s->d.m;
+  if ((4 * n + 4) * m > kStripScratchDoubles) return VOLPOT_ERR_ARG;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (s->device != prev) (void)hipSetDevice(s->device);
+  double* base = nullptr;
+  hipError_t e = strip_scratch(&base);
+  if (e == hipSuccess) {
+    // every element of the work vectors is written before it is read within one apply, so the
+    // previous call's contents need no clearing
+    StripDevice d = s->d;
+    d.s = base;
+    d.w = d.s + n * m;
+    d.z = d.w + n * m;
+    d.t = d.z + (n + 1) * m;
+    d.h = d.t + (n + 1) * m;
+    e = launch_strip_solve(d, f_dev, v_dev, reinterpret_cast<hipStream_t>(hip_stream));
+  }
+  if (s->device != prev && prev >= 0) (void)hipSetDevice(prev);
+  return e == hipSuccess ? VOLPOT_OK : VOLPOT_ERR_HIP;
+}
+
 void volpot_strip_destroy(volpot_strip_t s) {
   if (!s) return;
   if (s->block) {

@@ -14,6 +14,9 @@
 // one barrier per chunk). All sums have a fixed order, so repeated applies are bitwise identical.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "strip.hpp"
 
 namespace vp {
@@ -273,7 +276,31 @@ __global__ void __launch_bounds__(kSolThreads)
   if (tile == 0 && tid < 2 * q) x[size_t(k) * B + (tid < q ? tid : B - 2 * q + tid)] = 0.0;
 }
 
+// Work vectors of the apply (s, w, z, t, h) for callers that cannot allocate: one static array
+// per device, held until the process ends. Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device (strip_scratch); the array's name is not a device
+// address on the host.
+static __device__ __align__(256) double scratch[kStripScratchDoubles];
+
 }  // namespace
+
+hipError_t strip_scratch(double** out) {
+  static std::mutex mu;
+  static std::vector<double*> per_device;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (per_device.size() <= size_t(dev)) per_device.resize(size_t(dev) + 1, nullptr);
+  if (!per_device[size_t(dev)]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_device[size_t(dev)] = static_cast<double*>(p);
+  }
+  *out = per_device[size_t(dev)];
+  return hipSuccess;
+}
 
 hipError_t launch_strip_solve(const StripDevice& d, const double* f, double* v, hipStream_t stream) {
   if (d.m < 2 || d.m > kMaxM) return hipErrorInvalidValue;  // the plan keeps 4 <= n_r <= 32

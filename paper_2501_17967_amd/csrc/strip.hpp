@@ -28,6 +28,12 @@ struct StripDevice {
 // v (n x B) from the node samples f (n x B): Lap v = f inside, the boundary and interface rows zero
 hipError_t launch_strip_solve(const StripDevice& d, const double* f, double* v, hipStream_t stream);
 
+// Static work memory of the apply without allocation: (4 n + 4) m doubles are needed (s, w: n m;
+// z, t: (n + 1) m; h: 2 m). strip_scratch gives its address on the current device (looked up once
+// per device).
+constexpr int64_t kStripScratchDoubles = int64_t(1) << 17;  // 1 MiB per device
+hipError_t strip_scratch(double** out);
+
 // Plan-time factorization on the GPU (strip_factor.hip).
 struct StripFactorDevice {
   int32_t n, N, Bi, m, q;  // elements, padded interior size (multiple of 16), Bi = m q, m, q

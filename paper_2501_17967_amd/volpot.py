@@ -37,7 +37,7 @@ EXPORTED = [
     "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune", "volpot_layer_plan", "volpot_layer_apply",
     "volpot_plan_points", "volpot_apply_points", "volpot_tree_create", "volpot_tree_pending", "volpot_tree_nodes",
     "volpot_tree_submit", "volpot_tree_leaves", "volpot_tree_destroy", "volpot_strip_plan", "volpot_strip_nodes",
-    "volpot_strip_apply", "volpot_strip_destroy",
+    "volpot_strip_apply", "volpot_strip_destroy", "volpot_strip_apply_noalloc",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -146,6 +146,7 @@ def lib():
                                         ctypes.POINTER(_vp)]
         L.volpot_strip_nodes.argtypes = [_vp, _dp]
         L.volpot_strip_apply.argtypes = [_vp, _vp, _vp, _vp]
+        L.volpot_strip_apply_noalloc.argtypes = [_vp, _vp, _vp, _vp]
         L.volpot_strip_destroy.argtypes = [_vp]
         L.volpot_strip_destroy.restype = None
         _lib = L
@@ -232,16 +233,21 @@ class StripPlan:
         self.nodes = np.zeros(self.shape + (2,))
         _check(lib().volpot_strip_nodes(h, self.nodes.ctypes.data_as(_dp)), "volpot_strip_nodes")
 
-    def apply(self, f, out=None, stream=None):
+    def apply(self, f, out=None, stream=None, noalloc=False):
+        """v at the nodes. noalloc=True calls volpot_strip_apply_noalloc (work vectors in the
+        library's static per-device array; ``out`` must then be given, so nothing is allocated)."""
         import torch
 
         if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64 and f.numel() == np.prod(self.shape)):
             raise TypeError("expected a CUDA float64 tensor of %d node values" % int(np.prod(self.shape)))
+        if noalloc and (out is None or not f.is_contiguous()):
+            raise ValueError("noalloc needs a contiguous f and a given out")
         f = f.contiguous()
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float64, device=f.device)
-        _check(lib().volpot_strip_apply(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                        _stream_handle(stream)), "volpot_strip_apply")
+        fn = lib().volpot_strip_apply_noalloc if noalloc else lib().volpot_strip_apply
+        _check(fn(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+               "volpot_strip_apply_noalloc" if noalloc else "volpot_strip_apply")
         return out
 
     def close(self):
