@@ -179,6 +179,97 @@ int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centr
 struct Entry { int32_t rel; int8_t fam; int32_t src; };
 struct R1 { int8_t fam; int32_t idx; double coef; };
 
+// Interaction lists in compressed rows: row i holds (relation, index) pairs.
+using RelIdx = std::pair<int32_t, int32_t>;
+struct Lists {
+  std::vector<int64_t> ptr{0};
+  std::vector<RelIdx> e;
+  struct Row {
+    const RelIdx *b, *e;
+    const RelIdx* begin() const { return b; }
+    const RelIdx* end() const { return e; }
+    size_t size() const { return size_t(e - b); }
+    bool empty() const { return b == e; }
+  };
+  Row operator[](size_t i) const { return {e.data() + ptr[i], e.data() + ptr[i + 1]}; }
+  size_t rows() const { return ptr.size() - 1; }
+};
+
+// f(i) for i in [0, n) on up to 16 host threads, in chunks of `grain`; the first exception
+// thrown by any call is rethrown.
+template <class F>
+static void par_for(int64_t n, const F& f, int64_t grain = 2048) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned nt = unsigned(std::min<int64_t>(hw, (n + grain - 1) / grain));
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next(0);
+  std::exception_ptr err;
+  std::atomic<bool> failed(false);
+  auto work = [&]() {
+    try {
+      for (int64_t i0; !failed.load() && (i0 = next.fetch_add(grain)) < n;)
+        for (int64_t i = i0; i < std::min(n, i0 + grain); ++i) f(i);
+    } catch (...) {
+      if (!failed.exchange(true)) err = std::current_exception();
+    }
+  };
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+}
+
+// Rows of `n_out` lists for items [0, n): row(i, outs) appends item i's entries to outs[k] for
+// list k. Contiguous chunks of items are filled concurrently and concatenated in item order.
+template <class F>
+static void build_rows(int64_t n, std::vector<Lists*> lists, const F& row) {
+  const int64_t chunk = 4096, nc = (n + chunk - 1) / chunk;
+  const size_t K = lists.size();
+  auto ent = std::vector<std::vector<std::vector<RelIdx>>>(static_cast<size_t>(nc), std::vector<std::vector<RelIdx>>(K));
+  auto cnt = std::vector<std::vector<std::vector<int64_t>>>(static_cast<size_t>(nc), std::vector<std::vector<int64_t>>(K));
+  par_for(nc, [&](int64_t c) {
+    std::vector<std::vector<RelIdx>*> outs(K);
+    for (size_t k = 0; k < K; ++k) outs[k] = &ent[size_t(c)][k];
+    for (int64_t i = c * chunk; i < std::min(n, (c + 1) * chunk); ++i) {
+      std::vector<size_t> before(K);
+      for (size_t k = 0; k < K; ++k) before[k] = outs[k]->size();
+      row(i, outs);
+      for (size_t k = 0; k < K; ++k) cnt[size_t(c)][k].push_back(int64_t(outs[k]->size() - before[k]));
+    }
+  }, 1);
+  for (size_t k = 0; k < K; ++k) {
+    Lists& L = *lists[k];
+    L.ptr.assign(1, 0);
+    L.ptr.reserve(size_t(n) + 1);
+    size_t total = 0;
+    for (int64_t c = 0; c < nc; ++c) total += ent[size_t(c)][k].size();
+    L.e.clear();
+    L.e.reserve(total);
+    for (int64_t c = 0; c < nc; ++c) {
+      for (int64_t m : cnt[size_t(c)][k]) L.ptr.push_back(L.ptr.back() + m);
+      L.e.insert(L.e.end(), ent[size_t(c)][k].begin(), ent[size_t(c)][k].end());
+    }
+  }
+}
+
+// The transpose of list A (rows over [0, n_rows_a)) into rows over [0, n_rows_t): row t holds
+// (relation, a) for every entry (relation, t) of row a, in increasing a.
+static Lists transpose_rows(const Lists& A, int64_t n_rows_t) {
+  Lists T;
+  T.ptr.assign(size_t(n_rows_t) + 1, 0);
+  for (const RelIdx& x : A.e) T.ptr[size_t(x.second) + 1]++;
+  for (int64_t t = 0; t < n_rows_t; ++t) T.ptr[size_t(t) + 1] += T.ptr[size_t(t)];
+  T.e.resize(A.e.size());
+  std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (size_t a = 0; a < A.rows(); ++a)
+    for (const RelIdx& x : A[a]) T.e[size_t(pos[size_t(x.second)]++)] = {x.first, int32_t(a)};
+  return T;
+}
+
 static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
                                const std::vector<std::vector<Entry>>& entries,
                                const std::vector<std::vector<R1>>& r1, const Matrices& mats);
@@ -509,22 +600,24 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
 
   // ---------------------------------------------------------------- lists
   const int64_t NB = P.n_boxes;
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> Ulist(P.n_leaves);  // (near rel, src leaf)
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> Wlist(P.n_leaves);  // (w rel, src box)
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> Vlist(NB);          // (v rel, src box)
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> Xlist(NB);          // (x rel, src leaf)
+  Lists Ulist;  // per leaf: (near rel, src leaf)
+  Lists Wlist;  // per leaf: (w rel, src box)
+  Lists Vlist;  // per box: (v rel, src box)
+  Lists Xlist;  // per box: (x rel, src leaf)
   const auto& NO = near_offsets();
   const auto& VO = v_offsets();
   const auto& WO = w_offsets();
   const auto& XO = x_offsets();
-  for (int64_t a = 0; a < P.n_leaves; ++a) {
+  build_rows(P.n_leaves, {&Ulist, &Wlist}, [&](int64_t a, std::vector<std::vector<RelIdx>*>& out) {
     int32_t ba = P.leaf_box[a];
     int32_t tr = P.box_tree[ba];
     uint64_t k = key_of(ba);
     int l = key_l(k);
     int64_t nmax = int64_t(1) << l;
     double sa = hw(ba);
-    std::vector<int32_t> adj{ba};
+    int32_t adj[32];
+    int na = 0;
+    adj[na++] = ba;
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
         if (!dx && !dy) continue;
@@ -533,31 +626,36 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         uint64_t q = pack(l, qx, qy);
         int32_t bq = find_box(tr, q);
         if (bq >= 0) {
-          if (P.box_leaf[bq] >= 0) { adj.push_back(bq); continue; }
+          if (P.box_leaf[bq] >= 0) { adj[na++] = bq; continue; }
           for (int c = 0; c < 4; ++c) {
             int32_t ch = P.box_child[bq][c];
-            if (touch(key_of(ch), k)) adj.push_back(ch);  // leaves by 2:1 balance
-            else Wlist[a].push_back({find_offset(WO, (cx(ch) - cx(ba)) / sa, (cy(ch) - cy(ba)) / sa, 0.5), ch});
+            if (touch(key_of(ch), k)) {
+              adj[na++] = ch;  // leaves by 2:1 balance
+            } else {
+              int r = find_offset(WO, (cx(ch) - cx(ba)) / sa, (cy(ch) - cy(ba)) / sa, 0.5);
+              if (r < 0) throw std::runtime_error("W relation not found");
+              out[1]->push_back({r, ch});
+            }
           }
         } else {
           uint64_t c = q;
           while (find_box(tr, c) < 0 || P.box_leaf[find_box(tr, c)] < 0) c = parent_key(c);
-          adj.push_back(find_box(tr, c));
+          adj[na++] = find_box(tr, c);
         }
       }
-    std::sort(adj.begin(), adj.end());
-    adj.erase(std::unique(adj.begin(), adj.end()), adj.end());
-    for (int32_t bb : adj) {
+    std::sort(adj, adj + na);
+    na = int(std::unique(adj, adj + na) - adj);
+    for (int i = 0; i < na; ++i) {
+      const int32_t bb = adj[i];
       int r = find_offset(NO, (cx(bb) - cx(ba)) / sa, (cy(bb) - cy(ba)) / sa, hw(bb) / sa);
       if (r < 0) throw std::runtime_error("near relation not found");
-      Ulist[a].push_back({r, P.box_leaf[bb]});
+      out[0]->push_back({r, P.box_leaf[bb]});
     }
-    for (auto& w : Wlist[a])
-      if (w.first < 0) throw std::runtime_error("W relation not found");
-  }
-  for (int32_t b = 0; b < NB; ++b) {
+  });
+  build_rows(NB, {&Vlist}, [&](int64_t bi, std::vector<std::vector<RelIdx>*>& out) {
+    const int32_t b = int32_t(bi);
     int l = P.box_level[b];
-    if (l < 2) continue;
+    if (l < 2) return;
     int32_t tr = P.box_tree[b];
     uint64_t k = key_of(b);
     int32_t par = P.box_parent[b];
@@ -576,18 +674,24 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
           if (touch(key_of(ch), k)) continue;
           int r = find_offset(VO, (cx(ch) - cx(b)) / s, (cy(ch) - cy(b)) / s, 1.0);
           if (r < 0) throw std::runtime_error("V relation not found");
-          Vlist[b].push_back({r, ch});
+          out[0]->push_back({r, ch});
         }
       }
+  });
+  {  // X: the dual of W, with its own offsets (from the source box's point of view)
+    Xlist = transpose_rows(Wlist, NB);
+    std::atomic<bool> bad_x(false);
+    par_for(NB, [&](int64_t c) {
+      const double s = hw(int32_t(c));
+      for (int64_t e = Xlist.ptr[size_t(c)]; e < Xlist.ptr[size_t(c) + 1]; ++e) {
+        RelIdx& x = Xlist.e[size_t(e)];
+        const int32_t ba = P.leaf_box[x.second];
+        x.first = find_offset(XO, (cx(ba) - cx(int32_t(c))) / s, (cy(ba) - cy(int32_t(c))) / s, 2.0);
+        if (x.first < 0) bad_x = true;
+      }
+    });
+    if (bad_x) throw std::runtime_error("X relation not found");
   }
-  for (int64_t a = 0; a < P.n_leaves; ++a)
-    for (auto& w : Wlist[a]) {
-      int32_t c = w.second, ba = P.leaf_box[a];
-      double s = hw(c);
-      int r = find_offset(XO, (cx(ba) - cx(c)) / s, (cy(ba) - cy(c)) / s, 2.0);
-      if (r < 0) throw std::runtime_error("X relation not found");
-      Xlist[c].push_back({r, int32_t(a)});
-    }
 
   // ---------------------------------------------------------------- layer sources
   // Each curve node belongs to the leaf that holds it (a node on an edge between boxes goes to
@@ -704,20 +808,12 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   std::sort(leaf_order.begin(), leaf_order.end(), [&](int32_t x, int32_t y) { return P.leaf_box[x] < P.leaf_box[y]; });
 
   // inverse lists for the adjoint
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> Uinv(P.n_leaves), Winv(NB), Vinv(NB), Xinv(P.n_leaves);
-  for (int64_t a = 0; a < P.n_leaves; ++a) {
-    for (auto& e : Ulist[a]) Uinv[e.second].push_back({e.first, int32_t(a)});
-    for (auto& e : Wlist[a]) Winv[e.second].push_back({e.first, int32_t(a)});
-  }
-  for (int32_t b = 0; b < NB; ++b) {
-    for (auto& e : Vlist[b]) Vinv[e.second].push_back({e.first, b});
-    for (auto& e : Xlist[b]) Xinv[e.second].push_back({e.first, b});
-  }
-  for (int64_t a = 0; a < P.n_leaves; ++a) {
-    P.pairs_near += int64_t(Ulist[a].size());
-    P.pairs_w += int64_t(Wlist[a].size());
-  }
-  for (int32_t b = 0; b < NB; ++b) { P.pairs_v += int64_t(Vlist[b].size()); P.pairs_x += int64_t(Xlist[b].size()); }
+  const Lists Uinv = transpose_rows(Ulist, P.n_leaves), Winv = transpose_rows(Wlist, NB),
+              Vinv = transpose_rows(Vlist, NB), Xinv = transpose_rows(Xlist, P.n_leaves);
+  P.pairs_near = int64_t(Ulist.e.size());
+  P.pairs_w = int64_t(Wlist.e.size());
+  P.pairs_v = int64_t(Vlist.e.size());
+  P.pairs_x = int64_t(Xlist.e.size());
 
   // K: the inner dimension shared by every relation of the stage; it fixes the k-chunk
   auto init_stage = [](Stage& st, int kind, const std::string& name, int level, int M, int K, int NT, int8_t out,
@@ -881,14 +977,14 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i) {
-      int32_t b = tg[i];
+    par_for(int64_t(tg.size()), [&](int64_t i) {
+      int32_t b = tg[size_t(i)];
       double ls = lnS(P.box_level[b]);
       for (auto& e : Vlist[b])
-        if (use(e.second)) { E[i].push_back({kRelM2L + e.first, 0, e.second}); R[i].push_back({0, e.second, ls}); }
+        if (use(e.second)) { E[size_t(i)].push_back({kRelM2L + e.first, 0, e.second}); R[size_t(i)].push_back({0, e.second, ls}); }
       if (!layer)
-        for (auto& e : Xlist[b]) R[i].push_back({0, P.leaf_box[e.second], ls});
-    }
+        for (auto& e : Xlist[b]) R[size_t(i)].push_back({0, P.leaf_box[e.second], ls});
+    });
     defer(std::move(st), tg, std::move(E), std::move(R), false);
   }
   if (layer) {  // P2L: the nodes of X-list leaves, added onto FARV
@@ -919,8 +1015,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       st.fam[0] = {A_INS, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
-      for (size_t i = 0; i < tg.size(); ++i)
-        for (auto& e : Xlist[tg[i]]) E[i].push_back({kRelS2L + e.first, 0, e.second});
+      par_for(int64_t(tg.size()), [&](int64_t i) {
+        for (auto& e : Xlist[tg[size_t(i)]]) E[size_t(i)].push_back({kRelS2L + e.first, 0, e.second});
+      });
       defer(std::move(st), tg, std::move(E), std::move(R), false);
     }
   }
@@ -931,18 +1028,30 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   // classes share most relations), box order within a class. A tile then holds
   // few relations whose slots are mostly empty: each segment costs the same whatever its
   // occupancy.
-  auto by_signature = [&](const std::vector<std::vector<std::pair<int32_t, int32_t>>>& lists) {
-    std::map<std::vector<int32_t>, int32_t> cls;  // signature -> rank in lexicographic order
-    std::vector<std::vector<int32_t>> sigs(size_t(P.n_leaves));
-    for (int32_t a : leaf_order) {
-      for (auto& e : lists[size_t(a)]) sigs[size_t(a)].push_back(e.first);
-      std::sort(sigs[size_t(a)].begin(), sigs[size_t(a)].end());
-      cls.emplace(sigs[size_t(a)], 0);
-    }
-    int32_t rank = 0;
-    for (auto& kv : cls) kv.second = rank++;
+  auto by_signature = [&](const Lists& lists) {
+    // a leaf's signature as a bit set of its near relations (33 < 64; one source per relation)
+    std::vector<uint64_t> sig(size_t(P.n_leaves), 0);
+    par_for(P.n_leaves, [&](int64_t a) {
+      for (auto& e : lists[size_t(a)]) sig[size_t(a)] |= uint64_t(1) << e.first;
+    });
+    std::vector<uint64_t> cls(sig);
+    std::sort(cls.begin(), cls.end());
+    cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
+    // lexicographic order of the sorted relation lists: compare the lowest differing relation
+    auto lex_less = [](uint64_t x, uint64_t y) {
+      while (x && y) {
+        const int bx = __builtin_ctzll(x), by = __builtin_ctzll(y);
+        if (bx != by) return bx < by;
+        x &= x - 1;
+        y &= y - 1;
+      }
+      return x == 0 && y != 0;  // a proper prefix comes first
+    };
+    std::sort(cls.begin(), cls.end(), lex_less);
     std::vector<int32_t> c(size_t(P.n_leaves));
-    for (int32_t a : leaf_order) c[size_t(a)] = cls[sigs[size_t(a)]];
+    par_for(P.n_leaves, [&](int64_t a) {
+      c[size_t(a)] = int32_t(std::lower_bound(cls.begin(), cls.end(), sig[size_t(a)], lex_less) - cls.begin());
+    });
     std::vector<int32_t> o(leaf_order);
     std::stable_sort(o.begin(), o.end(), [&](int32_t x, int32_t y) { return c[size_t(x)] < c[size_t(y)]; });
     return o;
@@ -986,8 +1095,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.fam[0] = {A_INS, kNP, 0};
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
-    for (size_t i = 0; i < part.size(); ++i)
-      for (auto& e : Ulist[part[i]]) E[i].push_back({kRelNear + e.first, 0, e.second});
+    par_for(int64_t(part.size()), [&](int64_t i) {
+      for (auto& e : Ulist[part[size_t(i)]]) E[size_t(i)].push_back({kRelNear + e.first, 0, e.second});
+    });
     defer(std::move(st), part, std::move(E), std::move(R), false);
   }
   if (layer) {  // LOCT: L2T + M2T of active W boxes and their kappa(s_a) * mass terms (P2P adds on)
@@ -997,13 +1107,14 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
-    for (size_t i = 0; i < leaf_order.size(); ++i) {
-      int32_t a = leaf_order[i];
+    par_for(int64_t(leaf_order.size()), [&](int64_t i) {
+      int32_t a = leaf_order[size_t(i)];
       double kap = P.leaf_kappa[a];
       for (auto& e : Wlist[a])
-        if (use(e.second)) { E[i].push_back({kRelM2T + e.first, 0, e.second}); R[i].push_back({0, e.second, kap}); }
-      if (levels[a] >= 2) { E[i].push_back({kRelL2T, 1, P.leaf_box[a]}); P.n_l2t++; }
-    }
+        if (use(e.second)) { E[size_t(i)].push_back({kRelM2T + e.first, 0, e.second}); R[size_t(i)].push_back({0, e.second, kap}); }
+      if (levels[a] >= 2) E[size_t(i)].push_back({kRelL2T, 1, P.leaf_box[a]});
+    });
+    for (int32_t a : leaf_order) P.n_l2t += levels[a] >= 2;
     defer(std::move(st), leaf_order, std::move(E), std::move(R), false);
   }
   if (!layer) {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
@@ -1014,13 +1125,14 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
-    for (size_t i = 0; i < leaf_order.size(); ++i) {
-      int32_t a = leaf_order[i];
+    par_for(int64_t(leaf_order.size()), [&](int64_t i) {
+      int32_t a = leaf_order[size_t(i)];
       double kap = P.leaf_kappa[a];
-      for (auto& e : Ulist[a]) R[i].push_back({0, P.leaf_box[e.second], kap});
-      for (auto& e : Wlist[a]) { E[i].push_back({kRelM2T + e.first, 0, e.second}); R[i].push_back({0, e.second, kap}); }
-      if (levels[a] >= 2) { E[i].push_back({kRelL2T, 1, P.leaf_box[a]}); P.n_l2t++; }
-    }
+      for (auto& e : Ulist[a]) R[size_t(i)].push_back({0, P.leaf_box[e.second], kap});
+      for (auto& e : Wlist[a]) { E[size_t(i)].push_back({kRelM2T + e.first, 0, e.second}); R[size_t(i)].push_back({0, e.second, kap}); }
+      if (levels[a] >= 2) E[size_t(i)].push_back({kRelL2T, 1, P.leaf_box[a]});
+    });
+    for (int32_t a : leaf_order) P.n_l2t += levels[a] >= 2;
     defer(std::move(st), leaf_order, std::move(E), std::move(R), false);
   }
 
@@ -1051,7 +1163,8 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.r1fam[0] = {A_LB, kNE, 0}; st.r1fam[1] = {A_USUM, 1, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
-    for (size_t i = 0; i < tg.size(); ++i) {
+    par_for(int64_t(tg.size()), [&](int64_t ii) {
+      const size_t i = size_t(ii);
       int32_t b = tg[i];
       double ls = lnS(P.box_level[b]);
       for (auto& e : Vinv[b]) { E[i].push_back({kRelM2L + e.first + kNumFwd, 0, e.second}); R[i].push_back({0, e.second, ls}); }
@@ -1061,7 +1174,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         for (auto& e : Uinv[leaf]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
         for (auto& e : Xinv[leaf]) R[i].push_back({0, e.second, lnS(P.box_level[e.second])});
       }
-    }
+    });
     defer(std::move(st), tg, std::move(E), std::move(R), true);
   }
   {  // AFARW: M2T^T, added onto AFARV for the boxes that have a W^-1 list
@@ -1073,8 +1186,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       st.fam[0] = {A_IN, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
-      for (size_t i = 0; i < tg.size(); ++i)
-        for (auto& e : Winv[tg[i]]) E[i].push_back({kRelM2T + e.first + kNumFwd, 0, e.second});
+      par_for(int64_t(tg.size()), [&](int64_t i) {
+        for (auto& e : Winv[tg[size_t(i)]]) E[size_t(i)].push_back({kRelM2T + e.first + kNumFwd, 0, e.second});
+      });
       defer(std::move(st), tg, std::move(E), std::move(R), true);
     }
   }
@@ -1086,8 +1200,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.fam[0] = {A_IN, kNP, 0};
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
-    for (size_t i = 0; i < part.size(); ++i)
-      for (auto& e : Uinv[part[i]]) E[i].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
+    par_for(int64_t(part.size()), [&](int64_t i) {
+      for (auto& e : Uinv[part[size_t(i)]]) E[size_t(i)].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
+    });
     defer(std::move(st), part, std::move(E), std::move(R), true);
   }
   {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
@@ -1097,11 +1212,11 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     st.fam[0] = {A_AB, kNE, 0}; st.fam[1] = {A_LB, kNE, 0};
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
-    for (size_t i = 0; i < leaf_order.size(); ++i) {
-      int32_t b = leaf_order[i];
-      E[i].push_back({kRelS2M + kNumFwd, 0, P.leaf_box[b]});
-      for (auto& e : Xinv[b]) E[i].push_back({kRelS2L + e.first + kNumFwd, 1, e.second});
-    }
+    par_for(int64_t(leaf_order.size()), [&](int64_t i) {
+      int32_t b = leaf_order[size_t(i)];
+      E[size_t(i)].push_back({kRelS2M + kNumFwd, 0, P.leaf_box[b]});
+      for (auto& e : Xinv[b]) E[size_t(i)].push_back({kRelS2L + e.first + kNumFwd, 1, e.second});
+    });
     defer(std::move(st), leaf_order, std::move(E), std::move(R), true);
   }
   }  // adjoint
@@ -1120,7 +1235,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         std::vector<std::vector<R1>>().swap(jobs[j].R);
       }
     };
-    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
     for (unsigned i = 1; i < nt; ++i) pool.emplace_back(work);
     work();
