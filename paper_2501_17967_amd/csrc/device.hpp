@@ -112,4 +112,28 @@ hipError_t launch_tree_nodes(const int64_t* keys, int64_t n, const TreeRule& r, 
 // Chebyshev tail of each box's 256 samples.
 hipError_t launch_tree_tail(const double* values, int64_t n, const TreeRule& r, double* tails, hipStream_t stream);
 
+// Device work of the builder (tree.hip). Keys are packed (level << 58 | ix << 29 | iy).
+struct TreeWork {
+  // growable device buffers (element capacities alongside), owned by the builder
+  uint64_t *pend = nullptr, *next = nullptr, *leaves = nullptr, *tmp = nullptr, *anc = nullptr;
+  double* tails = nullptr;
+  int32_t *flag = nullptr, *pos = nullptr;
+  void* scratch = nullptr;
+  size_t cap_pend = 0, cap_next = 0, cap_leaves = 0, cap_tmp = 0, cap_anc = 0, cap_tails = 0, cap_flag = 0,
+         cap_pos = 0, scratch_bytes = 0;
+  int64_t n_pend = 0, n_leaves = 0;  // pending boxes (keys in pend) and leaves so far (in leaves)
+};
+// Device copy of the first round's keys (host, n): pend and n_pend.
+hipError_t tree_upload_pending(TreeWork& w, const uint64_t* keys, int64_t n, hipStream_t stream);
+// One round: tails of the pending boxes from their samples, the split decision (level below
+// max_level and tail not <= tol), the split boxes' children as the next pending boxes and the
+// others appended to the leaves; n_pend and n_leaves are updated (synchronises the stream).
+hipError_t tree_round(TreeWork& w, const double* values, const TreeRule& r, double tol, int max_level,
+                      hipStream_t stream);
+// The 2:1 balance of the leaves over edges and corners (split every leaf that a leaf two or more
+// levels finer touches, to a fixpoint); leaves then holds n_leaves keys (level << 58 | iy << 29 |
+// ix), ascending: by level, then y, then x (synchronises).
+hipError_t tree_balance(TreeWork& w, hipStream_t stream);
+void tree_free(TreeWork& w);
+
 }  // namespace vp

@@ -67,3 +67,32 @@ def test_polynomial_source_is_one_box(device):
     f = lambda p: 1.0 + p[:, 0] ** 3 * p[:, 1] ** 5
     got, _, _ = _gpu_build(f, 1e-12, 1.0, 0, 10)
     assert got == {(0, 0, 0)}
+
+
+@pytest.mark.parametrize("centre", [(0.37, -0.61), (-0.999, 0.999)])
+def test_deep_point_source_needs_many_balance_rounds(device, centre):
+    # a near-singular source d^2 / (|x - c|^2 + d^2), d = 1e-5, refines down to level 18 around
+    # one point (next to a corner of the root for the second case): the 2:1 balance ripples
+    # outwards over many levels
+    d2 = 1e-10
+    f = lambda p: d2 / ((p[:, 0] - centre[0]) ** 2 + (p[:, 1] - centre[1]) ** 2 + d2)
+    print("tree case: point source at %s" % (centre,), flush=True)
+    got, c, l = _gpu_build(f, 1e-10, 1.0, 0, 24)
+    ref = qt.build(f, 1e-10, 1.0, 0, 24)
+    assert got == set(ref)
+    assert max(k[0] for k in got) >= 15
+    from paper_2501_17967_amd import validate_tree
+    assert validate_tree(c, l)[0] == 0
+
+
+def test_size_matched_tree_matches_the_generator(device):
+    # the benchmark's size-matched 20-Gaussian tree (background level 7, about 17k leaves)
+    rng = np.random.default_rng(0)
+    g = gen.sample_gaussians(rng, 20, -0.9, 0.9, 1e-3, 1e-1)
+    print("tree case: size-matched 20-Gaussian tree", flush=True)
+    got, _, _ = _gpu_build(_gauss_f(g), 1e-11, g.scale, 7, 24)
+    w = gen.config2(0, size_matched=True)
+    s = 2.0 ** (-w.levels.astype(float))
+    ref = {(int(a), int(x), int(y)) for a, x, y in zip(w.levels, np.round((w.centres[:, 0] + 1) / (2 * s) - 0.5),
+                                                        np.round((w.centres[:, 1] + 1) / (2 * s) - 0.5))}
+    assert got == ref
