@@ -63,8 +63,8 @@ typedef struct {
   int32_t use_graph;       /* 1: capture each apply once per (input, output) pointer pair into
                               a hipGraph and replay it. Default 0. */
   int32_t tile_leaf;       /* slots per tile of the near-field stages (256 rows): 32 or 64;
-                              0 = default (32). The 256-row stages with K = 80 (L2T + M2T and
-                              S2M^T + S2L^T) always use 16-slot tiles. */
+                              0 = default (32). The 256-row stages with K = 80 take
+                              tile_leaf_exp. */
   int32_t tile_box;        /* slots per tile of the 80-row (expansion) stages: 16, 32 or 64;
                               0 = default (32) */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
@@ -85,6 +85,9 @@ typedef struct {
                               takes (leaf centres, curve nodes, evaluation points) and every
                               output is in the caller's coordinates: u is the potential of the
                               caller's box sizes, including the log kernel's ln h term. */
+  int32_t tile_leaf_exp;   /* slots per tile of the leaf stages whose sources are expansions
+                              (L2T + M2T, and S2M^T + S2L^T in the adjoint; K = 80): 16, 32 or
+                              64; 0 = default (16) */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -296,7 +299,8 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
 
 /* Autotuner (for callers that apply one tree shape many times, e.g. batched forests): searches
- * the launch shapes tile_box 16|32|64, tile_leaf 32|64, split_min 0|1|-1 and overlap 0|16|24|32|48
+ * the launch shapes tile_box 16|32|64, tile_leaf 32|64, tile_leaf_exp 16|32|64, split_min 0|1|-1
+ * and overlap 0|16|24|32|48
  * one knob at a time from the defaults (the other fields are taken from base, nullable),
  * building a plan for each candidate and timing one forward plus one adjoint apply on internal
  * device buffers after a warm-up (HIP events, private stream, best of 5); writes the fastest

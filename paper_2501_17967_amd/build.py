@@ -48,7 +48,8 @@ def build(verbose=False):
     if failed:
         raise RuntimeError("libvolpot build failed")
     tmp = OUT + ".tmp%d" % os.getpid()
-    link = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
+    link = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-lpthread"]
     r = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         raise RuntimeError("libvolpot link failed:\n" + r.stdout.decode(errors="replace"))

@@ -1,6 +1,7 @@
 // C ABI of the box code (declared in include/volpot.h): plan lifecycle, device upload of the
 // shared tables and per-plan schedules, and the stage launch sequence of apply / adjoint.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -453,6 +454,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, dou
     if (s.custom != C_NONE) {
       hipEvent_t ea, eb;
       timed_begin(p, timing, s.kind, st, &ea, &eb);
+      roctxRangePushA(s.name.c_str());
       hipError_t e = hipSuccess;
       if (s.custom == C_P2M)
         e = launch_p2m(s.n_tiles, d.c_tgt, p->d_bptr, p->d_geo, p->d_sxy, p->d_sq, p->d_smu, p->d_mp, st);
@@ -461,6 +463,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, dou
       else
         e = launch_p2p(s.n_tiles, d.c_tgt, d.c_ptr, d.c_idx, p->d_leaf_box, p->d_bptr, p->d_geo, p->d_sxy, p->d_sq,
                        p->d_smu, p->nodes, out, st);
+      roctxRangePop();
       timed_end(p, s.kind, st, ea, eb);
       if (e != hipSuccess) return VOLPOT_ERR_HIP;
       continue;
@@ -489,7 +492,9 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, dou
     g.n_blocks = s.n_blocks;
     hipEvent_t ea, eb;
     timed_begin(p, timing, s.kind, st, &ea, &eb);
+    roctxRangePushA(s.name.c_str());  // a host range per stage, named as in volpot_plan_stage
     hipError_t e = launch_grg(s.M, s.NT, s.KC, g, st);
+    roctxRangePop();
     timed_end(p, s.kind, st, ea, eb);
     if (e != hipSuccess) return VOLPOT_ERR_HIP;
   }
@@ -580,7 +585,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   int rc;
   try {
     rc = build_plan(n_trees, offsets, cref, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr, layer, points, root);
+                    nullptr, layer, points, root, o.tile_leaf_exp);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {

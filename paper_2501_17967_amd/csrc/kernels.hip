@@ -393,6 +393,7 @@ __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__
 // Every (M, NT, KC) instantiation: MT, NTT, WM, WN, KC, threads
 #define VP_CONFIGS(X)                                                                            \
   X(256, 32, 32, 4, 2, 4, 1, 256) X(256, 64, 32, 4, 2, 4, 2, 512) X(256, 16, 16, 4, 1, 4, 1, 256) \
+  X(256, 32, 16, 4, 2, 4, 1, 256) X(256, 64, 16, 4, 2, 4, 2, 512)                                 \
   X(80, 64, 40, 5, 1, 1, 4, 256) X(80, 32, 40, 5, 1, 1, 2, 128) X(80, 16, 40, 5, 1, 1, 1, 64)     \
   X(80, 64, 32, 5, 1, 1, 4, 256) X(80, 32, 32, 5, 1, 1, 2, 128) X(80, 16, 32, 5, 1, 1, 1, 64)
 

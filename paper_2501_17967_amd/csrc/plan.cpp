@@ -522,7 +522,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
                int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer,
-               const PointTargets* points, const RootBox& root) {
+               const PointTargets* points, const RootBox& root, int tile_leaf_exp) {
   if (layer && (n_trees != 1 || layer->n < 0 || (layer->n > 0 && (!layer->xy || !layer->weights || !layer->normals))))
     return VOLPOT_ERR_ARG;
   if (points && (layer || n_trees != 1 || points->n < 0 || (points->n > 0 && !points->xy))) return VOLPOT_ERR_ARG;
@@ -796,9 +796,10 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
   const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 32;
   // The leaf stages with K = 80 (L2T, M2T and their transposes' counterparts S2M^T, S2L^T) do
-  // little work per tile and are bound by the latency of their few dependent k-chunks; 16-slot
-  // tiles give twice as many independent workgroups to hide it.
-  constexpr int kNTK80 = 16;
+  // little work per tile: on small trees 16-slot tiles give more independent workgroups to hide
+  // the latency of their few dependent k-chunks; on large trees and forests wider tiles read
+  // each 256 x 80 table once for more slots.
+  const int kNTK80 = (tile_leaf_exp == 32 || tile_leaf_exp == 64) ? tile_leaf_exp : 16;
   auto quadrant = [&](int32_t b) { return int(P.box_x[b] & 1) + 2 * int(P.box_y[b] & 1); };
   std::vector<std::vector<int32_t>> boxes_at(P.max_level + 1);
   for (int32_t b = 0; b < NB; ++b) boxes_at[P.box_level[b]].push_back(b);

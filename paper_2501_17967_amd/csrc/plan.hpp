@@ -227,6 +227,6 @@ struct RootBox {
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
                const LayerSources* layer = nullptr, const PointTargets* points = nullptr,
-               const RootBox& root = RootBox());
+               const RootBox& root = RootBox(), int tile_leaf_exp = 16);
 
 }  // namespace vp

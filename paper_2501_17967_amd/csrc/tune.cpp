@@ -1,5 +1,5 @@
 // Autotuner of the launch shapes: for one tree or forest, time candidate combinations of
-// leaf-stage tile, expansion-stage tile and split policy on the current device (one forward
+// leaf-stage tiles, expansion-stage tile and split policy on the current device (one forward
 // and one adjoint apply after a warm-up, HIP events on a private stream), one knob at a time
 // (coordinate descent from the defaults: expansion tile, leaf tile, split policy, streams),
 // and report the fastest. Optionally remembers the answer in a text file keyed by a signature of the
@@ -20,8 +20,12 @@
 namespace {
 
 struct Candidate {
-  int32_t tile_leaf, tile_box, split_min, overlap;
+  int32_t tile_leaf, tile_box, split_min, overlap, tile_leaf_exp;
 };
+bool same(const Candidate& a, const Candidate& b) {
+  return a.tile_leaf == b.tile_leaf && a.tile_box == b.tile_box && a.split_min == b.split_min &&
+         a.overlap == b.overlap && a.tile_leaf_exp == b.tile_leaf_exp;
+}
 
 // A candidate replaces the current choice only when it is faster by more than this fraction,
 // and the defaults are kept unless the winner still beats them by as much when both are timed
@@ -39,6 +43,7 @@ uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, i
       h *= 1099511628211ull;
     }
   };
+  mix(2);  // the cache line format: key, tile_leaf, tile_box, split_min, overlap, tile_leaf_exp, ms
   mix(uint64_t(n_trees));
   std::vector<int64_t> hist(32, 0);
   for (int64_t i = 0; i < off[n_trees]; ++i) hist[size_t(std::min(std::max(levels[i], 0), 31))]++;
@@ -63,14 +68,19 @@ bool cache_lookup(const char* path, uint64_t key, volpot_options* best, double* 
   while (std::getline(in, line)) {  // the last entry for a key wins
     std::istringstream ss(line);
     unsigned long long k = 0;
-    int tl = 0, tb = 0, sm = 0, one = 0;
+    int tl = 0, tb = 0, sm = 0, one = 0, te = 0;
     double t = 0;
-    if (!(ss >> std::hex >> k >> std::dec >> tl >> tb >> sm >> one >> t)) continue;
-    if (k != key) continue;
+    std::string rest;
+    if (!(ss >> std::hex >> k >> std::dec >> tl >> tb >> sm >> one >> te >> t) || (ss >> rest)) continue;
+    // a line that does not hold a valid shape is ignored (the shape is then timed again)
+    if (k != key || !(tl == 32 || tl == 64) || !(tb == 16 || tb == 32 || tb == 64) || sm < -1 || one < 0 ||
+        !(te == 16 || te == 32 || te == 64) || !(t > 0.0))
+      continue;
     best->tile_leaf = tl;
     best->tile_box = tb;
     best->split_min = sm;
     best->overlap = one;
+    best->tile_leaf_exp = te;
     *ms = t;
     found = true;
   }
@@ -81,8 +91,8 @@ void cache_store(const char* path, uint64_t key, const volpot_options& o, double
   if (!path) return;
   std::ofstream out(path, std::ios::app);
   char buf[128];
-  std::snprintf(buf, sizeof(buf), "%016llx %d %d %d %d %.6f\n", (unsigned long long)key, o.tile_leaf, o.tile_box,
-                o.split_min, o.overlap, ms);
+  std::snprintf(buf, sizeof(buf), "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, o.tile_leaf, o.tile_box,
+                o.split_min, o.overlap, o.tile_leaf_exp, ms);
   out << buf;
 }
 
@@ -129,6 +139,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     oc.tile_box = c.tile_box;
     oc.split_min = c.split_min;
     oc.overlap = c.overlap;
+    oc.tile_leaf_exp = c.tile_leaf_exp;
     volpot_plan_t plan = nullptr;
     int r = volpot_plan_forest(n_trees, tree_offsets, centres, levels, p, &oc, &plan);
     if (r != VOLPOT_OK) return r;
@@ -148,17 +159,17 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     return r;
   };
   // coordinate descent over the four knobs, one at a time, from the defaults
-  Candidate cur{32, 32, 0, 0};
+  const Candidate def{32, 32, 0, 0, 16};
+  Candidate cur = def;
   double best_t = 1e30;
   auto try_axis = [&](int axis, std::initializer_list<int32_t> values) {
     Candidate keep = cur;
     for (int32_t v : values) {
       if (rc != VOLPOT_OK) return;
       Candidate c = keep;
-      (axis == 0 ? c.tile_box : axis == 1 ? c.tile_leaf : axis == 2 ? c.split_min : c.overlap) = v;
-      if (c.tile_leaf == cur.tile_leaf && c.tile_box == cur.tile_box && c.split_min == cur.split_min &&
-          c.overlap == cur.overlap)
-        continue;  // already timed
+      (axis == 0 ? c.tile_box : axis == 1 ? c.tile_leaf : axis == 2 ? c.split_min : axis == 3 ? c.overlap
+                                                                                          : c.tile_leaf_exp) = v;
+      if (same(c, cur)) continue;  // already timed
       double t = 0;
       rc = time_it(c, &t);
       if (rc == VOLPOT_OK && t < best_t * (1.0 - kMargin)) {
@@ -177,16 +188,17 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
   if (rc == VOLPOT_OK) {
     try_axis(0, {16, 32, 64});
     try_axis(1, {32, 64});
+    try_axis(4, {16, 32, 64});
     try_axis(2, {0, 1, -1});
     try_axis(3, {0, 16, 24, 32, 48});
   }
-  if (rc == VOLPOT_OK && !(cur.tile_leaf == 32 && cur.tile_box == 32 && cur.split_min == 0 && cur.overlap == 0)) {
+  if (rc == VOLPOT_OK && !same(cur, def)) {
     // confirm against the defaults, timed again now, so that a noisy reading cannot win
     double t_best = 0, t_def = 0;
     rc = time_it(cur, &t_best);
-    if (rc == VOLPOT_OK) rc = time_it(Candidate{32, 32, 0, 0}, &t_def);
+    if (rc == VOLPOT_OK) rc = time_it(def, &t_def);
     if (rc == VOLPOT_OK) {
-      if (t_def <= t_best * (1.0 + kMargin)) cur = Candidate{32, 32, 0, 0};
+      if (t_def <= t_best * (1.0 + kMargin)) cur = def;
       best_t = std::min(t_best, t_def);
     }
   }
@@ -195,6 +207,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     best->tile_box = cur.tile_box;
     best->split_min = cur.split_min;
     best->overlap = cur.overlap;
+    best->tile_leaf_exp = cur.tile_leaf_exp;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

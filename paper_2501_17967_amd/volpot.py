@@ -53,15 +53,17 @@ class VolpotError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
                 ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double)]
+                ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double),
+                ("tile_leaf_exp", ctypes.c_int32)]
 
 
 def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0,
-             root_centre=(0.0, 0.0), root_halfwidth=0.0):
+             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0):
     o = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
                 table_cache.encode() if table_cache else None, int(split_min), int(overlap))
     o.root_centre[0], o.root_centre[1] = float(root_centre[0]), float(root_centre[1])
     o.root_halfwidth = float(root_halfwidth)
+    o.tile_leaf_exp = int(tile_leaf_exp)
     return o
 
 
@@ -168,7 +170,8 @@ def _host_tree(centres, levels):
 
 def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
     """Fastest launch shape for this tree or forest on the current device (volpot_autotune):
-    returns ({"tile_leaf", "tile_box", "split_min", "overlap"}, ms per forward + adjoint apply). The result
+    returns ({"tile_leaf", "tile_box", "split_min", "overlap", "tile_leaf_exp"}, ms per forward + adjoint
+    apply). The result
     is looked up in / appended to the text file ``cache`` when given."""
     c, l = _host_tree(centres, levels)
     off = np.ascontiguousarray(np.asarray([0, c.shape[0]] if tree_offsets is None else tree_offsets, dtype=np.int64))
@@ -178,7 +181,7 @@ def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
                                  None, cache.encode() if cache else None, ctypes.byref(best), ctypes.byref(ms)),
            "volpot_autotune")
     return ({"tile_leaf": best.tile_leaf, "tile_box": best.tile_box, "split_min": best.split_min,
-             "overlap": best.overlap}, ms.value)
+             "overlap": best.overlap, "tile_leaf_exp": best.tile_leaf_exp}, ms.value)
 
 
 def build_tree(f, eps, scale, min_level=0, max_level=24, p=16, stream=None):
@@ -296,11 +299,11 @@ class Plan:
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
                  tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0),
-                 root_halfwidth=0.0):
+                 root_halfwidth=0.0, tile_leaf_exp=0):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
-                       root_halfwidth)
+                       root_halfwidth, tile_leaf_exp)
         h = _vp()
         L = lib()
         if tree_offsets is None:
@@ -409,14 +412,14 @@ class PointPlan(Plan):
     Plan's calls work on it."""
 
     def __init__(self, centres, levels, points, p=16, *, host_only=False, use_graph=False, tile_leaf=0, tile_box=0,
-                 table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0), root_halfwidth=0.0):
+                 table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0):
         c, l = _host_tree(centres, levels)
         x = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 2))
         self.n_leaves = c.shape[0]
         self.n_points = x.shape[0]
         self.n_trees = 1
         opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
-                       root_halfwidth)
+                       root_halfwidth, tile_leaf_exp)
         h = _vp()
         _check(lib().volpot_plan_points(c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), self.n_leaves, p, self.n_points,
                                         x.ctypes.data_as(_dp), ctypes.byref(opt), ctypes.byref(h)), "volpot_plan_points")

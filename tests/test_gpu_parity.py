@@ -207,14 +207,18 @@ def test_split_schedules_agree_and_repeat(vp, torch_mod, split_min):
     plan.close()
 
 
-@pytest.mark.parametrize("tile_leaf,tile_box,split_min", [(64, 64, 0), (64, 16, 1)])
-def test_tile_shapes_vs_box_code_oracle(vp, torch_mod, tile_leaf, tile_box, split_min):
-    # 64-slot leaf tiles run the near field in its own instantiation (a k-chunk of 16, four
-    # accumulator columns per wave); every stage against the oracle, and repeat applies bitwise
+@pytest.mark.parametrize("tile_leaf,tile_box,split_min,tile_leaf_exp",
+                         [(64, 64, 0, 64), (64, 16, 1, 32), (32, 32, 0, 64), (32, 32, 1, 32)])
+def test_tile_shapes_vs_box_code_oracle(vp, torch_mod, tile_leaf, tile_box, split_min, tile_leaf_exp):
+    # 64-slot near-field tiles and 32- and 64-slot tiles of the leaf stages that read expansions
+    # run in instantiations of their own; every stage against the oracle, and repeat applies
+    # bitwise
     w = gen.config2(0)
-    _say("case tile_leaf=%d tile_box=%d split_min=%d (%d leaves)" % (tile_leaf, tile_box, split_min, w.n_leaves))
+    _say("case tile_leaf=%d tile_box=%d split_min=%d tile_leaf_exp=%d (%d leaves)"
+         % (tile_leaf, tile_box, split_min, tile_leaf_exp, w.n_leaves))
     r = np.random.default_rng(29).standard_normal(w.f.shape)
-    plan = vp.Plan(w.centres, w.levels, tile_leaf=tile_leaf, tile_box=tile_box, split_min=split_min)
+    plan = vp.Plan(w.centres, w.levels, tile_leaf=tile_leaf, tile_box=tile_box, split_min=split_min,
+                   tile_leaf_exp=tile_leaf_exp)
     f, rd = _gpu(torch_mod, w.f), _gpu(torch_mod, r)
     u, fb = plan.apply(f).cpu().numpy(), plan.apply_adjoint(rd).cpu().numpy()
     u2, fb2 = plan.apply(f).cpu().numpy(), plan.apply_adjoint(rd).cpu().numpy()
@@ -366,12 +370,26 @@ def test_autotune_picks_a_valid_shape_and_caches(vp, torch_mod, tmp_path):
     w = gen.config2(0)
     _say("case autotune config2 seed 0")
     cache = str(tmp_path / "tune.txt")
+    with open(cache, "w") as fh:  # lines that hold no valid shape are ignored, never taken
+        fh.write("garbage\n0123456789abcdef 32 32 0 0 16\n")
     best, ms = vp.autotune(w.centres, w.levels, cache=cache)
     assert best["tile_leaf"] in (32, 64) and best["tile_box"] in (16, 32, 64) and best["split_min"] in (0, 1, -1)
+    assert best["tile_leaf_exp"] in (16, 32, 64)
     assert ms > 0
     again, ms2 = vp.autotune(w.centres, w.levels, cache=cache)  # answered from the cache file
     assert again == best and abs(ms2 - ms) <= 1e-6 * ms
-    assert len(open(cache).read().splitlines()) == 1
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 3
+    # a corrupted entry for this very key (a tile size the library does not have) is not taken:
+    # the shape is timed again and a valid line appended
+    key = lines[-1].split()[0]
+    cache2 = str(tmp_path / "tune2.txt")
+    with open(cache2, "w") as fh:
+        fh.write("%s 48 32 0 0 16 0.5\n%s 32 32 0 0\n" % (key, key))
+    again2, _ = vp.autotune(w.centres, w.levels, cache=cache2)
+    assert again2["tile_leaf"] in (32, 64) and again2["tile_leaf_exp"] in (16, 32, 64)
+    lines2 = open(cache2).read().splitlines()
+    assert len(lines2) == 3 and lines2[-1].split()[0] == key
     ref, _ = _run(vp, torch_mod, w)
     u, _ = _run(vp, torch_mod, w, **best)
     assert rel(u, ref) <= 1e-14
