@@ -1,20 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark of the MI355X machine code: volume-potential unknowns/s, FP64, forward + adjoint.
+"""Benchmark of the MI355X machine code: volume-potential unknowns/s, FP64, forward + adjoint,
+batched versus serial.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline] [--no-batched]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--forest-only]
 
-Workload (one "step" = one forward apply and one adjoint apply, every stage of the box code):
-the adaptive 20-Gaussian source on the size-matched quadtree (background level 7, Chebyshev-
-tail rule eps = 1e-11, 2:1 balanced; 16,837 leaves = 4.31M unknowns for seed 0), p = 16. Inputs
-are resident in HBM before the timed region; plan and table construction are outside it.
+Headline workload (one "step" = one forward apply and one adjoint apply of every stage of the
+box code, each apply one hipGraph replay): a forest of 256 independent adaptive trees, each from
+the 20-Gaussian generator with a Gaussian count uniform in 1..40 (sigma log-U[1e-3, 1e-1],
+centres U[-0.9, 0.9]^2), refined by the Chebyshev-tail rule with eps = 1e-11 from a minimum
+level of 3 and 2:1 balanced (356,506 leaves, 91.3M unknowns for seed 0), p = 16. Inputs are
+resident in HBM before the timed region; plan, table construction and the autotuner's search
+run before it. `value` = unknowns x K / wall time of K steps with nothing else recorded.
 
-The launch shape (tile sizes, split policy, stream overlap) is the autotuner's choice unless
-given on the command line; tuning runs before the timed region. `value` comes from K steps with
-nothing else recorded; the roofline of the dominant kernel (the near-field stage and its
-transpose) from HIP events around its launches in a second pass of K steps.
+Also measured: the same trees applied one after another with single-tree plans (each tree
+takes the fastest, on that tree, of the shapes the autotuner picks for the median tree of each
+size octile), the roofline of the dominant kernel (the near-field stage and its transpose, HIP
+events around its launches in an eager plan of the same shape, K steps after the timed region),
+the CPU oracle on every 8th tree, and the single-tree legs (the star-cut 200-Gaussian tree with
+cut boxes at level 13, 168k leaves; the size-matched 20-Gaussian tree, 17k leaves), the glue
+layer potentials, the off-grid points, the quadtree construction and the strip solve.
 
-Printed: one JSON line with the metric, the roofline, the CPU oracle timed on this host, and the
-batched forest (256 uneven trees, hipGraph replay, autotuned) versus 256 sequential applies.
+Printed: one JSON line.
 """
 import argparse
 import hashlib
@@ -39,20 +45,6 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_2501_17967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def traffic_from_profile(shape):
-    """HBM bytes per launch of the leaf-stage kernel from the committed counter summary, or
-    None when the summary is missing or was taken on other sources or another launch shape."""
-    path = os.path.join(ROOT, "profiles", "leaf_stage_traffic.json")
-    try:
-        with open(path) as fh:
-            d = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if d.get("kernel_hash") != kernel_source_hash() or d.get("launch_shape") != shape:
-        return None
-    return d.get("bytes_per_launch")
 
 
 def _timed(fn, reps):
@@ -289,14 +281,337 @@ def strip_leg(args, dev):
     return res
 
 
+def _kernel_traffic(name, shape, workload):
+    """HBM bytes per launch of the near-field kernel from the committed counter summary, or None
+    when it is missing or was taken on other sources, another launch shape or another workload."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("launch_shape") != shape or d.get("workload") != workload:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def _near_roofline(plan, info, steps, f, ubar, u, fbar, traffic, timed_in):
+    """The dominant kernel (the near-field stage and its transpose, one kernel instantiation):
+    HIP events around its launches only, on the stream they run on, over `steps` forward +
+    adjoint steps; achieved = the plan's algorithmic near-field flops per launch / mean launch
+    time. Returns (roofline dict, wall ms per step of the pass)."""
+    import torch
+
+    plan.set_timing(True, kinds=("near", "adj_near"))
+    plan.stage_times()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(f, out=u)
+        plan.apply_adjoint(ubar, out=fbar)
+    torch.cuda.synchronize()
+    t_pass = time.perf_counter() - t0
+    st = plan.stage_times()
+    plan.set_timing(False)
+    n = st["near"][1] + st["adj_near"][1]
+    per_step = n / steps
+    flops = (info["flops_kind"]["near"] + info["flops_kind"]["adj_near"]) / per_step
+    avg_ms = (st["near"][0] + st["adj_near"][0]) / max(n, 1)
+    achieved = flops / (avg_ms * 1e-3)
+    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
+            "kernel": "grg_kernel, 256-row tiles, k-chunk 32: near-field stage (forward) and its transpose (adjoint)",
+            "flops_per_launch": flops, "avg_launch_ms": avg_ms, "launches": n, "launches_per_step": per_step,
+            "timed_in": timed_in}, 1e3 * t_pass / steps
+
+
+def _stage_breakdown(plan, steps, f, ubar, u, fbar):
+    plan.set_timing(True)
+    plan.stage_times()
+    for _ in range(steps):
+        plan.apply(f, out=u)
+        plan.apply_adjoint(ubar, out=fbar)
+    stb = plan.stage_times()
+    plan.set_timing(False)
+    return {k: v[0] / steps for k, v in stb.items()}
+
+
+def forest_leg(args, dev):
+    """The headline: 256 uneven adaptive trees (1-40 Gaussians each, sigma log-U[1e-3, 1e-1],
+    min level 3, Chebyshev-tail rule eps 1e-11, 2:1 balanced) applied together, forward + adjoint
+    per step, each apply one hipGraph replay, autotuned launch shape; against the same trees
+    applied one after another with single-tree plans."""
+    import numpy as np
+    import torch
+
+    from paper_2501_17967_amd import Plan, autotune
+    from workloads import gen
+
+    t0 = time.perf_counter()
+    trees = gen.config4(args.seed, n_trees=args.batched_trees)
+    t_gen = time.perf_counter() - t0
+    off = np.cumsum([0] + [t.n_leaves for t in trees])
+    Nb = int(off[-1]) * 256
+    C = np.vstack([t.centres for t in trees])
+    Lv = np.concatenate([t.levels for t in trees])
+    sizes = np.array([t.n_leaves for t in trees])
+    print("bench: forest of %d trees, %d leaves (%d..%d per tree), gen %.1fs"
+          % (len(trees), off[-1], sizes.min(), sizes.max(), t_gen), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    if args.tile_leaf and args.tile_box and args.split_min is not None and args.overlap is not None:
+        shape = {"tile_leaf": args.tile_leaf, "tile_box": args.tile_box, "split_min": args.split_min,
+                 "overlap": args.overlap, "tile_leaf_exp": args.tile_leaf_exp or 16}
+    else:
+        shape, _ = autotune(C, Lv, tree_offsets=off)
+    t_tune = time.perf_counter() - t0
+    print("bench: forest launch shape %s (autotuner %.1fs)" % (shape, t_tune), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    forest = Plan(C, Lv, tree_offsets=off, use_graph=True, **shape)
+    t_plan = time.perf_counter() - t0
+    info = forest.info()
+    F = torch.from_numpy(np.vstack([t.f for t in trees])).to(dev)
+    Rb = torch.from_numpy(np.random.default_rng(args.seed + 1).standard_normal(F.shape)).to(dev)
+    U = torch.empty_like(F)
+    FB = torch.empty_like(F)
+    for _ in range(args.warmup):
+        forest.apply(F, out=U)
+        forest.apply_adjoint(Rb, out=FB)
+    # timed region: K steps of forward + adjoint (graph replays), nothing else recorded
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        forest.apply(F, out=U)
+        forest.apply_adjoint(Rb, out=FB)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    tb_f = _timed(lambda: forest.apply(F, out=U), args.steps)
+    tb_a = _timed(lambda: forest.apply_adjoint(Rb, out=FB), args.steps)
+    forest.apply(F, out=U)
+    forest.apply_adjoint(Rb, out=FB)
+    torch.cuda.synchronize()
+    # roofline: the same launches from an eager plan of the same shape (events cannot sit inside
+    # the captured graphs), K more steps right after the timed region
+    twin = Plan(C, Lv, tree_offsets=off, **shape)
+    U2, FB2 = torch.empty_like(F), torch.empty_like(F)
+    twin.apply(F, out=U2)
+    twin.apply_adjoint(Rb, out=FB2)
+    traffic = _kernel_traffic("forest_near_traffic.json", shape, "config4-forest-256")
+    roof, pass_ms = _near_roofline(twin, info, args.steps, F, Rb, U2, FB2, traffic,
+                                   "an eager plan of the same shape, K steps right after the timed region")
+    stage_ms = _stage_breakdown(twin, max(3, args.steps // 4), F, Rb, U2, FB2)
+    twin_same = bool(torch.equal(U2, U) and torch.equal(FB2, FB))
+    twin.close()
+    ms_step = 1e3 * t_total / args.steps
+    res = {"value": Nb * args.steps / t_total, "ms_per_step": ms_step,
+           "config": {"workload": "forest of %d adaptive trees: 1-40 Gaussians each (sigma log-U[1e-3, 1e-1], "
+                                  "centres U[-0.9, 0.9]^2), Chebyshev-tail rule eps 1e-11, min level 3, 2:1 "
+                                  "balanced, seed %d" % (len(trees), args.seed),
+                      "n_trees": len(trees), "n_leaves": int(off[-1]), "unknowns": Nb,
+                      "leaves_min": int(sizes.min()), "leaves_max": int(sizes.max()), "max_level": int(info["max_level"]),
+                      "p": 16, "expansion_order": int(info["order"]), "step": "forward + adjoint, one hipGraph replay each",
+                      "launch_shape": shape, "autotune_s": t_tune, "plan_s": t_plan, "gen_s": t_gen},
+           "roofline": roof,
+           "fwd_unknowns_per_s": Nb / tb_f, "adj_unknowns_per_s": Nb / tb_a,
+           "whole_path_tflops": (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps) / 1e12,
+           "stage_ms_per_step": stage_ms, "roofline_pass_ms_per_step": pass_ms,
+           "eager_twin_bitwise_equal": twin_same}
+
+    if args.no_sequential:
+        forest.close()
+        return res
+    # sequential: one single-tree plan per tree, each with the fastest of the shapes the
+    # autotuner picks for the median tree of each size octile (timed per tree)
+    print("bench: sequential single-tree applies", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    order = np.argsort(sizes, kind="stable")
+    cands = [{"tile_leaf": 32, "tile_box": 32, "split_min": 0, "overlap": 0, "tile_leaf_exp": 16}]
+    for part in np.array_split(order, 8):
+        med = trees[int(part[len(part) // 2])]
+        sh, _ = autotune(med.centres, med.levels)
+        if sh not in cands:
+            cands.append(sh)
+    views = [F[off[i]:off[i + 1]] for i in range(len(trees))]
+    rviews = [Rb[off[i]:off[i + 1]] for i in range(len(trees))]
+    outs = [torch.empty_like(v) for v in views]
+    outa = [torch.empty_like(v) for v in views]
+    singles, chosen = [], []
+    for i, t in enumerate(trees):
+        best = None
+        for sh in cands:
+            p_ = Plan(t.centres, t.levels, **sh)
+            p_.apply(views[i], out=outs[i])
+            p_.apply_adjoint(rviews[i], out=outa[i])
+            ts = min(_timed(lambda: (p_.apply(views[i], out=outs[i]), p_.apply_adjoint(rviews[i], out=outa[i])), 2)
+                     for _ in range(2))
+            if best is None or ts < best[0]:
+                if best is not None:
+                    best[1].close()
+                best = (ts, p_, sh)
+            else:
+                p_.close()
+        singles.append(best[1])
+        chosen.append(cands.index(best[2]))
+    t_seq_tune = time.perf_counter() - t0
+
+    def seq_fwd():
+        for p_, x, o in zip(singles, views, outs):
+            p_.apply(x, out=o)
+
+    def seq_adj():
+        for p_, x, o in zip(singles, rviews, outa):
+            p_.apply_adjoint(x, out=o)
+
+    seq_fwd()
+    seq_adj()
+    ts_f = _timed(seq_fwd, 3)
+    ts_a = _timed(seq_adj, 3)
+    dev_f = max(float((outs[i] - U[off[i]:off[i + 1]]).abs().max() / U[off[i]:off[i + 1]].abs().max())
+                for i in range(len(trees)))
+    dev_a = max(float((outa[i] - FB[off[i]:off[i + 1]]).abs().max() / FB[off[i]:off[i + 1]].abs().max())
+                for i in range(len(trees)))
+    for p_ in singles:
+        p_.close()
+    res["batched"] = {"batched_fwd_adj_unknowns_per_s": Nb / (tb_f + tb_a),
+                      "sequential_fwd_adj_unknowns_per_s": Nb / (ts_f + ts_a),
+                      "speedup_fwd_adj": (ts_f + ts_a) / (tb_f + tb_a),
+                      "sequential_fwd_unknowns_per_s": Nb / ts_f, "sequential_adj_unknowns_per_s": Nb / ts_a,
+                      "sequential_shapes": cands, "sequential_shape_counts": [chosen.count(k) for k in range(len(cands))],
+                      "sequential_setup_s": t_seq_tune,
+                      "max_rel_diff_batched_vs_sequential": {"forward": dev_f, "adjoint": dev_a}}
+
+    if not args.no_cpu_baseline:
+        from oracle import fmm, tree
+
+        print("bench: cpu baseline (oracle box code on every 8th tree)", file=sys.stderr, flush=True)
+        sample = list(range(0, len(trees), 8))
+        ub = Rb.cpu().numpy()
+        ug, fg = U.cpu().numpy(), FB.cpu().numpy()
+        t_cpu, n_cpu, ef, ea = 0.0, 0, 0.0, 0.0
+        for i in sample:
+            t = trees[i]
+            bc = fmm.BoxCode(tree.Tree(t.centres, t.levels))
+            a = time.perf_counter()
+            u_o = bc.apply(t.f)
+            fb_o = bc.apply_adjoint(ub[off[i]:off[i + 1]])
+            t_cpu += time.perf_counter() - a
+            n_cpu += t.n_leaves * 256
+            ef = max(ef, float(np.max(np.abs(ug[off[i]:off[i + 1]] - u_o)) / np.max(np.abs(u_o))))
+            ea = max(ea, float(np.max(np.abs(fg[off[i]:off[i + 1]] - fb_o)) / np.max(np.abs(fb_o))))
+        res["cpu_baseline"] = {"value": n_cpu / t_cpu, "unit": "unknowns/s", "cores": _oracle_cores(), "kind": "oracle",
+                               "sample": "trees 0, 8, ..., %d of the forest (%d trees, %d unknowns), one forward + one "
+                                         "adjoint apply of the oracle box code (NumPy, order 50) each, in sequence: "
+                                         "%.1f s" % (sample[-1], len(sample), n_cpu, t_cpu)}
+        res["rel_err_vs_oracle"] = {"forward": ef, "adjoint": ea, "trees": len(sample)}
+    forest.close()
+    return res
+
+
+def single_tree_leg(args, dev, w, label, cpu="full"):
+    """One tree, forward + adjoint per step, eager applies, autotuned shape (overlap included);
+    roofline of the near field from events in a second pass; the oracle on the same workload."""
+    import numpy as np
+    import torch
+
+    from paper_2501_17967_amd import Plan, autotune
+
+    t0 = time.perf_counter()
+    shape, _ = autotune(w.centres, w.levels)
+    t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = Plan(w.centres, w.levels, **shape)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info()
+    N = w.unknowns
+    print("bench: %s, %d leaves, shape %s (autotuner %.1fs, plan %.2fs)" % (w.name, w.n_leaves, shape, t_tune, t_plan),
+          file=sys.stderr, flush=True)
+    f = torch.from_numpy(w.f).to(dev)
+    ubar = torch.from_numpy(np.random.default_rng(args.seed + 1).standard_normal(w.f.shape)).to(dev)
+    u, fbar = torch.empty_like(f), torch.empty_like(f)
+    for _ in range(args.warmup):
+        plan.apply(f, out=u)
+        plan.apply_adjoint(ubar, out=fbar)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(f, out=u)
+        plan.apply_adjoint(ubar, out=fbar)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    traffic = _kernel_traffic("%s_near_traffic.json" % label, shape, label)
+    roof, pass_ms = _near_roofline(plan, info, args.steps, f, ubar, u, fbar, traffic,
+                                   "a second pass of the same steps, right after the timed region")
+    stage_ms = _stage_breakdown(plan, args.steps, f, ubar, u, fbar)
+    t_fwd = _timed(lambda: plan.apply(f, out=u), args.steps)
+    t_adj = _timed(lambda: plan.apply_adjoint(ubar, out=fbar), args.steps)
+    plan.apply(f, out=u)
+    plan.apply_adjoint(ubar, out=fbar)
+    torch.cuda.synchronize()
+    lv = np.bincount(w.levels)
+    res = {"workload": w.name, "n_leaves": int(w.n_leaves), "unknowns": int(N), "max_level": int(info["max_level"]),
+           "leaves_per_level": {int(l): int(c) for l, c in enumerate(lv) if c},
+           "launch_shape": shape, "autotune_s": t_tune, "plan_s": t_plan,
+           "fwd_adj_unknowns_per_s": N * args.steps / t_total, "ms_per_step": 1e3 * t_total / args.steps,
+           "fwd_unknowns_per_s": N / t_fwd, "adj_unknowns_per_s": N / t_adj,
+           "roofline": roof, "roofline_pass_ms_per_step": pass_ms,
+           "whole_path_tflops": (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps) / 1e12,
+           "stage_ms_per_step": stage_ms}
+    if not args.no_cpu_baseline and cpu == "direct":
+        # the oracle box code needs minutes on a tree this size; its plain direct sum (adaptive
+        # quadrature over every leaf) at a bounded sample of nodes serves as the baseline and as
+        # the full-size check of the benchmark's own output
+        from oracle import quad, tree
+
+        print("bench: cpu baseline for %s (direct sum at sampled nodes)" % w.name, file=sys.stderr, flush=True)
+        rng = np.random.default_rng(args.seed + 13)
+        samples = [(int(a), int(m)) for a, m in zip(rng.integers(0, w.n_leaves, 48), rng.integers(0, 256, 48))]
+        T = tree.Tree(w.centres, w.levels)
+        a = time.perf_counter()
+        ud = quad.direct_potential(T, w.f, samples)
+        t_cpu = time.perf_counter() - a
+        ug = u.cpu().numpy().reshape(w.n_leaves, 256)
+        got = np.array([ug[i, m] for i, m in samples])
+        res["cpu_baseline"] = {"value": len(samples) / t_cpu, "unit": "unknowns/s (forward)", "cores": _oracle_cores(),
+                               "kind": "oracle",
+                               "sample": "the oracle's plain direct sum (adaptive quadrature of every leaf) at %d random "
+                                         "leaf nodes of the full tree: %.1f s" % (len(samples), t_cpu)}
+        res["rel_err_vs_oracle"] = {"forward_sampled": float(np.max(np.abs(got - ud)) / np.max(np.abs(ug)))}
+    elif not args.no_cpu_baseline and cpu:
+        from oracle import fmm, tree
+
+        print("bench: cpu baseline for %s" % w.name, file=sys.stderr, flush=True)
+        bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+        ub = ubar.cpu().numpy()
+        runs = []
+        for _ in range(3 if cpu == "median3" else 1):
+            a = time.perf_counter()
+            u_o = bc.apply(w.f)
+            fb_o = bc.apply_adjoint(ub)
+            runs.append(time.perf_counter() - a)
+        t_cpu = sorted(runs)[len(runs) // 2]
+        res["cpu_baseline"] = {"value": N / t_cpu, "unit": "unknowns/s", "cores": _oracle_cores(), "kind": "oracle",
+                               "sample": "the full workload, one forward + one adjoint apply of the oracle box code "
+                                         "(NumPy, order 50)%s: %.1f s" % (", median of 3 runs" if len(runs) == 3 else "", t_cpu)}
+        ug, fg = u.cpu().numpy(), fbar.cpu().numpy()
+        res["rel_err_vs_oracle"] = {"forward": float(np.max(np.abs(ug - u_o)) / np.max(np.abs(u_o))),
+                                    "adjoint": float(np.max(np.abs(fg - fb_o)) / np.max(np.abs(fb_o)))}
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--forest-only", action="store_true",
+                    help="run only the headline forest leg and print its line (for profiling)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the sequential single-tree applies and the CPU baseline of the forest (for profiling)")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-tree legs (config 3-SM and 2-SM)")
+    ap.add_argument("--single-only", default="", help="run only this single-tree leg (3sm or 2sm) and print it")
     ap.add_argument("--no-layer", action="store_true", help="skip the layer-potential evaluation leg")
     ap.add_argument("--layer-only", action="store_true",
                     help="run only the layer-potential leg and print its object (for profiling)")
@@ -310,10 +625,11 @@ def main():
     ap.add_argument("--strip-only", action="store_true",
                     help="run only the strip-solve leg and print its object (for profiling)")
     ap.add_argument("--batched-trees", type=int, default=256)
-    ap.add_argument("--tile-leaf", type=int, default=0, help="0: chosen by the autotuner")
-    ap.add_argument("--tile-box", type=int, default=0, help="0: chosen by the autotuner")
-    ap.add_argument("--split-min", type=int, default=None, help="default: chosen by the autotuner")
-    ap.add_argument("--overlap", type=int, default=None, help="default: chosen by the autotuner")
+    ap.add_argument("--tile-leaf", type=int, default=0, help="forest shape (all four given: no autotuning)")
+    ap.add_argument("--tile-box", type=int, default=0)
+    ap.add_argument("--split-min", type=int, default=None)
+    ap.add_argument("--overlap", type=int, default=None)
+    ap.add_argument("--tile-leaf-exp", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -322,253 +638,68 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
+    dev = torch.device("cuda:0")
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        a = torch.ones(n, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.calibrate_copy_mib, "copies": 5}))
         return
-
     if args.layer_only:
-        print(json.dumps({"layer_potential": layer_leg(args, torch.device("cuda:0"))}), flush=True)
+        print(json.dumps({"layer_potential": layer_leg(args, dev)}), flush=True)
         return
     if args.strip_only:
-        print(json.dumps({"strip": strip_leg(args, torch.device("cuda:0"))}), flush=True)
+        print(json.dumps({"strip": strip_leg(args, dev)}), flush=True)
         return
     if args.points_only:
-        print(json.dumps({"points": points_leg(args, torch.device("cuda:0"))}), flush=True)
+        print(json.dumps({"points": points_leg(args, dev)}), flush=True)
         return
     if args.tree_only:
-        print(json.dumps({"tree": tree_leg(args, torch.device("cuda:0"))}), flush=True)
+        print(json.dumps({"tree": tree_leg(args, dev)}), flush=True)
         return
 
-    from paper_2501_17967_amd import Plan, autotune
     from workloads import gen
 
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    w = gen.config2(args.seed, size_matched=True)
-    t_gen = time.perf_counter() - t0
-    # launch shape: the autotuner's choice unless fixed on the command line (outside the timed region)
-    t0 = time.perf_counter()
-    if args.tile_leaf and args.tile_box and args.split_min is not None and args.overlap is not None:
-        shape = {}
-    else:
-        shape, _ = autotune(w.centres, w.levels)
-    t_tune = time.perf_counter() - t0
-    if args.tile_leaf:
-        shape["tile_leaf"] = args.tile_leaf
-    if args.tile_box:
-        shape["tile_box"] = args.tile_box
-    if args.split_min is not None:
-        shape["split_min"] = args.split_min
-    if args.overlap is not None:
-        shape["overlap"] = args.overlap
-    print("bench: launch shape %s (autotuner %.1fs)" % (shape, t_tune), file=sys.stderr, flush=True)
-    plan_shape = {"tile_leaf": 32, "tile_box": 32, "split_min": 0, "overlap": 0}
-    plan_shape.update(shape)
-    t0 = time.perf_counter()
-    plan = Plan(w.centres, w.levels, **plan_shape)
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
-    info = plan.info()
-    N = w.unknowns
-    print("bench: %s, %d leaves, %d unknowns, max level %d; gen %.1fs plan %.2fs"
-          % (w.name, w.n_leaves, N, info["max_level"], t_gen, t_plan), file=sys.stderr, flush=True)
+    singles = {"3sm": lambda: (gen.config3(args.seed, lcut=13), "config3-sm", "direct"),
+               "2sm": lambda: (gen.config2(args.seed, size_matched=True), "config2-sm", "median3")}
+    if args.single_only:
+        w, label, cpu = singles[args.single_only]()
+        print(json.dumps({label: single_tree_leg(args, dev, w, label, cpu)}), flush=True)
+        return
 
-    f = torch.from_numpy(w.f).to(dev)
-    rng = np.random.default_rng(args.seed + 1)
-    ubar = torch.from_numpy(rng.standard_normal(w.f.shape)).to(dev)
-    u = torch.empty_like(f)
-    fbar = torch.empty_like(f)
-    for _ in range(args.warmup):
-        plan.apply(f, out=u)
-        plan.apply_adjoint(ubar, out=fbar)
-    torch.cuda.synchronize()
-
-    # timed region: K steps of forward + adjoint, nothing else recorded (with the overlap
-    # option, event records between launches on the caller's stream delay the concurrent
-    # far-field chain: about 15% of the step)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.apply(f, out=u)
-        plan.apply_adjoint(ubar, out=fbar)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t0
-    ms_step = 1e3 * t_total / args.steps
-    value = N * args.steps / t_total
-
-    # roofline pass: the same K steps again, HIP events around the launches of the dominant
-    # kernel only (the near-field stage and its transpose), on the stream they run on
-    plan.set_timing(True, kinds=("near", "adj_near"))
-    plan.stage_times()  # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.apply(f, out=u)
-        plan.apply_adjoint(ubar, out=fbar)
-    torch.cuda.synchronize()
-    t_events = time.perf_counter() - t0
-    st = plan.stage_times()
-    plan.set_timing(False)
-
-    # forward-only and adjoint-only throughput (no timing events)
-    def timed(fn, reps):
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - a) / reps
-
-    t_fwd = timed(lambda: plan.apply(f, out=u), args.steps)
-    t_adj = timed(lambda: plan.apply_adjoint(ubar, out=fbar), args.steps)
-
-    # roofline of the dominant kernel: the near-field stage (forward) and its transpose
-    # (adjoint) -- the same kernel instantiation, one launch each per step
-    # (with the overlap option the near field of each apply runs as two launches)
-    leaf_ms = st["near"][0] + st["adj_near"][0]
-    leaf_n = st["near"][1] + st["adj_near"][1]
-    launches_per_step = leaf_n / args.steps
-    flops_per_launch = (info["flops_kind"]["near"] + info["flops_kind"]["adj_near"]) / launches_per_step
-    avg_ms = leaf_ms / max(leaf_n, 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3)
-    traffic = traffic_from_profile(plan_shape)
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
-                "kernel": "grg_kernel, 256-row tiles: near-field stage (forward) and its transpose (adjoint)",
-                "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms, "launches": leaf_n,
-                "launches_per_step": launches_per_step,
-                "timed_in": "a second pass of the same steps, right after the timed region",
-                "pass_ms_per_step": 1e3 * t_events / args.steps}
-    # per-stage breakdown: a separate pass with every launch timed (events perturb the overlap)
-    plan.set_timing(True)
-    plan.stage_times()
-    for _ in range(args.steps):
-        plan.apply(f, out=u)
-        plan.apply_adjoint(ubar, out=fbar)
-    stb = plan.stage_times()
-    plan.set_timing(False)
-    stage_ms = {k: v[0] / args.steps for k, v in stb.items()}
-    whole = (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps)
-
+    fr = forest_leg(args, dev)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": fr.pop("value"),
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": fr.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name + " (adaptive 20-Gaussian source, size-matched quadtree, seed %d)" % args.seed,
-                   "n_leaves": int(w.n_leaves), "unknowns": int(N), "max_level": int(info["max_level"]), "p": 16,
-                   "expansion_order": int(info["order"]), "step": "forward + adjoint",
-                   "launch_shape": plan_shape, "autotune_s": t_tune},
-        "roofline": roofline,
-        "fwd_unknowns_per_s": N / t_fwd,
-        "adj_unknowns_per_s": N / t_adj,
-        "whole_path_tflops": whole / 1e12,
-        "stage_ms_per_step": stage_ms,
-        "plan_s": t_plan,
+        "config": fr.pop("config"),
+        "roofline": fr.pop("roofline"),
     }
-
-    if not args.no_cpu_baseline:
-        from oracle import fmm, tree
-
-        print("bench: cpu baseline (oracle box code on the same workload)", file=sys.stderr, flush=True)
-        try:
-            from threadpoolctl import threadpool_info
-
-            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        except Exception:
-            cores = len(os.sched_getaffinity(0))
-        bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
-        ub = ubar.cpu().numpy()
-        t_runs = []
-        for _ in range(3):
-            a = time.perf_counter()
-            u_o = bc.apply(w.f)
-            fb_o = bc.apply_adjoint(ub)
-            t_runs.append(time.perf_counter() - a)
-        t_cpu = sorted(t_runs)[1]
-        u_g = u.cpu().numpy()
-        fb_g = fbar.cpu().numpy()
-        out["cpu_baseline"] = {"value": N / t_cpu, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
-                               "sample": "the full workload, one forward + one adjoint apply of the oracle box "
-                                         "code (NumPy, order 50), median of 3 runs: %.2f s each" % t_cpu}
-        out["rel_err_vs_oracle"] = {
-            "forward": float(np.max(np.abs(u_g - u_o)) / np.max(np.abs(u_o))),
-            "adjoint": float(np.max(np.abs(fb_g - fb_o)) / np.max(np.abs(fb_o)))}
-
-    if not args.no_batched:
-        print("bench: batched forest of %d trees" % args.batched_trees, file=sys.stderr, flush=True)
-        trees = gen.config4(0, n_trees=args.batched_trees)
-        off = np.cumsum([0] + [t.n_leaves for t in trees])
-        Nb = int(off[-1]) * 256
-        C = np.vstack([t.centres for t in trees])
-        Lv = np.concatenate([t.levels for t in trees])
-        t0 = time.perf_counter()
-        fshape, _ = autotune(C, Lv, tree_offsets=off)
-        t_ftune = time.perf_counter() - t0
-        print("bench: forest launch shape %s (autotuner %.1fs)" % (fshape, t_ftune), file=sys.stderr, flush=True)
-        forest = Plan(C, Lv, tree_offsets=off, use_graph=True, **fshape)
-        F = torch.from_numpy(np.vstack([t.f for t in trees])).to(dev)
-        Ub = torch.empty_like(F)
-        Fb = torch.empty_like(F)
-        for _ in range(2):
-            forest.apply(F, out=Ub)
-            forest.apply_adjoint(F, out=Fb)
-        reps = max(3, args.steps // 2)
-        tb_f = timed(lambda: forest.apply(F, out=Ub), reps)
-        tb_a = timed(lambda: forest.apply_adjoint(F, out=Fb), reps)
-        # sequential applies: one plan per tree, each with the shape the autotuner picks for
-        # the median-size tree (tuning all 256 separately would take minutes)
-        med = trees[int(np.argsort([t.n_leaves for t in trees])[len(trees) // 2])]
-        sshape, _ = autotune(med.centres, med.levels)
-        singles = [Plan(t.centres, t.levels, **sshape) for t in trees]
-        views = [F[off[i]:off[i + 1]] for i in range(len(trees))]
-        outs = [Ub[off[i]:off[i + 1]].clone() for i in range(len(trees))]
-        outa = [o.clone() for o in outs]
-
-        def seq_fwd():
-            for p_, x, o in zip(singles, views, outs):
-                p_.apply(x, out=o)
-
-        def seq_adj():
-            for p_, x, o in zip(singles, views, outa):
-                p_.apply_adjoint(x, out=o)
-
-        seq_fwd(); seq_adj()
-        ts_f = timed(seq_fwd, 2)
-        ts_a = timed(seq_adj, 2)
-        dev_max = max(float((outs[i] - Ub[off[i]:off[i + 1]]).abs().max() / Ub[off[i]:off[i + 1]].abs().max())
-                      for i in range(len(trees)))
-        out["batched"] = {"workload": "forest of %d adaptive trees, 1-40 Gaussians each, min level 3" % len(trees),
-                          "n_leaves": int(off[-1]), "unknowns": Nb,
-                          "leaves_min": int(min(t.n_leaves for t in trees)),
-                          "leaves_max": int(max(t.n_leaves for t in trees)),
-                          "batched_fwd_unknowns_per_s": Nb / tb_f, "batched_adj_unknowns_per_s": Nb / tb_a,
-                          "batched_fwd_adj_unknowns_per_s": Nb / (tb_f + tb_a),
-                          "sequential_fwd_adj_unknowns_per_s": Nb / (ts_f + ts_a),
-                          "speedup_fwd_adj": (ts_f + ts_a) / (tb_f + tb_a),
-                          "launch_shape": fshape, "autotune_s": t_ftune, "sequential_launch_shape": sshape,
-                          "max_rel_diff_batched_vs_sequential": dev_max}
-        for p_ in singles:
-            p_.close()
-        forest.close()
-
+    if "cpu_baseline" in fr:
+        out["cpu_baseline"] = fr.pop("cpu_baseline")
+    out.update(fr)
+    if args.forest_only:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_single:
+        for key in ("3sm", "2sm"):
+            w, label, cpu = singles[key]()
+            out[label.replace("-", "_")] = single_tree_leg(args, dev, w, label, cpu)
+            del w
     if not args.no_layer:
         out["layer_potential"] = layer_leg(args, dev)
     if not args.no_points:
@@ -577,8 +708,6 @@ def main():
         out["tree"] = tree_leg(args, dev)
     if not args.no_strip:
         out["strip"] = strip_leg(args, dev)
-
-    plan.close()
     print(json.dumps(out), flush=True)
 
 
