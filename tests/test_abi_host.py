@@ -361,3 +361,44 @@ def test_root_box_option_maps_the_tree(vp):
         with pytest.raises(vp.VolpotError) as e:
             vp.Plan(w.centres, w.levels, host_only=True, root_halfwidth=bad)
         assert e.value.code == vp.ERR_ARG
+
+
+_TABLE_SCRIPT = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[3])
+from paper_2501_17967_amd import volpot as vp
+from workloads import gen
+w = gen.config1(0)
+p = vp.Plan(w.centres, w.levels, host_only=True, table_cache=sys.argv[1])
+np.save(sys.argv[2], np.stack([p.table(0, r) for r in (0, 5, 20, 32)]))
+"""
+
+
+def test_corrupt_table_cache_is_rejected_and_rewritten(tmp_path):
+    # the near tables are cached on disk with a magic, a shape header and a hash of the data; a
+    # cache whose data or length do not match is not used: the tables are computed again (in a
+    # fresh process, since a process computes them once) and the file rewritten
+    import subprocess
+    import sys
+
+    cache = tmp_path / "cache"
+    cache.mkdir()
+
+    def run(tag):
+        out = tmp_path / ("t_%s.npy" % tag)
+        subprocess.run([sys.executable, "-c", _TABLE_SCRIPT, str(cache), str(out), ROOT], check=True, timeout=300)
+        return np.load(out)
+
+    ref = run("first")
+    (f,) = list(cache.iterdir())
+    good = f.read_bytes()
+    assert good[:8] == b"VPNEAR01"
+    bad = bytearray(good)
+    bad[len(bad) // 2] ^= 0x40  # one flipped bit in the data
+    f.write_bytes(bytes(bad))
+    assert np.array_equal(run("flipped"), ref)
+    assert f.read_bytes() == good
+    f.write_bytes(good[: len(good) // 3])  # truncated
+    assert np.array_equal(run("truncated"), ref)
+    assert f.read_bytes() == good
