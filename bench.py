@@ -360,11 +360,14 @@ def forest_leg(args, dev):
     t0 = time.perf_counter()
     if args.tile_leaf and args.tile_box and args.split_min is not None and args.overlap is not None:
         shape = {"tile_leaf": args.tile_leaf, "tile_box": args.tile_box, "split_min": args.split_min,
-                 "overlap": args.overlap, "tile_leaf_exp": args.tile_leaf_exp or 16}
+                 "overlap": args.overlap, "tile_leaf_exp": args.tile_leaf_exp or 16,
+                 "kchunk_leaf": args.kchunk_leaf or 32}
     else:
         shape, _ = autotune(C, Lv, tree_offsets=off)
     t_tune = time.perf_counter() - t0
     print("bench: forest launch shape %s (autotuner %.1fs)" % (shape, t_tune), file=sys.stderr, flush=True)
+    if args.eps:
+        shape = dict(shape, eps=args.eps)
     t0 = time.perf_counter()
     forest = Plan(C, Lv, tree_offsets=off, use_graph=True, **shape)
     t_plan = time.perf_counter() - t0
@@ -424,7 +427,7 @@ def forest_leg(args, dev):
     print("bench: sequential single-tree applies", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     order = np.argsort(sizes, kind="stable")
-    cands = [{"tile_leaf": 32, "tile_box": 32, "split_min": 0, "overlap": 0, "tile_leaf_exp": 16}]
+    cands = [{"tile_leaf": 32, "tile_box": 32, "split_min": 0, "overlap": 0, "tile_leaf_exp": 16, "kchunk_leaf": 32}]
     for part in np.array_split(order, 8):
         med = trees[int(part[len(part) // 2])]
         sh, _ = autotune(med.centres, med.levels)
@@ -630,6 +633,9 @@ def main():
     ap.add_argument("--split-min", type=int, default=None)
     ap.add_argument("--overlap", type=int, default=None)
     ap.add_argument("--tile-leaf-exp", type=int, default=0)
+    ap.add_argument("--kchunk-leaf", type=int, default=0)
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="far-field tolerance of the forest plans (0: the library's default, order 39)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()

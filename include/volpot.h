@@ -88,13 +88,24 @@ typedef struct {
   int32_t tile_leaf_exp;   /* slots per tile of the leaf stages whose sources are expansions
                               (L2T + M2T, and S2M^T + S2L^T in the adjoint; K = 80): 16, 32 or
                               64; 0 = default (16) */
+  double eps;              /* far-field tolerance (Sec. 4.2.1: the user gives p and epsilon):
+                              a bound on the relative max-norm error of u from truncating the
+                              expansions. It selects the expansion order P, the smallest of 15,
+                              23, 31, 39 whose bound is below eps (bounds 3e-7, 3e-10, 1e-12,
+                              1e-13: about ten times the largest error measured against the CPU
+                              oracle at that order). 0 = default 1e-13 (P = 39).
+                              VOLPOT_ERR_UNSUPPORTED below 1e-13, and for layer-potential and
+                              point plans at any P other than 39. */
+  int32_t kchunk_leaf;     /* k-chunk of the near-field stages: 32 (default; 0) or 16 (shorter
+                              chunks, less LDS and fewer registers: three blocks per compute
+                              unit instead of two) */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
  * non-zeros of every applied real matrix (zero padding of MFMA tiles not counted). */
 typedef struct {
   int64_t n_leaves, n_boxes, n_trees;
-  int32_t max_level, order, n_reals, n_stages;
+  int32_t max_level, order, n_reals, n_stages;  /* order: the expansion order P; n_reals = 2 (P + 1) */
   int64_t pairs_near, pairs_v, pairs_w, pairs_x, n_m2m, n_l2l, n_s2m, n_l2t;
   double flops_total;       /* forward apply */
   double flops_adjoint;     /* adjoint apply (the same pairs, transposed) */
@@ -299,8 +310,8 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
 
 /* Autotuner (for callers that apply one tree shape many times, e.g. batched forests): searches
- * the launch shapes tile_box 16|32|64, tile_leaf 32|64, tile_leaf_exp 16|32|64, split_min 0|1|-1
- * and overlap 0|16|24|32|48
+ * the launch shapes tile_box 16|32|64, tile_leaf 32|64, kchunk_leaf 32|16, tile_leaf_exp 16|32|64,
+ * split_min 0|1|-1 and overlap 0|16|24|32|48
  * one knob at a time from the defaults (the other fields are taken from base, nullable),
  * building a plan for each candidate and timing one forward plus one adjoint apply on internal
  * device buffers after a warm-up (HIP events, private stream, best of 5); writes the fastest

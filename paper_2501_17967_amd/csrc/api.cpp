@@ -23,7 +23,7 @@ namespace {
 
 // ---------------------------------------------------------------- shared device tables
 struct DeviceTables {
-  int device = -1;
+  int device = -1, q = kTerms;  // device and expansion terms
   double* buf = nullptr;
   RelDesc* d_rels = nullptr;
   std::vector<RelDesc> rels;  // host copy (device pointers)
@@ -31,17 +31,17 @@ struct DeviceTables {
   int refs = 0;
 };
 std::mutex g_mu;
-std::map<int, DeviceTables*> g_tables;
+std::map<std::pair<int, int>, DeviceTables*> g_tables;  // per (device, expansion terms)
 
-int acquire_tables(int device, DeviceTables** out) {
+int acquire_tables(int device, int q, DeviceTables** out) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_tables.find(device);
+  auto it = g_tables.find({device, q});
   if (it != g_tables.end()) {
     it->second->refs++;
     *out = it->second;
     return VOLPOT_OK;
   }
-  const Matrices& M = matrices();
+  const Matrices& M = matrices(q);
   std::vector<size_t> off(kNumRel);
   size_t total = 0;
   for (int r = 0; r < kNumRel; ++r) {
@@ -60,6 +60,7 @@ int acquire_tables(int device, DeviceTables** out) {
   auto* T = new (std::nothrow) DeviceTables();
   if (!T) return VOLPOT_ERR_OOM;
   T->device = device;
+  T->q = q;
   T->bytes = total * sizeof(double) + kNumRel * sizeof(RelDesc);
   if (hipMalloc(&T->buf, total * sizeof(double)) != hipSuccess) { delete T; return VOLPOT_ERR_OOM; }
   if (hipMalloc(&T->d_rels, kNumRel * sizeof(RelDesc)) != hipSuccess) { (void)hipFree(T->buf); delete T; return VOLPOT_ERR_OOM; }
@@ -72,7 +73,7 @@ int acquire_tables(int device, DeviceTables** out) {
     return VOLPOT_ERR_HIP;
   }
   T->refs = 1;
-  g_tables[device] = T;
+  g_tables[{device, q}] = T;
   *out = T;
   return VOLPOT_OK;
 }
@@ -87,7 +88,7 @@ void release_tables(DeviceTables* T) {
     (void)hipFree(T->buf);
     (void)hipFree(T->d_rels);
     (void)hipSetDevice(prev);
-    g_tables.erase(T->device);
+    g_tables.erase({T->device, T->q});
     delete T;
   }
 }
@@ -211,7 +212,7 @@ int upload(volpot_plan_s* p) {
   int rc = schedule_all(p, 0);
   if (rc != VOLPOT_OK) return rc;
   size_t total = 0;
-  const size_t nb = size_t(P.n_boxes) * kNE * sizeof(double);
+  const size_t nb = size_t(P.n_boxes) * P.ne * sizeof(double);
   struct Off { size_t tt, tsp, sd, ss, rp, ri, rf, rc, pc, bp, tc, ct, cp, ci; };
   std::vector<std::vector<int32_t>> zeros;  // arrival counters start at zero
   std::vector<std::vector<SegDesc>> segd;   // segment descriptors (table pointers of this device)
@@ -555,6 +556,11 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   std::memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
   if (o.table_cache) set_table_cache_dir(o.table_cache);
+  // expansion order from the far-field tolerance (0: the default 1e-13)
+  const double eps = o.eps == 0.0 ? kDefaultEps : o.eps;
+  if (!(eps > 0.0)) return VOLPOT_ERR_ARG;
+  const int ne = reals_for_eps(eps);
+  if (ne == 0) return VOLPOT_ERR_UNSUPPORTED;
   RootBox root;
   if (o.root_halfwidth != 0.0) {
     root = RootBox{o.root_centre[0], o.root_centre[1], o.root_halfwidth};
@@ -585,7 +591,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   int rc;
   try {
     rc = build_plan(n_trees, offsets, cref, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr, layer, points, root, o.tile_leaf_exp);
+                    nullptr, layer, points, root, o.tile_leaf_exp, ne, o.kchunk_leaf);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {
@@ -601,7 +607,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
     if (rc != VOLPOT_OK) { delete plan; return rc; }
   } else {
     if (hipGetDevice(&plan->device) != hipSuccess) { delete plan; return VOLPOT_ERR_HIP; }
-    rc = acquire_tables(plan->device, &plan->tables);
+    rc = acquire_tables(plan->device, plan->host.ne / 2, &plan->tables);
     if (rc == VOLPOT_OK) rc = upload(plan);
     if (rc != VOLPOT_OK) { free_plan(plan); return rc; }
   }
@@ -610,6 +616,24 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+namespace vp {
+// Reals per expansion for a far-field tolerance: the smallest order among 15, 23, 31 and 39 whose
+// error bound lies below eps, 0 when none does. The bounds are about ten times the largest
+// relative max-norm error of u against the oracle over adaptive trees at each order (2.3e-8 at
+// 15, 2.7e-11 at 23; at 31 and 39 the truncation lies under the rounding of the sums, about
+// 1e-14); the truncation part decays like 0.547^P, the rate of the V-list translations.
+int reals_for_eps(double eps) {
+  static const struct { double bound; int ne; } kOrders[] = {{3e-7, 32}, {3e-10, 48}, {1e-12, 64}, {1e-13, 80}};
+  for (const auto& o : kOrders)
+    if (eps >= o.bound) return o.ne;
+  return 0;
+}
+}  // namespace vp
+
+namespace {
 
 }  // namespace
 
@@ -705,8 +729,8 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   out->n_boxes = P.n_boxes;
   out->n_trees = P.n_trees;
   out->max_level = P.max_level;
-  out->order = kTerms - 1;
-  out->n_reals = kNE;
+  out->order = plan->host.ne / 2 - 1;
+  out->n_reals = plan->host.ne;
   out->n_stages = int32_t(P.fwd.size() + P.adj.size());
   out->pairs_near = P.pairs_near; out->pairs_v = P.pairs_v; out->pairs_w = P.pairs_w; out->pairs_x = P.pairs_x;
   out->n_m2m = P.n_m2m; out->n_l2l = P.n_l2l; out->n_s2m = P.n_s2m; out->n_l2t = P.n_l2t;
@@ -845,7 +869,7 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n) {
   if (!plan || !out) return VOLPOT_ERR_ARG;
-  const Matrices& M = matrices();
+  const Matrices& M = matrices(plan->host.ne / 2);
   int id;
   if (kind == 0 && index >= 0 && index < 33) id = kRelNear + index;
   else if (kind == 1 && index == 0) id = kRelS2M;

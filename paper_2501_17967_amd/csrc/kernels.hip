@@ -395,7 +395,13 @@ __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__
   X(256, 32, 32, 4, 2, 4, 1, 256) X(256, 64, 32, 4, 2, 4, 2, 512) X(256, 16, 16, 4, 1, 4, 1, 256) \
   X(256, 32, 16, 4, 2, 4, 1, 256) X(256, 64, 16, 4, 2, 4, 2, 512)                                 \
   X(80, 64, 40, 5, 1, 1, 4, 256) X(80, 32, 40, 5, 1, 1, 2, 128) X(80, 16, 40, 5, 1, 1, 1, 64)     \
-  X(80, 64, 32, 5, 1, 1, 4, 256) X(80, 32, 32, 5, 1, 1, 2, 128) X(80, 16, 32, 5, 1, 1, 1, 64)
+  X(80, 64, 32, 5, 1, 1, 4, 256) X(80, 32, 32, 5, 1, 1, 2, 128) X(80, 16, 32, 5, 1, 1, 1, 64)     \
+  X(64, 64, 16, 4, 1, 1, 4, 256) X(64, 32, 16, 4, 1, 1, 2, 128) X(64, 16, 16, 4, 1, 1, 1, 64)     \
+  X(64, 64, 32, 4, 1, 1, 4, 256) X(64, 32, 32, 4, 1, 1, 2, 128) X(64, 16, 32, 4, 1, 1, 1, 64)     \
+  X(48, 64, 16, 3, 1, 1, 4, 256) X(48, 32, 16, 3, 1, 1, 2, 128) X(48, 16, 16, 3, 1, 1, 1, 64)     \
+  X(48, 64, 32, 3, 1, 1, 4, 256) X(48, 32, 32, 3, 1, 1, 2, 128) X(48, 16, 32, 3, 1, 1, 1, 64)     \
+  X(32, 64, 16, 2, 1, 1, 4, 256) X(32, 32, 16, 2, 1, 1, 2, 128) X(32, 16, 16, 2, 1, 1, 1, 64)     \
+  X(32, 64, 32, 2, 1, 1, 4, 256) X(32, 32, 32, 2, 1, 1, 2, 128) X(32, 16, 32, 2, 1, 1, 1, 64)
 
 hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream) {
   if (p.n_blocks <= 0) return hipSuccess;

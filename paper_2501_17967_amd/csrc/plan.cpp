@@ -313,7 +313,7 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
   st.tile_tgt.assign(size_t(st.n_tiles) * NT, -1);
   st.tile_seg_ptr.assign(st.n_tiles + 1, 0);
   st.r1_ptr.assign(size_t(st.n_tiles) * NT + 1, 0);
-  st.seg_rel.clear(); st.seg_fam.clear(); st.seg_src.clear();
+  st.seg_rel.clear(); st.seg_k.clear(); st.seg_fam.clear(); st.seg_src.clear();
   st.r1_idx.clear(); st.r1_fam.clear(); st.r1_coef.clear();
   st.flops = 0; st.n_pairs = 0; st.flops_issued = 0;
   std::vector<int32_t> seg_of(size_t(kNumRel) * 16, -1), used;
@@ -342,6 +342,7 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
     for (int32_t key : used) {
       seg_of[size_t(key)] = int32_t(st.seg_rel.size());
       st.seg_rel.push_back(key / 16);
+      st.seg_k.push_back(mats.K[key / 16]);
       st.seg_fam.push_back(int8_t(key % 16));
       st.flops_issued += 2.0 * st.M * mats.K[key / 16] * NT;
     }
@@ -436,14 +437,13 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
 }
 
 void build_schedule(Stage& st, int max_blocks, int min_units) {
-  const Matrices& mats = matrices();
   const int T = st.n_tiles;
   st.pieces.clear();
   st.blk_ptr.assign(1, 0);
   st.n_blocks = 0;
   st.n_slots = 0;
   if (T <= 0) return;
-  auto chunks = [&](int32_t seg) { return int64_t(mats.K[st.seg_rel[seg]] / st.KC); };
+  auto chunks = [&](int32_t seg) { return int64_t(st.seg_k[size_t(seg)] / st.KC); };
   std::vector<int64_t> tu(T + 1, 0);  // first unit of each tile
   for (int t = 0; t < T; ++t) {
     int64_t n = 0;
@@ -522,13 +522,17 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
                int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer,
-               const PointTargets* points, const RootBox& root, int tile_leaf_exp) {
+               const PointTargets* points, const RootBox& root, int tile_leaf_exp, int ne, int kchunk_leaf) {
+  if (!(ne == 32 || ne == 48 || ne == 64 || ne == 80)) return VOLPOT_ERR_UNSUPPORTED;
+  if ((layer || points) && ne != kNE) return VOLPOT_ERR_UNSUPPORTED;  // their kernels take 40 terms
+  const int kNE = ne;  // reals per expansion of this plan (the namespace constant is the default)
   if (layer && (n_trees != 1 || layer->n < 0 || (layer->n > 0 && (!layer->xy || !layer->weights || !layer->normals))))
     return VOLPOT_ERR_ARG;
   if (points && (layer || n_trees != 1 || points->n < 0 || (points->n > 0 && !points->xy))) return VOLPOT_ERR_ARG;
   const double kLn2 = std::log(2.0);
   const double kInv2Pi = 1.0 / (2.0 * M_PI);
   P = Plan();
+  P.ne = ne;
   P.n_trees = n_trees;
   P.n_leaves = offsets[n_trees];
   std::vector<TreeBoxes> trees(n_trees);
@@ -792,8 +796,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   }
 
   // ---------------------------------------------------------------- stages
-  const Matrices& mats = matrices();
+  const Matrices& mats = matrices(ne / 2);
   const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
+  const int KCL = kchunk_leaf == 16 ? 16 : 32;  // k-chunk of the near-field stages
   const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 32;
   // The leaf stages with K = 80 (L2T, M2T and their transposes' counterparts S2M^T, S2L^T) do
   // little work per tile: on small trees 16-slot tiles give more independent workgroups to hide
@@ -821,7 +826,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
                        int32_t ostride) {
     st.kind = kind; st.name = name; st.level = level; st.M = M; st.NT = NT; st.out_arr = out; st.out_stride = ostride;
     st.K = K;
-    st.KC = (K == kNP) ? 32 : (M == kNP ? 16 : 40);
+    st.KC = (K == kNP) ? 32 : (M == kNP ? 16 : (K == 80 ? 40 : 16));
     for (auto& f : st.fam) f = {A_NONE, 0, 0};
     for (auto& f : st.r1fam) f = {A_NONE, 0, 0};
   };
@@ -1093,6 +1098,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
     const std::vector<int32_t> part(near_order.begin() + long(halves[h].first), near_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+    st.KC = KCL;
     st.fam[0] = {A_INS, kNP, 0};
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
@@ -1197,6 +1203,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
     const std::vector<int32_t> part(anear_order.begin() + long(halves[h].first), anear_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+    st.KC = KCL;
     st.out_scaled = 1;
     st.fam[0] = {A_IN, kNP, 0};
     std::vector<std::vector<Entry>> E(part.size());

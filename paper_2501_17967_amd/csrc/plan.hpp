@@ -41,7 +41,9 @@ namespace vp {
 constexpr int kP = 16;         // nodes per dimension
 constexpr int kNP = 256;       // nodes per leaf
 constexpr int kTerms = 40;     // complex expansion terms (order 39)
-constexpr int kNE = 80;        // reals per expansion (Re, Im interleaved)
+constexpr int kNE = 80;        // reals per expansion (Re, Im interleaved), at the default order
+constexpr double kDefaultEps = 1e-13;  // far-field tolerance when the options leave it at 0
+int reals_for_eps(double eps);  // 32, 48, 64 or 80 reals (orders 15, 23, 31, 39); 0: eps too small
 constexpr int kMaxLevel = 29;
 
 // ---------------------------------------------------------------- relations (matrix ids)
@@ -73,7 +75,9 @@ struct Matrices {
   std::vector<std::vector<double>> a;
   std::vector<double> nnz;  // non-zero count of each
 };
-const Matrices& matrices();  // built once per process (near tables by polar quadrature)
+// The relation matrices for expansions of q complex terms (order q - 1; q = 16, 24, 32 or 40),
+// built once per process and q; the near tables (polar quadrature) are the same for every q.
+const Matrices& matrices(int q = kTerms);
 // The quadrature rules of the point-moment kernel (moments.hip): leaf nodes and barycentric
 // weights, the 24-point tensor rule, the 12-point edge rule and the 16-point log-product rule.
 struct MomentRules;
@@ -135,6 +139,7 @@ struct Stage {
   std::vector<int32_t> tile_tgt;      // n_tiles * NT, -1 = empty slot
   std::vector<int32_t> tile_seg_ptr;  // n_tiles + 1
   std::vector<int32_t> seg_rel;       // relation id
+  std::vector<int32_t> seg_k;         // its K (a multiple of KC)
   std::vector<int8_t> seg_fam;        // index into fam[]
   std::vector<int32_t> seg_src;       // n_seg * NT source index, -1 = none
   std::vector<int32_t> r1_ptr;        // n_tiles * NT + 1
@@ -153,6 +158,7 @@ struct Stage {
 };
 
 struct Plan {
+  int ne = kNE;  // reals per expansion (2 x terms)
   int64_t n_leaves = 0, n_boxes = 0;
   int32_t n_trees = 0, max_level = 0;
   // boxes sorted by (level, tree, morton)
@@ -227,6 +233,6 @@ struct RootBox {
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
                const LayerSources* layer = nullptr, const PointTargets* points = nullptr,
-               const RootBox& root = RootBox(), int tile_leaf_exp = 16);
+               const RootBox& root = RootBox(), int tile_leaf_exp = 16, int ne = kNE, int kchunk_leaf = 32);
 
 }  // namespace vp

@@ -25,6 +25,7 @@
 #include <stdexcept>
 #include <cmath>
 #include <complex>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -481,13 +482,32 @@ static std::vector<cd> quad_basis(int n, int nfun, F g) {
   return out;
 }
 
-static Matrices build_matrices() {
+// the near tables: the same for every expansion order, computed (or read from the cache) once
+static const std::vector<std::vector<double>>& near_tables() {
+  static std::once_flag once;
+  static std::vector<std::vector<double>>* T = nullptr;
+  std::call_once(once, []() {
+    T = new std::vector<std::vector<double>>();
+    std::string path;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      if (!g_cache_dir.empty()) path = g_cache_dir + "/volpot_near_p16_v1.bin";
+    }
+    if (path.empty() || !cache_load(path, *T)) {
+      *T = near_tables_compute();
+      if (!path.empty()) cache_store(path, *T);
+    }
+  });
+  return *T;
+}
+
+static Matrices build_matrices(const int Q) {
+  const int kNE = 2 * Q;  // reals per expansion for this order
   Matrices M;
   M.M.assign(kNumRel, 0);
   M.K.assign(kNumRel, 0);
   M.a.assign(kNumRel, {});
   M.nnz.assign(kNumRel, 0.0);
-  const int Q = kTerms;
   const Basis& B = basis();
   std::vector<cd> xi(kNP);
   for (int m = 0; m < kNP; ++m) xi[m] = cd(B.t[m % kP], B.t[m / kP]);
@@ -567,17 +587,8 @@ static Matrices build_matrices() {
   }
   // near tables
   {
-    std::vector<std::vector<double>> T;
-    std::string path;
-    {
-      std::lock_guard<std::mutex> lk(g_cache_mu);
-      if (!g_cache_dir.empty()) path = g_cache_dir + "/volpot_near_p16_v1.bin";
-    }
-    if (path.empty() || !cache_load(path, T)) {
-      T = near_tables_compute();
-      if (!path.empty()) cache_store(path, T);
-    }
-    for (int r = 0; r < 33; ++r) set(kRelNear + r, kNP, kNP, std::move(T[r]));
+    const std::vector<std::vector<double>>& T = near_tables();
+    for (int r = 0; r < 33; ++r) set(kRelNear + r, kNP, kNP, std::vector<double>(T[size_t(r)]));
   }
   // M2T_r: source box (rho = 1/2) at d = (source - target centre) / s_target
   const auto& WO = w_offsets();
@@ -619,11 +630,13 @@ static Matrices build_matrices() {
   return M;
 }
 
-const Matrices& matrices() {
-  static std::once_flag once;
-  static Matrices* M = nullptr;
-  std::call_once(once, []() { M = new Matrices(build_matrices()); });
-  return *M;
+const Matrices& matrices(int q) {
+  static std::mutex mu;
+  static std::map<int, const Matrices*> built;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = built.find(q);
+  if (it == built.end()) it = built.emplace(q, new Matrices(build_matrices(q))).first;
+  return *it->second;
 }
 
 }  // namespace vp

@@ -20,11 +20,11 @@
 namespace {
 
 struct Candidate {
-  int32_t tile_leaf, tile_box, split_min, overlap, tile_leaf_exp;
+  int32_t tile_leaf, tile_box, split_min, overlap, tile_leaf_exp, kchunk_leaf;
 };
 bool same(const Candidate& a, const Candidate& b) {
   return a.tile_leaf == b.tile_leaf && a.tile_box == b.tile_box && a.split_min == b.split_min &&
-         a.overlap == b.overlap && a.tile_leaf_exp == b.tile_leaf_exp;
+         a.overlap == b.overlap && a.tile_leaf_exp == b.tile_leaf_exp && a.kchunk_leaf == b.kchunk_leaf;
 }
 
 // A candidate replaces the current choice only when it is faster by more than this fraction,
@@ -43,7 +43,7 @@ uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, i
       h *= 1099511628211ull;
     }
   };
-  mix(2);  // the cache line format: key, tile_leaf, tile_box, split_min, overlap, tile_leaf_exp, ms
+  mix(3);  // the cache line format: key, tile_leaf, tile_box, split_min, overlap, tile_leaf_exp, kchunk_leaf, ms
   mix(uint64_t(n_trees));
   std::vector<int64_t> hist(32, 0);
   for (int64_t i = 0; i < off[n_trees]; ++i) hist[size_t(std::min(std::max(levels[i], 0), 31))]++;
@@ -68,19 +68,20 @@ bool cache_lookup(const char* path, uint64_t key, volpot_options* best, double* 
   while (std::getline(in, line)) {  // the last entry for a key wins
     std::istringstream ss(line);
     unsigned long long k = 0;
-    int tl = 0, tb = 0, sm = 0, one = 0, te = 0;
+    int tl = 0, tb = 0, sm = 0, one = 0, te = 0, kc = 0;
     double t = 0;
     std::string rest;
-    if (!(ss >> std::hex >> k >> std::dec >> tl >> tb >> sm >> one >> te >> t) || (ss >> rest)) continue;
+    if (!(ss >> std::hex >> k >> std::dec >> tl >> tb >> sm >> one >> te >> kc >> t) || (ss >> rest)) continue;
     // a line that does not hold a valid shape is ignored (the shape is then timed again)
     if (k != key || !(tl == 32 || tl == 64) || !(tb == 16 || tb == 32 || tb == 64) || sm < -1 || one < 0 ||
-        !(te == 16 || te == 32 || te == 64) || !(t > 0.0))
+        !(te == 16 || te == 32 || te == 64) || !(kc == 16 || kc == 32) || !(t > 0.0))
       continue;
     best->tile_leaf = tl;
     best->tile_box = tb;
     best->split_min = sm;
     best->overlap = one;
     best->tile_leaf_exp = te;
+    best->kchunk_leaf = kc;
     *ms = t;
     found = true;
   }
@@ -91,8 +92,8 @@ void cache_store(const char* path, uint64_t key, const volpot_options& o, double
   if (!path) return;
   std::ofstream out(path, std::ios::app);
   char buf[128];
-  std::snprintf(buf, sizeof(buf), "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, o.tile_leaf, o.tile_box,
-                o.split_min, o.overlap, o.tile_leaf_exp, ms);
+  std::snprintf(buf, sizeof(buf), "%016llx %d %d %d %d %d %d %.6f\n", (unsigned long long)key, o.tile_leaf,
+                o.tile_box, o.split_min, o.overlap, o.tile_leaf_exp, o.kchunk_leaf, ms);
   out << buf;
 }
 
@@ -140,6 +141,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     oc.split_min = c.split_min;
     oc.overlap = c.overlap;
     oc.tile_leaf_exp = c.tile_leaf_exp;
+    oc.kchunk_leaf = c.kchunk_leaf;
     volpot_plan_t plan = nullptr;
     int r = volpot_plan_forest(n_trees, tree_offsets, centres, levels, p, &oc, &plan);
     if (r != VOLPOT_OK) return r;
@@ -159,7 +161,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     return r;
   };
   // coordinate descent over the four knobs, one at a time, from the defaults
-  const Candidate def{32, 32, 0, 0, 16};
+  const Candidate def{32, 32, 0, 0, 16, 32};
   Candidate cur = def;
   double best_t = 1e30;
   auto try_axis = [&](int axis, std::initializer_list<int32_t> values) {
@@ -168,7 +170,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
       if (rc != VOLPOT_OK) return;
       Candidate c = keep;
       (axis == 0 ? c.tile_box : axis == 1 ? c.tile_leaf : axis == 2 ? c.split_min : axis == 3 ? c.overlap
-                                                                                          : c.tile_leaf_exp) = v;
+                     : axis == 4 ? c.tile_leaf_exp : c.kchunk_leaf) = v;
       if (same(c, cur)) continue;  // already timed
       double t = 0;
       rc = time_it(c, &t);
@@ -188,6 +190,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
   if (rc == VOLPOT_OK) {
     try_axis(0, {16, 32, 64});
     try_axis(1, {32, 64});
+    try_axis(5, {32, 16});
     try_axis(4, {16, 32, 64});
     try_axis(2, {0, 1, -1});
     try_axis(3, {0, 16, 24, 32, 48});
@@ -208,6 +211,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     best->split_min = cur.split_min;
     best->overlap = cur.overlap;
     best->tile_leaf_exp = cur.tile_leaf_exp;
+    best->kchunk_leaf = cur.kchunk_leaf;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

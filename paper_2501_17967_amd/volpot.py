@@ -54,16 +54,18 @@ class Options(ctypes.Structure):
     _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
                 ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double),
-                ("tile_leaf_exp", ctypes.c_int32)]
+                ("tile_leaf_exp", ctypes.c_int32), ("eps", ctypes.c_double), ("kchunk_leaf", ctypes.c_int32)]
 
 
 def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0,
-             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0):
+             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0):
     o = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
                 table_cache.encode() if table_cache else None, int(split_min), int(overlap))
     o.root_centre[0], o.root_centre[1] = float(root_centre[0]), float(root_centre[1])
     o.root_halfwidth = float(root_halfwidth)
     o.tile_leaf_exp = int(tile_leaf_exp)
+    o.eps = float(eps)
+    o.kchunk_leaf = int(kchunk_leaf)
     return o
 
 
@@ -170,8 +172,8 @@ def _host_tree(centres, levels):
 
 def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
     """Fastest launch shape for this tree or forest on the current device (volpot_autotune):
-    returns ({"tile_leaf", "tile_box", "split_min", "overlap", "tile_leaf_exp"}, ms per forward + adjoint
-    apply). The result
+    returns ({"tile_leaf", "tile_box", "split_min", "overlap", "tile_leaf_exp", "kchunk_leaf"}, ms per
+    forward + adjoint apply). The result
     is looked up in / appended to the text file ``cache`` when given."""
     c, l = _host_tree(centres, levels)
     off = np.ascontiguousarray(np.asarray([0, c.shape[0]] if tree_offsets is None else tree_offsets, dtype=np.int64))
@@ -181,7 +183,7 @@ def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
                                  None, cache.encode() if cache else None, ctypes.byref(best), ctypes.byref(ms)),
            "volpot_autotune")
     return ({"tile_leaf": best.tile_leaf, "tile_box": best.tile_box, "split_min": best.split_min,
-             "overlap": best.overlap, "tile_leaf_exp": best.tile_leaf_exp}, ms.value)
+             "overlap": best.overlap, "tile_leaf_exp": best.tile_leaf_exp, "kchunk_leaf": best.kchunk_leaf}, ms.value)
 
 
 def build_tree(f, eps, scale, min_level=0, max_level=24, p=16, stream=None):
@@ -299,11 +301,11 @@ class Plan:
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
                  tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0),
-                 root_halfwidth=0.0, tile_leaf_exp=0):
+                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
-                       root_halfwidth, tile_leaf_exp)
+                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf)
         h = _vp()
         L = lib()
         if tree_offsets is None:

@@ -1,0 +1,53 @@
+"""GPU tests of the far-field tolerance option (volpot_options.eps -> expansion order P): for each
+order the library offers below the default (P = 15, 23, 31), the forward and adjoint applies on
+adaptive trees against the oracle (order 50), relative max-norm error within the bound the
+library states for that order (the bound is what eps is compared with), and the errors decaying
+with P. The parity test cases of the default order (P = 39) are in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+from oracle import fmm, tree
+from tests.conftest import rel_max_err
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {15: 3e-7, 23: 3e-10, 31: 1e-12, 39: 1e-13}  # the bounds on u that include/volpot.h states
+
+
+def _cases():
+    return [gen.config2(0), gen.config3(0), gen.random_small_tree(3, max_level=6, n_splits=12),
+            gen.config2(1, size_matched=True)]
+
+
+@pytest.fixture(scope="module")
+def oracle_results():
+    out = []
+    for w in _cases():
+        r = np.random.default_rng(w.n_leaves).standard_normal(w.f.shape)
+        bc = fmm.BoxCode(tree.Tree(w.centres, w.levels))
+        out.append((w, r, bc.apply(w.f), bc.apply_adjoint(r)))
+    return out
+
+
+def test_orders_meet_their_bounds(device, oracle_results):
+    import torch
+
+    from paper_2501_17967_amd import Plan
+
+    worst = {}
+    for P in (15, 23, 31, 39):
+        for w, r, u_o, fb_o in oracle_results:
+            plan = Plan(w.centres, w.levels, eps=BOUND[P])
+            assert plan.info()["order"] == P
+            u = plan.apply(torch.from_numpy(w.f).to(device)).cpu().numpy()
+            fb = plan.apply_adjoint(torch.from_numpy(r).to(device)).cpu().numpy()
+            plan.close()
+            ef, ea = rel_max_err(u, u_o), rel_max_err(fb, fb_o)
+            print("order %d, %s (%d leaves): rel err forward %.2e adjoint %.2e" % (P, w.name, w.n_leaves, ef, ea),
+                  flush=True)
+            worst[P] = max(worst.get(P, 0.0), ef)
+            # the bound is on u; the adjoint of a random cotangent carries its own rounding (its
+            # sums cancel), about 1e-13 of its max-norm at the highest orders
+            assert ef <= BOUND[P] and ea <= max(BOUND[P], 1e-12), (P, w.name, ef, ea)
+    assert worst[15] > worst[23] > worst[31]

@@ -207,18 +207,21 @@ def test_split_schedules_agree_and_repeat(vp, torch_mod, split_min):
     plan.close()
 
 
-@pytest.mark.parametrize("tile_leaf,tile_box,split_min,tile_leaf_exp",
-                         [(64, 64, 0, 64), (64, 16, 1, 32), (32, 32, 0, 64), (32, 32, 1, 32)])
-def test_tile_shapes_vs_box_code_oracle(vp, torch_mod, tile_leaf, tile_box, split_min, tile_leaf_exp):
-    # 64-slot near-field tiles and 32- and 64-slot tiles of the leaf stages that read expansions
-    # run in instantiations of their own; every stage against the oracle, and repeat applies
-    # bitwise
+@pytest.mark.parametrize("tile_leaf,tile_box,split_min,tile_leaf_exp,kchunk_leaf,overlap",
+                         [(64, 64, 0, 64, 32, 16), (64, 16, 1, 32, 32, 16), (32, 32, 0, 64, 32, 8),
+                          (32, 32, 1, 32, 32, 8), (32, 32, 0, 16, 16, 0), (64, 32, 1, 16, 16, 0),
+                          (32, 16, 0, 16, 16, 16)])
+def test_tile_shapes_vs_box_code_oracle(vp, torch_mod, tile_leaf, tile_box, split_min, tile_leaf_exp, kchunk_leaf,
+                                        overlap):
+    # 64-slot near-field tiles, near-field k-chunks of 16, and 32- and 64-slot tiles of the leaf
+    # stages that read expansions run in instantiations of their own, with and without the
+    # overlapped streams; every stage against the oracle, and repeat applies bitwise
     w = gen.config2(0)
-    _say("case tile_leaf=%d tile_box=%d split_min=%d tile_leaf_exp=%d (%d leaves)"
-         % (tile_leaf, tile_box, split_min, tile_leaf_exp, w.n_leaves))
+    _say("case tile_leaf=%d tile_box=%d split_min=%d tile_leaf_exp=%d kchunk_leaf=%d overlap=%d (%d leaves)"
+         % (tile_leaf, tile_box, split_min, tile_leaf_exp, kchunk_leaf, overlap, w.n_leaves))
     r = np.random.default_rng(29).standard_normal(w.f.shape)
     plan = vp.Plan(w.centres, w.levels, tile_leaf=tile_leaf, tile_box=tile_box, split_min=split_min,
-                   tile_leaf_exp=tile_leaf_exp)
+                   tile_leaf_exp=tile_leaf_exp, kchunk_leaf=kchunk_leaf, overlap=overlap)
     f, rd = _gpu(torch_mod, w.f), _gpu(torch_mod, r)
     u, fb = plan.apply(f).cpu().numpy(), plan.apply_adjoint(rd).cpu().numpy()
     u2, fb2 = plan.apply(f).cpu().numpy(), plan.apply_adjoint(rd).cpu().numpy()
@@ -357,7 +360,9 @@ def test_autograd_through_a_forest_plan(vp, torch_mod):
     d = rng.standard_normal(gn.shape)
     d /= np.max(np.abs(d))
     dt = _gpu(torch_mod, d)
-    h = 1e-6
+    # J is quadratic, so the central difference is exact for any step up to rounding, which is
+    # about 1e-16 |J| / h: a step of 1e-3 keeps it far below the bar for a random direction
+    h = 1e-3
     with torch_mod.no_grad():
         fd = float((J(f + h * dt) - J(f - h * dt)) / (2 * h))
     an = float(np.sum(gn * d))
@@ -374,7 +379,7 @@ def test_autotune_picks_a_valid_shape_and_caches(vp, torch_mod, tmp_path):
         fh.write("garbage\n0123456789abcdef 32 32 0 0 16\n")
     best, ms = vp.autotune(w.centres, w.levels, cache=cache)
     assert best["tile_leaf"] in (32, 64) and best["tile_box"] in (16, 32, 64) and best["split_min"] in (0, 1, -1)
-    assert best["tile_leaf_exp"] in (16, 32, 64)
+    assert best["tile_leaf_exp"] in (16, 32, 64) and best["kchunk_leaf"] in (16, 32)
     assert ms > 0
     again, ms2 = vp.autotune(w.centres, w.levels, cache=cache)  # answered from the cache file
     assert again == best and abs(ms2 - ms) <= 1e-6 * ms
@@ -385,7 +390,7 @@ def test_autotune_picks_a_valid_shape_and_caches(vp, torch_mod, tmp_path):
     key = lines[-1].split()[0]
     cache2 = str(tmp_path / "tune2.txt")
     with open(cache2, "w") as fh:
-        fh.write("%s 48 32 0 0 16 0.5\n%s 32 32 0 0\n" % (key, key))
+        fh.write("%s 48 32 0 0 16 32 0.5\n%s 32 32 0 0 16\n" % (key, key))
     again2, _ = vp.autotune(w.centres, w.levels, cache=cache2)
     assert again2["tile_leaf"] in (32, 64) and again2["tile_leaf_exp"] in (16, 32, 64)
     lines2 = open(cache2).read().splitlines()
