@@ -196,8 +196,11 @@ int schedule_all(volpot_plan_s* p, int nominal) {
         const int per_cu = blocks / std::max(cus, 1);
         if (p->overlap > 0 && s.concurrent) blocks = std::max(1, blocks - per_cu * p->overlap);
         if (p->overlap > 0 && s.helper) blocks = std::max(1, std::min(blocks, per_cu * p->overlap));
-        // default: a block gets at least one whole segment (K / KC chunks)
-        build_schedule(s, blocks, p->split_min != 0 ? p->split_min : s.K / s.KC);
+        // default: a block gets at least one whole segment (K / KC chunks). A tile's fixed cost
+        // (index loads, rank-one terms, the output pass) is weighted as one segment: without it,
+        // blocks whose share is many one-segment tiles ran about twice as long as the others
+        // in the leaf stages
+        build_schedule(s, blocks, p->split_min != 0 ? p->split_min : s.K / s.KC, s.K / s.KC);
       }
   } catch (const std::bad_alloc&) {
     return VOLPOT_ERR_OOM;

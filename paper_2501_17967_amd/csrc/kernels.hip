@@ -267,9 +267,13 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 // re-arms the counter. No block ever waits for another.
 // The near-field instantiation (256 rows, 32 slots, 4 waves) is held to two blocks per compute
 // unit (256 registers per lane): the other block works while this one waits at a barrier or
-// for memory. The other instantiations keep the compiler's own register choice.
+// for memory. Its k-chunk-16 form, which also runs the leaf stages that read expansions
+// (K = 64 or 80), is held to three (168 registers): those stages are latency-bound, and the
+// third block took 7% off them. The other instantiations keep the compiler's own choice.
 template <int MT, int NTT, int WM, int WN, int KC>
-constexpr int min_blocks() { return (MT == 4 && NTT == 2 && WM == 4 && WN == 1 && KC == 32) ? 2 : 1; }
+constexpr int min_blocks() {
+  return (MT == 4 && NTT == 2 && WM == 4 && WN == 1) ? (KC == 32 ? 2 : KC == 16 ? 3 : 1) : 1;
+}
 
 template <int MT, int NTT, int WM, int WN, int KC>
 __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>())) grg_kernel(const GrgParams p) {

@@ -436,7 +436,7 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   for (Stage& s : last) v.push_back(std::move(s));
 }
 
-void build_schedule(Stage& st, int max_blocks, int min_units) {
+void build_schedule(Stage& st, int max_blocks, int min_units, int tile_cost) {
   const int T = st.n_tiles;
   st.pieces.clear();
   st.blk_ptr.assign(1, 0);
@@ -444,18 +444,28 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
   st.n_slots = 0;
   if (T <= 0) return;
   auto chunks = [&](int32_t seg) { return int64_t(st.seg_k[size_t(seg)] / st.KC); };
-  std::vector<int64_t> tu(T + 1, 0);  // first unit of each tile
+  // Work units: a tile's k-chunks, then tile_cost more for its fixed cost (index loads, rank-one
+  // terms, the output pass), which only the block that ends the tile pays. A tile without
+  // segments still has one unit.
+  std::vector<int64_t> tu(T + 1, 0), tc(T, 0);  // first unit, chunk units of each tile
   for (int t = 0; t < T; ++t) {
     int64_t n = 0;
     for (int32_t g = st.tile_seg_ptr[t]; g < st.tile_seg_ptr[t + 1]; ++g) n += chunks(g);
-    tu[t + 1] = tu[t] + std::max<int64_t>(n, 1);
+    tc[t] = std::max<int64_t>(n, 1);
+    tu[t + 1] = tu[t] + tc[t] + std::max(0, tile_cost);
   }
   const int64_t U = tu[T];
   // min_units < 0: one block per tile, no tile cut
   const bool whole = min_units < 0;
   const int64_t mu = std::max(1, min_units);
   const int64_t G = whole ? T : std::max<int64_t>(1, std::min<int64_t>(std::max(1, max_blocks), (U + mu - 1) / mu));
-  auto first = [&](int64_t b) { return whole ? tu[b] : b * U / G; };  // first unit of block b
+  // first unit of block b; a boundary inside a tile's fixed-cost units moves to the tile's end
+  auto first = [&](int64_t b) {
+    if (whole) return tu[b];
+    const int64_t u = b * U / G;
+    const int64_t t = std::upper_bound(tu.begin(), tu.end(), u) - tu.begin() - 1;
+    return (t < T && u - tu[size_t(t)] >= tc[size_t(t)]) ? tu[size_t(t) + 1] : u;
+  };
   // pass 1: pieces per tile
   std::vector<int32_t> npc(T, 0);
   for (int64_t b = 0, t = 0; b < G; ++b)
@@ -488,7 +498,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
         while (o >= chunks(g)) { o -= chunks(g); ++g; }
         pc.seg = g;
         pc.k0 = int32_t(o * st.KC);
-        pc.n_chunks = int32_t(end - u);
+        pc.n_chunks = int32_t(std::min(end, tu[t] + tc[t]) - u);
       }
       st.pieces.push_back(pc);
       u = end;
@@ -506,7 +516,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
       if (pc.seg < st.tile_seg_ptr[pc.tile] || pc.seg >= st.tile_seg_ptr[pc.tile + 1] || pc.k0 % st.KC)
         throw std::runtime_error("schedule: bad segment");
       if (o + pc.k0 / st.KC != got[pc.tile]) throw std::runtime_error("schedule: chunks out of order");
-      if (tu[pc.tile] + got[pc.tile] + pc.n_chunks > tu[pc.tile + 1]) throw std::runtime_error("schedule: overrun");
+      if (got[pc.tile] + pc.n_chunks > tc[pc.tile]) throw std::runtime_error("schedule: overrun");
       got[pc.tile] += pc.n_chunks;
     } else {
       if (st.tile_seg_ptr[pc.tile + 1] != st.tile_seg_ptr[pc.tile] || pc.n_pieces != 1)
@@ -516,7 +526,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units) {
       throw std::runtime_error("schedule: bad slot");
   }
   for (int t = 0; t < T; ++t)
-    if (st.tile_seg_ptr[t + 1] > st.tile_seg_ptr[t] && got[t] != tu[t + 1] - tu[t])
+    if (st.tile_seg_ptr[t + 1] > st.tile_seg_ptr[t] && got[t] != tc[t])
       throw std::runtime_error("schedule: tile not covered");
 }
 

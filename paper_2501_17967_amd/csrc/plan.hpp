@@ -212,10 +212,11 @@ int validate_forest(int32_t n_trees, const int64_t* offsets, const double* centr
 
 // Validates and builds the host plan. Returns a VOLPOT_* status; bad_leaf gets the first
 // offending caller leaf index on tree errors.
-// Cut a stage's work (units: one k-chunk of one segment; a tile without segments is one unit)
-// into at most max_blocks contiguous, equal ranges of at least min_units units each.
+// Cut a stage's work (units: one k-chunk of one segment; a tile without segments is one unit;
+// tile_cost more per tile for its fixed cost, which is never cut) into at most max_blocks
+// contiguous, equal ranges of at least min_units units each.
 // min_units < 0 gives one block per tile instead (no tile is cut).
-void build_schedule(Stage& st, int max_blocks, int min_units);
+void build_schedule(Stage& st, int max_blocks, int min_units, int tile_cost = 0);
 
 // overlap > 0: near field split in two launches, each concurrent with one chain of the far
 // field on the helper stream (stage order and flags below); 0: one stream, plan order.

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/volpot.h"
+#include "plan.hpp"
 
 namespace {
 
@@ -34,8 +35,9 @@ bool same(const Candidate& a, const Candidate& b) {
 constexpr double kMargin = 0.015;
 
 // Shape signature: trees, leaves per level over the whole forest, sizes of the trees, the
-// device's architecture and compute-unit count. FNV-1a over the values.
-uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, int dev) {
+// expansion length (reals per expansion), the device's architecture and compute-unit count.
+// FNV-1a over the values.
+uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, int ne, int dev) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) {
     for (int b = 0; b < 8; ++b) {
@@ -52,6 +54,7 @@ uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, i
   for (int32_t t = 0; t < n_trees; ++t) sizes.push_back(off[t + 1] - off[t]);
   std::sort(sizes.begin(), sizes.end());
   for (int64_t s : sizes) mix(uint64_t(s));
+  mix(uint64_t(ne));
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
     for (const char* c = prop.gcnArchName; *c; ++c) mix(uint64_t(uint8_t(*c)));
@@ -113,7 +116,9 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
   o.use_graph = 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return VOLPOT_ERR_HIP;
-  const uint64_t key = signature(n_trees, tree_offsets, levels, dev);
+  const int ne = vp::reals_for_eps(o.eps == 0.0 ? vp::kDefaultEps : o.eps);
+  if (ne == 0) return VOLPOT_ERR_UNSUPPORTED;
+  const uint64_t key = signature(n_trees, tree_offsets, levels, ne, dev);
   double ms = 0;
   *best = o;
   if (cache_lookup(cache_path, key, best, &ms)) {

@@ -170,17 +170,20 @@ def _host_tree(centres, levels):
     return c, l
 
 
-def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None):
+def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None, eps=0.0):
     """Fastest launch shape for this tree or forest on the current device (volpot_autotune):
     returns ({"tile_leaf", "tile_box", "split_min", "overlap", "tile_leaf_exp", "kchunk_leaf"}, ms per
-    forward + adjoint apply). The result
-    is looked up in / appended to the text file ``cache`` when given."""
+    forward + adjoint apply). The candidates are timed at the expansion order that the far-field
+    tolerance ``eps`` selects (0: the default). The result is looked up in / appended to the
+    text file ``cache`` when given."""
     c, l = _host_tree(centres, levels)
     off = np.ascontiguousarray(np.asarray([0, c.shape[0]] if tree_offsets is None else tree_offsets, dtype=np.int64))
     best = Options()
+    base = _options(eps=eps)
     ms = ctypes.c_double(0.0)
     _check(lib().volpot_autotune(off.size - 1, off.ctypes.data_as(_lp), c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), p,
-                                 None, cache.encode() if cache else None, ctypes.byref(best), ctypes.byref(ms)),
+                                 ctypes.byref(base), cache.encode() if cache else None, ctypes.byref(best),
+                                 ctypes.byref(ms)),
            "volpot_autotune")
     return ({"tile_leaf": best.tile_leaf, "tile_box": best.tile_box, "split_min": best.split_min,
              "overlap": best.overlap, "tile_leaf_exp": best.tile_leaf_exp, "kchunk_leaf": best.kchunk_leaf}, ms.value)

@@ -158,7 +158,8 @@ def test_schedules_cover_stages(vp, split_min):
                 continue
             chunks = (256 if s["rows"] == 80 and s["kchunk"] == 32 else 80 if s["rows"] == 80 else
                       256 if s["kchunk"] == 32 else 80) // s["kchunk"]
-            units = s["n_segments"] * chunks  # every tile here has at least one segment
+            # every tile here has at least one segment; its fixed cost counts as one more
+            units = (s["n_segments"] + s["n_tiles"]) * chunks
             if split_min == -1:
                 assert s["n_blocks"] == s["n_tiles"] and s["n_split_tiles"] == 0, s
             else:
