@@ -99,6 +99,13 @@ typedef struct {
   int32_t kchunk_leaf;     /* k-chunk of the near-field stages: 32 (default; 0) or 16 (shorter
                               chunks, less LDS and fewer registers: three blocks per compute
                               unit instead of two) */
+  int32_t dense_m2l;       /* 0 (default): the M2L stages (FARV and its transpose) apply each
+                              translation in factored form, diag(d^-l) H diag((-1)^k d^-k)
+                              with one real, offset-free core H shared by all 40 V-list offsets
+                              (the translation formula of Sec. 4.2's box code, split), half the
+                              matrix-core work of the dense form; the ln|d| a_0 term joins the
+                              rank-one ln s terms. 1: dense 2q x 2q real matrices per offset.
+                              Both agree to rounding (the tests compare them). */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -330,10 +337,14 @@ int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, const double* 
 typedef struct {
   char name[24];           /* e.g. "NEAR", "M2M[5]", "AFARV" */
   int32_t kind;            /* stage kind, numbered as in volpot_info.flops_kind */
-  int32_t rows, tile, kchunk; /* output rows per slot (80 or 256), slots per tile, k-chunk */
+  int32_t rows, tile, kchunk; /* output rows per slot (2q or 256; the padded core's rows when
+                              factored), slots per tile, k-chunk */
   int32_t helper;          /* 1: runs on the plan's helper stream */
   int64_t n_tiles, n_segments, n_blocks, n_split_tiles;
   double flops, flops_issued;
+  int32_t inner;           /* inner dimension K of the stage's products (reals; complex terms
+                              when factored) */
+  int32_t factored;        /* 1: the factored M2L form (see volpot_options.dense_m2l) */
 } volpot_stage_info;
 
 /* Number of stages of the forward (adjoint = 0) or adjoint (1) apply, in launch order. */

@@ -42,13 +42,21 @@ int acquire_tables(int device, int q, DeviceTables** out) {
     return VOLPOT_OK;
   }
   const Matrices& M = matrices(q);
-  std::vector<size_t> off(kNumRel);
+  std::vector<size_t> off(kNumRel), woff(kNumRel);
   size_t total = 0;
   for (int r = 0; r < kNumRel; ++r) {
     off[r] = total;
     total += size_t(M.M[r]) * M.K[r];
   }
+  for (int r = 0; r < kNumRel; ++r) {  // the factored relations' diagonals after the tables
+    woff[r] = total;
+    total += M.w_in[r].size() + M.w_out[r].size();
+  }
   std::vector<double> host(total);
+  for (int r = 0; r < kNumRel; ++r) {
+    std::copy(M.w_in[r].begin(), M.w_in[r].end(), host.begin() + std::ptrdiff_t(woff[r]));
+    std::copy(M.w_out[r].begin(), M.w_out[r].end(), host.begin() + std::ptrdiff_t(woff[r] + M.w_in[r].size()));
+  }
   for (int r = 0; r < kNumRel; ++r) {
     const int rows = M.M[r], cols = M.K[r], nt = rows / 16;
     const double* a = M.a[r].data();
@@ -65,7 +73,11 @@ int acquire_tables(int device, int q, DeviceTables** out) {
   if (hipMalloc(&T->buf, total * sizeof(double)) != hipSuccess) { delete T; return VOLPOT_ERR_OOM; }
   if (hipMalloc(&T->d_rels, kNumRel * sizeof(RelDesc)) != hipSuccess) { (void)hipFree(T->buf); delete T; return VOLPOT_ERR_OOM; }
   std::vector<RelDesc> rd(kNumRel);
-  for (int r = 0; r < kNumRel; ++r) rd[r] = {T->buf + off[r], M.M[r], M.K[r]};
+  for (int r = 0; r < kNumRel; ++r) {
+    const bool w = !M.w_in[r].empty();
+    rd[r] = {T->buf + off[r], M.M[r], M.K[r], w ? T->buf + woff[r] : nullptr,
+             w ? T->buf + woff[r] + M.w_in[r].size() : nullptr};
+  }
   T->rels = rd;
   if (hipMemcpy(T->buf, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(T->d_rels, rd.data(), kNumRel * sizeof(RelDesc), hipMemcpyHostToDevice) != hipSuccess) {
@@ -174,7 +186,7 @@ size_t add_bytes(size_t& total, const std::vector<T>& v) {
 // many blocks as fit on the device at once (fewer for small stages), each given an equal
 // share of the stage's k-chunks. nominal > 0 replaces the device query (host-only plans).
 int schedule_all(volpot_plan_s* p, int nominal) {
-  std::map<std::array<int, 3>, int> resident;
+  std::map<std::array<int, 4>, int> resident;
   int cus = 256;
   if (nominal <= 0) {
     int dev = 0;
@@ -185,10 +197,10 @@ int schedule_all(volpot_plan_s* p, int nominal) {
     for (auto* v : {&p->host.fwd, &p->host.adj})
       for (Stage& s : *v) {
         if (s.custom != C_NONE) continue;  // own kernels, one block per target
-        auto key = std::array<int, 3>{s.M, s.NT, s.KC};
+        auto key = std::array<int, 4>{s.M, s.NT, s.KC, s.cx_rel >= 0};
         auto it = resident.find(key);
         if (it == resident.end())
-          it = resident.emplace(key, nominal > 0 ? nominal : grg_resident_blocks(s.M, s.NT, s.KC)).first;
+          it = resident.emplace(key, nominal > 0 ? nominal : grg_resident_blocks(s.M, s.NT, s.KC, s.cx_rel >= 0)).first;
         if (it->second <= 0) return VOLPOT_ERR_HIP;
         // a stage that runs beside the helper stream leaves `overlap` compute units' share free
         // (helper-stream stages get that share only)
@@ -224,7 +236,8 @@ int upload(volpot_plan_s* p) {
     segd.emplace_back(s.seg_rel.size());
     for (size_t i = 0; i < s.seg_rel.size(); ++i) {
       const RelDesc& rd = p->tables->rels[size_t(s.seg_rel[i])];
-      segd.back()[i] = {rd.A, rd.K, int32_t(s.seg_fam[i])};
+      const RelDesc& ra = s.cx_rel >= 0 ? p->tables->rels[size_t(s.cx_rel)] : rd;  // factored: the core
+      segd.back()[i] = {ra.A, ra.K, int32_t(s.seg_fam[i]), rd.w_in, rd.w_out};
     }
     o.tt = add_bytes(total, s.tile_tgt); o.tsp = add_bytes(total, s.tile_seg_ptr); o.sd = add_bytes(total, segd.back());
     o.ss = add_bytes(total, s.seg_src); o.rp = add_bytes(total, s.r1_ptr);
@@ -353,7 +366,7 @@ int upload(volpot_plan_s* p) {
   size_t part[2] = {0, 0};
   for (auto* v : {&P.fwd, &P.adj})
     for (const Stage& s : *v) {
-      size_t need = size_t(s.n_slots) * s.M * s.NT * sizeof(double);
+      size_t need = size_t(s.n_slots) * s.M * s.NT * (s.cx_rel >= 0 ? 2 : 1) * sizeof(double);
       part[s.helper ? 0 : 1] = std::max(part[s.helper ? 0 : 1], need);
     }
   for (int i = 0; i < 2; ++i)
@@ -494,10 +507,11 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, dou
     g.pieces = d.pieces; g.blk_ptr = d.blk_ptr; g.tile_count = d.tile_count;
     g.partial = p->d_part[s.helper ? 0 : 1];  // helper-marked stages never share a buffer with the others
     g.n_blocks = s.n_blocks;
+    g.cx_core = s.cx_rel >= 0 ? p->tables->rels[size_t(s.cx_rel)].A : nullptr;
     hipEvent_t ea, eb;
     timed_begin(p, timing, s.kind, st, &ea, &eb);
     roctxRangePushA(s.name.c_str());  // a host range per stage, named as in volpot_plan_stage
-    hipError_t e = launch_grg(s.M, s.NT, s.KC, g, st);
+    hipError_t e = launch_grg(s.M, s.NT, s.KC, s.cx_rel >= 0, g, st);
     roctxRangePop();
     timed_end(p, s.kind, st, ea, eb);
     if (e != hipSuccess) return VOLPOT_ERR_HIP;
@@ -594,7 +608,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   int rc;
   try {
     rc = build_plan(n_trees, offsets, cref, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr, layer, points, root, o.tile_leaf_exp, ne, o.kchunk_leaf);
+                    nullptr, layer, points, root, o.tile_leaf_exp, ne, o.kchunk_leaf, o.dense_m2l != 0);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {
@@ -796,6 +810,8 @@ int volpot_plan_stage(volpot_plan_t plan, int32_t adjoint, int32_t index, volpot
   for (int32_t c : pieces) out->n_split_tiles += c > 1;
   out->flops = s.flops;
   out->flops_issued = s.flops_issued;
+  out->inner = s.K;
+  out->factored = s.cx_rel >= 0;
   return VOLPOT_OK;
 }
 

@@ -12,16 +12,22 @@ struct PieceDesc {
   int32_t tile, seg, k0, n_chunks, slot, slot0, n_pieces, pad;
 };
 
-// One segment of a tile: its relation table (fragment-major), inner dimension and source family
+// One segment of a tile: its relation table (fragment-major), inner dimension and source family;
+// in a factored stage also the relation's complex diagonals (interleaved Re, Im): w_in scales
+// the K source terms before the table, w_out the table's rows after it
 struct SegDesc {
   const double* A;
   int32_t K;
   int32_t fam;
+  const double* w_in;
+  const double* w_out;
 };
 
 struct RelDesc {
   const double* A;  // fragment-major: frag[(kk * (M/16) + row_tile) * 64 + lane] = A[16 row_tile + lane%16][4 kk + lane/16]
   int32_t M, K;
+  const double* w_in;   // factored M2L relations only, else null
+  const double* w_out;
 };
 
 // Arguments of one stage launch (grouped-relation GEMM). Passed by value.
@@ -48,15 +54,19 @@ struct GrgParams {
   const PieceDesc* pieces;      // balanced schedule: block b runs pieces [blk_ptr[b], blk_ptr[b+1])
   const int32_t* blk_ptr;       // n_blocks + 1
   int32_t* tile_count;          // n_tiles arrival counters of split tiles, zero between launches
-  double* partial;              // partial sums of split tiles, M x NT doubles per slot
+  double* partial;              // partial sums of split tiles, M x NT doubles per slot (2 NT factored)
   int32_t n_blocks;
+  const double* cx_core;        // factored stages: the core table (fragment-major, M x K)
 };
 
-// Blocks of grg_kernel<M, NT, KC> that fit on the current device at once (0 on error).
-int grg_resident_blocks(int M, int NT, int KC);
+// Blocks of the grouped-product kernel for (M, NT, KC, factored) that fit on the current device
+// at once (0 on error).
+int grg_resident_blocks(int M, int NT, int KC, bool factored = false);
 
-// Launch one stage: (M, NT, KC) in {(256, 32|64, 16|32), (80, 16|32|64, 32|40)}.
-hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream);
+// Launch one stage: M rows, NT slots per tile, k-chunk KC; factored (the M2L core between two
+// complex diagonals): M = the padded core rows, KC = the complex terms q, 2 NT columns.
+// hipErrorInvalidValue for a shape without an instantiation.
+hipError_t launch_grg(int M, int NT, int KC, bool factored, const GrgParams& p, hipStream_t stream);
 // out = s2[leaf] * x  (n_leaves x 256)
 hipError_t launch_prescale(const double* x, const double* s2, double* out, int64_t n_leaves, hipStream_t stream);
 // usum[a] = sum of the 256 values of leaf a

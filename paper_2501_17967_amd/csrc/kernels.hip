@@ -126,6 +126,74 @@ struct Loader {
   }
 };
 
+// Column of part h (0 real, 1 imaginary) of slot t in a factored tile: each group of 16 slots
+// takes 32 columns, the real parts first, so that one wave's two column fragments hold both
+// parts of the same 16 slots in the same lanes.
+__device__ __forceinline__ int cx_col(int t, int h) { return (t >> 4) * 32 + h * 16 + (t & 15); }
+
+// The loading side of a factored M2L stage: one chunk is one whole segment, the Q complex terms
+// of NT sources. Thread tid owns term k = tid % Q of the slots t = tid / Q + G q (G = NTHR / Q
+// thread groups; threads past G Q idle here), so it needs one input weight w_in[k] per segment.
+// Each source term is scaled by its complex weight on the way into LDS, its parts to columns
+// cx_col(t, 0) and cx_col(t, 1); thread tid < MP also stages the output weight w_out[tid] of
+// the segment.
+template <int NT, int NTHR, int Q, int MP>
+struct LoaderCX {
+  static constexpr int G = NTHR / Q;
+  static constexpr int B_PER = (NT + G - 1) / G;
+  static_assert(G >= 1 && NTHR >= MP, "factored loader needs a thread per term and per output row");
+  int s;
+  gdp base;
+  int stride;
+  int si[B_PER];  // source index per owned slot (-1: none)
+  d2 rb[B_PER], rw, ro;
+
+  __device__ __forceinline__ void segment(const GrgParams& p, int tid) {
+    gip src = (gip)(p.seg_src + (size_t)s * NT);
+    const int g = tid / Q;
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const int t = g + G * q;
+      si[q] = (g < G && t < NT) ? src[t] : -1;
+    }
+    const SegDesc sd = p.segs[s];
+    base = (gdp)pick4(p.fam_base, sd.fam);
+    stride = pick4(p.fam_stride, sd.fam);
+    const int k = tid % Q;
+    rw = ((gd2p)sd.w_in)[k];
+    ro = ((gd2p)sd.w_out)[tid < MP ? tid : 0];
+  }
+  __device__ __forceinline__ void load(int tid) {
+    const int k = tid % Q;
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const bool ok = si[q] >= 0;
+      const d2 v = *(gd2p)(base + (size_t)(ok ? si[q] : 0) * stride + 2 * k);
+      rb[q] = ok ? v : d2{0.0, 0.0};
+    }
+  }
+  template <int LDB>
+  __device__ __forceinline__ void store(int tid, double* Bs, double* Ws) const {
+    const int k = tid % Q, g = tid / Q;
+    if (g < G) {
+#pragma unroll
+      for (int q = 0; q < B_PER; ++q) {
+        const int t = g + G * q;
+        if (NT % G == 0 || t < NT) {
+          const d2 v = rb[q];
+          Bs[cx_col(t, 0) * LDB + k] = v.x * rw.x - v.y * rw.y;
+          Bs[cx_col(t, 1) * LDB + k] = v.x * rw.y + v.y * rw.x;
+        }
+      }
+    }
+    if (tid < MP) reinterpret_cast<d2*>(Ws)[tid] = ro;
+  }
+  __device__ __forceinline__ void advance(const GrgParams& p, int tid) {
+    ++s;
+    segment(p, tid);
+  }
+};
+
 // One k-step (4 values of k) of the tile product for one wave: MT x NTT MFMA fragments.
 template <int MT, int NTT, int M, int LDB>
 __device__ __forceinline__ void mfma_step(const double* __restrict__ Aw, const double* __restrict__ Bw, int kk,
@@ -179,14 +247,21 @@ __device__ __forceinline__ void mfma_chunk(const double* __restrict__ Aw, const 
 // are added in thread order: a fixed order, so the result is repeatable.
 // Indices the epilogue of a tile needs, loaded when its piece starts so that their latency
 // hides behind the piece's products.
-template <int NTT, int NT, int NTHR>
+// In a factored stage column c of the tile is part (c / 16) % 2 (real, imaginary) of slot
+// (c / 32) 16 + c % 16 (the inverse of cx_col).
+__device__ __forceinline__ int cx_slot(int col) { return (col >> 5) * 16 + (col & 15); }
+
+template <int NTT, int NT, int NTHR, bool CX>
 struct EpiIdx {
   int tgt[NTT];
   double sc[NTT];
   int e0, e1;
   __device__ __forceinline__ void load(const GrgParams& p, int tile, int tid, int lane, int wn) {
 #pragma unroll
-    for (int j = 0; j < NTT; ++j) tgt[j] = p.tile_tgt[tile * NT + (wn * NTT + j) * 16 + (lane & 15)];
+    for (int j = 0; j < NTT; ++j) {
+      const int col = (wn * NTT + j) * 16 + (lane & 15);
+      tgt[j] = p.tile_tgt[tile * NT + (CX ? cx_slot(col) : col)];
+    }
     const int ti = tile * NT + tid / (NTHR / NT);
     e0 = p.r1_ptr[ti];
     e1 = p.r1_ptr[ti + 1];
@@ -195,8 +270,10 @@ struct EpiIdx {
   }
 };
 
-template <int MT, int NTT, int WM, int NT, int NTHR>
-__device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<NTT, NT, NTHR>& ix,
+// Factored stages (CX) have NT slots in 2 NT columns and write only the QV complex rows of
+// the padded core: reals 2 l and 2 l + 1 of each slot's expansion.
+template <int MT, int NTT, int WM, int NT, int NTHR, bool CX, int QV>
+__device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<NTT, NT, NTHR, CX>& ix,
                                               const d4 (&acc)[MT][NTT], double* r1s, double* r1p, int tid, int lane,
                                               int wm, int wn) {
   constexpr int TPS = NTHR / NT;
@@ -230,12 +307,16 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < NTT; ++j) {
-    const int slot = (wn * NTT + j) * 16 + (lane & 15);
+    const int col = (wn * NTT + j) * 16 + (lane & 15);
+    const int slot = CX ? cx_slot(col) : col;
+    const int part = CX ? (col >> 4) & 1 : 0;
     const int tgt = ix.tgt[j];
     if (tgt < 0) continue;
     const double sc = ix.sc[j];
     const double r1 = r1s[slot];
     double* __restrict__ o = p.out + (size_t)tgt * p.out_stride;
+    // output index of accumulator row `row` (-1: a padding row of a factored stage)
+    auto index = [&](int row) { return CX ? (row < QV ? 2 * row + part : -1) : row; };
     double prev[MT][4];
 #pragma unroll
     for (int i = 0; i < MT; ++i)
@@ -246,16 +327,20 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 #pragma unroll
       for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) prev[i][r] = a[(wm * MT + i) * 16 + 4 * r + (lane >> 4)];
+        for (int r = 0; r < 4; ++r) {
+          const int x = index((wm * MT + i) * 16 + 4 * r + (lane >> 4));
+          if (x >= 0) prev[i][r] = a[x];
+        }
     }
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = (wm * MT + i) * 16 + 4 * r + (lane >> 4);
+        const int x = index((wm * MT + i) * 16 + 4 * r + (lane >> 4));
+        if (x < 0) continue;
         double v = acc[i][j][r];
-        if (p.r1_all_rows || row == 0) v += r1;
-        o[row] = v * sc + prev[i][r];
+        if (p.r1_all_rows || x == 0) v += r1;
+        o[x] = v * sc + prev[i][r];
       }
   }
 }
@@ -270,20 +355,33 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 // for memory. Its k-chunk-16 form, which also runs the leaf stages that read expansions
 // (K = 64 or 80), is held to three (168 registers): those stages are latency-bound, and the
 // third block took 7% off them. The other instantiations keep the compiler's own choice.
-template <int MT, int NTT, int WM, int WN, int KC>
+// The factored M2L instantiations ask for three waves per SIMD (two for q = 40, whose
+// accumulators are half as large again).
+template <int MT, int NTT, int WM, int WN, int KC, bool CX>
 constexpr int min_blocks() {
-  return (MT == 4 && NTT == 2 && WM == 4 && WN == 1) ? (KC == 32 ? 2 : KC == 16 ? 3 : 1) : 1;
+  return (!CX && MT == 4 && NTT == 2 && WM == 4 && WN == 1) ? (KC == 32 ? 2 : KC == 16 ? 3 : 1) : 1;
 }
+template <int KC, bool CX>
+constexpr int waves_per_simd() { return CX ? (KC == 40 ? 2 : 3) : 1; }
 
-template <int MT, int NTT, int WM, int WN, int KC>
-__global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>())) grg_kernel(const GrgParams p) {
+// Factored M2L (CX): the tile's columns are the real and imaginary parts of NT = NCOL / 2 slots,
+// the table is the offset-free core (M padded rows, K = KC complex terms), held in LDS for the
+// whole launch. Each chunk is one whole segment (one offset): its sources are scaled by the
+// offset's input diagonal while staged, multiplied by the core into a fresh accumulator, and the
+// product is scaled by the offset's output diagonal (a complex multiply across each lane pair)
+// as it is added to the tile's sum.
+template <int MT, int NTT, int WM, int WN, int KC, bool CX>
+__global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC, CX>()))
+__attribute__((amdgpu_waves_per_eu(waves_per_simd<KC, CX>()))) grg_kernel(const GrgParams p) {
   constexpr int M = 16 * MT * WM;
-  constexpr int NT = 16 * NTT * WN;
+  constexpr int NCOL = 16 * NTT * WN;
+  constexpr int NT = CX ? NCOL / 2 : NCOL;  // slots
   constexpr int NTHR = 64 * WM * WN;
   constexpr int LDB = KC + 1;  // odd row stride: conflict-free B fragment reads
   constexpr int WPART = MT * NTT * 256;  // partial-sum doubles per wave
   __shared__ double As[M * KC];
-  __shared__ double Bs[NT * LDB];
+  __shared__ double Bs[NCOL * LDB];
+  __shared__ double Ws[CX ? 2 * M : 2];
   __shared__ double r1s[NT];
   __shared__ double r1p[NTHR];
   __shared__ int last_s;
@@ -294,10 +392,15 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
   const double* __restrict__ Aw = As + (wm * MT) * 64 + lane;
   const double* __restrict__ Bw = Bs + ((wn * NTT) * 16 + (lane & 15)) * LDB + (lane >> 4);
 
-  const int pc1 = p.blk_ptr[blk + 1];
-  for (int pc = p.blk_ptr[blk]; pc < pc1; ++pc) {
+  const int pc0 = p.blk_ptr[blk], pc1 = p.blk_ptr[blk + 1];
+  if (CX && pc0 < pc1) {  // the core, once (made visible by the first piece's barrier)
+    gd2p A2 = (gd2p)p.cx_core;
+    d2* As2 = reinterpret_cast<d2*>(As);
+    for (int i = tid; i < M * KC / 2; i += NTHR) As2[i] = A2[i];
+  }
+  for (int pc = pc0; pc < pc1; ++pc) {
     const PieceDesc P = p.pieces[pc];
-    EpiIdx<NTT, NT, NTHR> ix;
+    EpiIdx<NTT, NT, NTHR, CX> ix;
     ix.load(p, P.tile, tid, lane, wn);
     d4 acc[MT][NTT];
 #pragma unroll
@@ -306,7 +409,46 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
       for (int j = 0; j < NTT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     __syncthreads();  // the previous piece no longer reads LDS
 
-    if (P.n_chunks > 0) {
+    if constexpr (CX) {
+     if (P.n_chunks > 0) {
+      LoaderCX<NT, NTHR, KC, M> L;
+      L.s = P.seg;
+      L.segment(p, tid);
+      L.load(tid);
+      L.template store<LDB>(tid, Bs, Ws);
+      __syncthreads();
+      const d2* __restrict__ W2 = reinterpret_cast<const d2*>(Ws);
+      static_assert(!CX || NTT == 2, "a factored wave holds both parts of its slots");
+      for (int left = P.n_chunks;;) {
+        const bool more = --left > 0;
+        if (more) {  // next segment in flight while this one is multiplied
+          L.advance(p, tid);
+          L.load(tid);
+        }
+        d4 part[MT][NTT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < NTT; ++j) part[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        mfma_chunk<MT, NTT, M, LDB, KC>(Aw, Bw, part);
+        // acc += w_out[l] * part, complex: fragment 0 holds the real and fragment 1 the
+        // imaginary part of (l, slot) in the same lane
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const d2 w = W2[(wm * MT + i) * 16 + 4 * r + (lane >> 4)];
+            const double re = part[i][0][r], im = part[i][NTT - 1][r];
+            acc[i][0][r] = fma(w.x, re, fma(-w.y, im, acc[i][0][r]));
+            acc[i][NTT - 1][r] = fma(w.x, im, fma(w.y, re, acc[i][NTT - 1][r]));
+          }
+        if (!more) break;
+        __syncthreads();  // every wave is done reading the segment and its weights
+        L.template store<LDB>(tid, Bs, Ws);
+        __syncthreads();  // the next segment is visible
+      }
+     }
+    } else if (P.n_chunks > 0) {
       Loader<M, NT, NTHR, KC> L;
       L.s = P.seg;
       L.k0 = P.k0;
@@ -337,7 +479,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
       // the barrier); compiler-only fences keep the compiler from moving any of the atomics
       // across them. An agent-scope acquire on the counter would invalidate the L2 of the block's
       // XCD (every other block's table lines with it).
-      double* __restrict__ mine = p.partial + (size_t)P.slot * (M * NT) + wave * WPART + lane;
+      double* __restrict__ mine = p.partial + (size_t)P.slot * (M * NCOL) + wave * WPART + lane;
 #pragma unroll
       for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -356,7 +498,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (!last_s) continue;
       for (int q = 0; q < P.n_pieces; ++q) {
-        const double* __restrict__ part = p.partial + (size_t)(P.slot0 + q) * (M * NT) + wave * WPART + lane;
+        const double* __restrict__ part = p.partial + (size_t)(P.slot0 + q) * (M * NCOL) + wave * WPART + lane;
 #pragma unroll
         for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -370,7 +512,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (min_blocks<MT, NTT, WM, WN, KC>
       }
       if (tid == 0) __hip_atomic_store(p.tile_count + P.tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    tile_epilogue<MT, NTT, WM, NT, NTHR>(p, ix, acc, r1s, r1p, tid, lane, wm, wn);
+    tile_epilogue<MT, NTT, WM, NT, NTHR, CX, KC>(p, ix, acc, r1s, r1p, tid, lane, wm, wn);
   }
 }
 
@@ -407,33 +549,53 @@ __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__
   X(32, 64, 16, 2, 1, 1, 4, 256) X(32, 32, 16, 2, 1, 1, 2, 128) X(32, 16, 16, 2, 1, 1, 1, 64)     \
   X(32, 64, 32, 2, 1, 1, 4, 256) X(32, 32, 32, 2, 1, 1, 2, 128) X(32, 16, 32, 2, 1, 1, 1, 64)
 
-hipError_t launch_grg(int M, int NT, int KC, const GrgParams& p, hipStream_t stream) {
+// Factored M2L instantiations: padded core rows, slots, complex terms q (= k-chunk); MT, NTT, WM,
+// WN, threads (2 NT columns in 16-wide fragments, two per wave)
+#define VP_CONFIGS_CX(X)                                                                          \
+  X(48, 16, 40, 3, 2, 1, 1, 64) X(48, 32, 40, 3, 2, 1, 2, 128) X(48, 64, 40, 3, 2, 1, 4, 256)     \
+  X(32, 16, 32, 2, 2, 1, 1, 64) X(32, 32, 32, 2, 2, 1, 2, 128) X(32, 64, 32, 2, 2, 1, 4, 256)     \
+  X(32, 16, 24, 2, 2, 1, 1, 64) X(32, 32, 24, 2, 2, 1, 2, 128) X(32, 64, 24, 2, 2, 1, 4, 256)     \
+  X(16, 16, 16, 1, 2, 1, 1, 64) X(16, 32, 16, 1, 2, 1, 2, 128) X(16, 64, 16, 1, 2, 1, 4, 256)
+
+hipError_t launch_grg(int M, int NT, int KC, bool factored, const GrgParams& p, hipStream_t stream) {
   if (p.n_blocks <= 0) return hipSuccess;
   dim3 grid(p.n_blocks);
 #define VP_LAUNCH(m, nt, kc, MT, NTT, WM, WN, THR)                                                  \
-  if (M == m && NT == nt && KC == kc) {                                                           \
-    hipLaunchKernelGGL((grg_kernel<MT, NTT, WM, WN, kc>), grid, dim3(THR), 0, stream, p);          \
+  if (!factored && M == m && NT == nt && KC == kc) {                                              \
+    hipLaunchKernelGGL((grg_kernel<MT, NTT, WM, WN, kc, false>), grid, dim3(THR), 0, stream, p);   \
     return hipGetLastError();                                                                     \
   }
   VP_CONFIGS(VP_LAUNCH)
 #undef VP_LAUNCH
+#define VP_LAUNCH_CX(m, nt, kc, MT, NTT, WM, WN, THR)                                               \
+  if (factored && M == m && NT == nt && KC == kc) {                                               \
+    hipLaunchKernelGGL((grg_kernel<MT, NTT, WM, WN, kc, true>), grid, dim3(THR), 0, stream, p);    \
+    return hipGetLastError();                                                                     \
+  }
+  VP_CONFIGS_CX(VP_LAUNCH_CX)
+#undef VP_LAUNCH_CX
   return hipErrorInvalidValue;
 }
 
-int grg_resident_blocks(int M, int NT, int KC) {
+int grg_resident_blocks(int M, int NT, int KC, bool factored) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-#define VP_OCC(m, nt, kc, MT, NTT, WM, WN, THR)                                                     \
-  if (M == m && NT == nt && KC == kc) {                                                           \
+#define VP_OCC(m, nt, kc, MT, NTT, WM, WN, THR, CXV)                                                \
+  if (factored == CXV && M == m && NT == nt && KC == kc) {                                        \
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                             \
-            &per_cu, reinterpret_cast<const void*>(&grg_kernel<MT, NTT, WM, WN, kc>), THR, 0) !=  \
+            &per_cu, reinterpret_cast<const void*>(&grg_kernel<MT, NTT, WM, WN, kc, CXV>), THR, 0) != \
         hipSuccess)                                                                               \
       return 0;                                                                                   \
     return per_cu * cus;                                                                          \
   }
-  VP_CONFIGS(VP_OCC)
+#define VP_OCC_D(m, nt, kc, MT, NTT, WM, WN, THR) VP_OCC(m, nt, kc, MT, NTT, WM, WN, THR, false)
+#define VP_OCC_C(m, nt, kc, MT, NTT, WM, WN, THR) VP_OCC(m, nt, kc, MT, NTT, WM, WN, THR, true)
+  VP_CONFIGS(VP_OCC_D)
+  VP_CONFIGS_CX(VP_OCC_C)
+#undef VP_OCC_C
+#undef VP_OCC_D
 #undef VP_OCC
   return 0;
 }

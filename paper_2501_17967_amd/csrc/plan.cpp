@@ -317,6 +317,11 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
   st.r1_idx.clear(); st.r1_fam.clear(); st.r1_coef.clear();
   st.flops = 0; st.n_pairs = 0; st.flops_issued = 0;
   std::vector<int32_t> seg_of(size_t(kNumRel) * 16, -1), used;
+  // a factored stage multiplies every segment by its core (cx_rel) and reads 2 K reals per source
+  const bool cx = st.cx_rel >= 0;
+  auto table = [&](int rel) { return cx ? st.cx_rel : rel; };
+  auto src_len = [&](int rel) { return cx ? 2 * mats.K[size_t(st.cx_rel)] : mats.K[size_t(rel)]; };
+  if (cx && (st.cx_rel >= kNumRel || st.KC != mats.K[size_t(st.cx_rel)])) throw std::runtime_error("bad factored stage");
   for (int t = 0; t < st.n_tiles; ++t) {
     // segments keyed by (relation, source family), ordered by relation then family
     used.clear();
@@ -327,10 +332,11 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
       for (const Entry& e : entries[ti]) {
         // the kernel reads M x K of the relation's table and K values of each source
         if (e.rel < 0 || e.rel >= kNumRel || e.fam < 0 || e.fam >= 4) throw std::runtime_error("bad entry");
-        if (mats.M[e.rel] != st.M) throw std::runtime_error("relation rows differ from stage rows");
-        if (st.fam[e.fam].stride < mats.K[e.rel]) throw std::runtime_error("source shorter than relation");
+        if (cx && mats.w_in[size_t(e.rel)].empty()) throw std::runtime_error("relation has no factored form");
+        if (mats.M[table(e.rel)] != st.M) throw std::runtime_error("relation rows differ from stage rows");
+        if (st.fam[e.fam].stride < src_len(e.rel)) throw std::runtime_error("source shorter than relation");
         // the kernel walks K in full chunks of KC
-        if (mats.K[e.rel] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
+        if (mats.K[table(e.rel)] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
         const int32_t key = e.rel * 16 + e.fam;
         if (seg_of[size_t(key)] < 0) {
           seg_of[size_t(key)] = 0;
@@ -342,9 +348,9 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
     for (int32_t key : used) {
       seg_of[size_t(key)] = int32_t(st.seg_rel.size());
       st.seg_rel.push_back(key / 16);
-      st.seg_k.push_back(mats.K[key / 16]);
+      st.seg_k.push_back(mats.K[table(key / 16)]);
       st.seg_fam.push_back(int8_t(key % 16));
-      st.flops_issued += 2.0 * st.M * mats.K[key / 16] * NT;
+      st.flops_issued += 2.0 * st.M * mats.K[table(key / 16)] * NT * (cx ? 2 : 1);
     }
     st.seg_src.resize(st.seg_rel.size() * NT, -1);
     for (int s = 0; s < NT; ++s) {
@@ -354,7 +360,8 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
         int32_t& slot = st.seg_src[size_t(seg_of[size_t(e.rel * 16 + e.fam)]) * NT + s];
         if (slot != -1) throw std::runtime_error("duplicate relation for one target");
         slot = e.src;
-        st.flops += 2.0 * mats.nnz[e.rel];
+        // factored: the core on both parts, then the two complex diagonals (6 and 8 flops a term)
+        st.flops += cx ? 4.0 * mats.nnz[size_t(st.cx_rel)] + 14.0 * mats.K[size_t(st.cx_rel)] : 2.0 * mats.nnz[e.rel];
         st.n_pairs += 1;
       }
     }
@@ -532,7 +539,8 @@ void build_schedule(Stage& st, int max_blocks, int min_units, int tile_cost) {
 
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
                int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer,
-               const PointTargets* points, const RootBox& root, int tile_leaf_exp, int ne, int kchunk_leaf) {
+               const PointTargets* points, const RootBox& root, int tile_leaf_exp, int ne, int kchunk_leaf,
+               bool dense_m2l) {
   if (!(ne == 32 || ne == 48 || ne == 64 || ne == 80)) return VOLPOT_ERR_UNSUPPORTED;
   if ((layer || points) && ne != kNE) return VOLPOT_ERR_UNSUPPORTED;  // their kernels take 40 terms
   const int kNE = ne;  // reals per expansion of this plan (the namespace constant is the default)
@@ -840,6 +848,13 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (auto& f : st.fam) f = {A_NONE, 0, 0};
     for (auto& f : st.r1fam) f = {A_NONE, 0, 0};
   };
+  // the factored M2L: rows of the padded core, K and the k-chunk in complex terms (one chunk a
+  // segment); the output keeps its 2q reals per box
+  auto m2l_factored = [&](Stage& st, bool adj) {
+    st.cx_rel = kRelH + (adj ? kNumFwd : 0);
+    st.M = mats.M[size_t(st.cx_rel)];
+    st.K = st.KC = mats.K[size_t(st.cx_rel)];
+  };
   // boxes at levels >= 2 ordered by (level, quadrant, tree, morton): targets of one tile then
   // share their V-list offset pattern
   std::vector<int32_t> deep_by_quadrant;
@@ -989,6 +1004,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) { return cls[sig[size_t(x)]] < cls[sig[size_t(y)]]; });
     }
     Stage st; init_stage(st, K_DOWN, "FARV", -1, kNE, kNE, NTB, A_FAR, kNE);
+    if (!dense_m2l) m2l_factored(st, false);
     st.fam[0] = {A_MP, kNE, 0};
     st.r1fam[0] = {A_MP, kNE, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -996,8 +1012,12 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     par_for(int64_t(tg.size()), [&](int64_t i) {
       int32_t b = tg[size_t(i)];
       double ls = lnS(P.box_level[b]);
+      // the factored form leaves the ln|d| a_0 term of each pair to the rank-one terms
       for (auto& e : Vlist[b])
-        if (use(e.second)) { E[size_t(i)].push_back({kRelM2L + e.first, 0, e.second}); R[size_t(i)].push_back({0, e.second, ls}); }
+        if (use(e.second)) {
+          E[size_t(i)].push_back({kRelM2L + e.first, 0, e.second});
+          R[size_t(i)].push_back({0, e.second, ls + (dense_m2l ? 0.0 : mats.lnd[size_t(kRelM2L + e.first)])});
+        }
       if (!layer)
         for (auto& e : Xlist[b]) R[size_t(i)].push_back({0, P.leaf_box[e.second], ls});
     });
@@ -1176,6 +1196,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   {  // AFARV: M2L^T plus every log term
     const auto& tg = afar_tg;
     Stage st; init_stage(st, K_ADOWN, "AFARV", -1, kNE, kNE, NTB, A_AFAR, kNE);
+    if (!dense_m2l) m2l_factored(st, true);
     st.fam[0] = {A_LB, kNE, 0};
     st.r1fam[0] = {A_LB, kNE, 0}; st.r1fam[1] = {A_USUM, 1, 0};
     std::vector<std::vector<Entry>> E(tg.size());
@@ -1184,7 +1205,10 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       const size_t i = size_t(ii);
       int32_t b = tg[i];
       double ls = lnS(P.box_level[b]);
-      for (auto& e : Vinv[b]) { E[i].push_back({kRelM2L + e.first + kNumFwd, 0, e.second}); R[i].push_back({0, e.second, ls}); }
+      for (auto& e : Vinv[b]) {
+        E[i].push_back({kRelM2L + e.first + kNumFwd, 0, e.second});
+        R[i].push_back({0, e.second, ls + (dense_m2l ? 0.0 : mats.lnd[size_t(kRelM2L + e.first)])});
+      }
       for (auto& e : Winv[b]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
       int32_t leaf = P.box_leaf[b];
       if (leaf >= 0) {

@@ -58,7 +58,12 @@ constexpr int kRelM2T = 102;  // +20 offsets
 constexpr int kRelL2T = 122;
 constexpr int kRelM2M2 = 123; // +4 qc + qg: M2M_qc M2M_qg, grandchild (quadrant qg of child qc) to box
 constexpr int kRelL2L2 = 139; // +4 qc + qg: L2L_qg L2L_qc, box to grandchild
-constexpr int kNumFwd = 155;
+// The core of the factored M2L: K_r = diag(d^-l) H diag((-1)^k d^-k) + ln|d| e0 e0^T, with H the
+// real, offset-free matrix H[0][0] = 0, H[0][k] = 1, H[l][0] = -1/l, H[l][k] = C(k+l-1, l),
+// acting on the real and imaginary parts alike. Stored with its q rows padded to a multiple of
+// 16 (zero rows), q columns; the adjoint id holds H^T padded the same way.
+constexpr int kRelH = 155;
+constexpr int kNumFwd = 156;
 constexpr int kNumRel = 2 * kNumFwd;
 
 struct Offset { double dx, dy, rho; };
@@ -74,7 +79,14 @@ struct Matrices {
   std::vector<int> M, K;
   std::vector<std::vector<double>> a;
   std::vector<double> nnz;  // non-zero count of each
+  // M2L relations (forward and adjoint ids) in factored form: the complex diagonals applied to
+  // the source before kRelH (w_in, q values) and to the product after it (w_out, q values and
+  // zeros up to the padded row count), interleaved (Re, Im); ln|d| of the offset (lnd).
+  // The adjoint takes the conjugates, in swapped roles.
+  std::vector<std::vector<double>> w_in, w_out;
+  std::vector<double> lnd;
 };
+constexpr int pad16(int n) { return (n + 15) / 16 * 16; }
 // The relation matrices for expansions of q complex terms (order q - 1; q = 16, 24, 32 or 40),
 // built once per process and q; the near tables (polar quadrature) are the same for every q.
 const Matrices& matrices(int q = kTerms);
@@ -120,6 +132,10 @@ struct Stage {
   int NT = 0;      // slots per tile
   int K = 0;       // inner dimension shared by every relation of the stage
   int KC = 0;      // k-chunk of the kernel instantiation
+  // >= 0: factored M2L (kRelH or its adjoint id): every segment multiplies by this core, between
+  // the complex diagonals of its own relation; K is then in complex terms, one chunk per
+  // segment, and the tile's columns are the real and imaginary parts of its slots
+  int cx_rel = -1;
   double flops_issued = 0;  // MFMA work of the tiles, empty slots included
   int n_tiles = 0;
   int8_t out_arr = A_NONE;
@@ -234,6 +250,7 @@ struct RootBox {
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
                const LayerSources* layer = nullptr, const PointTargets* points = nullptr,
-               const RootBox& root = RootBox(), int tile_leaf_exp = 16, int ne = kNE, int kchunk_leaf = 32);
+               const RootBox& root = RootBox(), int tile_leaf_exp = 16, int ne = kNE, int kchunk_leaf = 32,
+               bool dense_m2l = false);
 
 }  // namespace vp

@@ -508,6 +508,9 @@ static Matrices build_matrices(const int Q) {
   M.K.assign(kNumRel, 0);
   M.a.assign(kNumRel, {});
   M.nnz.assign(kNumRel, 0.0);
+  M.w_in.assign(kNumRel, {});
+  M.w_out.assign(kNumRel, {});
+  M.lnd.assign(kNumRel, 0.0);
   const Basis& B = basis();
   std::vector<cd> xi(kNP);
   for (int m = 0; m < kNP; ++m) xi[m] = cd(B.t[m % kP], B.t[m / kP]);
@@ -571,6 +574,31 @@ static Matrices build_matrices(const int Q) {
     std::vector<double> R;
     real_from_linear(K, Q, Q, R);
     set(kRelM2L + int(r), kNE, kNE, std::move(R));
+    // the same map factored: w_out = d^-l, w_in = (-1)^k d^-k around the core kRelH; the
+    // adjoint (the real transpose) conjugates both diagonals and swaps their roles
+    const int id = kRelM2L + int(r), ia = id + kNumFwd, QP = pad16(Q);
+    M.w_in[id].assign(size_t(2 * Q), 0.0);
+    M.w_out[id].assign(size_t(2 * QP), 0.0);
+    M.w_in[ia].assign(size_t(2 * Q), 0.0);
+    M.w_out[ia].assign(size_t(2 * QP), 0.0);
+    for (int k = 0; k < Q; ++k) {
+      const cd dl = std::pow(d, -k), dr = ((k & 1) ? -1.0 : 1.0) * dl;
+      M.w_out[id][size_t(2 * k)] = dl.real(); M.w_out[id][size_t(2 * k + 1)] = dl.imag();
+      M.w_in[id][size_t(2 * k)] = dr.real(); M.w_in[id][size_t(2 * k + 1)] = dr.imag();
+      M.w_in[ia][size_t(2 * k)] = dl.real(); M.w_in[ia][size_t(2 * k + 1)] = -dl.imag();
+      M.w_out[ia][size_t(2 * k)] = dr.real(); M.w_out[ia][size_t(2 * k + 1)] = -dr.imag();
+    }
+    M.lnd[id] = M.lnd[ia] = std::log(std::abs(d));
+  }
+  {  // the offset-free core of the factored M2L, rows padded to a multiple of 16
+    const int QP = pad16(Q);
+    std::vector<double> H(size_t(QP) * Q, 0.0);
+    for (int k = 1; k < Q; ++k) H[size_t(k)] = 1.0;
+    for (int l = 1; l < Q; ++l) {
+      H[size_t(l) * Q] = -1.0 / double(l);
+      for (int k = 1; k < Q; ++k) H[size_t(l) * Q + k] = binom_exact(k + l - 1, l);
+    }
+    set(kRelH, QP, Q, std::move(H));
   }
   // S2L_r: source leaf (rho = 2) at d = (source - target centre) / s_target
   const auto& XO = x_offsets();
@@ -621,6 +649,14 @@ static Matrices build_matrices(const int Q) {
     for (int i = 0; i < r; ++i)
       for (int j = 0; j < c; ++j) T[size_t(j) * r + i] = M.a[id][size_t(i) * c + j];
     set(id + kNumFwd, c, r, std::move(T));
+  }
+  {  // the core's transpose keeps the padded shape: rows k (padded), columns l
+    const int QP = pad16(Q);
+    const std::vector<double>& H = M.a[kRelH];
+    std::vector<double> T(size_t(QP) * Q, 0.0);
+    for (int l = 0; l < Q; ++l)
+      for (int k = 0; k < Q; ++k) T[size_t(k) * Q + l] = H[size_t(l) * Q + k];
+    set(kRelH + kNumFwd, QP, Q, std::move(T));
   }
   for (int id = 0; id < kNumRel; ++id) {
     double n = 0;

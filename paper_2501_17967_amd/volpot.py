@@ -54,11 +54,12 @@ class Options(ctypes.Structure):
     _fields_ = [("host_only", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_leaf", ctypes.c_int32),
                 ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double),
-                ("tile_leaf_exp", ctypes.c_int32), ("eps", ctypes.c_double), ("kchunk_leaf", ctypes.c_int32)]
+                ("tile_leaf_exp", ctypes.c_int32), ("eps", ctypes.c_double), ("kchunk_leaf", ctypes.c_int32),
+                ("dense_m2l", ctypes.c_int32)]
 
 
 def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0,
-             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0):
+             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False):
     o = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
                 table_cache.encode() if table_cache else None, int(split_min), int(overlap))
     o.root_centre[0], o.root_centre[1] = float(root_centre[0]), float(root_centre[1])
@@ -66,6 +67,7 @@ def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_ca
     o.tile_leaf_exp = int(tile_leaf_exp)
     o.eps = float(eps)
     o.kchunk_leaf = int(kchunk_leaf)
+    o.dense_m2l = int(bool(dense_m2l))
     return o
 
 
@@ -87,7 +89,8 @@ class StageInfo(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("kind", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("kchunk", ctypes.c_int32), ("helper", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int64), ("n_segments", ctypes.c_int64), ("n_blocks", ctypes.c_int64),
-                ("n_split_tiles", ctypes.c_int64), ("flops", ctypes.c_double), ("flops_issued", ctypes.c_double)]
+                ("n_split_tiles", ctypes.c_int64), ("flops", ctypes.c_double), ("flops_issued", ctypes.c_double),
+                ("inner", ctypes.c_int32), ("factored", ctypes.c_int32)]
 
 
 _lib = None
@@ -170,16 +173,16 @@ def _host_tree(centres, levels):
     return c, l
 
 
-def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None, eps=0.0):
+def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None, eps=0.0, dense_m2l=False):
     """Fastest launch shape for this tree or forest on the current device (volpot_autotune):
     returns ({"tile_leaf", "tile_box", "split_min", "overlap", "tile_leaf_exp", "kchunk_leaf"}, ms per
     forward + adjoint apply). The candidates are timed at the expansion order that the far-field
-    tolerance ``eps`` selects (0: the default). The result is looked up in / appended to the
-    text file ``cache`` when given."""
+    tolerance ``eps`` selects (0: the default), with the M2L form ``dense_m2l`` selects. The
+    result is looked up in / appended to the text file ``cache`` when given."""
     c, l = _host_tree(centres, levels)
     off = np.ascontiguousarray(np.asarray([0, c.shape[0]] if tree_offsets is None else tree_offsets, dtype=np.int64))
     best = Options()
-    base = _options(eps=eps)
+    base = _options(eps=eps, dense_m2l=dense_m2l)
     ms = ctypes.c_double(0.0)
     _check(lib().volpot_autotune(off.size - 1, off.ctypes.data_as(_lp), c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), p,
                                  ctypes.byref(base), cache.encode() if cache else None, ctypes.byref(best),
@@ -304,11 +307,11 @@ class Plan:
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
                  tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0),
-                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0):
+                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
-                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf)
+                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf, dense_m2l)
         h = _vp()
         L = lib()
         if tree_offsets is None:

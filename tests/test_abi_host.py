@@ -156,8 +156,8 @@ def test_schedules_cover_stages(vp, split_min):
         for s in plan.stages(adj):
             if s["n_tiles"] == 0:
                 continue
-            chunks = (256 if s["rows"] == 80 and s["kchunk"] == 32 else 80 if s["rows"] == 80 else
-                      256 if s["kchunk"] == 32 else 80) // s["kchunk"]
+            chunks = s["inner"] // s["kchunk"]  # k-chunks per segment (one in a factored stage)
+            assert chunks * s["kchunk"] == s["inner"], s
             # every tile here has at least one segment; its fixed cost counts as one more
             units = (s["n_segments"] + s["n_tiles"]) * chunks
             if split_min == -1:

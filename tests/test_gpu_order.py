@@ -51,3 +51,30 @@ def test_orders_meet_their_bounds(device, oracle_results):
             # sums cancel), about 1e-13 of its max-norm at the highest orders
             assert ef <= BOUND[P] and ea <= max(BOUND[P], 1e-12), (P, w.name, ef, ea)
     assert worst[15] > worst[23] > worst[31]
+
+
+@pytest.mark.parametrize("P", [15, 23, 31, 39])
+def test_factored_m2l_matches_the_dense_form(device, oracle_results, P):
+    # the factored M2L (offset-free core between two complex diagonals, the ln|d| a_0 term among
+    # the rank-one terms) and the dense per-offset matrices compute the same map: forward and
+    # adjoint agree to rounding, and the factored plan meets the order's bound against the oracle
+    import torch
+
+    from paper_2501_17967_amd import Plan
+
+    for w, r, u_o, fb_o in oracle_results[:3]:
+        f, rr = torch.from_numpy(w.f).to(device), torch.from_numpy(r).to(device)
+        out = {}
+        for dense in (False, True):
+            plan = Plan(w.centres, w.levels, eps=BOUND[P], dense_m2l=dense)
+            farv = [s for s in plan.stages() + plan.stages(adjoint=True) if s["name"] in ("FARV", "AFARV")]
+            assert len(farv) == 2 and all(s["factored"] == (not dense) for s in farv)
+            out[dense] = (plan.apply(f).cpu().numpy(), plan.apply_adjoint(rr).cpu().numpy())
+            plan.close()
+        df = rel_max_err(out[False][0], out[True][0])
+        da = rel_max_err(out[False][1], out[True][1])
+        ef = rel_max_err(out[False][0], u_o)
+        print("order %d, %s: factored vs dense %.2e / %.2e (fwd / adj), factored vs oracle %.2e"
+              % (P, w.name, df, da, ef), flush=True)
+        assert df <= 1e-13 and da <= 1e-12, (P, w.name, df, da)
+        assert ef <= BOUND[P], (P, w.name, ef)
