@@ -12,8 +12,9 @@
 // the value rows (a selection of m = n_r - 2 entries) and to k + 1 only through the m derivative
 // rows, so every coupling has rank m. The Dirichlet unknowns are zero, so only the interior rows
 // and columns of a block (Bi = m q of them, a contiguous range) enter. The factorization:
-//   host   assembly of the interior blocks A_k (row-equilibrated) and couplings U~_k
-//   GPU    A_k^-1 for all elements (batched blocked Gauss-Jordan on FP64 MFMA) and
+//   host   nodes, differentiation matrices, inverse-map factors and interface normals
+//   GPU    assembly of the interior blocks A_k (row-equilibrated), the couplings U~_k and the
+//          row scales; A_k^-1 for all elements (batched blocked Gauss-Jordan on FP64 MFMA) and
 //          R_k = U~_{k-1} A_k^-1 (strip_factor.hip)
 //   host   the block elimination of the non-periodic part on m x m pieces only:
 //          D_k = A_k + P'_k M_k U~_{k-1}, M_k = E_{k-1}[S, P], E_k = D_k^-1 = A_k^-1 - C_k MG_k R_k
@@ -151,16 +152,16 @@ void parallel_for(int n, Fn fn) {  // rethrows the first exception a task threw
 
 struct StripHost {
   int n = 0, q = 0, nr = 0, B = 0, m = 0, Bi = 0, N = 0;  // N: Bi rounded up to a multiple of 16
-  std::vector<double> X;   // n * B * 2 node coordinates
-  std::unique_ptr<double[]> A;  // n * N * N: interior blocks, column-major, identity beyond Bi
-                                // (zeroed per element, in parallel, by assemble)
-  std::vector<double> U;   // n * m * Bi: derivative rows of element k on element k + 1's interior
-  std::vector<double> rs;  // n * B: row scale of each PDE row (1 elsewhere)
+  std::vector<double> X;    // n * B * 2 node coordinates
+  std::vector<double> met;  // n * 6 * B: xi_x, xi_y, eta_x, eta_y, x_xi, y_xi per node
+  std::vector<double> nrm;  // n * 2: unit normal of the interface between element k and k + 1
+  std::vector<double> Dq, Dr;  // differentiation along the panels (q x q) and across (nr x nr)
 };
 
-// Nodes, operators and the row-equilibrated interior blocks.
+// Nodes, differentiation matrices, the inverse-map factors of every node and the interface
+// normals; the blocks themselves are assembled on the GPU from these (strip_factor.hip).
 void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl) {
-  const int n = S.n, q = S.q, nr = S.nr, B = S.B, m = S.m, Bi = S.Bi, N = S.N;
+  const int n = S.n, q = S.q, nr = S.nr, B = S.B;
   std::vector<double> sg;
   gauss_legendre(n_gl, sg);
   const auto tq = cheb2(q), tr = cheb2(nr);
@@ -195,15 +196,16 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
         S.X[((size_t(k) * B) + size_t(i) * q + j) * 2 + 1] = a * yt + c * y;
       }
     }
-  const Mat Dq = diff_matrix(tq), Dr = diff_matrix(tr);
+  S.Dq = diff_matrix(tq);
+  S.Dr = diff_matrix(tr);
+  const Mat& Dq = S.Dq;
+  const Mat& Dr = S.Dr;
   // per element and node: the inverse-map factors of D_X = M[xi_x] D_xi + M[eta_x] D_eta (and
-  // D_Y), and x_xi, y_xi (the orientation of the interface normal). Row (i, j) of D_X has its
-  // nonzeros in grid row i (xi_x Dq[j][.]) and grid column j (eta_x Dr[i][.]).
-  struct Metric { std::vector<double> xix, xiy, etx, ety, xxi, yxi; };
-  std::vector<Metric> met(static_cast<size_t>(n));
+  // D_Y), and x_xi, y_xi (the orientation of the interface normal)
+  S.met.assign(size_t(n) * 6 * B, 0.0);
+  S.nrm.assign(size_t(n) * 2, 0.0);
   parallel_for(n, [&](int k) {
-    Metric& o = met[size_t(k)];
-    for (auto* v : {&o.xix, &o.xiy, &o.etx, &o.ety, &o.xxi, &o.yxi}) v->assign(size_t(B), 0.0);
+    double* o = S.met.data() + size_t(k) * 6 * B;
     const double* Xk = S.X.data() + size_t(k) * B * 2;
     for (int i = 0; i < nr; ++i)
       for (int j = 0; j < q; ++j) {
@@ -219,83 +221,20 @@ void assemble(StripHost& S, const double* gamma, const double* gamma_t, int n_gl
         const double J = xxi * yeta - xeta * yxi;
         if (!(std::fabs(J) > 0.0) || !std::isfinite(J)) throw std::invalid_argument("degenerate element map");
         const size_t r = size_t(i) * q + j;
-        o.xix[r] = yeta / J;
-        o.xiy[r] = -xeta / J;
-        o.etx[r] = -yxi / J;
-        o.ety[r] = xxi / J;
-        o.xxi[r] = xxi;
-        o.yxi[r] = yxi;
+        o[r] = yeta / J;
+        o[B + r] = -xeta / J;
+        o[2 * B + r] = -yxi / J;
+        o[3 * B + r] = xxi / J;
+        o[4 * B + r] = xxi;
+        o[5 * B + r] = yxi;
       }
-  });
-  // v += sx D_X[row] + sy D_Y[row] of element o (dense B vector)
-  auto add_grad = [&](const Metric& o, int row, double sx, double sy, double* v) {
-    const int i = row / q, j = row % q;
-    const double a = sx * o.xix[size_t(row)] + sy * o.xiy[size_t(row)];
-    const double e = sx * o.etx[size_t(row)] + sy * o.ety[size_t(row)];
-    for (int c = 0; c < q; ++c) v[size_t(i) * q + c] += a * Dq[size_t(j) * q + c];
-    for (int c = 0; c < nr; ++c) v[size_t(c) * q + j] += e * Dr[size_t(i) * nr + c];
-  };
-  S.A.reset(new double[size_t(n) * N * N]);
-  S.U.assign(size_t(n) * m * Bi, 0.0);
-  S.rs.assign(size_t(n) * B, 1.0);
-  parallel_for(n, [&](int k) {
-    const Metric& o = met[size_t(k)];
-    const Metric& on = met[size_t((k + 1) % n)];
-    double* Ak = S.A.get() + size_t(k) * N * N;  // column-major: (p, c) at c N + p
-    std::fill(Ak, Ak + size_t(N) * N, 0.0);
     // interface normal between element k and k + 1: the segment from Gamma's to Gamma~'s shared point
-    const double* Xk = S.X.data() + size_t(k) * B * 2;
     const double px = Xk[size_t(q - 1) * 2], py = Xk[size_t(q - 1) * 2 + 1];
     const double ptx = Xk[(size_t(nr - 1) * q + q - 1) * 2], pty = Xk[(size_t(nr - 1) * q + q - 1) * 2 + 1];
     const double len = std::hypot(ptx - px, pty - py);
     if (!(len > 0.0) || !std::isfinite(len)) throw std::invalid_argument("degenerate interface");
-    const double nx = (pty - py) / len, ny = -(ptx - px) / len;
-    std::vector<double> rowv(static_cast<size_t>(B)), uvec(static_cast<size_t>(B)), dx(static_cast<size_t>(B)),
-        dy(static_cast<size_t>(B));
-    for (int i = 1; i < nr - 1; ++i)
-      for (int j = 0; j < q; ++j) {
-        const int row = i * q + j, p = row - q;  // p: interior index
-        if (j == 0) {  // value row: unit coefficient here, -1 on the previous element's last column
-          Ak[size_t(p) * N + p] = 1.0;
-          continue;
-        }
-        std::fill(rowv.begin(), rowv.end(), 0.0);
-        double nrm = 0.0;
-        if (j == q - 1) {  // derivative along the interface normal, oriented along increasing j
-          double sx = nx, sy = ny;
-          if (sx * o.xxi[size_t(row)] + sy * o.yxi[size_t(row)] < 0) { sx = -sx; sy = -sy; }
-          std::fill(uvec.begin(), uvec.end(), 0.0);
-          add_grad(o, row, sx, sy, rowv.data());
-          add_grad(on, i * q, -sx, -sy, uvec.data());  // the next element's first-column node
-          for (int c = 0; c < B; ++c) nrm += std::fabs(rowv[size_t(c)]) + std::fabs(uvec[size_t(c)]);
-        } else {  // Laplacian row (D_X D_X + D_Y D_Y)[row] = sum_c D_X[row][c] D_X[c] + D_Y[row][c] D_Y[c]
-          std::fill(dx.begin(), dx.end(), 0.0);
-          std::fill(dy.begin(), dy.end(), 0.0);
-          add_grad(o, row, 1.0, 0.0, dx.data());
-          add_grad(o, row, 0.0, 1.0, dy.data());
-          auto term = [&](int c) {
-            if (dx[size_t(c)] != 0.0 || dy[size_t(c)] != 0.0) add_grad(o, c, dx[size_t(c)], dy[size_t(c)], rowv.data());
-          };
-          for (int c = 0; c < q; ++c) term(i * q + c);            // grid row i
-          for (int c = 0; c < nr; ++c)
-            if (c != i) term(c * q + j);                           // grid column j
-          for (int c = 0; c < B; ++c) nrm += std::fabs(rowv[size_t(c)]);
-        }
-        // Row equilibration: the Laplacian rows have 1-norms up to ~1e7 (spectral second
-        // derivatives on thin elements), the value rows 2. Scaling the PDE and derivative rows
-        // (with their coupling to element k + 1) to unit 1-norm leaves the solution unchanged and
-        // keeps the block inverses and the sweeps well conditioned; the right-hand side of a PDE
-        // row is scaled with it (rs, applied on the GPU). The Dirichlet columns are dropped (the
-        // unknowns there are zero).
-        const double sc = 1.0 / nrm;
-        for (int c = 0; c < Bi; ++c) Ak[size_t(c) * N + p] = sc * rowv[size_t(q + c)];
-        if (j == q - 1) {
-          for (int c = 0; c < Bi; ++c) S.U[(size_t(k) * m + (i - 1)) * Bi + c] = sc * uvec[size_t(q + c)];
-        } else {
-          S.rs[size_t(k) * B + row] = sc;
-        }
-      }
-    for (int p = Bi; p < N; ++p) Ak[size_t(p) * N + p] = 1.0;  // padding
+    S.nrm[size_t(k) * 2] = (pty - py) / len;
+    S.nrm[size_t(k) * 2 + 1] = -(ptx - px) / len;
   });
 }
 
@@ -406,8 +345,8 @@ namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// The factorization: host assembly, GPU inverses, host chain, GPU blocks; the apply's arrays
-// in one allocation (s->block).
+// The factorization: host geometry, GPU assembly and inverses, host chain, GPU blocks; the
+// apply's arrays in one allocation (s->block).
 int strip_factor(volpot_strip_s* s, StripHost& H) {
   const int n = H.n, m = H.m, Bi = H.Bi, N = H.N, B = H.B, q = H.q;
   const size_t mm = size_t(m) * m, m2 = size_t(2) * m;
@@ -435,8 +374,14 @@ int strip_factor(volpot_strip_s* s, StripHost& H) {
   size_t w = 0;
   const size_t wA = w; w += al256(size_t(n) * N * N * 8);
   const size_t wAi = w; w += al256(size_t(n) * N * N * 8);
-  const size_t wRb = w; w += al256(size_t(n) * 16 * N * 8);
+  const size_t wPv = w; w += al256(size_t(n) * N * 4);
+  const size_t wPm = w; w += al256(size_t(n) * kPermInts * 4);
   const size_t wFl = w; w += al256(size_t(n) * 4);
+  const size_t wMt = w; w += al256(H.met.size() * 8);
+  const size_t wNm = w; w += al256(H.nrm.size() * 8);
+  const size_t wDq = w; w += al256(H.Dq.size() * 8);
+  const size_t wDr = w; w += al256(H.Dr.size() * 8);
+  const size_t wSc = w; w += al256(size_t(n) * Bi * 8);
   const size_t wU = w; w += al256(size_t(n) * m * Bi * 8);
   const size_t wRm = w; w += al256(size_t(n) * m * Bi * 8);
   const size_t wPc = w; w += al256(size_t(n) * 4 * mm * 8);
@@ -451,17 +396,27 @@ int strip_factor(volpot_strip_s* s, StripHost& H) {
     f.n = n; f.N = N; f.Bi = Bi; f.m = m; f.q = q;
     f.A = reinterpret_cast<double*>(work + wA);
     f.Ainv = reinterpret_cast<double*>(work + wAi);
-    f.Rb = reinterpret_cast<double*>(work + wRb);
+    f.nr = H.nr; f.B = B;
+    f.met = reinterpret_cast<const double*>(work + wMt);
+    f.nrm = reinterpret_cast<const double*>(work + wNm);
+    f.Dq = reinterpret_cast<const double*>(work + wDq);
+    f.Dr = reinterpret_cast<const double*>(work + wDr);
+    f.rowsc = reinterpret_cast<double*>(work + wSc);
+    f.rs = reinterpret_cast<double*>(b + oR);
+    f.piv = reinterpret_cast<int32_t*>(work + wPv);
+    f.perm = reinterpret_cast<int32_t*>(work + wPm);
     f.flag = reinterpret_cast<int32_t*>(work + wFl);
-    f.U = reinterpret_cast<const double*>(work + wU);
+    f.U = reinterpret_cast<double*>(work + wU);
     f.R = reinterpret_cast<double*>(work + wRm);
     f.pieces = reinterpret_cast<double*>(work + wPc);
     f.MG = reinterpret_cast<const double*>(work + wMG);
     f.Q = reinterpret_cast<double*>(work + wQ);
     f.W = reinterpret_cast<double*>(b + oW);
     f.EiT = reinterpret_cast<double*>(b + oEiT);
-    if (hipMemcpy(f.A, H.A.get(), size_t(n) * N * N * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(work + wU, H.U.data(), H.U.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+    if (hipMemcpy(work + wMt, H.met.data(), H.met.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(work + wNm, H.nrm.data(), H.nrm.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(work + wDq, H.Dq.data(), H.Dq.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(work + wDr, H.Dr.data(), H.Dr.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
     if (launch_strip_factor(f, 0, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
     std::vector<int32_t> flag(static_cast<size_t>(n));
     std::vector<double> pieces(size_t(n) * 4 * mm);
@@ -484,8 +439,7 @@ int strip_factor(volpot_strip_s* s, StripHost& H) {
         hipMemcpy(b + oH, C.H.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b + oPz, C.Pz.data(), nmm * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b + oPt, C.Pt.data(), C.Pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b + oK, C.K.data(), C.K.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b + oR, H.rs.data(), H.rs.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
+        hipMemcpy(b + oK, C.K.data(), C.K.size() * 8, hipMemcpyHostToDevice) != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
     if (launch_strip_factor(f, 1, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) { fail(VOLPOT_ERR_HIP); break; }
   } while (false);
   (void)hipFree(work);

@@ -35,13 +35,22 @@ constexpr int64_t kStripScratchDoubles = int64_t(1) << 17;  // 1 MiB per device
 hipError_t strip_scratch(double** out);
 
 // Plan-time factorization on the GPU (strip_factor.hip).
+constexpr int kPermInts = 72;  // count, 32 destination rows, 32 source rows (padded)
 struct StripFactorDevice {
   int32_t n, N, Bi, m, q;  // elements, padded interior size (multiple of 16), Bi = m q, m, q
+  int32_t nr, B;           // nodes across the strip, B = nr q nodes per element
+  const double* met;       // n x 6 x B: xi_x, xi_y, eta_x, eta_y, x_xi, y_xi per node
+  const double* nrm;       // n x 2: normal of the interface between element k and k + 1
+  const double* Dq;        // q x q, row-major: differentiation along the panels
+  const double* Dr;        // nr x nr: across the strip
+  double* rowsc;           // n x Bi: scale of each interior row (1 for the value rows)
+  double* rs;              // n x B: scale of the right-hand side of each row (the plan's)
   double* A;               // n x N x N: interior blocks, column-major (destroyed)
-  double* Rb;              // n x 16 x N work: a panel's exchanged rows
+  int32_t* piv;            // n x N: the pivot row of each column
+  int32_t* perm;           // n x kPermInts: the last panel's net row permutation
   int32_t* flag;           // n: 1 where a block is singular
   double* Ainv;            // n x N x N: the inverses, column-major
-  const double* U;         // n x m x Bi: U~_k (element k's derivative rows on element k + 1)
+  double* U;               // n x m x Bi: U~_k (element k's derivative rows on element k + 1)
   double* R;               // n x m x Bi: R_k = U~_{k-1} A_k^-1
   double* pieces;          // n x 4 x m x m: A^-1[S, P], A^-1[S, V], R[:, P], R[:, V]
   const double* MG;        // n x m x m: the chain's M_k G_k^-1 (host)
@@ -49,7 +58,7 @@ struct StripFactorDevice {
   double* W;               // n x 2m x Bi: the apply's right-hand-side functionals
   double* EiT;             // n x Bi x Bi: the apply's interior blocks of E_k, column c contiguous
 };
-// stage 0: inverses, R and the pieces; stage 1 (after the host chain): Q, W and EiT
+// stage 0: assembly, inverses, R and the pieces; stage 1 (after the host chain): Q, W and EiT
 hipError_t launch_strip_factor(const StripFactorDevice& f, int stage, hipStream_t stream);
 
 }  // namespace vp
