@@ -307,6 +307,7 @@ def _near_roofline(plan, info, steps, f, ubar, u, fbar, traffic, timed_in):
     time. Returns (roofline dict, wall ms per step of the pass)."""
     import torch
 
+    near = [s for s in plan.stages() if s["kind"] == "near"]
     plan.set_timing(True, kinds=("near", "adj_near"))
     plan.stage_times()  # reset
     torch.cuda.synchronize()
@@ -325,7 +326,8 @@ def _near_roofline(plan, info, steps, f, ubar, u, fbar, traffic, timed_in):
     achieved = flops / (avg_ms * 1e-3)
     return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
-            "kernel": "grg_kernel, 256-row tiles, k-chunk 32: near-field stage (forward) and its transpose (adjoint)",
+            "kernel": "grg_kernel, 256-row tiles of %d slots, k-chunk %d: near-field stage (forward) and its "
+                      "transpose (adjoint)" % (near[0]["tile"], near[0]["kchunk"]),
             "flops_per_launch": flops, "avg_launch_ms": avg_ms, "launches": n, "launches_per_step": per_step,
             "timed_in": timed_in}, 1e3 * t_pass / steps
 
@@ -339,6 +341,15 @@ def _stage_breakdown(plan, steps, f, ubar, u, fbar):
     stb = plan.stage_times()
     plan.set_timing(False)
     return {k: v[0] / steps for k, v in stb.items()}
+
+
+def _shape_given(args):
+    return bool(args.tile_leaf and args.tile_box and args.split_min is not None and args.overlap is not None)
+
+
+def _shape_from_args(args):
+    return {"tile_leaf": args.tile_leaf, "tile_box": args.tile_box, "split_min": args.split_min,
+            "overlap": args.overlap, "tile_leaf_exp": args.tile_leaf_exp or 16, "kchunk_leaf": args.kchunk_leaf or 32}
 
 
 def forest_leg(args, dev):
@@ -363,10 +374,8 @@ def forest_leg(args, dev):
     print("bench: forest of %d trees, %d leaves (%d..%d per tree), gen %.1fs"
           % (len(trees), off[-1], sizes.min(), sizes.max(), t_gen), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    if args.tile_leaf and args.tile_box and args.split_min is not None and args.overlap is not None:
-        shape = {"tile_leaf": args.tile_leaf, "tile_box": args.tile_box, "split_min": args.split_min,
-                 "overlap": args.overlap, "tile_leaf_exp": args.tile_leaf_exp or 16,
-                 "kchunk_leaf": args.kchunk_leaf or 32}
+    if _shape_given(args):
+        shape = _shape_from_args(args)
     else:
         shape, _ = autotune(C, Lv, tree_offsets=off, eps=args.eps, dense_m2l=args.dense_m2l)
     t_tune = time.perf_counter() - t0
@@ -543,7 +552,10 @@ def single_tree_leg(args, dev, w, label, cpu="full"):
     from paper_2501_17967_amd import Plan, autotune
 
     t0 = time.perf_counter()
-    shape, _ = autotune(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l)
+    if args.single_only and _shape_given(args):  # a fixed shape (profiling runs)
+        shape = _shape_from_args(args)
+    else:
+        shape, _ = autotune(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l)
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
     plan = Plan(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l, **shape)
@@ -654,7 +666,9 @@ def main():
     ap.add_argument("--strip-only", action="store_true",
                     help="run only the strip-solve leg and print its object (for profiling)")
     ap.add_argument("--batched-trees", type=int, default=256)
-    ap.add_argument("--tile-leaf", type=int, default=0, help="forest shape (all four given: no autotuning)")
+    ap.add_argument("--tile-leaf", type=int, default=0,
+                    help="launch shape of the forest (and of --single-only): with tile-box, split-min and overlap "
+                         "all given, no autotuning")
     ap.add_argument("--tile-box", type=int, default=0)
     ap.add_argument("--split-min", type=int, default=None)
     ap.add_argument("--overlap", type=int, default=None)
