@@ -106,6 +106,13 @@ typedef struct {
                               matrix-core work of the dense form; the ln|d| a_0 term joins the
                               rank-one ln s terms. 1: dense 2q x 2q real matrices per offset.
                               Both agree to rounding (the tests compare them). */
+  int32_t deterministic;   /* results are bitwise repeatable in every mode: each output has one
+                              owner and a fixed summation order (the partial sums of a tile cut
+                              between blocks are added in piece order). 0 (default): tiles may be
+                              cut; the block that finishes a cut tile last, found by an atomic
+                              arrival counter, adds its pieces. 1: no atomic operations at all:
+                              every tile belongs to one block (split_min is taken as -1). The
+                              two modes sum in different orders and agree to rounding. */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the

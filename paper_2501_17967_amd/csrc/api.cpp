@@ -617,7 +617,7 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   if (rc != VOLPOT_OK) { delete plan; return rc; }
   plan->host_only = o.host_only != 0;
   plan->use_graph = o.use_graph != 0;
-  plan->split_min = o.split_min;
+  plan->split_min = o.deterministic ? -1 : o.split_min;  // no cut tiles: no arrival counters
   plan->overlap = std::max(0, o.overlap);
   if (plan->host_only) {  // schedules for a nominal device, so that they can be inspected
     rc = schedule_all(plan, 1024);

@@ -198,7 +198,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     try_axis(1, {32, 64});
     try_axis(5, {32, 16});
     try_axis(4, {16, 32, 64});
-    try_axis(2, {0, 1, -1});
+    if (!o.deterministic) try_axis(2, {0, 1, -1});  // deterministic plans never cut tiles
     try_axis(3, {0, 16, 24, 32, 48});
   }
   if (rc == VOLPOT_OK && !same(cur, def)) {

@@ -55,11 +55,12 @@ class Options(ctypes.Structure):
                 ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double),
                 ("tile_leaf_exp", ctypes.c_int32), ("eps", ctypes.c_double), ("kchunk_leaf", ctypes.c_int32),
-                ("dense_m2l", ctypes.c_int32)]
+                ("dense_m2l", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0,
-             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False):
+             root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False,
+             deterministic=False):
     o = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
                 table_cache.encode() if table_cache else None, int(split_min), int(overlap))
     o.root_centre[0], o.root_centre[1] = float(root_centre[0]), float(root_centre[1])
@@ -68,6 +69,7 @@ def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_ca
     o.eps = float(eps)
     o.kchunk_leaf = int(kchunk_leaf)
     o.dense_m2l = int(bool(dense_m2l))
+    o.deterministic = int(bool(deterministic))
     return o
 
 
@@ -307,11 +309,11 @@ class Plan:
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
                  tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0),
-                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False):
+                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False, deterministic=False):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
-                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf, dense_m2l)
+                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf, dense_m2l, deterministic)
         h = _vp()
         L = lib()
         if tree_offsets is None:

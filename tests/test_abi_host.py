@@ -170,6 +170,19 @@ def test_schedules_cover_stages(vp, split_min):
             assert s["flops_issued"] >= s["flops"] * (1 - 1e-12) or s["rows"] == 256 and s["kchunk"] == 16, s
 
 
+def test_deterministic_plans_cut_no_tile(vp):
+    # deterministic = 1: every tile belongs to one block (no arrival counters), whatever
+    # split_min asks for
+    w = gen.config2(0)
+    for split_min in (0, 1):
+        plan = vp.Plan(w.centres, w.levels, host_only=True, split_min=split_min, deterministic=True)
+        for adj in (False, True):
+            for s in plan.stages(adj):
+                if s["n_tiles"]:
+                    assert s["n_blocks"] == s["n_tiles"] and s["n_split_tiles"] == 0, s
+        plan.close()
+
+
 def test_overlap_launch_order(vp):
     # with overlap the near field is cut in two launches, each placed beside one far-field
     # chain (helper stream), and every stage still comes after the stages it reads

@@ -232,6 +232,24 @@ def test_tile_shapes_vs_box_code_oracle(vp, torch_mod, tile_leaf, tile_box, spli
     assert np.array_equal(u, u2) and np.array_equal(fb, fb2)
 
 
+def test_deterministic_option_matches_default(vp, torch_mod):
+    # no cut tiles (no atomics): the same map, another summation order; repeatable bit for bit
+    w = gen.config3(0)
+    _say("case deterministic option, %d leaves" % w.n_leaves)
+    f = _gpu(torch_mod, w.f)
+    r = _gpu(torch_mod, np.random.default_rng(5).standard_normal(w.f.shape))
+    out = {}
+    for det in (False, True):
+        plan = vp.Plan(w.centres, w.levels, deterministic=det)
+        assert all(s["n_split_tiles"] == 0 for s in plan.stages() + plan.stages(adjoint=True)) or not det
+        u1, a1 = plan.apply(f).cpu().numpy(), plan.apply_adjoint(r).cpu().numpy()
+        u2, a2 = plan.apply(f).cpu().numpy(), plan.apply_adjoint(r).cpu().numpy()
+        assert np.array_equal(u1, u2) and np.array_equal(a1, a2)
+        out[det] = (u1, a1)
+        plan.close()
+    assert rel(out[True][0], out[False][0]) <= 1e-14 and rel(out[True][1], out[False][1]) <= 1e-13
+
+
 def test_graph_replays_match_eager(vp, torch_mod):
     w = gen.config2(0)
     _say("case graph replay")
