@@ -252,7 +252,7 @@ def strip_leg(args, dev):
     torch.cuda.synchronize()
     t_plan_first = time.perf_counter() - t0
     sp.close()
-    t0 = time.perf_counter()  # a second plan: host assembly, GPU inversion, host chain, GPU blocks
+    t0 = time.perf_counter()  # a second plan: host geometry, GPU assembly and inversion, host chain, GPU blocks
     sp = StripPlan(g, gt, q, n_r)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
