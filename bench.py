@@ -343,6 +343,43 @@ def _stage_breakdown(plan, steps, f, ubar, u, fbar):
     return {k: v[0] / steps for k, v in stb.items()}
 
 
+def measured_peaks(dev):
+    """The device's sustained FP64 matrix-core rate (volpot_peak_mfma: only MFMA on register
+    operands, 2,048 workgroups of 4 waves) and HBM copy rate (torch copy_ of 2 GiB, read + write),
+    each timed with events after a warm-up."""
+    import torch
+
+    from paper_2501_17967_amd.volpot import peak_mfma
+
+    blocks, iters = 2048, 20000
+    out = torch.empty(256 * blocks, dtype=torch.float64, device=dev)
+    peak_mfma(blocks, 200, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 0.0
+    for _ in range(3):
+        e0.record()
+        flops = peak_mfma(blocks, iters, out)
+        e1.record()
+        e1.synchronize()
+        best = max(best, flops / (e0.elapsed_time(e1) * 1e-3))
+    n = (2 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    bw = 0.0
+    for _ in range(3):
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        bw = max(bw, 5 * 2 * 8 * n / (e0.elapsed_time(e1) * 1e-3))
+    del a, b, out
+    return {"fp64_mfma_tflops": best / 1e12, "hbm_copy_gbs": bw / 1e9,
+            "how": "FP64 MFMA only on register operands (2048 x 256 threads, 8 chains per wave), best of 3; "
+                   "torch copy_ of 2 GiB (read + write bytes), best of 3 x 5 copies"}
+
+
 def _shape_given(args):
     return bool(args.tile_leaf and args.tile_box and args.split_min is not None and args.overlap is not None)
 
@@ -757,6 +794,10 @@ def main():
         out["tree"] = tree_leg(args, dev)
     if not args.no_strip:
         out["strip"] = strip_leg(args, dev)
+    # last, so that its power draw cannot slow the timed legs
+    print("bench: measured peaks", file=sys.stderr, flush=True)
+    out["measured_peaks"] = measured_peaks(dev)
+    out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / out["measured_peaks"]["fp64_mfma_tflops"]
     print(json.dumps(out), flush=True)
 
 

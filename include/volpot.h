@@ -340,6 +340,16 @@ int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, const double* 
                     const int32_t* levels, int32_t p, const volpot_options* base,
                     const char* cache_path, volpot_options* best, double* best_ms);
 
+/* Measurement: the FP64 matrix-core rate this device sustains, the measured companion of the
+ * published 78.6 TFLOP/s in roofline reports. Launches `blocks` workgroups of 256 threads on the
+ * stream; every wave runs `iters` rounds of 8 independent v_mfma_f64_16x16x4f64 (2,048 flops
+ * each) on register operands, so one launch does blocks * 4 * iters * 8 * 2048 flops; time it
+ * with events on the same stream. Thread t of block k writes out_dev[256 k + t], the sum of its
+ * accumulators: iters * 8 * sum over its 4 output rows i of sum_{c<4} A[i][c] B[c][j], with
+ * lane l = 16 c + m holding A[m][c] = 1 + l / 1024 and B[c][m] = 1 - l / 1024 (out_dev holds
+ * 256 blocks doubles, caller-owned). VOLPOT_ERR_ARG for blocks or iters <= 0 or a null out_dev. */
+int volpot_peak_mfma(int32_t blocks, int32_t iters, double* out_dev, void* hip_stream);
+
 /* One stage (one kernel launch) of an apply, for inspection and tuning. */
 typedef struct {
   char name[24];           /* e.g. "NEAR", "M2M[5]", "AFARV" */

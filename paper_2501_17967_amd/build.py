@@ -30,7 +30,7 @@ def build(verbose=False):
         cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         jobs.append(cmd)
         objs.append(obj)
-    for src in ("kernels.hip", "layer.hip", "points.hip", "tree.hip", "strip.hip", "strip_factor.hip", "moments.hip"):
+    for src in ("kernels.hip", "layer.hip", "points.hip", "tree.hip", "strip.hip", "strip_factor.hip", "moments.hip", "peak.hip"):
         kobj = os.path.join(BUILD, src + ".o")
         jobs.append([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", kobj])
         objs.append(kobj)

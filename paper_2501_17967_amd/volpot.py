@@ -37,7 +37,7 @@ EXPORTED = [
     "volpot_plan_n_stages", "volpot_plan_stage", "volpot_autotune", "volpot_layer_plan", "volpot_layer_apply",
     "volpot_plan_points", "volpot_apply_points", "volpot_tree_create", "volpot_tree_pending", "volpot_tree_nodes",
     "volpot_tree_submit", "volpot_tree_leaves", "volpot_tree_destroy", "volpot_strip_plan", "volpot_strip_nodes",
-    "volpot_strip_apply", "volpot_strip_destroy", "volpot_strip_apply_noalloc",
+    "volpot_strip_apply", "volpot_strip_destroy", "volpot_strip_apply_noalloc", "volpot_peak_mfma",
 ]
 
 STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
@@ -158,8 +158,20 @@ def lib():
         L.volpot_strip_apply_noalloc.argtypes = [_vp, _vp, _vp, _vp]
         L.volpot_strip_destroy.argtypes = [_vp]
         L.volpot_strip_destroy.restype = None
+        L.volpot_peak_mfma.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp]
         _lib = L
     return _lib
+
+
+def peak_mfma(blocks, iters, out, stream=None):
+    """Launch the matrix-core rate kernel (volpot_peak_mfma) on `stream` (default: torch's
+    current stream): blocks x 4 waves x iters x 8 FP64 MFMA of 2,048 flops; `out` is a float64
+    CUDA tensor of 256 * blocks values (each thread's accumulator sum). Returns the flop count."""
+    if out.dtype.itemsize != 8 or out.numel() < 256 * blocks or not out.is_cuda:
+        raise ValueError("out must be a float64 device tensor of 256 * blocks values")
+    _check(lib().volpot_peak_mfma(int(blocks), int(iters), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           "volpot_peak_mfma")
+    return float(blocks) * 4 * iters * 8 * 2048
 
 
 def _check(code, what):
