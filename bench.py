@@ -414,11 +414,11 @@ def forest_leg(args, dev):
     if _shape_given(args):
         shape = _shape_from_args(args)
     else:
-        shape, _ = autotune(C, Lv, tree_offsets=off, eps=args.eps, dense_m2l=args.dense_m2l)
+        shape, _ = autotune(C, Lv, tree_offsets=off, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near)
     t_tune = time.perf_counter() - t0
     print("bench: forest launch shape %s (autotuner %.1fs)" % (shape, t_tune), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    forest = Plan(C, Lv, tree_offsets=off, use_graph=True, eps=args.eps, dense_m2l=args.dense_m2l, **shape)
+    forest = Plan(C, Lv, tree_offsets=off, use_graph=True, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near, **shape)
     t_plan = time.perf_counter() - t0
     info = forest.info()
     F = torch.from_numpy(np.vstack([t.f for t in trees])).to(dev)
@@ -443,7 +443,7 @@ def forest_leg(args, dev):
     torch.cuda.synchronize()
     # roofline: the same launches from an eager plan of the same shape (events cannot sit inside
     # the captured graphs), K more steps right after the timed region
-    twin = Plan(C, Lv, tree_offsets=off, eps=args.eps, dense_m2l=args.dense_m2l, **shape)
+    twin = Plan(C, Lv, tree_offsets=off, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near, **shape)
     U2, FB2 = torch.empty_like(F), torch.empty_like(F)
     twin.apply(F, out=U2)
     twin.apply_adjoint(Rb, out=FB2)
@@ -456,7 +456,7 @@ def forest_leg(args, dev):
     # the same step at the library's default tolerance (order 39), same launch shape, for context
     at_default = None
     if args.eps:
-        f39 = Plan(C, Lv, tree_offsets=off, use_graph=True, dense_m2l=args.dense_m2l, **shape)
+        f39 = Plan(C, Lv, tree_offsets=off, use_graph=True, dense_m2l=args.dense_m2l, dense_near=args.dense_near, **shape)
         for _ in range(max(1, args.warmup)):
             f39.apply(F, out=U2)
             f39.apply_adjoint(Rb, out=FB2)
@@ -480,6 +480,7 @@ def forest_leg(args, dev):
                       "leaves_min": int(sizes.min()), "leaves_max": int(sizes.max()), "max_level": int(info["max_level"]),
                       "p": 16, "far_field_eps": args.eps, "expansion_order": int(info["order"]),
                       "m2l": "dense" if args.dense_m2l else "factored",
+                      "near": "dense" if args.dense_near else "rank-64 factors of the non-self tables",
                       "step": "forward + adjoint, one hipGraph replay each",
                       "launch_shape": shape, "autotune_s": t_tune, "plan_s": t_plan, "gen_s": t_gen},
            "roofline": roof,
@@ -501,7 +502,7 @@ def forest_leg(args, dev):
     cands = [{"tile_leaf": 32, "tile_box": 32, "split_min": 0, "overlap": 0, "tile_leaf_exp": 16, "kchunk_leaf": 32}]
     for part in np.array_split(order, 8):
         med = trees[int(part[len(part) // 2])]
-        sh, _ = autotune(med.centres, med.levels, eps=args.eps, dense_m2l=args.dense_m2l)
+        sh, _ = autotune(med.centres, med.levels, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near)
         if sh not in cands:
             cands.append(sh)
     views = [F[off[i]:off[i + 1]] for i in range(len(trees))]
@@ -512,7 +513,7 @@ def forest_leg(args, dev):
     for i, t in enumerate(trees):
         best = None
         for sh in cands:
-            p_ = Plan(t.centres, t.levels, eps=args.eps, dense_m2l=args.dense_m2l, **sh)
+            p_ = Plan(t.centres, t.levels, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near, **sh)
             p_.apply(views[i], out=outs[i])
             p_.apply_adjoint(rviews[i], out=outa[i])
             ts = min(_timed(lambda: (p_.apply(views[i], out=outs[i]), p_.apply_adjoint(rviews[i], out=outa[i])), 2)
@@ -592,10 +593,10 @@ def single_tree_leg(args, dev, w, label, cpu="full"):
     if args.single_only and _shape_given(args):  # a fixed shape (profiling runs)
         shape = _shape_from_args(args)
     else:
-        shape, _ = autotune(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l)
+        shape, _ = autotune(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near)
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = Plan(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l, **shape)
+    plan = Plan(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near, **shape)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
@@ -716,6 +717,8 @@ def main():
                          "which selects expansion order 31 (0: the library's default, 1e-13, order 39)")
     ap.add_argument("--dense-m2l", action="store_true",
                     help="dense per-offset M2L matrices instead of the factored form (for comparison)")
+    ap.add_argument("--dense-near", action="store_true",
+                    help="dense 256 x 256 adjacent-leaf tables instead of their rank-64 factors (for comparison)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()

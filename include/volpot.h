@@ -113,6 +113,15 @@ typedef struct {
                               arrival counter, adds its pieces. 1: no atomic operations at all:
                               every tile belongs to one block (split_min is taken as -1). The
                               two modes sum in different orders and agree to rounding. */
+  int32_t dense_near;      /* 0 (default, volume plans): the adjacent-leaf tables other than a
+                              leaf's own apply in rank-64 form T_r = U_r V_r (Householder QR
+                              with column pivoting of each 256 x 256 table, stopped after 64
+                              columns; the discarded part is below 1e-14 of the table, whose
+                              numerical rank is 38 to 58): a first stage forms V_r f for every
+                              such pair (64 values a pair in plan memory), the near field then
+                              applies U_r to those and the self table to the leaf's own data,
+                              about half the matrix-core work. 1: the dense tables. The two agree
+                              to rounding (the tests compare them). */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -123,15 +132,16 @@ typedef struct {
   int64_t pairs_near, pairs_v, pairs_w, pairs_x, n_m2m, n_l2l, n_s2m, n_l2t;
   double flops_total;       /* forward apply */
   double flops_adjoint;     /* adjoint apply (the same pairs, transposed) */
-  double flops_kind[9];     /* per stage kind: 0 upward (S2M, M2M chain), 1 downward (M2L + S2L
+  double flops_kind[11];    /* per stage kind: 0 upward (S2M, M2M chain), 1 downward (M2L + S2L
                                for all levels, L2L chain), 2 near field, 3 L2T + M2T + log terms,
                                4 adjoint upward (L2T^T, L2L^T chain), 5 adjoint downward (M2L^T,
                                M2T^T, M2M^T chain), 6 adjoint near field, 7 S2M^T + S2L^T,
-                               8 adjoint row sums */
-  int64_t launches_kind[9]; /* kernel launches per apply of each stage kind */
+                               8 adjoint row sums, 9 the low-rank near field's first stage
+                               (V_r f per pair), 10 its transpose's (U_r^T ubar per pair) */
+  int64_t launches_kind[11]; /* kernel launches per apply of each stage kind */
   double bytes_min;         /* mandatory HBM traffic: 16 B per unknown (f in, u out) */
   int64_t device_bytes;     /* device memory the plan holds (tables shared per device) */
-  double flops_issued_kind[9]; /* matrix-core work the kernels issue per stage kind: every tile
+  double flops_issued_kind[11]; /* matrix-core work the kernels issue per stage kind: every tile
                                   multiplies each of its relation tables by all of its slots,
                                   occupied or not (>= flops_kind) */
   /* layer-potential plans (volpot_layer_plan; zero otherwise) */
@@ -143,6 +153,7 @@ typedef struct {
   /* plans with evaluation points (volpot_plan_points; zero otherwise) */
   int64_t n_points;         /* evaluation points */
   int64_t pairs_points;     /* (point, adjacent leaf) pairs, each a precomputed 3 x 256 moment block */
+  int64_t pairs_lowrank;    /* adjacent-leaf pairs in rank-64 form (0 with dense_near) */
 } volpot_info;
 
 /* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
@@ -319,7 +330,9 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 
 /* Inspection: copy a host-side table of the plan (row-major) into out (n doubles).
  *   kind 0: near table of relation index (0..32, see volpot_near_relation), 256 x 256
- *   kind 1: S2M (80 x 256);   kind 2: L2T (256 x 80)
+ *   kind 1: S2M (2q x 256);   kind 2: L2T (256 x 2q), q = P + 1 of the plan's order
+ *   kind 3: U_r (256 x 64) and kind 4: V_r (64 x 256) of relation index 1..32, the rank-64
+ *           factors the low-rank near field applies (T_r ~ U_r V_r)
  * Returns VOLPOT_ERR_ARG for an unknown kind/index or n too small. */
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
 
@@ -331,9 +344,11 @@ int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* o
  * device buffers after a warm-up (HIP events, private stream, best of 5); writes the fastest
  * options to *best and their time in milliseconds to *best_ms (nullable). A candidate must beat
  * the current choice by more than 1.5%, and the result must beat the defaults by as much when
- * both are timed again, so that differences within timing noise keep the defaults. With cache_path (nullable) the result is looked up in, and appended to, that text file,
- * keyed by a signature of the trees' level histogram and sizes, of the expansion order that
- * base's eps selects and of the device, so that a shape is timed once. VOLPOT_ERR_UNSUPPORTED
+ * both are timed again, so that differences within timing noise keep the defaults. With
+ * cache_path (nullable) the result is looked up in, and appended to, that text file, keyed by a
+ * signature of the trees' level histogram and sizes, of the expansion order that base's eps
+ * selects, of base's dense_m2l and dense_near and of the device, so that a shape is timed
+ * once. VOLPOT_ERR_UNSUPPORTED
  * for an eps no order meets. Allocates and synchronises; not for use inside a timed region.
  * Arguments as volpot_plan_forest (a single tree: n_trees = 1, offsets {0, n_leaves}). */
 int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, const double* centres,

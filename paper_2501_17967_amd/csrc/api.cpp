@@ -76,7 +76,7 @@ int acquire_tables(int device, int q, DeviceTables** out) {
   for (int r = 0; r < kNumRel; ++r) {
     const bool w = !M.w_in[r].empty();
     rd[r] = {T->buf + off[r], M.M[r], M.K[r], w ? T->buf + woff[r] : nullptr,
-             w ? T->buf + woff[r] + M.w_in[r].size() : nullptr};
+             w ? T->buf + woff[r] + M.w_in[r].size() : nullptr, M.koff[r]};
   }
   T->rels = rd;
   if (hipMemcpy(T->buf, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -138,6 +138,7 @@ struct volpot_plan_s {
   char* d_block = nullptr;
   double *d_mp = nullptr, *d_loc = nullptr, *d_lb = nullptr, *d_ab = nullptr, *d_usum = nullptr, *d_leaf_s2 = nullptr;
   double *d_far = nullptr, *d_afar = nullptr;  // far-field parts before the downward chains
+  double *d_nw = nullptr, *d_nwa = nullptr;    // low-rank near field: per pair V_r f~, U_r^T ubar
   double* d_fs = nullptr;  // prescaled input s^2 f
   double* d_part[2] = {nullptr, nullptr};  // partial sums of split tiles: helper-stream, caller-stream stages
   int split_min = 0;
@@ -237,7 +238,7 @@ int upload(volpot_plan_s* p) {
     for (size_t i = 0; i < s.seg_rel.size(); ++i) {
       const RelDesc& rd = p->tables->rels[size_t(s.seg_rel[i])];
       const RelDesc& ra = s.cx_rel >= 0 ? p->tables->rels[size_t(s.cx_rel)] : rd;  // factored: the core
-      segd.back()[i] = {ra.A, ra.K, int32_t(s.seg_fam[i]), rd.w_in, rd.w_out};
+      segd.back()[i] = {ra.A, ra.K, int32_t(s.seg_fam[i]), rd.w_in, rd.w_out, rd.koff};
     }
     o.tt = add_bytes(total, s.tile_tgt); o.tsp = add_bytes(total, s.tile_seg_ptr); o.sd = add_bytes(total, segd.back());
     o.ss = add_bytes(total, s.seg_src); o.rp = add_bytes(total, s.r1_ptr);
@@ -258,6 +259,9 @@ int upload(volpot_plan_s* p) {
   size_t o_ab = (total + 255) & ~size_t(255); total = o_ab + (vol ? nb : 0);
   size_t o_far = (total + 255) & ~size_t(255); total = o_far + nb;
   size_t o_afar = (total + 255) & ~size_t(255); total = o_afar + (vol ? nb : 0);
+  const size_t nlr = size_t(P.pairs_lr) * kNearRank * sizeof(double);
+  size_t o_nw = (total + 255) & ~size_t(255); total = o_nw + nlr;
+  size_t o_nwa = (total + 255) & ~size_t(255); total = o_nwa + (vol ? nlr : 0);
   size_t o_us = (total + 255) & ~size_t(255); total = o_us + (vol ? size_t(P.n_leaves) * sizeof(double) : 0);
   size_t o_fs = (total + 255) & ~size_t(255); total = o_fs + (vol ? size_t(P.n_leaves) * kNP * sizeof(double) : 0);
   std::vector<double> s2(P.leaf_s2);
@@ -319,6 +323,8 @@ int upload(volpot_plan_s* p) {
   p->d_ab = reinterpret_cast<double*>(b + o_ab);
   p->d_far = reinterpret_cast<double*>(b + o_far);
   p->d_afar = reinterpret_cast<double*>(b + o_afar);
+  p->d_nw = reinterpret_cast<double*>(b + o_nw);
+  p->d_nwa = reinterpret_cast<double*>(b + o_nwa);
   p->d_usum = reinterpret_cast<double*>(b + o_us);
   p->d_fs = reinterpret_cast<double*>(b + o_fs);
   p->d_leaf_s2 = reinterpret_cast<double*>(b + o_s2);
@@ -393,6 +399,8 @@ const double* arr_ptr(volpot_plan_s* p, int8_t a, const double* in, double* out)
     case A_USUM: return p->d_usum;
     case A_FAR: return p->d_far;
     case A_AFAR: return p->d_afar;
+    case A_NW: return p->d_nw;
+    case A_NWA: return p->d_nwa;
     default: return nullptr;
   }
 }
@@ -608,7 +616,8 @@ int make_plan(int32_t n_trees, const int64_t* offsets, const double* centres, co
   int rc;
   try {
     rc = build_plan(n_trees, offsets, cref, levels, o.tile_leaf, o.tile_box, std::max(0, o.overlap), plan->host,
-                    nullptr, layer, points, root, o.tile_leaf_exp, ne, o.kchunk_leaf, o.dense_m2l != 0);
+                    nullptr, layer, points, root, o.tile_leaf_exp, ne, o.kchunk_leaf, o.dense_m2l != 0,
+                    o.dense_near != 0);
   } catch (const std::bad_alloc&) {
     rc = VOLPOT_ERR_OOM;
   } catch (...) {
@@ -780,6 +789,7 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
   out->pairs_p2l = P.pairs_p2l;
   out->n_points = P.n_pts;
   out->pairs_points = int64_t(P.pt_near_leaf.size());
+  out->pairs_lowrank = P.pairs_lr;
   out->device_bytes = plan->device_bytes + (plan->tables ? int64_t(plan->tables->bytes) : 0);
   return VOLPOT_OK;
 }
@@ -893,6 +903,8 @@ int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* o
   if (kind == 0 && index >= 0 && index < 33) id = kRelNear + index;
   else if (kind == 1 && index == 0) id = kRelS2M;
   else if (kind == 2 && index == 0) id = kRelL2T;
+  else if (kind == 3 && index >= 1 && index < 33) id = kRelNU + index - 1;
+  else if (kind == 4 && index >= 1 && index < 33) id = kRelNV + index - 1;
   else return VOLPOT_ERR_ARG;
   if (n < int64_t(M.a[id].size())) return VOLPOT_ERR_ARG;
   std::memcpy(out, M.a[id].data(), M.a[id].size() * sizeof(double));

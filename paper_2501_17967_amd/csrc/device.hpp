@@ -21,6 +21,8 @@ struct SegDesc {
   int32_t fam;
   const double* w_in;
   const double* w_out;
+  int32_t k_off;  // the relation reads its K source values from this offset on (self-table slices)
+  int32_t pad;
 };
 
 struct RelDesc {
@@ -28,6 +30,7 @@ struct RelDesc {
   int32_t M, K;
   const double* w_in;   // factored M2L relations only, else null
   const double* w_out;
+  int32_t koff;         // offset into the source vector (self-table slices), else 0
 };
 
 // Arguments of one stage launch (grouped-relation GEMM). Passed by value.

@@ -79,7 +79,7 @@ struct Loader {
     const SegDesc sd = p.segs[s];
     A = (gdp)sd.A;
     K = sd.K;
-    base = (gdp)pick4(p.fam_base, sd.fam);
+    base = (gdp)pick4(p.fam_base, sd.fam) + sd.k_off;
     stride = pick4(p.fam_stride, sd.fam);
   }
   __device__ __forceinline__ void load(int tid) {

@@ -334,7 +334,8 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
         if (e.rel < 0 || e.rel >= kNumRel || e.fam < 0 || e.fam >= 4) throw std::runtime_error("bad entry");
         if (cx && mats.w_in[size_t(e.rel)].empty()) throw std::runtime_error("relation has no factored form");
         if (mats.M[table(e.rel)] != st.M) throw std::runtime_error("relation rows differ from stage rows");
-        if (st.fam[e.fam].stride < src_len(e.rel)) throw std::runtime_error("source shorter than relation");
+        if (st.fam[e.fam].stride < mats.koff[size_t(table(e.rel))] + src_len(e.rel))
+          throw std::runtime_error("source shorter than relation");
         // the kernel walks K in full chunks of KC
         if (mats.K[table(e.rel)] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
         const int32_t key = e.rel * 16 + e.fam;
@@ -381,9 +382,9 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
 }
 
 // Launch order and stream flags. Built order: [S2M] [M2M chain] [FARV] [FARX] [L2L chain]
-// [NEAR or NEAR_A NEAR_B] [LOCT] (adjoint: [AL2T] [AL2L chain] [AFARV] [AFARW] [AM2M chain]
-// [ANEAR...] [ALOCT]). Launch order:
-//   S2M, M2M chain (helper), NEAR_A, FARV (join), FARX + L2L chain (helper), NEAR_B, LOCT (join)
+// [NEARC] [NEAR or NEAR_A NEAR_B] [LOCT] (adjoint: [AL2T] [AL2L chain] [AFARV] [AFARW] [AM2M chain]
+// [ANEARC] [ANEAR...] [ALOCT]). Launch order:
+//   S2M, M2M chain (helper), NEARC, NEAR_A, FARV (join), FARX + L2L chain (helper), NEAR_B, LOCT (join)
 // so that, with the overlap option, each latency-bound chain runs beside half of the near
 // field, which does not depend on the far field. Without overlap everything runs in this
 // order on one stream, which is also a valid order. A layer plan has P2M in S2M's place, P2L in
@@ -391,10 +392,11 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
 static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   const int k_up = adjoint ? K_AUP : K_UP, k_down = adjoint ? K_ADOWN : K_DOWN;
   const int k_near = adjoint ? K_ANEAR : K_NEAR, k_loct = adjoint ? K_ALOCT : K_LOCT;
-  std::vector<Stage> head, up_chain, far, down_chain, near, tail;
+  std::vector<Stage> head, up_chain, far, down_chain, pre, near, tail;
   for (Stage& s : v) {
     s.helper = s.join_before = s.fork_before = s.concurrent = 0;
-    if (s.kind == k_up && s.level < 0) head.push_back(std::move(s));        // S2M / AL2T
+    if (s.pre_near) pre.push_back(std::move(s));                            // NEARC / ANEARC
+    else if (s.kind == k_up && s.level < 0) head.push_back(std::move(s));   // S2M / AL2T
     else if (s.kind == k_up) up_chain.push_back(std::move(s));              // M2M[l] / AL2L[l]
     else if (s.kind == k_down && s.level < 0) far.push_back(std::move(s));  // FARV, FARX / AFARV, AFARW
     else if (s.kind == k_down) down_chain.push_back(std::move(s));          // L2L[l] / AM2M[l]
@@ -421,6 +423,10 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   if (near.size() == 1 && near[0].custom == C_P2P) last.push_back(std::move(near[0])), near.clear();
   for (Stage& s : head) v.push_back(std::move(s));
   chain(up_chain);
+  for (Stage& s : pre) {  // the low-rank near field's first stage, right before the near field
+    s.concurrent = 1;
+    v.push_back(std::move(s));
+  }
   put_near(0);
   // M2L (FARV / AFARV) on the caller's stream; the small S2L / M2T^T stage (FARX / AFARW),
   // which only the downward chain reads, opens that chain on the helper stream
@@ -540,7 +546,7 @@ void build_schedule(Stage& st, int max_blocks, int min_units, int tile_cost) {
 int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, const int32_t* levels,
                int tile_leaf, int tile_box, int overlap, Plan& P, int64_t* bad, const LayerSources* layer,
                const PointTargets* points, const RootBox& root, int tile_leaf_exp, int ne, int kchunk_leaf,
-               bool dense_m2l) {
+               bool dense_m2l, bool dense_near) {
   if (!(ne == 32 || ne == 48 || ne == 64 || ne == 80)) return VOLPOT_ERR_UNSUPPORTED;
   if ((layer || points) && ne != kNE) return VOLPOT_ERR_UNSUPPORTED;  // their kernels take 40 terms
   const int kNE = ne;  // reals per expansion of this plan (the namespace constant is the default)
@@ -1125,15 +1131,52 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     defer(std::move(st), {}, {}, {}, false);
   }
   if (layer) halves.clear();
+  // Low-rank near field (volume plans unless dense_near): every adjacent-leaf pair other than a
+  // leaf with itself gets a row of A_NW holding V_r f~ of its source (stage NEARC), and the near
+  // field proper applies U_r to those rows and the self table, in four 64-column slices, to the
+  // leaf's own f~. lr_idx: the row of each entry of Ulist (-1 for the self entry).
+  const bool lr = !layer && !dense_near;
+  std::vector<int64_t> lr_idx;
+  if (lr) {
+    lr_idx.assign(Ulist.e.size(), -1);
+    int64_t n = 0;
+    for (size_t g = 0; g < Ulist.e.size(); ++g)
+      if (Ulist.e[g].first != 0) lr_idx[g] = n++;
+    if (n >= (int64_t(1) << 31)) throw std::runtime_error("too many adjacent-leaf pairs");
+    P.pairs_lr = n;
+    Stage st; init_stage(st, K_NEARC, "NEARC", -1, kNearRank, kNP, NTB, A_NW, kNearRank);
+    st.pre_near = 1;
+    st.fam[0] = {A_INS, kNP, 0};
+    std::vector<int32_t> tg(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) tg[size_t(i)] = int32_t(i);
+    std::vector<std::vector<Entry>> E(static_cast<size_t>(n));
+    std::vector<std::vector<R1>> R(static_cast<size_t>(n));
+    par_for(P.n_leaves, [&](int64_t a) {
+      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
+        if (lr_idx[size_t(g)] >= 0)
+          E[size_t(lr_idx[size_t(g)])].push_back({kRelNV + Ulist.e[size_t(g)].first - 1, 0, Ulist.e[size_t(g)].second});
+    });
+    defer(std::move(st), tg, std::move(E), std::move(R), false);
+  }
   for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
     const std::vector<int32_t> part(near_order.begin() + long(halves[h].first), near_order.begin() + long(halves[h].second));
-    Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+    Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, lr ? 64 : kNP, NTL,
+                         A_OUT, kNP);
     st.KC = KCL;
     st.fam[0] = {A_INS, kNP, 0};
+    if (lr) st.fam[1] = {A_NW, kNearRank, 0};
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
     par_for(int64_t(part.size()), [&](int64_t i) {
-      for (auto& e : Ulist[part[size_t(i)]]) E[size_t(i)].push_back({kRelNear + e.first, 0, e.second});
+      const int32_t a = part[size_t(i)];
+      if (!lr) {
+        for (auto& e : Ulist[size_t(a)]) E[size_t(i)].push_back({kRelNear + e.first, 0, e.second});
+        return;
+      }
+      for (int q = 0; q < 4; ++q) E[size_t(i)].push_back({kRelNSF + q, 0, a});
+      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
+        if (lr_idx[size_t(g)] >= 0)
+          E[size_t(i)].push_back({kRelNU + Ulist.e[size_t(g)].first - 1, 1, int32_t(lr_idx[size_t(g)])});
     });
     defer(std::move(st), part, std::move(E), std::move(R), false);
   }
@@ -1234,16 +1277,47 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     }
   }
   down_pairs(true);
+  // the row of pair (target a, relation r != 0) in A_NW / A_NWA
+  auto pair_row = [&](int32_t a, int32_t r) -> int32_t {
+    for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
+      if (Ulist.e[size_t(g)].first == r) return int32_t(lr_idx[size_t(g)]);
+    throw std::runtime_error("adjacent-leaf pair not found");
+  };
+  if (lr) {  // ANEARC: U_r^T ubar of the target of every pair
+    const int64_t n = P.pairs_lr;
+    Stage st; init_stage(st, K_ANEARC, "ANEARC", -1, kNearRank, kNP, NTB, A_NWA, kNearRank);
+    st.pre_near = 1;
+    st.fam[0] = {A_IN, kNP, 0};
+    std::vector<int32_t> tg(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) tg[size_t(i)] = int32_t(i);
+    std::vector<std::vector<Entry>> E(static_cast<size_t>(n));
+    std::vector<std::vector<R1>> R(static_cast<size_t>(n));
+    par_for(P.n_leaves, [&](int64_t a) {
+      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
+        if (lr_idx[size_t(g)] >= 0)
+          E[size_t(lr_idx[size_t(g)])].push_back({kRelNU + Ulist.e[size_t(g)].first - 1 + kNumFwd, 0, int32_t(a)});
+    });
+    defer(std::move(st), tg, std::move(E), std::move(R), true);
+  }
   for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
     const std::vector<int32_t> part(anear_order.begin() + long(halves[h].first), anear_order.begin() + long(halves[h].second));
-    Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, kNP, NTL, A_OUT, kNP);
+    Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, lr ? 64 : kNP,
+                         NTL, A_OUT, kNP);
     st.KC = KCL;
     st.out_scaled = 1;
     st.fam[0] = {A_IN, kNP, 0};
+    if (lr) st.fam[1] = {A_NWA, kNearRank, 0};
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
     par_for(int64_t(part.size()), [&](int64_t i) {
-      for (auto& e : Uinv[part[size_t(i)]]) E[size_t(i)].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
+      const int32_t b = part[size_t(i)];
+      if (!lr) {
+        for (auto& e : Uinv[size_t(b)]) E[size_t(i)].push_back({kRelNear + e.first + kNumFwd, 0, e.second});
+        return;
+      }
+      for (int q = 0; q < 4; ++q) E[size_t(i)].push_back({kRelNSA + q, 0, b});
+      for (auto& e : Uinv[size_t(b)])
+        if (e.first != 0) E[size_t(i)].push_back({kRelNV + e.first - 1 + kNumFwd, 1, pair_row(e.second, e.first)});
     });
     defer(std::move(st), part, std::move(E), std::move(R), true);
   }

@@ -63,7 +63,17 @@ constexpr int kRelL2L2 = 139; // +4 qc + qg: L2L_qg L2L_qc, box to grandchild
 // acting on the real and imaginary parts alike. Stored with its q rows padded to a multiple of
 // 16 (zero rows), q columns; the adjoint id holds H^T padded the same way.
 constexpr int kRelH = 155;
-constexpr int kNumFwd = 156;
+// The adjacent-leaf tables of the 32 relations other than a leaf with itself (near relation
+// r = 1..32 at index r - 1) in rank-64 form T_r = U_r V_r (U_r 256 x 64, V_r 64 x 256, Householder
+// QR with column pivoting truncated after 64 columns); the self table (relation 0) as four
+// 64-column slices for the forward (T[:, 64q .. 64q + 63], read at offset 64q of the source leaf)
+// and four for the adjoint ((T[64q .. 64q + 63, :])^T, read at offset 64q of the cotangent).
+constexpr int kNearRank = 64;
+constexpr int kRelNU = 156;   // +32: U_r
+constexpr int kRelNV = 188;   // +32: V_r
+constexpr int kRelNSF = 220;  // +4: forward self slices
+constexpr int kRelNSA = 224;  // +4: adjoint self slices
+constexpr int kNumFwd = 228;
 constexpr int kNumRel = 2 * kNumFwd;
 
 struct Offset { double dx, dy, rho; };
@@ -85,6 +95,9 @@ struct Matrices {
   // The adjoint takes the conjugates, in swapped roles.
   std::vector<std::vector<double>> w_in, w_out;
   std::vector<double> lnd;
+  // offset (in doubles) into each source vector at which a relation reads its K values (the
+  // self-table slices; 0 for every other relation)
+  std::vector<int> koff;
 };
 constexpr int pad16(int n) { return (n + 15) / 16 * 16; }
 // The relation matrices for expansions of q complex terms (order q - 1; q = 16, 24, 32 or 40),
@@ -100,11 +113,14 @@ void set_table_cache_dir(const char* dir);
 // A_INS: the input with each leaf scaled by its s^2 (forward only; written by a prescale pass)
 // A_FAR / A_AFAR: the far-field parts (M2L + S2L, and their transposes) before the downward
 // chains add the parents' contributions into A_LOC / A_AB
-enum Arr : int8_t { A_IN = 0, A_INS, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_FAR, A_AFAR, A_NONE };
+// A_NW / A_NWA: per adjacent-leaf pair (other than a leaf with itself) the 64 values V_r f of the
+// low-rank near field, and U_r^T ubar of its transpose
+enum Arr : int8_t { A_IN = 0, A_INS, A_OUT, A_MP, A_LOC, A_LB, A_AB, A_USUM, A_FAR, A_AFAR, A_NW, A_NWA, A_NONE };
 // timing / accounting kinds: 0 upward (S2M, M2M), 1 downward (FARV/X, L2L), 2 NEAR, 3 LOCT,
 // 4 adjoint upward (AL2T, AL2L), 5 adjoint downward (AFARV/W, AM2M), 6 ANEAR, 7 ALOCT,
-// 8 adjoint row sums
-enum StageKind : int { K_UP = 0, K_DOWN, K_NEAR, K_LOCT, K_AUP, K_ADOWN, K_ANEAR, K_ALOCT, K_ASUM, K_NUM };
+// 8 adjoint row sums, 9 NEARC (the low-rank near field's V_r f per pair), 10 ANEARC (U_r^T ubar)
+enum StageKind : int { K_UP = 0, K_DOWN, K_NEAR, K_LOCT, K_AUP, K_ADOWN, K_ANEAR, K_ALOCT, K_ASUM, K_NEARC, K_ANEARC,
+                       K_NUM };
 
 struct FamDesc { int8_t arr; int32_t stride; int8_t unused; };
 
@@ -136,6 +152,7 @@ struct Stage {
   // the complex diagonals of its own relation; K is then in complex terms, one chunk per
   // segment, and the tile's columns are the real and imaginary parts of its slots
   int cx_rel = -1;
+  int8_t pre_near = 0;     // runs right before the near field (its compression stage)
   double flops_issued = 0;  // MFMA work of the tiles, empty slots included
   int n_tiles = 0;
   int8_t out_arr = A_NONE;
@@ -188,6 +205,7 @@ struct Plan {
   // pair counts
   int64_t pairs_near = 0, pairs_v = 0, pairs_w = 0, pairs_x = 0, n_m2m = 0, n_l2l = 0, n_s2m = 0,
           n_l2t = 0;
+  int64_t pairs_lr = 0;  // adjacent-leaf pairs in low-rank form (rows of A_NW / A_NWA), 0 if dense
   // layer potentials (point sources on a curve; empty for the volume potential)
   bool layer = false;
   int64_t n_src = 0, n_src_leaves = 0, n_active = 0, pairs_p2p = 0, pairs_p2l = 0;
@@ -251,6 +269,6 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres,
                const int32_t* levels, int tile_leaf, int tile_box, int overlap, Plan& plan, int64_t* bad_leaf,
                const LayerSources* layer = nullptr, const PointTargets* points = nullptr,
                const RootBox& root = RootBox(), int tile_leaf_exp = 16, int ne = kNE, int kchunk_leaf = 32,
-               bool dense_m2l = false);
+               bool dense_m2l = false, bool dense_near = false);
 
 }  // namespace vp

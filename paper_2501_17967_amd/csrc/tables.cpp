@@ -501,6 +501,82 @@ static const std::vector<std::vector<double>>& near_tables() {
   return *T;
 }
 
+// T (n x n, row-major) ~= Q R with Q (n x k, orthonormal columns) and R (k x n): Householder QR
+// with column pivoting (the column of largest remaining norm first), stopped after k columns;
+// R's columns are returned in T's original order. The discarded part is the trailing block
+// R[k:, k:] of the pivoted factorization.
+static void pivoted_qr(const std::vector<double>& T, int n, int k, std::vector<double>& Qk, std::vector<double>& Rk) {
+  std::vector<double> A(T);
+  std::vector<int> perm(static_cast<size_t>(n));
+  for (int c = 0; c < n; ++c) perm[size_t(c)] = c;
+  std::vector<std::vector<double>> V(static_cast<size_t>(k));
+  std::vector<double> beta(static_cast<size_t>(k), 0.0);
+  for (int j = 0; j < k; ++j) {
+    int p = j;
+    double best = -1.0;
+    for (int c = j; c < n; ++c) {
+      double sq = 0.0;
+      for (int i = j; i < n; ++i) sq += A[size_t(i) * n + c] * A[size_t(i) * n + c];
+      if (sq > best) { best = sq; p = c; }
+    }
+    if (p != j) {
+      for (int i = 0; i < n; ++i) std::swap(A[size_t(i) * n + j], A[size_t(i) * n + p]);
+      std::swap(perm[size_t(j)], perm[size_t(p)]);
+    }
+    std::vector<double>& v = V[size_t(j)];
+    v.assign(size_t(n - j), 0.0);
+    double nrm = 0.0;
+    for (int i = j; i < n; ++i) { v[size_t(i - j)] = A[size_t(i) * n + j]; nrm += v[size_t(i - j)] * v[size_t(i - j)]; }
+    nrm = std::sqrt(nrm);
+    const double alpha = v[0] >= 0.0 ? -nrm : nrm;
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (double x : v) vv += x * x;
+    beta[size_t(j)] = vv > 0.0 ? 2.0 / vv : 0.0;
+    for (int c = j; c < n; ++c) {  // A[j:, c] -= beta v (v . A[j:, c])
+      double d = 0.0;
+      for (int i = j; i < n; ++i) d += v[size_t(i - j)] * A[size_t(i) * n + c];
+      d *= beta[size_t(j)];
+      for (int i = j; i < n; ++i) A[size_t(i) * n + c] -= d * v[size_t(i - j)];
+    }
+  }
+  Rk.assign(size_t(k) * n, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int c = i; c < n; ++c) Rk[size_t(i) * n + perm[size_t(c)]] = A[size_t(i) * n + c];
+  Qk.assign(size_t(n) * k, 0.0);  // H_0 H_1 ... H_{k-1} applied to the first k unit vectors
+  for (int c = 0; c < k; ++c) Qk[size_t(c) * k + c] = 1.0;
+  for (int j = k - 1; j >= 0; --j) {
+    const std::vector<double>& v = V[size_t(j)];
+    for (int c = 0; c < k; ++c) {
+      double d = 0.0;
+      for (int i = j; i < n; ++i) d += v[size_t(i - j)] * Qk[size_t(i) * k + c];
+      d *= beta[size_t(j)];
+      for (int i = j; i < n; ++i) Qk[size_t(i) * k + c] -= d * v[size_t(i - j)];
+    }
+  }
+}
+
+// The rank-64 factors of the 32 adjacent-leaf tables other than the self table, computed once
+// (the near tables are the same for every expansion order).
+struct NearFactors {
+  std::vector<std::vector<double>> U, V;  // 32 each: 256 x 64 and 64 x 256
+};
+static const NearFactors& near_factors() {
+  static std::once_flag once;
+  static NearFactors* F = nullptr;
+  std::call_once(once, []() {
+    F = new NearFactors();
+    const std::vector<std::vector<double>>& T = near_tables();
+    F->U.resize(32);
+    F->V.resize(32);
+    std::vector<std::thread> th;
+    for (int r = 1; r <= 32; ++r)
+      th.emplace_back([&, r]() { pivoted_qr(T[size_t(r)], kNP, kNearRank, F->U[size_t(r - 1)], F->V[size_t(r - 1)]); });
+    for (auto& t : th) t.join();
+  });
+  return *F;
+}
+
 static Matrices build_matrices(const int Q) {
   const int kNE = 2 * Q;  // reals per expansion for this order
   Matrices M;
@@ -511,6 +587,7 @@ static Matrices build_matrices(const int Q) {
   M.w_in.assign(kNumRel, {});
   M.w_out.assign(kNumRel, {});
   M.lnd.assign(kNumRel, 0.0);
+  M.koff.assign(kNumRel, 0);
   const Basis& B = basis();
   std::vector<cd> xi(kNP);
   for (int m = 0; m < kNP; ++m) xi[m] = cd(B.t[m % kP], B.t[m / kP]);
@@ -617,6 +694,24 @@ static Matrices build_matrices(const int Q) {
   {
     const std::vector<std::vector<double>>& T = near_tables();
     for (int r = 0; r < 33; ++r) set(kRelNear + r, kNP, kNP, std::vector<double>(T[size_t(r)]));
+    // the low-rank form of relations 1..32 and the 64-column slices of the self table
+    const NearFactors& F = near_factors();
+    for (int r = 0; r < 32; ++r) {
+      set(kRelNU + r, kNP, kNearRank, std::vector<double>(F.U[size_t(r)]));
+      set(kRelNV + r, kNearRank, kNP, std::vector<double>(F.V[size_t(r)]));
+    }
+    const std::vector<double>& S = T[0];
+    for (int q = 0; q < 4; ++q) {
+      std::vector<double> fw(size_t(kNP) * 64), ad(size_t(kNP) * 64);
+      for (int i = 0; i < kNP; ++i)
+        for (int c = 0; c < 64; ++c) {
+          fw[size_t(i) * 64 + c] = S[size_t(i) * kNP + 64 * q + c];  // T[i][64q + c]
+          ad[size_t(i) * 64 + c] = S[size_t(64 * q + c) * kNP + i];  // (T[64q + c][i]): T^T's column block
+        }
+      set(kRelNSF + q, kNP, 64, std::move(fw));
+      set(kRelNSA + q, kNP, 64, std::move(ad));
+      M.koff[size_t(kRelNSF + q)] = M.koff[size_t(kRelNSA + q)] = 64 * q;
+    }
   }
   // M2T_r: source box (rho = 1/2) at d = (source - target centre) / s_target
   const auto& WO = w_offsets();

@@ -35,9 +35,10 @@ bool same(const Candidate& a, const Candidate& b) {
 constexpr double kMargin = 0.015;
 
 // Shape signature: trees, leaves per level over the whole forest, sizes of the trees, the
-// expansion length (reals per expansion) and M2L form, the device's architecture and
+// expansion length (reals per expansion), M2L and near-field forms, the device's architecture and
 // compute-unit count. FNV-1a over the values.
-uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, int ne, int dense_m2l, int dev) {
+uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, int ne, int dense_m2l, int dense_near,
+                   int dev) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) {
     for (int b = 0; b < 8; ++b) {
@@ -56,6 +57,7 @@ uint64_t signature(int32_t n_trees, const int64_t* off, const int32_t* levels, i
   for (int64_t s : sizes) mix(uint64_t(s));
   mix(uint64_t(ne));
   mix(uint64_t(dense_m2l != 0));
+  mix(uint64_t(dense_near != 0));
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
     for (const char* c = prop.gcnArchName; *c; ++c) mix(uint64_t(uint8_t(*c)));
@@ -119,7 +121,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
   if (hipGetDevice(&dev) != hipSuccess) return VOLPOT_ERR_HIP;
   const int ne = vp::reals_for_eps(o.eps == 0.0 ? vp::kDefaultEps : o.eps);
   if (ne == 0) return VOLPOT_ERR_UNSUPPORTED;
-  const uint64_t key = signature(n_trees, tree_offsets, levels, ne, o.dense_m2l, dev);
+  const uint64_t key = signature(n_trees, tree_offsets, levels, ne, o.dense_m2l, o.dense_near, dev);
   double ms = 0;
   *best = o;
   if (cache_lookup(cache_path, key, best, &ms)) {

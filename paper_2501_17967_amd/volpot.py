@@ -40,7 +40,8 @@ EXPORTED = [
     "volpot_strip_apply", "volpot_strip_destroy", "volpot_strip_apply_noalloc", "volpot_peak_mfma",
 ]
 
-STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum"]
+STAGE_KINDS = ["up", "down", "near", "loct", "adj_up", "adj_down", "adj_near", "adj_loct", "adj_sum", "nearc",
+               "adj_nearc"]
 
 
 class VolpotError(RuntimeError):
@@ -55,12 +56,12 @@ class Options(ctypes.Structure):
                 ("tile_box", ctypes.c_int32), ("table_cache", ctypes.c_char_p), ("split_min", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("root_centre", ctypes.c_double * 2), ("root_halfwidth", ctypes.c_double),
                 ("tile_leaf_exp", ctypes.c_int32), ("eps", ctypes.c_double), ("kchunk_leaf", ctypes.c_int32),
-                ("dense_m2l", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("dense_m2l", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("dense_near", ctypes.c_int32)]
 
 
 def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0,
              root_centre=(0.0, 0.0), root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False,
-             deterministic=False):
+             deterministic=False, dense_near=False):
     o = Options(int(host_only), int(use_graph), int(tile_leaf), int(tile_box),
                 table_cache.encode() if table_cache else None, int(split_min), int(overlap))
     o.root_centre[0], o.root_centre[1] = float(root_centre[0]), float(root_centre[1])
@@ -70,6 +71,7 @@ def _options(host_only=False, use_graph=False, tile_leaf=0, tile_box=0, table_ca
     o.kchunk_leaf = int(kchunk_leaf)
     o.dense_m2l = int(bool(dense_m2l))
     o.deterministic = int(bool(deterministic))
+    o.dense_near = int(bool(dense_near))
     return o
 
 
@@ -80,11 +82,12 @@ class Info(ctypes.Structure):
                 ("pairs_w", ctypes.c_int64), ("pairs_x", ctypes.c_int64), ("n_m2m", ctypes.c_int64),
                 ("n_l2l", ctypes.c_int64), ("n_s2m", ctypes.c_int64), ("n_l2t", ctypes.c_int64),
                 ("flops_total", ctypes.c_double), ("flops_adjoint", ctypes.c_double),
-                ("flops_kind", ctypes.c_double * 9), ("launches_kind", ctypes.c_int64 * 9),
+                ("flops_kind", ctypes.c_double * 11), ("launches_kind", ctypes.c_int64 * 11),
                 ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64),
-                ("flops_issued_kind", ctypes.c_double * 9), ("n_layer_nodes", ctypes.c_int64),
+                ("flops_issued_kind", ctypes.c_double * 11), ("n_layer_nodes", ctypes.c_int64),
                 ("n_source_leaves", ctypes.c_int64), ("n_active_boxes", ctypes.c_int64), ("pairs_p2p", ctypes.c_int64),
-                ("pairs_p2l", ctypes.c_int64), ("n_points", ctypes.c_int64), ("pairs_points", ctypes.c_int64)]
+                ("pairs_p2l", ctypes.c_int64), ("n_points", ctypes.c_int64), ("pairs_points", ctypes.c_int64),
+                ("pairs_lowrank", ctypes.c_int64)]
 
 
 class StageInfo(ctypes.Structure):
@@ -187,16 +190,17 @@ def _host_tree(centres, levels):
     return c, l
 
 
-def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None, eps=0.0, dense_m2l=False):
+def autotune(centres, levels, p=16, *, tree_offsets=None, cache=None, eps=0.0, dense_m2l=False, dense_near=False):
     """Fastest launch shape for this tree or forest on the current device (volpot_autotune):
     returns ({"tile_leaf", "tile_box", "split_min", "overlap", "tile_leaf_exp", "kchunk_leaf"}, ms per
     forward + adjoint apply). The candidates are timed at the expansion order that the far-field
-    tolerance ``eps`` selects (0: the default), with the M2L form ``dense_m2l`` selects. The
-    result is looked up in / appended to the text file ``cache`` when given."""
+    tolerance ``eps`` selects (0: the default), with the M2L and near-field forms that ``dense_m2l``
+    and ``dense_near`` select. The result is looked up in / appended to the text file ``cache``
+    when given."""
     c, l = _host_tree(centres, levels)
     off = np.ascontiguousarray(np.asarray([0, c.shape[0]] if tree_offsets is None else tree_offsets, dtype=np.int64))
     best = Options()
-    base = _options(eps=eps, dense_m2l=dense_m2l)
+    base = _options(eps=eps, dense_m2l=dense_m2l, dense_near=dense_near)
     ms = ctypes.c_double(0.0)
     _check(lib().volpot_autotune(off.size - 1, off.ctypes.data_as(_lp), c.ctypes.data_as(_dp), l.ctypes.data_as(_ip), p,
                                  ctypes.byref(base), cache.encode() if cache else None, ctypes.byref(best),
@@ -321,11 +325,12 @@ class Plan:
 
     def __init__(self, centres, levels, p=16, *, tree_offsets=None, host_only=False, use_graph=False,
                  tile_leaf=0, tile_box=0, table_cache=None, split_min=0, overlap=0, root_centre=(0.0, 0.0),
-                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False, deterministic=False):
+                 root_halfwidth=0.0, tile_leaf_exp=0, eps=0.0, kchunk_leaf=0, dense_m2l=False, deterministic=False,
+                 dense_near=False):
         c, l = _host_tree(centres, levels)
         self.n_leaves = c.shape[0]
         opt = _options(host_only, use_graph, tile_leaf, tile_box, table_cache, split_min, overlap, root_centre,
-                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf, dense_m2l, deterministic)
+                       root_halfwidth, tile_leaf_exp, eps, kchunk_leaf, dense_m2l, deterministic, dense_near)
         h = _vp()
         L = lib()
         if tree_offsets is None:
@@ -377,7 +382,8 @@ class Plan:
         return out
 
     def table(self, kind, index=0):
-        shape = {0: (256, 256), 1: (80, 256), 2: (256, 80)}[kind]
+        ne = self.info()["n_reals"]
+        shape = {0: (256, 256), 1: (ne, 256), 2: (256, ne), 3: (256, 64), 4: (64, 256)}[kind]
         out = np.zeros(shape)
         _check(lib().volpot_plan_table(self._h, kind, index, out.ctypes.data_as(_dp), out.size), "volpot_plan_table")
         return out

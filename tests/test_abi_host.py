@@ -107,6 +107,21 @@ def test_near_tables_agree_with_oracle(vp, host_plan):
     assert worst < 1e-14
 
 
+def test_low_rank_near_factors_reproduce_oracle_tables(vp, host_plan):
+    # the rank-64 factors the near field applies for every relation but the self one: U_r has
+    # orthonormal columns (pivoted QR) and U_r V_r stays within the tables' own quadrature error
+    # of the oracle's independently integrated tables
+    OT = quad.near_tables()
+    worst = 0.0
+    for r in range(1, 33):
+        U, V = host_plan.table(3, r), host_plan.table(4, r)
+        assert np.max(np.abs(U.T @ U - np.eye(64))) < 1e-13
+        worst = max(worst, np.max(np.abs(U @ V - OT[quad.relation_index(*vp.near_relation(r))])))
+    assert worst < 1e-14
+    with pytest.raises(vp.VolpotError):
+        host_plan.table(3, 0)  # the self relation is applied dense
+
+
 def test_s2m_and_l2t_reproduce_definitions(vp, host_plan):
     # S2M row 0 is the leaf mass weights W; rows 2, 3 (n = 1) are -int l_k eta_x, -int l_k eta_y
     W = onodes.tensor_weights()
@@ -201,7 +216,11 @@ def test_overlap_launch_order(vp):
             # the small far stage (S2L / M2T^T) opens the downward chain
             assert all(names.index(n) > names.index(far[-1]) for n in names if n.startswith(down + "["))
             assert names.index(far[-1]) == names.index(far[0]) + 1
-            nears = [n for n in names if n.startswith(near)]
+            # the low-rank near field's pair stage (V_r f~ / U_r^T u~) comes before the near
+            # launches that read its rows
+            pre = near + "C"
+            nears = [n for n in names if n.startswith(near) and n != pre]
+            assert names.index(pre) < names.index(nears[0])
             if overlap:
                 assert nears == [near + "_A", near + "_B"]
                 assert names.index(near + "_A") < i_far < names.index(near + "_B") < len(names) - 1

@@ -250,6 +250,26 @@ def test_deterministic_option_matches_default(vp, torch_mod):
     assert rel(out[True][0], out[False][0]) <= 1e-14 and rel(out[True][1], out[False][1]) <= 1e-13
 
 
+@pytest.mark.parametrize("overlap", [0, 16])
+def test_low_rank_near_matches_dense_near(vp, torch_mod, overlap):
+    # the default near field applies rank-64 factors of the non-self tables; dense_near applies
+    # the 256 x 256 tables. Same map to the factors' accuracy, forward and adjoint, with the near
+    # field in one launch or cut in two around the far field
+    w = gen.config3(0)
+    _say("case low-rank vs dense near field, overlap %d, %d leaves" % (overlap, w.n_leaves))
+    f = _gpu(torch_mod, w.f)
+    r = _gpu(torch_mod, np.random.default_rng(6).standard_normal(w.f.shape))
+    out = {}
+    for dense in (False, True):
+        plan = vp.Plan(w.centres, w.levels, dense_near=dense, overlap=overlap)
+        names = [s["name"] for s in plan.stages() + plan.stages(adjoint=True)]
+        assert ("NEARC" in names and "ANEARC" in names) != dense
+        assert (plan.info()["pairs_lowrank"] > 0) != dense
+        out[dense] = (plan.apply(f).cpu().numpy(), plan.apply_adjoint(r).cpu().numpy())
+        plan.close()
+    assert rel(out[False][0], out[True][0]) <= 1e-13 and rel(out[False][1], out[True][1]) <= 1e-13
+
+
 def test_graph_replays_match_eager(vp, torch_mod):
     w = gen.config2(0)
     _say("case graph replay")
