@@ -96,9 +96,10 @@ typedef struct {
                               oracle at that order). 0 = default 1e-13 (P = 39).
                               VOLPOT_ERR_UNSUPPORTED below 1e-13, and for layer-potential and
                               point plans at any P other than 39. */
-  int32_t kchunk_leaf;     /* k-chunk of the near-field stages: 32 (default; 0) or 16 (shorter
-                              chunks, less LDS and fewer registers: three blocks per compute
-                              unit instead of two) */
+  int32_t kchunk_leaf;     /* k-chunk of the dense near-field stages (dense_near = 1, layer
+                              plans): 32 (default; 0) or 16 (shorter chunks, less LDS and fewer
+                              registers: three blocks per compute unit instead of two). The
+                              low-rank near field always takes 16. */
   int32_t dense_m2l;       /* 0 (default): the M2L stages (FARV and its transpose) apply each
                               translation in factored form, diag(d^-l) H diag((-1)^k d^-k)
                               with one real, offset-free core H shared by all 40 V-list offsets
@@ -114,14 +115,14 @@ typedef struct {
                               every tile belongs to one block (split_min is taken as -1). The
                               two modes sum in different orders and agree to rounding. */
   int32_t dense_near;      /* 0 (default, volume plans): the adjacent-leaf tables other than a
-                              leaf's own apply in rank-64 form T_r = U_r V_r (Householder QR
-                              with column pivoting of each 256 x 256 table, stopped after 64
-                              columns; the discarded part is below 1e-14 of the table, whose
-                              numerical rank is 38 to 58): a first stage forms V_r f for every
-                              such pair (64 values a pair in plan memory), the near field then
-                              applies U_r to those and the self table to the leaf's own data,
-                              about half the matrix-core work. 1: the dense tables. The two agree
-                              to rounding (the tests compare them). */
+                              leaf's own apply in low-rank form T_r = U_r V_r (Householder QR
+                              with column pivoting of each 256 x 256 table, stopped after k_r =
+                              64 columns, or 48 where that loses only rounding-level terms: the
+                              corner and coarser neighbours): stages NEARC / NEARC48 form V_r f
+                              for every such pair (64 values a pair in plan memory), the near
+                              field then applies U_r to those and the self table to the leaf's
+                              own data, about 40% of the dense matrix-core work. 1: the dense
+                              tables. The two agree to rounding (the tests compare them). */
 } volpot_options;
 
 /* Algorithmic work of one apply, from the plan's exact pair counts. Flops are 2 x the
@@ -153,7 +154,7 @@ typedef struct {
   /* plans with evaluation points (volpot_plan_points; zero otherwise) */
   int64_t n_points;         /* evaluation points */
   int64_t pairs_points;     /* (point, adjacent leaf) pairs, each a precomputed 3 x 256 moment block */
-  int64_t pairs_lowrank;    /* adjacent-leaf pairs in rank-64 form (0 with dense_near) */
+  int64_t pairs_lowrank;    /* adjacent-leaf pairs in low-rank form (0 with dense_near) */
 } volpot_info;
 
 /* Build a plan for one tree (Sec. 4.2.1: boxes {B_k}, order p; here p = 16 only).
@@ -331,17 +332,18 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 /* Inspection: copy a host-side table of the plan (row-major) into out (n doubles).
  *   kind 0: near table of relation index (0..32, see volpot_near_relation), 256 x 256
  *   kind 1: S2M (2q x 256);   kind 2: L2T (256 x 2q), q = P + 1 of the plan's order
- *   kind 3: U_r (256 x 64) and kind 4: V_r (64 x 256) of relation index 1..32, the rank-64
- *           factors the low-rank near field applies (T_r ~ U_r V_r)
+ *   kind 3: U_r (256 x 64) and kind 4: V_r (64 x 256) of relation index 1..32, the factors
+ *           the low-rank near field applies (T_r ~ U_r V_r); a relation of rank 48 comes
+ *           zero-padded (columns 48..63 of U_r, rows 48..63 of V_r)
  * Returns VOLPOT_ERR_ARG for an unknown kind/index or n too small. */
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
 
 /* Autotuner (for callers that apply one tree shape many times, e.g. batched forests): searches
- * the launch shapes tile_box 16|32|64, tile_leaf 32|64, kchunk_leaf 32|16, tile_leaf_exp 16|32|64,
- * split_min 0|1|-1 and overlap 0|16|24|32|48
- * one knob at a time from the defaults (the other fields, eps among them, are taken from base,
- * nullable), building a plan for each candidate and timing one forward plus one adjoint apply on internal
- * device buffers after a warm-up (HIP events, private stream, best of 5); writes the fastest
+ * the launch shapes tile_box 16|32|64, tile_leaf 32|64, kchunk_leaf 32|16 (dense_near only),
+ * tile_leaf_exp 16|32|64, split_min 0|1|-1 and overlap 0|16|24|32|48 one knob at a time from the
+ * defaults (the other fields, eps among them, are taken from base, nullable), building a plan
+ * for each candidate and timing one forward plus one adjoint apply on internal device buffers
+ * after a warm-up (HIP events, private stream, best of 5); writes the fastest
  * options to *best and their time in milliseconds to *best_ms (nullable). A candidate must beat
  * the current choice by more than 1.5%, and the result must beat the defaults by as much when
  * both are timed again, so that differences within timing noise keep the defaults. With
@@ -375,8 +377,10 @@ typedef struct {
   int64_t n_tiles, n_segments, n_blocks, n_split_tiles;
   double flops, flops_issued;
   int32_t inner;           /* inner dimension K of the stage's products (reals; complex terms
-                              when factored) */
+                              when factored); the largest one where segments differ (the
+                              low-rank near field's K = 48 and 64) */
   int32_t factored;        /* 1: the factored M2L form (see volpot_options.dense_m2l) */
+  int64_t n_chunks;        /* k-chunks over all segments (each segment's K / kchunk) */
 } volpot_stage_info;
 
 /* Number of stages of the forward (adjoint = 0) or adjoint (1) apply, in launch order. */

@@ -822,6 +822,7 @@ int volpot_plan_stage(volpot_plan_t plan, int32_t adjoint, int32_t index, volpot
   out->flops_issued = s.flops_issued;
   out->inner = s.K;
   out->factored = s.cx_rel >= 0;
+  for (int32_t k : s.seg_k) out->n_chunks += k / s.KC;
   return VOLPOT_OK;
 }
 
@@ -903,9 +904,17 @@ int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* o
   if (kind == 0 && index >= 0 && index < 33) id = kRelNear + index;
   else if (kind == 1 && index == 0) id = kRelS2M;
   else if (kind == 2 && index == 0) id = kRelL2T;
-  else if (kind == 3 && index >= 1 && index < 33) id = kRelNU + index - 1;
-  else if (kind == 4 && index >= 1 && index < 33) id = kRelNV + index - 1;
-  else return VOLPOT_ERR_ARG;
+  else if ((kind == 3 || kind == 4) && index >= 1 && index < 33) {  // zero-padded to rank 64
+    id = (kind == 3 ? kRelNU : kRelNV) + index - 1;
+    const int rows = kind == 3 ? kNP : kNearRank, cols = kind == 3 ? kNearRank : kNP;
+    if (n < int64_t(rows) * cols) return VOLPOT_ERR_ARG;
+    const int m = M.M[size_t(id)], k = M.K[size_t(id)];
+    for (int i = 0; i < rows; ++i)
+      for (int c = 0; c < cols; ++c) out[size_t(i) * cols + c] = (i < m && c < k) ? M.a[size_t(id)][size_t(i) * k + c] : 0.0;
+    return VOLPOT_OK;
+  } else {
+    return VOLPOT_ERR_ARG;
+  }
   if (n < int64_t(M.a[id].size())) return VOLPOT_ERR_ARG;
   std::memcpy(out, M.a[id].data(), M.a[id].size() * sizeof(double));
   return VOLPOT_OK;

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <functional>
 #include <map>
 #include <stdexcept>
 #include <thread>
@@ -822,7 +823,9 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   // ---------------------------------------------------------------- stages
   const Matrices& mats = matrices(ne / 2);
   const int NTL = (tile_leaf == 32 || tile_leaf == 64) ? tile_leaf : 32;
-  const int KCL = kchunk_leaf == 16 ? 16 : 32;  // k-chunk of the near-field stages
+  // k-chunk of the near-field stages; the low-rank form's segments (K = 48 or 64) take 16
+  const bool lr = !layer && !dense_near;
+  const int KCL = (lr || kchunk_leaf == 16) ? 16 : 32;
   const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 32;
   // The leaf stages with K = 80 (L2T, M2T and their transposes' counterparts S2M^T, S2L^T) do
   // little work per tile: on small trees 16-slot tiles give more independent workgroups to hide
@@ -1132,11 +1135,30 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   }
   if (layer) halves.clear();
   // Low-rank near field (volume plans unless dense_near): every adjacent-leaf pair other than a
-  // leaf with itself gets a row of A_NW holding V_r f~ of its source (stage NEARC), and the near
-  // field proper applies U_r to those rows and the self table, in four 64-column slices, to the
-  // leaf's own f~. lr_idx: the row of each entry of Ulist (-1 for the self entry).
-  const bool lr = !layer && !dense_near;
+  // leaf with itself gets a row of A_NW holding V_r f~ of its source (stages NEARC, one per rank
+  // k_r, with k_r rows), and the near field proper applies U_r to those rows and the self table,
+  // in four 64-column slices, to the leaf's own f~. lr_idx: the row of each entry of Ulist (-1
+  // for the self entry).
   std::vector<int64_t> lr_idx;
+  auto near_rank = [&](int r) { return mats.M[size_t(kRelNV + r - 1)]; };
+  // one pair stage per rank: rows of the pairs whose relation has that rank, as (row, entry)
+  auto pair_stage = [&](int kind, const char* name, int rank, int8_t out, bool adj,
+                        const std::function<Entry(int64_t g, int64_t a)>& entry) {
+    std::vector<int32_t> tg;
+    std::vector<std::vector<Entry>> E;
+    for (int64_t a = 0; a < P.n_leaves; ++a)
+      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
+        if (lr_idx[size_t(g)] >= 0 && near_rank(Ulist.e[size_t(g)].first) == rank) {
+          tg.push_back(int32_t(lr_idx[size_t(g)]));
+          E.push_back({entry(g, a)});
+        }
+    if (tg.empty()) return;
+    Stage st; init_stage(st, kind, name, -1, rank, kNP, kPairTile, out, kNearRank);
+    st.pre_near = 1;
+    st.fam[0] = {adj ? A_IN : A_INS, kNP, 0};
+    std::vector<std::vector<R1>> R(tg.size());
+    defer(std::move(st), tg, std::move(E), std::move(R), adj);
+  };
   if (lr) {
     lr_idx.assign(Ulist.e.size(), -1);
     int64_t n = 0;
@@ -1144,19 +1166,10 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       if (Ulist.e[g].first != 0) lr_idx[g] = n++;
     if (n >= (int64_t(1) << 31)) throw std::runtime_error("too many adjacent-leaf pairs");
     P.pairs_lr = n;
-    Stage st; init_stage(st, K_NEARC, "NEARC", -1, kNearRank, kNP, NTB, A_NW, kNearRank);
-    st.pre_near = 1;
-    st.fam[0] = {A_INS, kNP, 0};
-    std::vector<int32_t> tg(static_cast<size_t>(n));
-    for (int64_t i = 0; i < n; ++i) tg[size_t(i)] = int32_t(i);
-    std::vector<std::vector<Entry>> E(static_cast<size_t>(n));
-    std::vector<std::vector<R1>> R(static_cast<size_t>(n));
-    par_for(P.n_leaves, [&](int64_t a) {
-      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
-        if (lr_idx[size_t(g)] >= 0)
-          E[size_t(lr_idx[size_t(g)])].push_back({kRelNV + Ulist.e[size_t(g)].first - 1, 0, Ulist.e[size_t(g)].second});
-    });
-    defer(std::move(st), tg, std::move(E), std::move(R), false);
+    for (int rank : {kNearRank, kNearRankLow})
+      pair_stage(K_NEARC, rank == kNearRank ? "NEARC" : "NEARC48", rank, A_NW, false, [&](int64_t g, int64_t) {
+        return Entry{kRelNV + Ulist.e[size_t(g)].first - 1, 0, Ulist.e[size_t(g)].second};
+      });
   }
   for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
     const std::vector<int32_t> part(near_order.begin() + long(halves[h].first), near_order.begin() + long(halves[h].second));
@@ -1283,22 +1296,11 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       if (Ulist.e[size_t(g)].first == r) return int32_t(lr_idx[size_t(g)]);
     throw std::runtime_error("adjacent-leaf pair not found");
   };
-  if (lr) {  // ANEARC: U_r^T ubar of the target of every pair
-    const int64_t n = P.pairs_lr;
-    Stage st; init_stage(st, K_ANEARC, "ANEARC", -1, kNearRank, kNP, NTB, A_NWA, kNearRank);
-    st.pre_near = 1;
-    st.fam[0] = {A_IN, kNP, 0};
-    std::vector<int32_t> tg(static_cast<size_t>(n));
-    for (int64_t i = 0; i < n; ++i) tg[size_t(i)] = int32_t(i);
-    std::vector<std::vector<Entry>> E(static_cast<size_t>(n));
-    std::vector<std::vector<R1>> R(static_cast<size_t>(n));
-    par_for(P.n_leaves, [&](int64_t a) {
-      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
-        if (lr_idx[size_t(g)] >= 0)
-          E[size_t(lr_idx[size_t(g)])].push_back({kRelNU + Ulist.e[size_t(g)].first - 1 + kNumFwd, 0, int32_t(a)});
-    });
-    defer(std::move(st), tg, std::move(E), std::move(R), true);
-  }
+  if (lr)  // ANEARC: U_r^T ubar of the target of every pair, one stage per rank
+    for (int rank : {kNearRank, kNearRankLow})
+      pair_stage(K_ANEARC, rank == kNearRank ? "ANEARC" : "ANEARC48", rank, A_NWA, true, [&](int64_t g, int64_t a) {
+        return Entry{kRelNU + Ulist.e[size_t(g)].first - 1 + kNumFwd, 0, int32_t(a)};
+      });
   for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
     const std::vector<int32_t> part(anear_order.begin() + long(halves[h].first), anear_order.begin() + long(halves[h].second));
     Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, lr ? 64 : kNP,

@@ -64,11 +64,16 @@ constexpr int kRelL2L2 = 139; // +4 qc + qg: L2L_qg L2L_qc, box to grandchild
 // 16 (zero rows), q columns; the adjoint id holds H^T padded the same way.
 constexpr int kRelH = 155;
 // The adjacent-leaf tables of the 32 relations other than a leaf with itself (near relation
-// r = 1..32 at index r - 1) in rank-64 form T_r = U_r V_r (U_r 256 x 64, V_r 64 x 256, Householder
-// QR with column pivoting truncated after 64 columns); the self table (relation 0) as four
-// 64-column slices for the forward (T[:, 64q .. 64q + 63], read at offset 64q of the source leaf)
-// and four for the adjoint ((T[64q .. 64q + 63, :])^T, read at offset 64q of the cotangent).
+// r = 1..32 at index r - 1) in low-rank form T_r = U_r V_r (U_r 256 x k_r, V_r k_r x 256,
+// Householder QR with column pivoting truncated after k_r columns). k_r is 48 where that
+// truncation is exact to rounding (corner neighbours and every coarser neighbour), else 64; the
+// rows of a pair's intermediate V_r f are kNearRank apart whatever k_r. The self table (relation
+// 0) as four 64-column slices for the forward (T[:, 64q .. 64q + 63], read at offset 64q of the
+// source leaf) and four for the adjoint ((T[64q .. 64q + 63, :])^T, read at offset 64q of the
+// cotangent).
 constexpr int kNearRank = 64;
+constexpr int kNearRankLow = 48;
+constexpr int kPairTile = 64;  // slots per tile of the stages that form V_r f (U_r^T u)
 constexpr int kRelNU = 156;   // +32: U_r
 constexpr int kRelNV = 188;   // +32: V_r
 constexpr int kRelNSF = 220;  // +4: forward self slices

@@ -556,11 +556,17 @@ static void pivoted_qr(const std::vector<double>& T, int n, int k, std::vector<d
   }
 }
 
-// The rank-64 factors of the 32 adjacent-leaf tables other than the self table, computed once
+// The low-rank factors of the 32 adjacent-leaf tables other than the self table, computed once
 // (the near tables are the same for every expansion order).
 struct NearFactors {
-  std::vector<std::vector<double>> U, V;  // 32 each: 256 x 64 and 64 x 256
+  std::vector<std::vector<double>> U, V;  // 32 each: 256 x k_r and k_r x 256
+  std::vector<int> rank;                  // k_r
 };
+// Truncating a relation's factors after kNearRankLow columns is kept when the discarded part
+// is below this fraction of the self table (Frobenius norms). For the 32 relations the
+// truncation error is either at rounding level (about 3e-15 of it) or above 1e-11: the
+// threshold sits between the two groups.
+constexpr double kNearRankLowTol = 1e-13;
 static const NearFactors& near_factors() {
   static std::once_flag once;
   static NearFactors* F = nullptr;
@@ -569,9 +575,31 @@ static const NearFactors& near_factors() {
     const std::vector<std::vector<double>>& T = near_tables();
     F->U.resize(32);
     F->V.resize(32);
+    F->rank.assign(32, kNearRank);
+    double self2 = 0.0;
+    for (double x : T[0]) self2 += x * x;
     std::vector<std::thread> th;
     for (int r = 1; r <= 32; ++r)
-      th.emplace_back([&, r]() { pivoted_qr(T[size_t(r)], kNP, kNearRank, F->U[size_t(r - 1)], F->V[size_t(r - 1)]); });
+      th.emplace_back([&, r, self2]() {
+        std::vector<double>& U = F->U[size_t(r - 1)];
+        std::vector<double>& V = F->V[size_t(r - 1)];
+        pivoted_qr(T[size_t(r)], kNP, kNearRank, U, V);
+        const int k = kNearRankLow;
+        double e2 = 0.0;  // || T_r - U_r[:, :k] V_r[:k, :] ||_F^2
+        for (int i = 0; i < kNP; ++i)
+          for (int j = 0; j < kNP; ++j) {
+            double s = T[size_t(r)][size_t(i) * kNP + j];
+            for (int c = 0; c < k; ++c) s -= U[size_t(i) * kNearRank + c] * V[size_t(c) * kNP + j];
+            e2 += s * s;
+          }
+        if (e2 > kNearRankLowTol * kNearRankLowTol * self2) return;
+        std::vector<double> Uk(size_t(kNP) * k);
+        for (int i = 0; i < kNP; ++i)
+          for (int c = 0; c < k; ++c) Uk[size_t(i) * k + c] = U[size_t(i) * kNearRank + c];
+        U.swap(Uk);
+        V.resize(size_t(k) * kNP);  // the first k rows
+        F->rank[size_t(r - 1)] = k;
+      });
     for (auto& t : th) t.join();
   });
   return *F;
@@ -697,8 +725,9 @@ static Matrices build_matrices(const int Q) {
     // the low-rank form of relations 1..32 and the 64-column slices of the self table
     const NearFactors& F = near_factors();
     for (int r = 0; r < 32; ++r) {
-      set(kRelNU + r, kNP, kNearRank, std::vector<double>(F.U[size_t(r)]));
-      set(kRelNV + r, kNearRank, kNP, std::vector<double>(F.V[size_t(r)]));
+      const int k = F.rank[size_t(r)];
+      set(kRelNU + r, kNP, k, std::vector<double>(F.U[size_t(r)]));
+      set(kRelNV + r, k, kNP, std::vector<double>(F.V[size_t(r)]));
     }
     const std::vector<double>& S = T[0];
     for (int q = 0; q < 4; ++q) {

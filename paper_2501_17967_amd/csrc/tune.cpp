@@ -198,7 +198,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
   if (rc == VOLPOT_OK) {
     try_axis(0, {16, 32, 64});
     try_axis(1, {32, 64});
-    try_axis(5, {32, 16});
+    if (o.dense_near) try_axis(5, {32, 16});  // the low-rank near field always takes k-chunk 16
     try_axis(4, {16, 32, 64});
     if (!o.deterministic) try_axis(2, {0, 1, -1});  // deterministic plans never cut tiles
     try_axis(3, {0, 16, 24, 32, 48});

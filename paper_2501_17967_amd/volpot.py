@@ -95,7 +95,7 @@ class StageInfo(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("kchunk", ctypes.c_int32), ("helper", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int64), ("n_segments", ctypes.c_int64), ("n_blocks", ctypes.c_int64),
                 ("n_split_tiles", ctypes.c_int64), ("flops", ctypes.c_double), ("flops_issued", ctypes.c_double),
-                ("inner", ctypes.c_int32), ("factored", ctypes.c_int32)]
+                ("inner", ctypes.c_int32), ("factored", ctypes.c_int32), ("n_chunks", ctypes.c_int64)]
 
 
 _lib = None
