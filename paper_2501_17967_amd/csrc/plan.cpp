@@ -397,6 +397,7 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   for (Stage& s : v) {
     s.helper = s.join_before = s.fork_before = s.concurrent = 0;
     if (s.pre_near) pre.push_back(std::move(s));                            // NEARC / ANEARC
+    else if (s.after_far) tail.push_back(std::move(s));                     // NEAR+LOCT / ANEAR+ALOCT
     else if (s.kind == k_up && s.level < 0) head.push_back(std::move(s));   // S2M / AL2T
     else if (s.kind == k_up) up_chain.push_back(std::move(s));              // M2M[l] / AL2L[l]
     else if (s.kind == k_down && s.level < 0) far.push_back(std::move(s));  // FARV, FARX / AFARV, AFARW
@@ -1171,13 +1172,31 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         return Entry{kRelNV + Ulist.e[size_t(g)].first - 1, 0, Ulist.e[size_t(g)].second};
       });
   }
+  // With the low-rank near field in one launch, the leaf stage (LOCT: L2T, M2T and the log
+  // terms, and its adjoint ALOCT) folds into it: the same targets, 256 rows and k-chunk 16, its
+  // segments read families 2 and 3. The folded stage then runs after the far field, in LOCT's
+  // place, and writes the output once instead of the near field writing it and LOCT adding on.
+  const bool fold = lr && halves.size() == 1;
+  // LOCT's segments and log terms of leaf a (families f0, f0 + 1: multipoles, locals)
+  auto loct_terms = [&](int32_t a, std::vector<Entry>& E, std::vector<R1>& R, int8_t f0) {
+    const double kap = P.leaf_kappa[a];
+    for (auto& e : Ulist[size_t(a)]) R.push_back({0, P.leaf_box[e.second], kap});
+    for (auto& e : Wlist[size_t(a)]) { E.push_back({kRelM2T + e.first, f0, e.second}); R.push_back({0, e.second, kap}); }
+    if (levels[a] >= 2) E.push_back({kRelL2T, int8_t(f0 + 1), P.leaf_box[a]});
+  };
   for (size_t h = 0; h < halves.size(); ++h) {  // NEAR: the adjacent-leaf tables
     const std::vector<int32_t> part(near_order.begin() + long(halves[h].first), near_order.begin() + long(halves[h].second));
-    Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : "NEAR", -1, kNP, lr ? 64 : kNP, NTL,
-                         A_OUT, kNP);
+    Stage st; init_stage(st, K_NEAR, halves.size() > 1 ? (h ? "NEAR_B" : "NEAR_A") : (fold ? "NEAR+LOCT" : "NEAR"), -1,
+                         kNP, lr ? 64 : kNP, NTL, A_OUT, kNP);
     st.KC = KCL;
     st.fam[0] = {A_INS, kNP, 0};
     if (lr) st.fam[1] = {A_NW, kNearRank, 0};
+    if (fold) {
+      st.after_far = 1;
+      st.r1_all_rows = 1;
+      st.fam[2] = {A_MP, kNE, 0}; st.fam[3] = {A_LOC, kNE, 0};
+      st.r1fam[0] = {A_MP, kNE, 0};
+    }
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
     par_for(int64_t(part.size()), [&](int64_t i) {
@@ -1190,7 +1209,10 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
         if (lr_idx[size_t(g)] >= 0)
           E[size_t(i)].push_back({kRelNU + Ulist.e[size_t(g)].first - 1, 1, int32_t(lr_idx[size_t(g)])});
+      if (fold) loct_terms(a, E[size_t(i)], R[size_t(i)], 2);
     });
+    if (fold)
+      for (int32_t a : part) P.n_l2t += levels[a] >= 2;
     defer(std::move(st), part, std::move(E), std::move(R), false);
   }
   if (layer) {  // LOCT: L2T + M2T of active W boxes and their kappa(s_a) * mass terms (P2P adds on)
@@ -1210,7 +1232,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (int32_t a : leaf_order) P.n_l2t += levels[a] >= 2;
     defer(std::move(st), leaf_order, std::move(E), std::move(R), false);
   }
-  if (!layer) {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
+  if (!layer && !fold) {  // LOCT: L2T + M2T + every kappa(s_a) * mass term, added onto NEAR
     Stage st; init_stage(st, K_LOCT, "LOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
     st.accumulate = 1;
     st.r1_all_rows = 1;
@@ -1219,11 +1241,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
     par_for(int64_t(leaf_order.size()), [&](int64_t i) {
-      int32_t a = leaf_order[size_t(i)];
-      double kap = P.leaf_kappa[a];
-      for (auto& e : Ulist[a]) R[size_t(i)].push_back({0, P.leaf_box[e.second], kap});
-      for (auto& e : Wlist[a]) { E[size_t(i)].push_back({kRelM2T + e.first, 0, e.second}); R[size_t(i)].push_back({0, e.second, kap}); }
-      if (levels[a] >= 2) E[size_t(i)].push_back({kRelL2T, 1, P.leaf_box[a]});
+      loct_terms(leaf_order[size_t(i)], E[size_t(i)], R[size_t(i)], 0);
     });
     for (int32_t a : leaf_order) P.n_l2t += levels[a] >= 2;
     defer(std::move(st), leaf_order, std::move(E), std::move(R), false);
@@ -1296,6 +1314,11 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       if (Ulist.e[size_t(g)].first == r) return int32_t(lr_idx[size_t(g)]);
     throw std::runtime_error("adjacent-leaf pair not found");
   };
+  // ALOCT's segments of leaf b (families f0, f0 + 1: multipole and local cotangents)
+  auto aloct_terms = [&](int32_t b, std::vector<Entry>& E, int8_t f0) {
+    E.push_back({kRelS2M + kNumFwd, f0, P.leaf_box[b]});
+    for (auto& e : Xinv[size_t(b)]) E.push_back({kRelS2L + e.first + kNumFwd, int8_t(f0 + 1), e.second});
+  };
   if (lr)  // ANEARC: U_r^T ubar of the target of every pair, one stage per rank
     for (int rank : {kNearRank, kNearRankLow})
       pair_stage(K_ANEARC, rank == kNearRank ? "ANEARC" : "ANEARC48", rank, A_NWA, true, [&](int64_t g, int64_t a) {
@@ -1303,12 +1326,16 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       });
   for (size_t h = 0; h < halves.size(); ++h) {  // ANEAR: transposed near tables
     const std::vector<int32_t> part(anear_order.begin() + long(halves[h].first), anear_order.begin() + long(halves[h].second));
-    Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : "ANEAR", -1, kNP, lr ? 64 : kNP,
-                         NTL, A_OUT, kNP);
+    Stage st; init_stage(st, K_ANEAR, halves.size() > 1 ? (h ? "ANEAR_B" : "ANEAR_A") : (fold ? "ANEAR+ALOCT" : "ANEAR"),
+                         -1, kNP, lr ? 64 : kNP, NTL, A_OUT, kNP);
     st.KC = KCL;
     st.out_scaled = 1;
     st.fam[0] = {A_IN, kNP, 0};
     if (lr) st.fam[1] = {A_NWA, kNearRank, 0};
+    if (fold) {
+      st.after_far = 1;
+      st.fam[2] = {A_AB, kNE, 0}; st.fam[3] = {A_LB, kNE, 0};
+    }
     std::vector<std::vector<Entry>> E(part.size());
     std::vector<std::vector<R1>> R(part.size());
     par_for(int64_t(part.size()), [&](int64_t i) {
@@ -1320,10 +1347,11 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
       for (int q = 0; q < 4; ++q) E[size_t(i)].push_back({kRelNSA + q, 0, b});
       for (auto& e : Uinv[size_t(b)])
         if (e.first != 0) E[size_t(i)].push_back({kRelNV + e.first - 1 + kNumFwd, 1, pair_row(e.second, e.first)});
+      if (fold) aloct_terms(b, E[size_t(i)], 2);
     });
     defer(std::move(st), part, std::move(E), std::move(R), true);
   }
-  {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
+  if (!fold) {  // ALOCT: S2M^T + S2L^T, added onto ANEAR
     Stage st; init_stage(st, K_ALOCT, "ALOCT", -1, kNP, kNE, kNTK80, A_OUT, kNP);
     st.accumulate = 1;
     st.out_scaled = 1;
@@ -1331,9 +1359,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<std::vector<Entry>> E(P.n_leaves);
     std::vector<std::vector<R1>> R(P.n_leaves);
     par_for(int64_t(leaf_order.size()), [&](int64_t i) {
-      int32_t b = leaf_order[size_t(i)];
-      E[size_t(i)].push_back({kRelS2M + kNumFwd, 0, P.leaf_box[b]});
-      for (auto& e : Xinv[b]) E[size_t(i)].push_back({kRelS2L + e.first + kNumFwd, 1, e.second});
+      aloct_terms(leaf_order[size_t(i)], E[size_t(i)], 0);
     });
     defer(std::move(st), leaf_order, std::move(E), std::move(R), true);
   }

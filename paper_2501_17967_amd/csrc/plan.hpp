@@ -158,6 +158,7 @@ struct Stage {
   // segment, and the tile's columns are the real and imaginary parts of its slots
   int cx_rel = -1;
   int8_t pre_near = 0;     // runs right before the near field (its compression stage)
+  int8_t after_far = 0;    // a near field with the leaf stage folded in: runs in the leaf stage's place
   double flops_issued = 0;  // MFMA work of the tiles, empty slots included
   int n_tiles = 0;
   int8_t out_arr = A_NONE;
