@@ -65,8 +65,10 @@ typedef struct {
   int32_t tile_leaf;       /* slots per tile of the near-field stages (256 rows): 32 or 64;
                               0 = default (32). The 256-row stages with K = 80 take
                               tile_leaf_exp. */
-  int32_t tile_box;        /* slots per tile of the 80-row (expansion) stages: 16, 32 or 64;
-                              0 = default (32) */
+  int32_t tile_box;        /* slots per tile of the expansion translation stages (M2M, L2L
+                              chains, M2L): 16, 32 or 64; 0 = default (32). The expansion
+                              stages whose other side is leaf data (S2M, S2L, their transposes,
+                              the low-rank near field's pair stages) take 64. */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
   int32_t split_min;       /* each stage is cut into as many equal shares of its k-chunks as the
                               device runs blocks at once; a share has at least this many chunks

@@ -354,11 +354,16 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 // unit (256 registers per lane): the other block works while this one waits at a barrier or
 // for memory. Its k-chunk-16 form, which also runs the leaf stages that read expansions
 // (K = 64 or 80), is held to three (168 registers): those stages are latency-bound, and the
-// third block took 7% off them. The other instantiations keep the compiler's own choice.
+// third block took 7% off them. The expansion-row instantiations of four 16-slot waves (up to
+// 64 rows) are held to four blocks (128 registers, no spills): their tiles are short (one
+// segment of K = 256 in eight chunks), and the compiler's own choice, three blocks with the
+// accumulators in extra registers, left the pair stages 15% slower. The other
+// instantiations keep the compiler's own choice.
 // The factored M2L instantiations ask for three waves per SIMD (two for q = 40, whose
 // accumulators are half as large again).
 template <int MT, int NTT, int WM, int WN, int KC, bool CX>
 constexpr int min_blocks() {
+  if (!CX && WM == 1 && WN == 4 && NTT == 1 && MT <= 4) return 4;
   return (!CX && MT == 4 && NTT == 2 && WM == 4 && WN == 1) ? (KC == 32 ? 2 : KC == 16 ? 3 : 1) : 1;
 }
 template <int KC, bool CX>

@@ -828,6 +828,8 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   const bool lr = !layer && !dense_near;
   const int KCL = (lr || kchunk_leaf == 16) ? 16 : 32;
   const int NTB = (tile_box == 16 || tile_box == 32 || tile_box == 64) ? tile_box : 32;
+  // the expansion-row stages that read or write leaf data (K or M = 256: S2M, S2L and their
+  // transposes, and the pair stages of the low-rank near field) take kLeafDataTile slots
   // The leaf stages with K = 80 (L2T, M2T and their transposes' counterparts S2M^T, S2L^T) do
   // little work per tile: on small trees 16-slot tiles give more independent workgroups to hide
   // the latency of their few dependent k-chunks; on large trees and forests wider tiles read
@@ -901,7 +903,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   if (!layer) {  // S2M: every leaf's multipole
     std::vector<int32_t> tg;
     for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0) tg.push_back(b);
-    Stage st; init_stage(st, K_UP, "S2M", -1, kNE, kNP, NTB, A_MP, kNE);
+    Stage st; init_stage(st, K_UP, "S2M", -1, kNE, kNP, kLeafDataTile, A_MP, kNE);
     st.fam[0] = {A_INS, kNP, 0};
     std::vector<std::vector<Entry>> E(tg.size());
     std::vector<std::vector<R1>> R(tg.size());
@@ -1056,7 +1058,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg;
     for (int32_t b : deep_by_quadrant) if (!Xlist[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
-      Stage st; init_stage(st, K_DOWN, "FARX", -1, kNE, kNP, NTB, A_FAR, kNE);
+      Stage st; init_stage(st, K_DOWN, "FARX", -1, kNE, kNP, kLeafDataTile, A_FAR, kNE);
         st.accumulate = 1;
       st.fam[0] = {A_INS, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
@@ -1154,7 +1156,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
           E.push_back({entry(g, a)});
         }
     if (tg.empty()) return;
-    Stage st; init_stage(st, kind, name, -1, rank, kNP, kPairTile, out, kNearRank);
+    Stage st; init_stage(st, kind, name, -1, rank, kNP, kLeafDataTile, out, kNearRank);
     st.pre_near = 1;
     st.fam[0] = {adj ? A_IN : A_INS, kNP, 0};
     std::vector<std::vector<R1>> R(tg.size());
@@ -1253,7 +1255,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg;
     for (int32_t b = 0; b < NB; ++b) if (P.box_leaf[b] >= 0 && P.box_level[b] >= 2) tg.push_back(b);
     if (!tg.empty()) {
-      Stage st; init_stage(st, K_AUP, "AL2T", -1, kNE, kNP, NTB, A_LB, kNE);
+      Stage st; init_stage(st, K_AUP, "AL2T", -1, kNE, kNP, kLeafDataTile, A_LB, kNE);
         st.fam[0] = {A_IN, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());
       std::vector<std::vector<R1>> R(tg.size());
@@ -1296,7 +1298,7 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     std::vector<int32_t> tg;
     for (int32_t b : afar_tg) if (!Winv[b].empty()) tg.push_back(b);
     if (!tg.empty()) {
-      Stage st; init_stage(st, K_ADOWN, "AFARW", -1, kNE, kNP, NTB, A_AFAR, kNE);
+      Stage st; init_stage(st, K_ADOWN, "AFARW", -1, kNE, kNP, kLeafDataTile, A_AFAR, kNE);
         st.accumulate = 1;
       st.fam[0] = {A_IN, kNP, 0};
       std::vector<std::vector<Entry>> E(tg.size());

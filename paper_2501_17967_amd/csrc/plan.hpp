@@ -73,7 +73,10 @@ constexpr int kRelH = 155;
 // cotangent).
 constexpr int kNearRank = 64;
 constexpr int kNearRankLow = 48;
-constexpr int kPairTile = 64;  // slots per tile of the stages that form V_r f (U_r^T u)
+// slots per tile of the expansion-row stages whose other side is leaf data (K or M = 256):
+// S2M, S2L, their transposes and the pair stages (V_r f, U_r^T u). 64 slots make four waves
+// of 16 slots each, which the kernel holds to four blocks per compute unit.
+constexpr int kLeafDataTile = 64;
 constexpr int kRelNU = 156;   // +32: U_r
 constexpr int kRelNV = 188;   // +32: V_r
 constexpr int kRelNSF = 220;  // +4: forward self slices
