@@ -383,13 +383,16 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
 }
 
 // Launch order and stream flags. Built order: [S2M] [M2M chain] [FARV] [FARX] [L2L chain]
-// [NEARC] [NEAR or NEAR_A NEAR_B] [LOCT] (adjoint: [AL2T] [AL2L chain] [AFARV] [AFARW] [AM2M chain]
-// [ANEARC] [ANEAR...] [ALOCT]). Launch order:
-//   S2M, M2M chain (helper), NEARC, NEAR_A, FARV (join), FARX + L2L chain (helper), NEAR_B, LOCT (join)
+// [NEARC NEARC48] [NEAR or NEAR_A NEAR_B] [LOCT] (adjoint: [AL2T] [AL2L chain] [AFARV] [AFARW]
+// [AM2M chain] [ANEARC...] [ANEAR...] [ALOCT]). Launch order of the dense near field:
+//   S2M, M2M chain (helper), NEAR_A, FARV (join), FARX + L2L chain (helper), NEAR_B, LOCT (join)
 // so that, with the overlap option, each latency-bound chain runs beside half of the near
-// field, which does not depend on the far field. Without overlap everything runs in this
-// order on one stream, which is also a valid order. A layer plan has P2M in S2M's place, P2L in
-// FARX's, and its direct sum P2P, which adds onto LOCT's output, last.
+// field, which does not depend on the far field. The low-rank near field, folded with the leaf
+// stage into one stage that needs the far field, puts its pair stages there instead:
+//   S2M, M2M chain (helper), NEARC, FARV (join), FARX, L2L chain (helper), NEARC48, NEAR+LOCT (join)
+// Without overlap everything runs in this order on one stream, which is also a valid order. A
+// layer plan has P2M in S2M's place, P2L in FARX's, and its direct sum P2P, which adds onto
+// LOCT's output, last.
 static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   const int k_up = adjoint ? K_AUP : K_UP, k_down = adjoint ? K_ADOWN : K_DOWN;
   const int k_near = adjoint ? K_ANEAR : K_NEAR, k_loct = adjoint ? K_ALOCT : K_LOCT;
@@ -423,26 +426,30 @@ static void arrange_stages(std::vector<Stage>& v, bool adjoint) {
   // layer plans: the direct sum (P2P) adds onto LOCT's output, so it runs last
   std::vector<Stage> last;
   if (near.size() == 1 && near[0].custom == C_P2P) last.push_back(std::move(near[0])), near.clear();
+  const bool folded = near.empty() && !tail.empty() && tail[0].after_far;
+  auto put_pre = [&](size_t i0, size_t i1) {  // the low-rank near field's pair stages [i0, i1)
+    for (size_t i = i0; i < std::min(i1, pre.size()); ++i) {
+      pre[i].concurrent = 1;
+      v.push_back(std::move(pre[i]));
+    }
+  };
   for (Stage& s : head) v.push_back(std::move(s));
   chain(up_chain);
-  for (Stage& s : pre) {  // the low-rank near field's first stage, right before the near field
-    s.concurrent = 1;
-    v.push_back(std::move(s));
-  }
+  put_pre(0, folded ? 1 : pre.size());
   put_near(0);
-  // M2L (FARV / AFARV) on the caller's stream; the small S2L / M2T^T stage (FARX / AFARW),
-  // which only the downward chain reads, opens that chain on the helper stream
+  // M2L (FARV / AFARV) on the caller's stream. The S2L / M2T^T stage (FARX / AFARW), which only
+  // the downward chain reads, opens that chain on the helper stream beside the dense near
+  // field's second half; beside the folded near field's second pair stage it stays on the
+  // caller's stream (it is as large as the pair stage)
   std::vector<Stage> down;
   for (size_t i = 0; i < far.size(); ++i) {
-    if (i == 0) {
-      far[i].join_before = 1;
-      v.push_back(std::move(far[i]));
-    } else {
-      down.push_back(std::move(far[i]));
-    }
+    if (i == 0) far[i].join_before = 1;
+    if (i == 0 || folded) v.push_back(std::move(far[i]));
+    else down.push_back(std::move(far[i]));
   }
   for (Stage& s : down_chain) down.push_back(std::move(s));
   chain(down);
+  put_pre(1, pre.size());
   put_near(1);
   for (size_t i = 0; i < tail.size(); ++i) {
     tail[i].join_before = i == 0;
@@ -1105,13 +1112,13 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     return o;
   };
   const std::vector<int32_t> near_order = by_signature(Ulist), anear_order = by_signature(Uinv);
-  // with overlap the leaf stages' targets are cut in two parts (at a tile boundary): the near
-  // field then runs as two launches, each beside one far-field chain. The downward chain is the
+  // with overlap the dense near field's targets are cut in two parts (at a tile boundary): it
+  // then runs as two launches, each beside one far-field chain. The downward chain is the
   // longer one (the S2L stage opens it), so the first part takes 45% of the leaves; on the
   // size-matched 20-Gaussian tree that gave 1.55 ms per forward + adjoint step, against 1.57 ms
   // at 50% and 1.59 ms at 55%.
   std::vector<std::pair<size_t, size_t>> halves;
-  if (overlap > 0 && leaf_order.size() > size_t(NTL)) {
+  if (overlap > 0 && leaf_order.size() > size_t(NTL) && !lr) {
     const size_t cut = (leaf_order.size() * 9 / 20 + NTL - 1) / NTL * NTL;
     halves = {{0, cut}, {cut, leaf_order.size()}};
   } else {
@@ -1174,11 +1181,12 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         return Entry{kRelNV + Ulist.e[size_t(g)].first - 1, 0, Ulist.e[size_t(g)].second};
       });
   }
-  // With the low-rank near field in one launch, the leaf stage (LOCT: L2T, M2T and the log
-  // terms, and its adjoint ALOCT) folds into it: the same targets, 256 rows and k-chunk 16, its
-  // segments read families 2 and 3. The folded stage then runs after the far field, in LOCT's
-  // place, and writes the output once instead of the near field writing it and LOCT adding on.
-  const bool fold = lr && halves.size() == 1;
+  // The low-rank near field is one launch into which the leaf stage (LOCT: L2T, M2T and the log
+  // terms, and its adjoint ALOCT) folds: the same targets, 256 rows and k-chunk 16, its
+  // segments read families 2 and 3. The folded stage runs after the far field, in LOCT's place,
+  // and writes the output once instead of the near field writing it and LOCT adding on; with
+  // overlap its pair stages run beside the chains.
+  const bool fold = lr;
   // LOCT's segments and log terms of leaf a (families f0, f0 + 1: multipoles, locals)
   auto loct_terms = [&](int32_t a, std::vector<Entry>& E, std::vector<R1>& R, int8_t f0) {
     const double kap = P.leaf_kappa[a];

@@ -205,35 +205,44 @@ def test_deterministic_plans_cut_no_tile(vp):
 
 
 def test_overlap_launch_order(vp):
-    # with overlap the near field is cut in two launches, each placed beside one far-field
-    # chain (helper stream), and every stage still comes after the stages it reads; without
-    # it the leaf stage is folded into the one near-field launch, which then runs last
+    # Dense near field: with overlap it is cut in two launches, each placed beside one far-field
+    # chain (helper stream), and the leaf stage runs last. Low-rank near field: the leaf stage is
+    # folded into its one launch, which runs last, and its two pair stages (V_r f~ / U_r^T u~ by
+    # rank) run beside the chains. Every stage still comes after the stages it reads
     w = gen.config2(0)
-    for overlap in (0, 16):
-        plan = vp.Plan(w.centres, w.levels, host_only=True, overlap=overlap)
-        for adj, (head, up, near, far, down, tail) in (
-                (False, ("S2M", "M2M", "NEAR", ("FARV", "FARX"), "L2L", "LOCT")),
-                (True, ("AL2T", "AL2L", "ANEAR", ("AFARV", "AFARW"), "AM2M", "ALOCT"))):
-            names = [s["name"] for s in plan.stages(adj)]
-            helper = [s["name"] for s in plan.stages(adj) if s["helper"]]
-            assert names[0] == head and names[-1] == (tail if overlap else near + "+" + tail)
-            assert helper == [n for n in names if n.startswith(up + "[") or n.startswith(down + "[") or n == far[1]]
-            i_far = names.index(far[0])
-            assert all(names.index(n) < i_far for n in names if n.startswith(up + "["))
-            # the small far stage (S2L / M2T^T) opens the downward chain
-            assert all(names.index(n) > names.index(far[-1]) for n in names if n.startswith(down + "["))
-            assert names.index(far[-1]) == names.index(far[0]) + 1
-            # the low-rank near field's pair stages (V_r f~ / U_r^T u~, one per rank) come
-            # before the near launches that read their rows
-            pre = [n for n in names if n.startswith(near + "C")]
-            assert sorted(pre) == sorted([near + "C", near + "C48"])
-            nears = [n for n in names if n.startswith(near) and n not in pre]
-            assert max(names.index(n) for n in pre) < names.index(nears[0])
-            if overlap:
-                assert nears == [near + "_A", near + "_B"]
-                assert names.index(near + "_A") < i_far < names.index(near + "_B") < len(names) - 1
-            else:
-                assert nears == [near + "+" + tail] and tail not in names
+    for dense in (True, False):
+        for overlap in (0, 16):
+            plan = vp.Plan(w.centres, w.levels, host_only=True, overlap=overlap, dense_near=dense)
+            for adj, (head, up, near, far, down, tail) in (
+                    (False, ("S2M", "M2M", "NEAR", ("FARV", "FARX"), "L2L", "LOCT")),
+                    (True, ("AL2T", "AL2L", "ANEAR", ("AFARV", "AFARW"), "AM2M", "ALOCT"))):
+                names = [s["name"] for s in plan.stages(adj)]
+                helper = [s["name"] for s in plan.stages(adj) if s["helper"]]
+                chains = [n for n in names if n.startswith(up + "[") or n.startswith(down + "[")]
+                assert names[0] == head
+                assert set(helper) == set(chains + ([far[1]] if dense else []))
+                i_far = names.index(far[0])
+                assert all(names.index(n) < i_far for n in names if n.startswith(up + "["))
+                # S2L / M2T^T comes right after M2L, before the downward chain
+                assert names.index(far[-1]) == i_far + 1
+                assert all(names.index(n) > names.index(far[-1]) for n in names if n.startswith(down + "["))
+                pre = [n for n in names if n.startswith(near + "C")]
+                nears = [n for n in names if n.startswith(near) and n not in pre]
+                if dense:
+                    assert pre == [] and names[-1] == tail
+                    if overlap:
+                        assert nears == [near + "_A", near + "_B"]
+                        assert names.index(near + "_A") < i_far < names.index(near + "_B") < len(names) - 1
+                    else:
+                        assert nears == [near]
+                else:
+                    assert nears == [near + "+" + tail] and names[-1] == nears[0] and tail not in names
+                    # the rank-64 pair stage beside the upward chain, the rank-48 one beside the
+                    # downward chain
+                    assert pre == [near + "C", near + "C48"]
+                    assert names.index(pre[0]) < i_far < names.index(far[-1]) < names.index(pre[1])
+                    assert all(names.index(n) < names.index(pre[1]) for n in names if n.startswith(down + "["))
+            plan.close()
 
 
 # ---------------------------------------------------------------- layer potentials (host side)
