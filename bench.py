@@ -43,10 +43,11 @@ PEAK_HBM = 8.0e12  # bytes/s
 
 
 def kernel_source_hash():
-    """Hash of the sources that decide what the leaf-stage launches do: the kernels and the
-    plan and scheduling code that cut the work into launches."""
+    """Hash of the sources that decide what the leaf-stage launches do: the kernels, the tables
+    (their ranks set the near field's segments) and the plan and scheduling code that cut the
+    work into launches."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.hpp", "plan.cpp", "api.cpp"):
+    for f in ("kernels.hip", "device.hpp", "plan.cpp", "plan.hpp", "tables.cpp", "api.cpp"):
         with open(os.path.join(ROOT, "paper_2501_17967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -326,8 +327,9 @@ def _near_roofline(plan, info, steps, f, ubar, u, fbar, traffic, timed_in):
     achieved = flops / (avg_ms * 1e-3)
     return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
-            "kernel": "grg_kernel, 256-row tiles of %d slots, k-chunk %d: near-field stage (forward) and its "
-                      "transpose (adjoint)" % (near[0]["tile"], near[0]["kchunk"]),
+            "kernel": "grg_kernel, 256-row tiles of %d slots, k-chunk %d: %s (forward) and %s (adjoint)"
+                      % (near[0]["tile"], near[0]["kchunk"], near[0]["name"],
+                         [s["name"] for s in plan.stages(True) if s["kind"] == "adj_near"][0]),
             "flops_per_launch": flops, "avg_launch_ms": avg_ms, "launches": n, "launches_per_step": per_step,
             "timed_in": timed_in}, 1e3 * t_pass / steps
 
@@ -455,7 +457,7 @@ def forest_leg(args, dev):
     twin.close()
     # the same step at the library's default tolerance (order 39), same launch shape, for context
     at_default = None
-    if args.eps:
+    if args.eps and not args.no_default_order:
         f39 = Plan(C, Lv, tree_offsets=off, use_graph=True, dense_m2l=args.dense_m2l, dense_near=args.dense_near, **shape)
         for _ in range(max(1, args.warmup)):
             f39.apply(F, out=U2)
@@ -480,7 +482,7 @@ def forest_leg(args, dev):
                       "leaves_min": int(sizes.min()), "leaves_max": int(sizes.max()), "max_level": int(info["max_level"]),
                       "p": 16, "far_field_eps": args.eps, "expansion_order": int(info["order"]),
                       "m2l": "dense" if args.dense_m2l else "factored",
-                      "near": "dense" if args.dense_near else "rank-64 factors of the non-self tables",
+                      "near": "dense" if args.dense_near else "rank-64/48 factors of the non-self tables",
                       "step": "forward + adjoint, one hipGraph replay each",
                       "launch_shape": shape, "autotune_s": t_tune, "plan_s": t_plan, "gen_s": t_gen},
            "roofline": roof,
@@ -690,6 +692,8 @@ def main():
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the sequential single-tree applies and the CPU baseline of the forest (for profiling)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-tree legs (config 3-SM and 2-SM)")
+    ap.add_argument("--no-default-order", action="store_true",
+                    help="skip the forest step at the library's default order (context; for profiling)")
     ap.add_argument("--single-only", default="", help="run only this single-tree leg (3sm or 2sm) and print it")
     ap.add_argument("--no-layer", action="store_true", help="skip the layer-potential evaluation leg")
     ap.add_argument("--layer-only", action="store_true",
@@ -718,7 +722,9 @@ def main():
     ap.add_argument("--dense-m2l", action="store_true",
                     help="dense per-offset M2L matrices instead of the factored form (for comparison)")
     ap.add_argument("--dense-near", action="store_true",
-                    help="dense 256 x 256 adjacent-leaf tables instead of their rank-64 factors (for comparison)")
+                    help="dense 256 x 256 adjacent-leaf tables instead of their low-rank factors (for comparison)")
+    ap.add_argument("--peaks-only", action="store_true",
+                    help="only measure this device's FP64 matrix-core and HBM copy rates, print them and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -738,6 +744,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.calibrate_copy_mib, "copies": 5}))
+        return
+    if args.peaks_only:
+        print(json.dumps({"measured_peaks": measured_peaks(dev)}), flush=True)
         return
     if args.layer_only:
         print(json.dumps({"layer_potential": layer_leg(args, dev)}), flush=True)
