@@ -123,7 +123,7 @@ typedef struct {
                               corner and coarser neighbours): stages NEARC / NEARC48 form V_r f
                               for every such pair (64 values a pair in plan memory), the near
                               field then applies U_r to those and the self table to the leaf's
-                              own data, about 40% of the dense matrix-core work. 1: the dense
+                              own data, about half the dense matrix-core work. 1: the dense
                               tables. The two agree to rounding (the tests compare them). */
 } volpot_options;
 
