@@ -127,6 +127,32 @@ def test_low_rank_near_factors_reproduce_oracle_tables(vp, host_plan):
         host_plan.table(3, 0)  # the self relation is applied dense
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_pair_stages_take_every_adjacent_pair_once(vp, seed):
+    # every adjacent pair other than a leaf with itself is one row of exactly one pair stage,
+    # the one of its relation's rank, forward (V_r: the R factor, row i zero in its first i
+    # pivot columns) and adjoint (U_r^T, dense); the plan's flops count the non-zeros
+    w = gen.random_small_tree(seed, max_level=6, n_splits=14)
+    T = tree.Tree(w.centres, w.levels)
+    U = T.lists()[0]  # each leaf's adjacent leaves, itself included
+    plan = vp.Plan(w.centres, w.levels, host_only=True)
+    n_pairs = sum(len(v) - 1 for v in U.values())
+    assert plan.info()["pairs_lowrank"] == n_pairs
+    for adj, kind in ((False, "nearc"), (True, "adj_nearc")):
+        got = 0
+        for s in plan.stages(adj):
+            if s["kind"] != kind:
+                continue
+            k = s["rows"]
+            assert (s["name"].endswith("48")) == (k == 48) and k in (48, 64), s
+            nnz = 256 * k if adj else 256 * k - k * (k - 1) // 2
+            c = s["flops"] / (2.0 * nnz)
+            assert abs(c - round(c)) < 1e-9, s
+            got += int(round(c))
+        assert got == n_pairs
+    plan.close()
+
+
 def test_s2m_and_l2t_reproduce_definitions(vp, host_plan):
     # S2M row 0 is the leaf mass weights W; rows 2, 3 (n = 1) are -int l_k eta_x, -int l_k eta_y
     W = onodes.tensor_weights()
