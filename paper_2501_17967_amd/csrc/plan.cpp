@@ -273,42 +273,73 @@ static Lists transpose_rows(const Lists& A, int64_t n_rows_t) {
 
 static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
                                const std::vector<std::vector<Entry>>& entries,
-                               const std::vector<std::vector<R1>>& r1, const Matrices& mats);
+                               const std::vector<std::vector<R1>>& r1, const std::vector<int32_t>& ord,
+                               const Matrices& mats);
 
 // Targets grouped by the set of relations they take, classes in lexicographic order of their
 // sorted relation lists (neighbouring classes share most relations), the given order within a
 // class. Every segment of a tile costs the same whatever its occupancy, so a tile should hold
 // targets that take the same relations: in adaptive trees, targets near refinement boundaries
-// take neighbours in many patterns.
+// take neighbours in many patterns. Classes are found by hashing each target's sorted keys
+// (equal hashes are compared key by key), so that the cost is linear in the entries.
 static void make_tiles(Stage& st, const std::vector<int32_t>& targets, const std::vector<std::vector<Entry>>& entries,
                        const std::vector<std::vector<R1>>& r1, const Matrices& mats) {
   const size_t n = targets.size();
-  std::vector<std::vector<int32_t>> sigs(n);
-  std::map<std::vector<int32_t>, int32_t> cls;
+  std::vector<int64_t> kp(n + 1, 0);  // sorted keys of target i: keys[kp[i] .. kp[i + 1])
+  for (size_t i = 0; i < n; ++i) kp[i + 1] = kp[i] + int64_t(entries[i].size());
+  std::vector<int32_t> keys(static_cast<size_t>(kp[n]));
+  std::vector<std::pair<uint64_t, int32_t>> hs(n);
   for (size_t i = 0; i < n; ++i) {
-    for (const Entry& e : entries[i]) sigs[i].push_back(e.rel * 16 + e.fam);
-    std::sort(sigs[i].begin(), sigs[i].end());
-    cls.emplace(sigs[i], 0);
+    int32_t* k = keys.data() + kp[i];
+    for (size_t e = 0; e < entries[i].size(); ++e) k[e] = entries[i][e].rel * 16 + entries[i][e].fam;
+    std::sort(k, k + entries[i].size());
+    uint64_t h = 1469598103934665603ull ^ uint64_t(entries[i].size());
+    for (size_t e = 0; e < entries[i].size(); ++e) h = (h ^ uint64_t(uint32_t(k[e]))) * 1099511628211ull;
+    hs[i] = {h, int32_t(i)};
   }
-  int32_t rank = 0;
-  for (auto& kv : cls) kv.second = rank++;
-  std::vector<int32_t> c(n), perm(n);
-  for (size_t i = 0; i < n; ++i) { c[i] = cls[sigs[i]]; perm[i] = int32_t(i); }
-  std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return c[size_t(x)] < c[size_t(y)]; });
-  std::vector<int32_t> t2(n);
-  std::vector<std::vector<Entry>> e2(n);
-  std::vector<std::vector<R1>> r2(n);
-  for (size_t i = 0; i < n; ++i) {
-    t2[i] = targets[size_t(perm[i])];
-    e2[i] = entries[size_t(perm[i])];
-    r2[i] = r1[size_t(perm[i])];
+  auto same = [&](int32_t a, int32_t b) {
+    return kp[a + 1] - kp[a] == kp[b + 1] - kp[b] &&
+           std::equal(keys.begin() + kp[a], keys.begin() + kp[a + 1], keys.begin() + kp[b]);
+  };
+  auto less = [&](int32_t a, int32_t b) {
+    return std::lexicographical_compare(keys.begin() + kp[a], keys.begin() + kp[a + 1], keys.begin() + kp[b],
+                                        keys.begin() + kp[b + 1]);
+  };
+  std::sort(hs.begin(), hs.end());
+  // class of each target; rep: one target of each class
+  std::vector<int32_t> c(n), rep;
+  for (size_t g = 0; g < n;) {
+    size_t g1 = g;
+    while (g1 < n && hs[g1].first == hs[g].first) ++g1;
+    const size_t c0 = rep.size();
+    for (size_t q = g; q < g1; ++q) {  // equal hashes: compare with the group's classes so far
+      const int32_t i = hs[q].second;
+      size_t r = c0;
+      while (r < rep.size() && !same(rep[r], i)) ++r;
+      if (r == rep.size()) rep.push_back(i);
+      c[size_t(i)] = int32_t(r);
+    }
+    g = g1;
   }
-  make_tiles_ordered(st, t2, e2, r2, mats);
+  std::vector<int32_t> byk(rep.size()), rank(rep.size());
+  for (size_t r = 0; r < rep.size(); ++r) byk[r] = int32_t(r);
+  std::sort(byk.begin(), byk.end(), [&](int32_t x, int32_t y) { return less(rep[size_t(x)], rep[size_t(y)]); });
+  for (size_t r = 0; r < byk.size(); ++r) rank[size_t(byk[r])] = int32_t(r);
+  // stable counting sort by class rank
+  std::vector<int64_t> start(rep.size() + 1, 0);
+  for (size_t i = 0; i < n; ++i) start[size_t(rank[size_t(c[i])]) + 1]++;
+  for (size_t r = 0; r < rep.size(); ++r) start[r + 1] += start[r];
+  std::vector<int32_t> ord(n);
+  for (size_t i = 0; i < n; ++i) ord[size_t(start[size_t(rank[size_t(c[i])])]++)] = int32_t(i);
+  make_tiles_ordered(st, targets, entries, r1, ord, mats);
 }
 
 static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
                                const std::vector<std::vector<Entry>>& entries,
-                               const std::vector<std::vector<R1>>& r1, const Matrices& mats) {
+                               const std::vector<std::vector<R1>>& r1, const std::vector<int32_t>& ord,
+                               const Matrices& mats) {
+  // slot ti of the tiled order holds target ord[ti]
+  auto at = [&](size_t ti) { return size_t(ord[ti]); };
   const int NT = st.NT;
   st.n_tiles = int((targets.size() + NT - 1) / NT);
   st.tile_tgt.assign(size_t(st.n_tiles) * NT, -1);
@@ -329,16 +360,9 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
     for (int s = 0; s < NT; ++s) {
       size_t ti = size_t(t) * NT + s;
       if (ti >= targets.size()) break;
-      st.tile_tgt[ti] = targets[ti];
-      for (const Entry& e : entries[ti]) {
-        // the kernel reads M x K of the relation's table and K values of each source
+      st.tile_tgt[ti] = targets[at(ti)];
+      for (const Entry& e : entries[at(ti)]) {
         if (e.rel < 0 || e.rel >= kNumRel || e.fam < 0 || e.fam >= 4) throw std::runtime_error("bad entry");
-        if (cx && mats.w_in[size_t(e.rel)].empty()) throw std::runtime_error("relation has no factored form");
-        if (mats.M[table(e.rel)] != st.M) throw std::runtime_error("relation rows differ from stage rows");
-        if (st.fam[e.fam].stride < mats.koff[size_t(table(e.rel))] + src_len(e.rel))
-          throw std::runtime_error("source shorter than relation");
-        // the kernel walks K in full chunks of KC
-        if (mats.K[table(e.rel)] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
         const int32_t key = e.rel * 16 + e.fam;
         if (seg_of[size_t(key)] < 0) {
           seg_of[size_t(key)] = 0;
@@ -347,6 +371,16 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
       }
     }
     std::sort(used.begin(), used.end());
+    for (int32_t key : used) {  // each (relation, family) of the tile, checked once
+      const int rel = key / 16, fam = key % 16;
+      // the kernel reads M x K of the relation's table and K values of each source
+      if (cx && mats.w_in[size_t(rel)].empty()) throw std::runtime_error("relation has no factored form");
+      if (mats.M[table(rel)] != st.M) throw std::runtime_error("relation rows differ from stage rows");
+      if (st.fam[fam].stride < mats.koff[size_t(table(rel))] + src_len(rel))
+        throw std::runtime_error("source shorter than relation");
+      // the kernel walks K in full chunks of KC
+      if (mats.K[table(rel)] % st.KC != 0) throw std::runtime_error("relation K not a multiple of the stage k-chunk");
+    }
     for (int32_t key : used) {
       seg_of[size_t(key)] = int32_t(st.seg_rel.size());
       st.seg_rel.push_back(key / 16);
@@ -358,7 +392,7 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
     for (int s = 0; s < NT; ++s) {
       size_t ti = size_t(t) * NT + s;
       if (ti >= targets.size()) break;
-      for (const Entry& e : entries[ti]) {
+      for (const Entry& e : entries[at(ti)]) {
         int32_t& slot = st.seg_src[size_t(seg_of[size_t(e.rel * 16 + e.fam)]) * NT + s];
         if (slot != -1) throw std::runtime_error("duplicate relation for one target");
         slot = e.src;
@@ -372,7 +406,7 @@ static void make_tiles_ordered(Stage& st, const std::vector<int32_t>& targets,
   }
   for (size_t ti = 0; ti < st.tile_tgt.size(); ++ti) {
     if (ti < targets.size())
-      for (const R1& e : r1[ti]) {
+      for (const R1& e : r1[at(ti)]) {
         st.r1_idx.push_back(e.idx);
         st.r1_fam.push_back(e.fam);
         st.r1_coef.push_back(e.coef);
