@@ -341,19 +341,20 @@ int volpot_stage_times(volpot_plan_t plan, double* ms, int64_t* launches, int32_
 int volpot_plan_table(volpot_plan_t plan, int32_t kind, int32_t index, double* out, int64_t n);
 
 /* Autotuner (for callers that apply one tree shape many times, e.g. batched forests): searches
- * the launch shapes tile_box 16|32|64, tile_leaf 32|64, kchunk_leaf 32|16 (dense_near only),
- * tile_leaf_exp 16|32|64, split_min 0|1|-1 and overlap 0|16|24|32|48 one knob at a time from the
- * defaults (the other fields, eps among them, are taken from base, nullable), building a plan
- * for each candidate and timing one forward plus one adjoint apply on internal device buffers
- * after a warm-up (HIP events, private stream, best of 5); writes the fastest
- * options to *best and their time in milliseconds to *best_ms (nullable). A candidate must beat
- * the current choice by more than 1.5%, and the result must beat the defaults by as much when
- * both are timed again, so that differences within timing noise keep the defaults. With
- * cache_path (nullable) the result is looked up in, and appended to, that text file, keyed by a
- * signature of the trees' level histogram and sizes, of the expansion order that base's eps
- * selects, of base's dense_m2l and dense_near and of the device, so that a shape is timed
- * once. VOLPOT_ERR_UNSUPPORTED
- * for an eps no order meets. Allocates and synchronises; not for use inside a timed region.
+ * the launch shapes tile_box 16|32|64, tile_leaf 32|64, kchunk_leaf 32|16 and tile_leaf_exp
+ * 16|32|64 (these two with dense_near only), split_min 0|1|-1 and overlap 0|16|24|32|48 one knob
+ * at a time from the defaults (the other fields, eps among them, are taken from base,
+ * nullable), building a plan for each candidate (the defaults' and the current choice's are
+ * kept for timing again) and timing one forward plus one adjoint apply on internal device
+ * buffers after a warm-up (HIP events, private stream, best of 5); writes the fastest options
+ * to *best and their time in milliseconds to *best_ms (nullable). A candidate must beat the
+ * current choice by more than 1.5%, and the result must beat the defaults by as much when both
+ * are timed again, so that differences within timing noise keep the defaults. With cache_path
+ * (nullable) the result is looked up in, and appended to, that text file, keyed by a signature
+ * of the trees' level histogram and sizes, of the expansion order that base's eps selects, of
+ * base's dense_m2l and dense_near and of the device, so that a shape is timed once.
+ * VOLPOT_ERR_UNSUPPORTED for an eps no order meets. Allocates (up to three plans at once) and
+ * synchronises; not for use inside a timed region.
  * Arguments as volpot_plan_forest (a single tree: n_trees = 1, offsets {0, n_leaves}). */
 int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, const double* centres,
                     const int32_t* levels, int32_t p, const volpot_options* base,

@@ -140,6 +140,15 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
                           hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
                           hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = VOLPOT_ERR_HIP;
+  const Candidate def{32, 32, 0, 0, 16, 32};
+  // Plans kept for timing again: slot 0 the defaults' (timed first and last), slot 1 the current
+  // choice's, and `last` the candidate just timed (kept as the choice if it wins).
+  volpot_plan_t kept[2] = {nullptr, nullptr}, last = nullptr;
+  Candidate kept_c[2] = {}, last_c = {};
+  auto drop = [](volpot_plan_t& pl) {
+    if (pl) volpot_plan_destroy(pl);
+    pl = nullptr;
+  };
   // time one candidate: best of `reps` forward + adjoint applies after a warm-up apply
   int reps = 5;
   auto time_it = [&](const Candidate& c, double* t_out) {
@@ -151,8 +160,14 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     oc.tile_leaf_exp = c.tile_leaf_exp;
     oc.kchunk_leaf = c.kchunk_leaf;
     volpot_plan_t plan = nullptr;
-    int r = volpot_plan_forest(n_trees, tree_offsets, centres, levels, p, &oc, &plan);
-    if (r != VOLPOT_OK) return r;
+    int r = VOLPOT_OK;
+    for (int k = 0; k < 2; ++k)
+      if (kept[k] && same(kept_c[k], c)) plan = kept[k];
+    const bool fresh = plan == nullptr;
+    if (fresh) {
+      r = volpot_plan_forest(n_trees, tree_offsets, centres, levels, p, &oc, &plan);
+      if (r != VOLPOT_OK) return r;
+    }
     double t_c = 1e30;
     for (int rep = 0; rep <= reps && r == VOLPOT_OK; ++rep) {
       if (hipEventRecord(e0, s) != hipSuccess) r = VOLPOT_ERR_HIP;
@@ -164,12 +179,20 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
       if (r == VOLPOT_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) r = VOLPOT_ERR_HIP;
       if (r == VOLPOT_OK && rep > 0) t_c = std::min(t_c, double(t));
     }
-    volpot_plan_destroy(plan);
+    if (fresh) {
+      drop(last);
+      if (!kept[0] && same(c, def)) {
+        kept[0] = plan;
+        kept_c[0] = c;
+      } else {
+        last = plan;
+        last_c = c;
+      }
+    }
     *t_out = t_c;
     return r;
   };
-  // coordinate descent over the four knobs, one at a time, from the defaults
-  const Candidate def{32, 32, 0, 0, 16, 32};
+  // coordinate descent over the knobs, one at a time, from the defaults
   Candidate cur = def;
   double best_t = 1e30;
   auto try_axis = [&](int axis, std::initializer_list<int32_t> values) {
@@ -185,6 +208,12 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
       if (rc == VOLPOT_OK && t < best_t * (1.0 - kMargin)) {
         best_t = t;
         cur = c;
+        if (last && same(last_c, c)) {  // the new choice's plan
+          drop(kept[1]);
+          kept[1] = last;
+          kept_c[1] = c;
+          last = nullptr;
+        }
       }
     }
   };
@@ -199,7 +228,7 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     try_axis(0, {16, 32, 64});
     try_axis(1, {32, 64});
     if (o.dense_near) try_axis(5, {32, 16});  // the low-rank near field always takes k-chunk 16
-    try_axis(4, {16, 32, 64});
+    if (o.dense_near) try_axis(4, {16, 32, 64});  // the low-rank near field folds the K = 80 leaf stage
     if (!o.deterministic) try_axis(2, {0, 1, -1});  // deterministic plans never cut tiles
     try_axis(3, {0, 16, 24, 32, 48});
   }
@@ -221,6 +250,9 @@ extern "C" int volpot_autotune(int32_t n_trees, const int64_t* tree_offsets, con
     best->tile_leaf_exp = cur.tile_leaf_exp;
     best->kchunk_leaf = cur.kchunk_leaf;
   }
+  drop(last);
+  drop(kept[0]);
+  drop(kept[1]);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (s) (void)hipStreamDestroy(s);
