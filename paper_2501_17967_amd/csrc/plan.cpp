@@ -1188,15 +1188,24 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   // one pair stage per rank: rows of the pairs whose relation has that rank, as (row, entry)
   auto pair_stage = [&](int kind, const char* name, int rank, int8_t out, bool adj,
                         const std::function<Entry(int64_t g, int64_t a)>& entry) {
-    std::vector<int32_t> tg;
-    std::vector<std::vector<Entry>> E;
-    for (int64_t a = 0; a < P.n_leaves; ++a)
+    // rows in leaf order: count each leaf's pairs of this rank, then fill concurrently
+    std::vector<int64_t> at(size_t(P.n_leaves) + 1, 0);
+    auto take = [&](int64_t g) { return lr_idx[size_t(g)] >= 0 && near_rank(Ulist.e[size_t(g)].first) == rank; };
+    par_for(P.n_leaves, [&](int64_t a) {
+      for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g) at[size_t(a) + 1] += take(g);
+    });
+    for (int64_t a = 0; a < P.n_leaves; ++a) at[size_t(a) + 1] += at[size_t(a)];
+    if (at[size_t(P.n_leaves)] == 0) return;
+    std::vector<int32_t> tg(static_cast<size_t>(at[size_t(P.n_leaves)]));
+    std::vector<std::vector<Entry>> E(tg.size());
+    par_for(P.n_leaves, [&](int64_t a) {
+      int64_t i = at[size_t(a)];
       for (int64_t g = Ulist.ptr[size_t(a)]; g < Ulist.ptr[size_t(a) + 1]; ++g)
-        if (lr_idx[size_t(g)] >= 0 && near_rank(Ulist.e[size_t(g)].first) == rank) {
-          tg.push_back(int32_t(lr_idx[size_t(g)]));
-          E.push_back({entry(g, a)});
+        if (take(g)) {
+          tg[size_t(i)] = int32_t(lr_idx[size_t(g)]);
+          E[size_t(i++)] = {entry(g, a)};
         }
-    if (tg.empty()) return;
+    });
     Stage st; init_stage(st, kind, name, -1, rank, kNP, kLeafDataTile, out, kNearRank);
     st.pre_near = 1;
     st.fam[0] = {adj ? A_IN : A_INS, kNP, 0};
