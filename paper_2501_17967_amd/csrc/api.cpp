@@ -464,7 +464,7 @@ int run(volpot_plan_s* p, bool adjoint, const double* in, const double* in2, dou
       timed_begin(p, timing, K_UP, main, &ea, &eb);
       if (launch_prescale(in, p->d_leaf_s2, p->d_fs, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
       timed_end(p, K_UP, main, ea, eb);
-    } else {  // leaf sums of the cotangent, for the adjoint log-scale terms
+    } else if (p->host.adj_leaf_sums) {  // leaf sums of the cotangent, for log terms of leaves above level 2
       timed_begin(p, timing, K_ASUM, main, &ea, &eb);
       if (launch_rowsum(in, p->d_usum, p->host.n_leaves, main) != hipSuccess) return VOLPOT_ERR_HIP;
       timed_end(p, K_ASUM, main, ea, eb);
@@ -772,9 +772,11 @@ int volpot_plan_info(volpot_plan_t plan, volpot_info* out) {
     out->flops_issued_kind[s.kind] += s.flops_issued;
     out->launches_kind[s.kind] += s.n_tiles > 0;
   }
-  out->flops_kind[K_ASUM] = double(P.n_leaves) * kNP;  // one add per value
-  out->flops_adjoint += out->flops_kind[K_ASUM];
-  out->launches_kind[K_ASUM] = 1;
+  if (P.adj_leaf_sums) {  // the leaf-sum pass runs only for plans with leaves above level 2
+    out->flops_kind[K_ASUM] = double(P.n_leaves) * kNP;  // one add per value
+    out->flops_adjoint += out->flops_kind[K_ASUM];
+    out->launches_kind[K_ASUM] = 1;
+  }
   out->bytes_min = 16.0 * double(P.n_leaves) * kNP;
   if (P.layer) {
     out->flops_kind[K_ASUM] = 0.0;

@@ -1320,6 +1320,15 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
   for (int l = 0; l < 2 && l <= P.max_level; ++l)
     for (int32_t b : boxes_at[l]) if (P.box_leaf[b] >= 0) afar_tg.push_back(b);
   afar_tg.insert(afar_tg.end(), deep_by_quadrant.begin(), deep_by_quadrant.end());
+  // The log term of leaf a's cotangent: kappa(s_a) times the sum of ubar over a's nodes. For a
+  // leaf at level >= 2 that sum is already in its lbar: L2T's first column is -1/(2 pi) at every
+  // node, so AL2T leaves -(1/2 pi) sum(ubar) in row 0. Leaves above level 2 (no L2T) read the
+  // leaf sums of a separate pass.
+  auto usum_term = [&](int32_t a) -> R1 {
+    if (levels[a] >= 2) return {0, P.leaf_box[a], -2.0 * M_PI * P.leaf_kappa[a]};
+    return {1, a, P.leaf_kappa[a]};
+  };
+  for (int64_t a = 0; a < P.n_leaves && !P.adj_leaf_sums; ++a) P.adj_leaf_sums = levels[a] < 2;
   {  // AFARV: M2L^T plus every log term
     const auto& tg = afar_tg;
     Stage st; init_stage(st, K_ADOWN, "AFARV", -1, kNE, kNE, NTB, A_AFAR, kNE);
@@ -1336,10 +1345,10 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
         E[i].push_back({kRelM2L + e.first + kNumFwd, 0, e.second});
         R[i].push_back({0, e.second, ls + (dense_m2l ? 0.0 : mats.lnd[size_t(kRelM2L + e.first)])});
       }
-      for (auto& e : Winv[b]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
+      for (auto& e : Winv[b]) R[i].push_back(usum_term(e.second));
       int32_t leaf = P.box_leaf[b];
       if (leaf >= 0) {
-        for (auto& e : Uinv[leaf]) R[i].push_back({1, e.second, P.leaf_kappa[e.second]});
+        for (auto& e : Uinv[leaf]) R[i].push_back(usum_term(e.second));
         for (auto& e : Xinv[leaf]) R[i].push_back({0, e.second, lnS(P.box_level[e.second])});
       }
     });

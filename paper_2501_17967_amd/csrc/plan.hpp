@@ -215,6 +215,7 @@ struct Plan {
   int64_t pairs_near = 0, pairs_v = 0, pairs_w = 0, pairs_x = 0, n_m2m = 0, n_l2l = 0, n_s2m = 0,
           n_l2t = 0;
   int64_t pairs_lr = 0;  // adjacent-leaf pairs in low-rank form (rows of A_NW / A_NWA), 0 if dense
+  bool adj_leaf_sums = false;  // the adjoint reads leaf sums of ubar (a leaf above level 2)
   // layer potentials (point sources on a curve; empty for the volume potential)
   bool layer = false;
   int64_t n_src = 0, n_src_leaves = 0, n_active = 0, pairs_p2p = 0, pairs_p2l = 0;
