@@ -139,8 +139,10 @@ typedef struct {
                                for all levels, L2L chain), 2 near field, 3 L2T + M2T + log terms,
                                4 adjoint upward (L2T^T, L2L^T chain), 5 adjoint downward (M2L^T,
                                M2T^T, M2M^T chain), 6 adjoint near field, 7 S2M^T + S2L^T,
-                               8 adjoint row sums, 9 the low-rank near field's first stage
-                               (V_r f per pair), 10 its transpose's (U_r^T ubar per pair) */
+                               8 adjoint row sums (plans with leaves above level 2 only),
+                               9 the low-rank near field's first stage (V_r f per pair), 10 its
+                               transpose's (U_r^T ubar per pair). The low-rank near field folds
+                               kinds 3 and 7 into kinds 2 and 6 (stages NEAR+LOCT, ANEAR+ALOCT). */
   int64_t launches_kind[11]; /* kernel launches per apply of each stage kind */
   double bytes_min;         /* mandatory HBM traffic: 16 B per unknown (f in, u out) */
   int64_t device_bytes;     /* device memory the plan holds (tables shared per device) */
