@@ -637,6 +637,23 @@ def single_tree_leg(args, dev, w, label, cpu="full"):
            "roofline": roof, "roofline_pass_ms_per_step": pass_ms,
            "whole_path_tflops": (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps) / 1e12,
            "stage_ms_per_step": stage_ms}
+    # the same steps with each apply one hipGraph replay (same shape), for comparison
+    gplan = Plan(w.centres, w.levels, eps=args.eps, dense_m2l=args.dense_m2l, dense_near=args.dense_near,
+                 use_graph=True, **shape)
+    ug, fg = torch.empty_like(f), torch.empty_like(f)
+    for _ in range(max(1, args.warmup)):
+        gplan.apply(f, out=ug)
+        gplan.apply_adjoint(ubar, out=fg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gplan.apply(f, out=ug)
+        gplan.apply_adjoint(ubar, out=fg)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    res["graph_replay"] = {"ms_per_step": 1e3 * t_graph / args.steps, "fwd_adj_unknowns_per_s": N * args.steps / t_graph,
+                           "bitwise_equal_to_eager": bool(torch.equal(ug, u) and torch.equal(fg, fbar))}
+    gplan.close()
     if not args.no_cpu_baseline and cpu == "direct":
         # the oracle box code needs minutes on a tree this size; its plain direct sum (adaptive
         # quadrature over every leaf) at a bounded sample of nodes serves as the baseline and as
