@@ -325,8 +325,11 @@ def _near_roofline(plan, info, steps, f, ubar, u, fbar, traffic, timed_in):
     flops = (info["flops_kind"]["near"] + info["flops_kind"]["adj_near"]) / per_step
     avg_ms = (st["near"][0] + st["adj_near"][0]) / max(n, 1)
     achieved = flops / (avg_ms * 1e-3)
+    # the counted HBM traffic over the same launch time, against the 8 TB/s peak (the second roofline)
+    hbm = None if traffic is None else {"achieved_gbs": traffic / (avg_ms * 1e-3) / 1e9, "peak_gbs": PEAK_HBM / 1e9,
+                                        "frac": traffic / (avg_ms * 1e-3) / PEAK_HBM}
     return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
+            "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic, "hbm": hbm,
             "kernel": "grg_kernel, 256-row tiles of %d slots, k-chunk %d: %s (forward) and %s (adjoint)"
                       % (near[0]["tile"], near[0]["kchunk"], near[0]["name"],
                          [s["name"] for s in plan.stages(True) if s["kind"] == "adj_near"][0]),
