@@ -64,6 +64,17 @@ def _timed(fn, reps):
     return (time.perf_counter() - a) / reps
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def _oracle_cores():
     try:
         from threadpoolctl import threadpool_info
@@ -578,6 +589,7 @@ def forest_leg(args, dev):
             ef = max(ef, float(np.max(np.abs(ug[off[i]:off[i + 1]] - u_o)) / np.max(np.abs(u_o))))
             ea = max(ea, float(np.max(np.abs(fg[off[i]:off[i + 1]] - fb_o)) / np.max(np.abs(fb_o))))
         res["cpu_baseline"] = {"value": n_cpu / t_cpu, "unit": "unknowns/s", "cores": _oracle_cores(), "kind": "oracle",
+                               "cpu": _cpu_model(),
                                "sample": "trees 0, 8, ..., %d of the forest (%d trees, %d unknowns), one forward + one "
                                          "adjoint apply of the oracle box code (NumPy, order 50) each, in sequence: "
                                          "%.1f s" % (sample[-1], len(sample), n_cpu, t_cpu)}
