@@ -498,7 +498,8 @@ def forest_leg(args, dev):
                       "m2l": "dense" if args.dense_m2l else "factored",
                       "near": "dense" if args.dense_near else "rank-64/48 factors of the non-self tables",
                       "step": "forward + adjoint, one hipGraph replay each",
-                      "launch_shape": shape, "autotune_s": t_tune, "plan_s": t_plan, "gen_s": t_gen},
+                      "launch_shape": shape, "autotune_s": t_tune, "plan_s": t_plan, "gen_s": t_gen,
+                      "plan_device_gb": info["device_bytes"] / 1e9},
            "roofline": roof,
            "fwd_unknowns_per_s": Nb / tb_f, "adj_unknowns_per_s": Nb / tb_a,
            "whole_path_tflops": (info["flops_total"] + info["flops_adjoint"]) / (t_total / args.steps) / 1e12,
