@@ -360,10 +360,12 @@ __device__ __forceinline__ void tile_epilogue(const GrgParams& p, const EpiIdx<N
 // accumulators in extra registers, left the pair stages 15% slower. The other
 // instantiations keep the compiler's own choice.
 // The factored M2L instantiations ask for three waves per SIMD (two for q = 40, whose
-// accumulators are half as large again).
+// accumulators are half as large again); the one with waves of 32 slots is held to three
+// blocks (164 registers, no spills; the compiler's choice, 176, left two).
 template <int MT, int NTT, int WM, int WN, int KC, bool CX>
 constexpr int min_blocks() {
   if (!CX && WM == 1 && WN == 4 && NTT == 1 && MT <= 4) return 4;
+  if (CX && NTT == 4) return 3;
   return (!CX && MT == 4 && NTT == 2 && WM == 4 && WN == 1) ? (KC == 32 ? 2 : KC == 16 ? 3 : 1) : 1;
 }
 template <int KC, bool CX>
@@ -423,7 +425,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<KC, CX>()))) grg_kernel(const 
       L.template store<LDB>(tid, Bs, Ws);
       __syncthreads();
       const d2* __restrict__ W2 = reinterpret_cast<const d2*>(Ws);
-      static_assert(!CX || NTT == 2, "a factored wave holds both parts of its slots");
+      static_assert(!CX || NTT % 2 == 0, "a factored wave holds both parts of its slots");
       for (int left = P.n_chunks;;) {
         const bool more = --left > 0;
         if (more) {  // next segment in flight while this one is multiplied
@@ -436,16 +438,19 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<KC, CX>()))) grg_kernel(const 
 #pragma unroll
           for (int j = 0; j < NTT; ++j) part[i][j] = d4{0.0, 0.0, 0.0, 0.0};
         mfma_chunk<MT, NTT, M, LDB, KC>(Aw, Bw, part);
-        // acc += w_out[l] * part, complex: fragment 0 holds the real and fragment 1 the
+        // acc += w_out[l] * part, complex: fragments 2j and 2j + 1 hold the real and the
         // imaginary part of (l, slot) in the same lane
 #pragma unroll
         for (int i = 0; i < MT; ++i)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const d2 w = W2[(wm * MT + i) * 16 + 4 * r + (lane >> 4)];
-            const double re = part[i][0][r], im = part[i][NTT - 1][r];
-            acc[i][0][r] = fma(w.x, re, fma(-w.y, im, acc[i][0][r]));
-            acc[i][NTT - 1][r] = fma(w.x, im, fma(w.y, re, acc[i][NTT - 1][r]));
+#pragma unroll
+            for (int j = 0; j < NTT; j += 2) {
+              const double re = part[i][j][r], im = part[i][j + 1][r];
+              acc[i][j][r] = fma(w.x, re, fma(-w.y, im, acc[i][j][r]));
+              acc[i][j + 1][r] = fma(w.x, im, fma(w.y, re, acc[i][j + 1][r]));
+            }
           }
         if (!more) break;
         __syncthreads();  // every wave is done reading the segment and its weights
@@ -555,13 +560,14 @@ __global__ void rowsum_kernel(const double* __restrict__ x, double* __restrict__
   X(32, 64, 32, 2, 1, 1, 4, 256) X(32, 32, 32, 2, 1, 1, 2, 128) X(32, 16, 32, 2, 1, 1, 1, 64)
 
 // Factored M2L instantiations: padded core rows, slots, complex terms q (= k-chunk); MT, NTT, WM,
-// WN, threads (2 NT columns in 16-wide fragments, two per wave). The 32-slot form at q = 32
-// splits the rows over two waves (16 rows each, 114 registers, four blocks per compute unit):
-// the order-31 M2L of the 256-tree forest took 3% less time than with 32-row waves (192
-// registers, two blocks).
+// WN, threads (2 NT columns in 16-wide fragments, an even number per wave). At q = 32 the rows
+// split over two waves (16 rows each): with 32 slots (one real and one imaginary fragment per
+// wave, 114 registers, four blocks per compute unit) the order-31 M2L of the 256-tree forest
+// took 3% less time than with 32-row waves (192 registers, two blocks); with 64 slots (waves of
+// 32 slots, four fragments, three blocks) 3% less again, which the plan uses at q = 32.
 #define VP_CONFIGS_CX(X)                                                                          \
   X(48, 16, 40, 3, 2, 1, 1, 64) X(48, 32, 40, 3, 2, 1, 2, 128) X(48, 64, 40, 3, 2, 1, 4, 256)     \
-  X(32, 16, 32, 2, 2, 1, 1, 64) X(32, 32, 32, 1, 2, 2, 2, 256) X(32, 64, 32, 2, 2, 1, 4, 256)     \
+  X(32, 16, 32, 2, 2, 1, 1, 64) X(32, 32, 32, 1, 2, 2, 2, 256) X(32, 64, 32, 1, 4, 2, 2, 256)     \
   X(32, 16, 24, 2, 2, 1, 1, 64) X(32, 32, 24, 2, 2, 1, 2, 128) X(32, 64, 24, 2, 2, 1, 4, 256)     \
   X(16, 16, 16, 1, 2, 1, 1, 64) X(16, 32, 16, 1, 2, 1, 2, 128) X(16, 64, 16, 1, 2, 1, 4, 256)
 
