@@ -68,8 +68,8 @@ typedef struct {
   int32_t tile_box;        /* slots per tile of the expansion translation stages (M2M, L2L
                               chains, M2L): 16, 32 or 64; 0 = default (32). The expansion
                               stages whose other side is leaf data (S2M, S2L, their transposes,
-                              the low-rank near field's pair stages) and the factored M2L at
-                              expansion order 31 take 64. */
+                              the low-rank near field's pair stages) take 64, and so does the
+                              factored M2L at expansion order 31 in place of 32. */
   const char* table_cache; /* directory for the host table cache; NULL = keep tables in memory */
   int32_t split_min;       /* each stage is cut into as many equal shares of its k-chunks as the
                               device runs blocks at once; a share has at least this many chunks

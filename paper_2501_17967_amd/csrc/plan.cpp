@@ -902,13 +902,13 @@ int build_plan(int32_t n_trees, const int64_t* offsets, const double* centres, c
     for (auto& f : st.r1fam) f = {A_NONE, 0, 0};
   };
   // the factored M2L: rows of the padded core, K and the k-chunk in complex terms (one chunk a
-  // segment); the output keeps its 2q reals per box. At q = 32 it takes 64-slot tiles (waves of
-  // 16 rows and 32 slots), whatever tile_box says
+  // segment); the output keeps its 2q reals per box. At q = 32 the default 32-slot tiles become
+  // 64-slot ones (waves of 16 rows and 32 slots); 16 slots, which small trees tune to, stay
   auto m2l_factored = [&](Stage& st, bool adj) {
     st.cx_rel = kRelH + (adj ? kNumFwd : 0);
     st.M = mats.M[size_t(st.cx_rel)];
     st.K = st.KC = mats.K[size_t(st.cx_rel)];
-    if (st.KC == 32) st.NT = 64;
+    if (st.KC == 32 && st.NT == 32) st.NT = 64;
   };
   // boxes at levels >= 2 ordered by (level, quadrant, tree, morton): targets of one tile then
   // share their V-list offset pattern
